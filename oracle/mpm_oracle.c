@@ -1,0 +1,633 @@
+/*
+ * FP64 CPU oracle for the MLS-MPM Neo-Hookean tissue substep of
+ * arXiv 2402.01181 (Sec. III-B "Material Point Method", Sec. III-C
+ * "Collision Detection and Handling").
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg.  Plain serial loops, no blocking, fusion or
+ * reordering beyond what the equations state.  Shares no code with the HIP
+ * library.
+ *
+ * Readings of the paper (where it is silent, ambiguous or garbled):
+ *  R1  Stress: the printed P = mu (F - F^T) + lambda log J F^-T is read as the
+ *      compressible Neo-Hookean P = mu (F - F^-T) + lambda ln J F^-T (the
+ *      printed F - F^T is antisymmetric and would give no stress under any
+ *      stretch).  P F^T = mu (F F^T - I) + lambda ln J I is used directly.
+ *  R2  The stress in the MLS force uses the current F; F is updated at the end
+ *      of G2P as F <- (I + dt C_new) F.  ("1 + dt C" of the paper is I + dt C.)
+ *  R3  Weights: quadratic B-spline, base = floor(x/dx - 0.5).
+ *  R4  The 4/dx^2 factor is the inverse of the quadratic-B-spline inertia
+ *      D_p = dx^2/4 I.
+ *  R5  Gravity is added after normalisation: v_i = (mv)_i/m_i + dt g.
+ *  R6  Domain boundary: sticky, v_i = 0 on nodes with any index < bound or
+ *      >= n - bound; applied last in the grid operation.
+ *  R7  Empty nodes (m_i == 0 exactly) get v_i = 0.
+ *  R8  Grid-operation order: normalise, gravity, tool projection, boundary.
+ *  R9  Contact iff the merged distance is < theta (per tool).
+ *  R10 Tool distance: analytic capsule SDF in the tool frame (segment on the
+ *      tool-frame x axis) and its analytic gradient as the normal, in place of
+ *      a sampled SDF and central differences.
+ *  R11 Normal n = R grad/|grad|; on the capsule axis n = R e_y.
+ *  R12 Friction: Coulomb projection v_rel' = max(0, 1 + mu_f v_n/|v_t|) v_t,
+ *      and 0 when |v_t| = 0 (the printed formula has no static clamp).
+ *  R13 Slip contact projects only when v_n < 0; sticky contact sets the node
+ *      velocity to the tool velocity whenever in contact.
+ *  R14 Tool velocity field v_co = u (no rotation); pose advances every
+ *      substep, T_{s+1} = T_s + dt u_s.
+ *  R15 z-buffer over tools: strict < scanning ids upward, so ties go to the
+ *      lowest id.
+ *  R16 J <= 1e-6 flags INVERTED and the stress uses ln(1e-6).
+ *  R17 A particle whose stencil leaves the grid (base < 0 or base + 2 > n - 1)
+ *      flags OUT_OF_DOMAIN and takes no part in the transfers; its state is
+ *      left unchanged.
+ */
+#include "mpm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(n, i, j, k) ((((size_t)(i)) * (size_t)(n) + (size_t)(j)) * (size_t)(n) + (size_t)(k))
+
+static double det3(const double A[9])
+{
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* Inverse-transpose via the cofactor matrix: F^-T = cof(F) / det F. */
+static void inv_transpose3(const double A[9], double out[9])
+{
+    double d = det3(A);
+    out[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+    out[1] = -(A[3] * A[8] - A[5] * A[6]) / d;
+    out[2] = (A[3] * A[7] - A[4] * A[6]) / d;
+    out[3] = -(A[1] * A[8] - A[2] * A[7]) / d;
+    out[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+    out[5] = -(A[0] * A[7] - A[1] * A[6]) / d;
+    out[6] = (A[1] * A[5] - A[2] * A[4]) / d;
+    out[7] = -(A[0] * A[5] - A[2] * A[3]) / d;
+    out[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+}
+
+/* Lame parameters from Young's modulus and Poisson's ratio (Sec. III-B, the
+ * mu / lambda equation). */
+void orc_lame(double E, double nu, double *mu, double *lam)
+{
+    *mu = E / (2.0 * (1.0 + nu));
+    *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+}
+
+/* Quadratic B-spline weights per axis (R3) and their derivatives with
+ * respect to fx.  w[d][o] is the weight of node base[d] + o along axis d. */
+void orc_weights(const double x[3], double inv_dx, int base[3], double fx[3], double w[3][3],
+                 double dw[3][3])
+{
+    for (int d = 0; d < 3; ++d) {
+        double s = x[d] * inv_dx;
+        base[d] = (int)floor(s - 0.5);
+        fx[d] = s - base[d];
+        double f = fx[d];
+        w[d][0] = 0.5 * (1.5 - f) * (1.5 - f);
+        w[d][1] = 0.75 - (f - 1.0) * (f - 1.0);
+        w[d][2] = 0.5 * (f - 0.5) * (f - 0.5);
+        if (dw) {
+            dw[d][0] = -(1.5 - f);
+            dw[d][1] = -2.0 * (f - 1.0);
+            dw[d][2] = f - 0.5;
+        }
+    }
+}
+
+/* Kirchhoff stress tau = P F^T of the Neo-Hookean model (R1, R16). */
+uint32_t orc_kirchhoff(const double F[9], double mu, double lam, double tau[9])
+{
+    uint32_t flags = 0;
+    double J = det3(F);
+    if (!(J > ORC_J_MIN)) {
+        flags |= ORC_FLAG_INVERTED;
+        J = ORC_J_MIN;
+    }
+    double lnJ = log(J);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double FFt = 0.0;
+            for (int c = 0; c < 3; ++c) FFt += F[3 * a + c] * F[3 * b + c];
+            tau[3 * a + b] = mu * (FFt - (a == b ? 1.0 : 0.0)) + (a == b ? lam * lnJ : 0.0);
+        }
+    return flags;
+}
+
+/* Capsule signed distance in the tool frame (R10): distance from the segment
+ * [-h, h] x e_x minus the radius.  q receives the offset from the closest
+ * segment point; *interior tells whether the closest point is strictly inside
+ * the segment. */
+double orc_capsule_sdf(const double xref[3], double radius, double half_len, double q[3], int *interior)
+{
+    double c = xref[0];
+    int in = 1;
+    if (c < -half_len) { c = -half_len; in = 0; }
+    if (c > half_len) { c = half_len; in = 0; }
+    q[0] = xref[0] - c;
+    q[1] = xref[1];
+    q[2] = xref[2];
+    if (interior) *interior = in;
+    return sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) - radius;
+}
+
+static int out_of_domain(const int base[3], int n)
+{
+    for (int d = 0; d < 3; ++d)
+        if (base[d] < 0 || base[d] + 2 > n - 1) return 1;
+    return 0;
+}
+
+/* P2G (Sec. III-B item 1, Eq. P2G and Eq. fip):
+ *   m_i    = sum_p w_ip m_p
+ *   (mv)_i = sum_p w_ip [ m_p v_p + m_p C_p (x_i - x_p) + f_ip dt ]
+ *   f_ip dt = -dt V0 (4/dx^2) tau_p (x_i - x_p)                          */
+uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
+                 const double *F, double *gm, double *gmv)
+{
+    const int n = P->n;
+    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
+    const double m = P->rho * P->V0;
+    double mu, lam;
+    uint32_t flags = 0;
+    orc_lame(P->E, P->nu, &mu, &lam);
+    memset(gm, 0, sizeof(double) * (size_t)n * n * n);
+    memset(gmv, 0, sizeof(double) * 3 * (size_t)n * n * n);
+    for (int p = 0; p < N; ++p) {
+        int base[3];
+        double fx[3], w[3][3], tau[9], A[9];
+        orc_weights(x + 3 * p, inv_dx, base, fx, w, NULL);
+        if (out_of_domain(base, n)) {
+            flags |= ORC_FLAG_OUT_OF_DOMAIN;
+            continue;
+        }
+        flags |= orc_kirchhoff(F + 9 * p, mu, lam, tau);
+        for (int k = 0; k < 9; ++k) A[k] = -P->dt * P->V0 * D * tau[k] + m * C[9 * p + k];
+        for (int o0 = 0; o0 < 3; ++o0)
+            for (int o1 = 0; o1 < 3; ++o1)
+                for (int o2 = 0; o2 < 3; ++o2) {
+                    double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+                    double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                    size_t i = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                    gm[i] += wt * m;
+                    for (int a = 0; a < 3; ++a) {
+                        double Ad = A[3 * a + 0] * dpos[0] + A[3 * a + 1] * dpos[1] + A[3 * a + 2] * dpos[2];
+                        gmv[3 * i + a] += wt * (m * v[3 * p + a] + Ad);
+                    }
+                }
+    }
+    return flags;
+}
+
+/* World-frame contact normal of tool t at tool-frame offset q (R11). */
+static void capsule_normal(const orc_tool *tl, const double q[3], double nrm[3])
+{
+    double len = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    double nl[3];
+    if (len < 1e-12) {
+        nl[0] = 0.0; nl[1] = 1.0; nl[2] = 0.0;
+    } else {
+        nl[0] = q[0] / len; nl[1] = q[1] / len; nl[2] = q[2] / len;
+    }
+    for (int a = 0; a < 3; ++a) nrm[a] = tl->R[3 * a + 0] * nl[0] + tl->R[3 * a + 1] * nl[1] + tl->R[3 * a + 2] * nl[2];
+}
+
+/* Grid operation (Sec. III-B item 2, Sec. III-C) for every node, with the
+ * tool poses T[t][3] and velocities u[t][3] of this substep. */
+void orc_grid_update(const orc_params *P, const orc_tool *tools, const double *T, const double *u,
+                     const double *gm, const double *gmv, double *gv, orc_node_rec *rec)
+{
+    const int n = P->n;
+    const double dx = 1.0 / n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                size_t id = IDX(n, i, j, k);
+                orc_node_rec r;
+                memset(&r, 0, sizeof r);
+                r.tool = -1;
+                double vv[3] = {0.0, 0.0, 0.0};
+                int wall = (i < P->bound || j < P->bound || k < P->bound || i >= n - P->bound ||
+                            j >= n - P->bound || k >= n - P->bound);
+                r.wall = wall;
+                if (gm[id] > 0.0) {
+                    for (int a = 0; a < 3; ++a) vv[a] = gmv[3 * id + a] / gm[id] + P->dt * P->g[a];
+                    memcpy(r.vhat, vv, sizeof vv);
+                    /* z-buffer: nearest tool, ties to the lowest id (R15) */
+                    double xi[3] = {i * dx, j * dx, k * dx};
+                    double best = INFINITY, bq[3] = {0, 0, 0};
+                    int bt = -1, bin = 0;
+                    for (int t = 0; t < P->n_tools; ++t) {
+                        const orc_tool *tl = &tools[t];
+                        double d[3] = {xi[0] - T[3 * t + 0], xi[1] - T[3 * t + 1], xi[2] - T[3 * t + 2]};
+                        double xr[3], q[3];
+                        int in;
+                        for (int a = 0; a < 3; ++a) xr[a] = tl->R[0 + a] * d[0] + tl->R[3 + a] * d[1] + tl->R[6 + a] * d[2];
+                        double phi = orc_capsule_sdf(xr, tl->radius, tl->half_len, q, &in);
+                        if (phi < best) { best = phi; bt = t; memcpy(bq, q, sizeof q); bin = in; }
+                    }
+                    if (bt >= 0 && best < tools[bt].theta) {
+                        const orc_tool *tl = &tools[bt];
+                        const double *uc = u + 3 * bt;
+                        double nrm[3];
+                        capsule_normal(tl, bq, nrm);
+                        r.tool = bt;
+                        memcpy(r.n, nrm, sizeof nrm);
+                        memcpy(r.q, bq, sizeof bq);
+                        r.interior = bin;
+                        if (tl->contact == ORC_CONTACT_STICKY) {
+                            for (int a = 0; a < 3; ++a) vv[a] = uc[a];
+                            r.branch = 2;
+                        } else {
+                            double vr[3] = {vv[0] - uc[0], vv[1] - uc[1], vv[2] - uc[2]};
+                            double vn = vr[0] * nrm[0] + vr[1] * nrm[1] + vr[2] * nrm[2];
+                            if (vn < 0.0) {
+                                double vt[3] = {vr[0] - vn * nrm[0], vr[1] - vn * nrm[1], vr[2] - vn * nrm[2]};
+                                double nt = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+                                double s = 0.0;
+                                if (nt > 0.0) {
+                                    s = 1.0 + tl->friction * vn / nt;
+                                    if (s < 0.0) s = 0.0;
+                                }
+                                r.branch = (s > 0.0) ? 1 : 2;
+                                for (int a = 0; a < 3; ++a) vv[a] = s * vt[a] + uc[a];
+                            }
+                        }
+                    }
+                    if (wall) vv[0] = vv[1] = vv[2] = 0.0;
+                }
+                for (int a = 0; a < 3; ++a) gv[3 * id + a] = vv[a];
+                if (rec) rec[id] = r;
+            }
+}
+
+/* G2P and advection (Sec. III-B item 3) followed by the F update (R2):
+ *   v_p = sum_i w_ip v_i,  C_p = (4/dx^2) sum_i w_ip v_i (x_i - x_p)^T,
+ *   x_p += dt v_p,  F_p <- (I + dt C_p) F_p.                              */
+uint32_t orc_g2p(const orc_params *P, int32_t N, double *x, double *v, double *C, double *F,
+                 const double *gv)
+{
+    const int n = P->n;
+    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
+    uint32_t flags = 0;
+    for (int p = 0; p < N; ++p) {
+        int base[3];
+        double fx[3], w[3][3];
+        orc_weights(x + 3 * p, inv_dx, base, fx, w, NULL);
+        if (out_of_domain(base, n)) {
+            flags |= ORC_FLAG_OUT_OF_DOMAIN;
+            continue;
+        }
+        double vp[3] = {0, 0, 0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int o0 = 0; o0 < 3; ++o0)
+            for (int o1 = 0; o1 < 3; ++o1)
+                for (int o2 = 0; o2 < 3; ++o2) {
+                    double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+                    double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                    const double *vi = gv + 3 * IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                    for (int a = 0; a < 3; ++a) {
+                        vp[a] += wt * vi[a];
+                        for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * dpos[b];
+                    }
+                }
+        double Fn[9];
+        for (int a = 0; a < 3; ++a) {
+            v[3 * p + a] = vp[a];
+            x[3 * p + a] += P->dt * vp[a];
+            for (int b = 0; b < 3; ++b) C[9 * p + 3 * a + b] = D * B[3 * a + b];
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c)
+                    s += ((a == c ? 1.0 : 0.0) + P->dt * C[9 * p + 3 * a + c]) * F[9 * p + 3 * c + b];
+                Fn[3 * a + b] = s;
+            }
+        memcpy(F + 9 * p, Fn, sizeof Fn);
+        if (!(det3(Fn) > ORC_J_MIN)) flags |= ORC_FLAG_INVERTED;
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(x[3 * p + a]) || !isfinite(v[3 * p + a])) flags |= ORC_FLAG_NONFINITE;
+    }
+    return flags;
+}
+
+/* One substep with tool poses T (advanced in place, R14) and velocities u. */
+uint32_t orc_substep(const orc_params *P, const orc_tool *tools, double *T, const double *u,
+                     int32_t N, double *x, double *v, double *C, double *F,
+                     double *gm, double *gmv, double *gv)
+{
+    uint32_t flags = orc_p2g(P, N, x, v, C, F, gm, gmv);
+    orc_grid_update(P, tools, T, u, gm, gmv, gv, NULL);
+    flags |= orc_g2p(P, N, x, v, C, F, gv);
+    for (int t = 0; t < P->n_tools; ++t)
+        for (int a = 0; a < 3; ++a) T[3 * t + a] += P->dt * u[3 * t + a];
+    return flags;
+}
+
+/* Velocities of every tool at absolute substep s; traj is [n_tools][n_traj][3]
+ * and the last entry is held beyond the end. */
+static void traj_at(const orc_params *P, const double *traj, int32_t n_traj, int32_t s, double *u)
+{
+    int k = s < n_traj ? s : n_traj - 1;
+    for (int t = 0; t < P->n_tools; ++t)
+        for (int a = 0; a < 3; ++a) u[3 * t + a] = traj[((size_t)t * n_traj + k) * 3 + a];
+}
+
+uint32_t orc_run(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
+                 int32_t s0, int32_t S, double *T, int32_t N, double *x, double *v, double *C,
+                 double *F)
+{
+    size_t nn = (size_t)P->n * P->n * P->n;
+    double *gm = malloc(sizeof(double) * nn), *gmv = malloc(sizeof(double) * 3 * nn),
+           *gv = malloc(sizeof(double) * 3 * nn);
+    double u[3 * 64];
+    uint32_t flags = 0;
+    for (int s = s0; s < s0 + S; ++s) {
+        if (P->n_tools > 0) traj_at(P, traj, n_traj, s, u);
+        flags |= orc_substep(P, tools, T, u, N, x, v, C, F, gm, gmv, gv);
+    }
+    free(gm); free(gmv); free(gv);
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint: exact transpose of the substep recurrence above, with a full tape
+ * (the state at the start of every substep) and the grid of each substep
+ * recomputed in reverse.                                                    */
+
+/* Reverse of the grid operation at one node.  vbar_out is the adjoint of the
+ * node's final velocity; returns the adjoint of vhat in vhbar and adds the
+ * tool-velocity and tool-position adjoints of the colliding tool. */
+static void grid_node_adjoint(const orc_tool *tools, const double *u, const orc_node_rec *r,
+                              const double vbar_out[3], double vhbar[3], double *ubar, double *Tbar)
+{
+    vhbar[0] = vhbar[1] = vhbar[2] = 0.0;
+    if (r->wall) return;
+    if (r->tool < 0 || r->branch == 0) {
+        memcpy(vhbar, vbar_out, 3 * sizeof(double));
+        return;
+    }
+    int t = r->tool;
+    const orc_tool *tl = &tools[t];
+    const double *uc = u + 3 * t;
+    for (int a = 0; a < 3; ++a) ubar[3 * t + a] += vbar_out[a];
+    if (r->branch == 2) return;
+    /* friction branch: v = s v_t + u, s = 1 + mu vn/|vt| */
+    const double *nrm = r->n;
+    double vr[3] = {r->vhat[0] - uc[0], r->vhat[1] - uc[1], r->vhat[2] - uc[2]};
+    double vn = vr[0] * nrm[0] + vr[1] * nrm[1] + vr[2] * nrm[2];
+    double vt[3] = {vr[0] - vn * nrm[0], vr[1] - vn * nrm[1], vr[2] - vn * nrm[2]};
+    double nt = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+    double s = 1.0 + tl->friction * vn / nt;
+    const double *a_ = vbar_out;
+    double sbar = a_[0] * vt[0] + a_[1] * vt[1] + a_[2] * vt[2];
+    double vtbar[3] = {s * a_[0], s * a_[1], s * a_[2]};
+    double vnbar = sbar * tl->friction / nt;
+    double ntbar = -sbar * tl->friction * vn / (nt * nt);
+    for (int k = 0; k < 3; ++k) vtbar[k] += ntbar * vt[k] / nt;
+    double vrbar[3], nbar[3];
+    double vtn = vtbar[0] * nrm[0] + vtbar[1] * nrm[1] + vtbar[2] * nrm[2];
+    vnbar -= vtn;
+    for (int k = 0; k < 3; ++k) {
+        vrbar[k] = vtbar[k] + vnbar * nrm[k];
+        nbar[k] = -vn * vtbar[k] + vnbar * vr[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        vhbar[k] = vrbar[k];
+        ubar[3 * t + k] -= vrbar[k];
+    }
+    /* n = R q/|q|, q = q(x_ref), x_ref = R^T (x_i - T) */
+    double ql = sqrt(r->q[0] * r->q[0] + r->q[1] * r->q[1] + r->q[2] * r->q[2]);
+    if (ql < 1e-12) return;
+    double nl[3] = {r->q[0] / ql, r->q[1] / ql, r->q[2] / ql};
+    double nlbar[3];
+    for (int b = 0; b < 3; ++b) nlbar[b] = tl->R[0 + b] * nbar[0] + tl->R[3 + b] * nbar[1] + tl->R[6 + b] * nbar[2];
+    double dotn = nlbar[0] * nl[0] + nlbar[1] * nl[1] + nlbar[2] * nl[2];
+    double qbar[3];
+    for (int b = 0; b < 3; ++b) qbar[b] = (nlbar[b] - dotn * nl[b]) / ql;
+    double xrbar[3] = {r->interior ? 0.0 : qbar[0], qbar[1], qbar[2]};
+    for (int a = 0; a < 3; ++a)
+        Tbar[3 * t + a] -= tl->R[3 * a + 0] * xrbar[0] + tl->R[3 * a + 1] * xrbar[1] + tl->R[3 * a + 2] * xrbar[2];
+}
+
+uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
+                     int32_t S, const double *T0, int32_t N, const double *x0, const double *v0,
+                     const double *C0, const double *F0, double *xbar, double *vbar, double *Cbar,
+                     double *Fbar, double *gE, double *gnu, double *gu, double *gT0)
+{
+    const int n = P->n, nt = P->n_tools;
+    const size_t nn = (size_t)n * n * n;
+    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
+    const double m = P->rho * P->V0, dt = P->dt;
+    double mu, lam;
+    orc_lame(P->E, P->nu, &mu, &lam);
+    uint32_t flags = 0;
+
+    /* forward with a full tape of substep-start states and tool poses */
+    double *tx = malloc(sizeof(double) * 3 * N * (size_t)S), *tv = malloc(sizeof(double) * 3 * N * (size_t)S);
+    double *tC = malloc(sizeof(double) * 9 * N * (size_t)S), *tF = malloc(sizeof(double) * 9 * N * (size_t)S);
+    double *tT = malloc(sizeof(double) * 3 * (nt > 0 ? nt : 1) * (size_t)(S + 1));
+    double *tu = malloc(sizeof(double) * 3 * (nt > 0 ? nt : 1) * (size_t)S);
+    double *x = malloc(sizeof(double) * 3 * N), *v = malloc(sizeof(double) * 3 * N);
+    double *C = malloc(sizeof(double) * 9 * N), *F = malloc(sizeof(double) * 9 * N);
+    double *gm = malloc(sizeof(double) * nn), *gmv = malloc(sizeof(double) * 3 * nn), *gv = malloc(sizeof(double) * 3 * nn);
+    double *gvbar = malloc(sizeof(double) * 3 * nn), *gmbar = malloc(sizeof(double) * nn), *gmvbar = malloc(sizeof(double) * 3 * nn);
+    orc_node_rec *rec = malloc(sizeof(orc_node_rec) * nn);
+    double *Tbar = calloc(3 * (nt > 0 ? nt : 1) * (size_t)S, sizeof(double));
+    double *T = malloc(sizeof(double) * 3 * (nt > 0 ? nt : 1));
+
+    memcpy(x, x0, sizeof(double) * 3 * N); memcpy(v, v0, sizeof(double) * 3 * N);
+    memcpy(C, C0, sizeof(double) * 9 * N); memcpy(F, F0, sizeof(double) * 9 * N);
+    if (nt > 0) memcpy(T, T0, sizeof(double) * 3 * nt);
+    for (int s = 0; s < S; ++s) {
+        memcpy(tx + 3 * (size_t)N * s, x, sizeof(double) * 3 * N);
+        memcpy(tv + 3 * (size_t)N * s, v, sizeof(double) * 3 * N);
+        memcpy(tC + 9 * (size_t)N * s, C, sizeof(double) * 9 * N);
+        memcpy(tF + 9 * (size_t)N * s, F, sizeof(double) * 9 * N);
+        if (nt > 0) {
+            memcpy(tT + 3 * (size_t)nt * s, T, sizeof(double) * 3 * nt);
+            traj_at(P, traj, n_traj, s, tu + 3 * (size_t)nt * s);
+        }
+        flags |= orc_substep(P, tools, T, nt > 0 ? tu + 3 * (size_t)nt * s : NULL, N, x, v, C, F, gm, gmv, gv);
+    }
+
+    double mubar = 0.0, lambar = 0.0;
+    if (nt > 0) memset(gu, 0, sizeof(double) * 3 * nt * (size_t)S);
+    for (int s = S - 1; s >= 0; --s) {
+        /* restore the substep-start state and recompute the substep's grid */
+        memcpy(x, tx + 3 * (size_t)N * s, sizeof(double) * 3 * N);
+        memcpy(v, tv + 3 * (size_t)N * s, sizeof(double) * 3 * N);
+        memcpy(C, tC + 9 * (size_t)N * s, sizeof(double) * 9 * N);
+        memcpy(F, tF + 9 * (size_t)N * s, sizeof(double) * 9 * N);
+        const double *Ts = tT + 3 * (size_t)nt * s, *us = tu + 3 * (size_t)nt * s;
+        orc_p2g(P, N, x, v, C, F, gm, gmv);
+        orc_grid_update(P, tools, Ts, us, gm, gmv, gv, rec);
+
+        /* reverse of F update, advection and G2P */
+        memset(gvbar, 0, sizeof(double) * 3 * nn);
+        for (int p = 0; p < N; ++p) {
+            int base[3];
+            double fx[3], w[3][3], dw[3][3];
+            orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
+            if (out_of_domain(base, n)) continue;  /* state passes through unchanged */
+            /* forward values of this particle's G2P */
+            double vp[3] = {0, 0, 0}, B[9] = {0};
+            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+                double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                const double *vi = gv + 3 * IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                for (int a = 0; a < 3; ++a) {
+                    vp[a] += wt * vi[a];
+                    for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * dpos[b];
+                }
+            }
+            double Cn[9];
+            for (int k = 0; k < 9; ++k) Cn[k] = D * B[k];
+            const double *Fp = F + 9 * p;
+            double *Fb = Fbar + 9 * p, *Cb = Cbar + 9 * p, *vb = vbar + 3 * p, *xb = xbar + 3 * p;
+            /* F' = (I + dt C') F */
+            double Fbn[9], Cbt[9];
+            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+                double s1 = 0.0, s2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    s1 += ((c == a ? 1.0 : 0.0) + dt * Cn[3 * c + a]) * Fb[3 * c + b];
+                    s2 += Fb[3 * a + c] * Fp[3 * b + c];
+                }
+                Fbn[3 * a + b] = s1;
+                Cbt[3 * a + b] = Cb[3 * a + b] + dt * s2;
+            }
+            /* x' = x + dt v' */
+            double vbt[3] = {vb[0] + dt * xb[0], vb[1] + dt * xb[1], vb[2] + dt * xb[2]};
+            double fxbar[3] = {0, 0, 0};
+            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+                int o[3] = {o0, o1, o2};
+                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+                double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                const double *vi = gv + 3 * id;
+                double g[3];
+                for (int a = 0; a < 3; ++a)
+                    g[a] = vbt[a] + D * (Cbt[3 * a + 0] * dpos[0] + Cbt[3 * a + 1] * dpos[1] + Cbt[3 * a + 2] * dpos[2]);
+                for (int a = 0; a < 3; ++a) gvbar[3 * id + a] += wt * g[a];
+                double wbar = vi[0] * g[0] + vi[1] * g[1] + vi[2] * g[2];
+                for (int b = 0; b < 3; ++b) {
+                    double dposbar = wt * D * (Cbt[0 + b] * vi[0] + Cbt[3 + b] * vi[1] + Cbt[6 + b] * vi[2]);
+                    double dwd = dw[b][o[b]];
+                    for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
+                    fxbar[b] += -dx * dposbar + wbar * dwd;
+                }
+            }
+            for (int a = 0; a < 3; ++a) xb[a] += inv_dx * fxbar[a];
+            memcpy(Fb, Fbn, sizeof Fbn);
+            for (int k = 0; k < 9; ++k) Cb[k] = 0.0;
+            vb[0] = vb[1] = vb[2] = 0.0;
+        }
+
+        /* reverse of the grid operation */
+        for (size_t id = 0; id < nn; ++id) {
+            gmbar[id] = 0.0;
+            gmvbar[3 * id] = gmvbar[3 * id + 1] = gmvbar[3 * id + 2] = 0.0;
+            if (!(gm[id] > 0.0)) continue;
+            double vhbar[3];
+            grid_node_adjoint(tools, us, &rec[id], gvbar + 3 * id, vhbar,
+                              gu + 3 * (size_t)nt * s, Tbar + 3 * (size_t)nt * s);
+            double pv[3];
+            for (int a = 0; a < 3; ++a) {
+                gmvbar[3 * id + a] = vhbar[a] / gm[id];
+                pv[a] = gmv[3 * id + a] / gm[id];
+            }
+            gmbar[id] = -(vhbar[0] * pv[0] + vhbar[1] * pv[1] + vhbar[2] * pv[2]) / gm[id];
+        }
+
+        /* reverse of P2G and of the stress */
+        for (int p = 0; p < N; ++p) {
+            int base[3];
+            double fx[3], w[3][3], dw[3][3], tau[9], A[9];
+            orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
+            if (out_of_domain(base, n)) continue;
+            const double *Fp = F + 9 * p;
+            orc_kirchhoff(Fp, mu, lam, tau);
+            for (int k = 0; k < 9; ++k) A[k] = -dt * P->V0 * D * tau[k] + m * C[9 * p + k];
+            double vbp[3] = {0, 0, 0}, Abar[9] = {0}, fxbar[3] = {0, 0, 0};
+            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+                int o[3] = {o0, o1, o2};
+                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+                double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                const double *Pb = gmvbar + 3 * id;
+                double contrib[3];
+                for (int a = 0; a < 3; ++a) {
+                    vbp[a] += m * wt * Pb[a];
+                    for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * Pb[a] * dpos[b];
+                    contrib[a] = m * v[3 * p + a] + A[3 * a + 0] * dpos[0] + A[3 * a + 1] * dpos[1] + A[3 * a + 2] * dpos[2];
+                }
+                double wbar = m * gmbar[id] + Pb[0] * contrib[0] + Pb[1] * contrib[1] + Pb[2] * contrib[2];
+                for (int b = 0; b < 3; ++b) {
+                    double dposbar = wt * (A[0 + b] * Pb[0] + A[3 + b] * Pb[1] + A[6 + b] * Pb[2]);
+                    double dwd = dw[b][o[b]];
+                    for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
+                    fxbar[b] += -dx * dposbar + wbar * dwd;
+                }
+            }
+            double *xb = xbar + 3 * p;
+            for (int a = 0; a < 3; ++a) {
+                xb[a] += inv_dx * fxbar[a];
+                vbar[3 * p + a] += vbp[a];
+            }
+            for (int k = 0; k < 9; ++k) Cbar[9 * p + k] += m * Abar[k];
+            double taub[9];
+            for (int k = 0; k < 9; ++k) taub[k] = -dt * P->V0 * D * Abar[k];
+            double J = det3(Fp);
+            double trt = taub[0] + taub[4] + taub[8];
+            double FFt_I = 0.0;
+            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+                double FFt = 0.0;
+                for (int c = 0; c < 3; ++c) FFt += Fp[3 * a + c] * Fp[3 * b + c];
+                FFt_I += taub[3 * a + b] * (FFt - (a == b ? 1.0 : 0.0));
+            }
+            mubar += FFt_I;
+            double *Fb = Fbar + 9 * p;
+            if (J > ORC_J_MIN) {
+                double Fit[9];
+                inv_transpose3(Fp, Fit);
+                lambar += trt * log(J);
+                for (int k = 0; k < 9; ++k) Fb[k] += lam * trt * Fit[k];
+            } else {
+                lambar += trt * log(ORC_J_MIN);
+            }
+            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+                double s1 = 0.0;
+                for (int c = 0; c < 3; ++c) s1 += (taub[3 * a + c] + taub[3 * c + a]) * Fp[3 * c + b];
+                Fb[3 * a + b] += mu * s1;
+            }
+        }
+    }
+
+    /* tool pose T_s = T_0 + dt sum_{s'<s} u_{s'} */
+    if (nt > 0) {
+        for (int t = 0; t < nt; ++t) {
+            double acc[3] = {0, 0, 0};
+            for (int s = S - 1; s >= 0; --s) {
+                for (int a = 0; a < 3; ++a) gu[3 * ((size_t)nt * s + t) + a] += dt * acc[a];
+                for (int a = 0; a < 3; ++a) acc[a] += Tbar[3 * ((size_t)nt * s + t) + a];
+            }
+            if (gT0) for (int a = 0; a < 3; ++a) gT0[3 * t + a] = acc[a];
+        }
+    }
+    /* chain rule through the Lame parameters */
+    double nu = P->nu, E = P->E;
+    double dmu_dE = 1.0 / (2.0 * (1.0 + nu)), dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+    double dlam_dE = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double dlam_dnu = E * (1.0 + 2.0 * nu * nu) / ((1.0 + nu) * (1.0 + nu) * (1.0 - 2.0 * nu) * (1.0 - 2.0 * nu));
+    *gE = mubar * dmu_dE + lambar * dlam_dE;
+    *gnu = mubar * dmu_dnu + lambar * dlam_dnu;
+
+    free(tx); free(tv); free(tC); free(tF); free(tT); free(tu);
+    free(x); free(v); free(C); free(F); free(gm); free(gmv); free(gv);
+    free(gvbar); free(gmbar); free(gmvbar); free(rec); free(Tbar); free(T);
+    return flags;
+}
