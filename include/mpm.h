@@ -1,0 +1,193 @@
+/*
+ * mpm.h -- C ABI of the MI355X (gfx950) MLS-MPM tissue library.
+ *
+ * The library steps the MLS-MPM substep of arXiv 2402.01181 for Neo-Hookean
+ * tissue touched by rigid capsule tools: P2G (Sec. III-B item 1, Eq. P2G and
+ * Eq. fip), the grid operation with boundary nodes and tool contact
+ * (Sec. III-B item 2, Sec. III-C), G2P with advection (Sec. III-B item 3)
+ * and the deformation-gradient update, for one or many independent
+ * environments at once, plus the reverse (adjoint) of those substeps.
+ *
+ * Conventions shared by every entry point:
+ *  - Device memory is owned by the CALLER: initial state, material table,
+ *    tool trajectories, gradient outputs and the single workspace the
+ *    library carves all its device buffers from.  The library owns only the
+ *    host-side context object.  It never calls hipMalloc/hipFree.
+ *  - Streams are hipStream_t passed as void*; NULL means the null stream.
+ *    A context is used from one stream at a time and is not thread-safe.
+ *  - Particle arrays are FP32, structure-of-arrays, component-major and
+ *    environment-concatenated: x[3][Ntot], v[3][Ntot], C[9][Ntot],
+ *    F[9][Ntot] (matrix entry (a,b) is component 3a+b), Ntot = sum of the
+ *    per-environment particle counts in environment order.
+ *  - Environment e has a cubic grid of grid_n[e]^3 nodes on the unit cube,
+ *    dx = 1/grid_n[e]; node (i,j,k) sits at (i,j,k)*dx.
+ *  - No exceptions cross the ABI.  Every call returns MPM_OK or a negative
+ *    code; argument errors return MPM_E_ARG and change nothing; HIP runtime
+ *    failures return MPM_E_HIP; mpm_last_error() describes the last error.
+ *  - Conditions met inside kernels set sticky per-environment status bits
+ *    (MPM_FLAG_*), read with mpm_read_state(..., MPM_F_STATUS, ...).
+ *    mpm_substep and mpm_substep_adjoint never synchronise with the host and
+ *    issue only kernel launches, so a caller may capture them in a hipGraph.
+ */
+#ifndef MPM355_MPM_H
+#define MPM355_MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpm_ctx mpm_ctx;
+typedef int32_t mpm_status;
+
+enum {
+    MPM_OK = 0,
+    MPM_E_ARG = -1,          /* invalid argument; nothing changed */
+    MPM_E_HIP = -2,          /* a HIP runtime call failed */
+    MPM_E_STATE = -3,        /* call not valid in the current state (e.g. no tape) */
+    MPM_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+    MPM_E_WORKSPACE = -5     /* workspace missing, misaligned or too small */
+};
+
+/* Sticky per-environment status bits. */
+enum {
+    MPM_FLAG_OUT_OF_DOMAIN = 1u,    /* a particle's 3x3x3 stencil left the grid; it was frozen */
+    MPM_FLAG_INVERTED = 2u,         /* det F <= 1e-6 (FP64); the stress used ln(1e-6) */
+    MPM_FLAG_NONFINITE = 4u,        /* a particle position or velocity became non-finite */
+    MPM_FLAG_BARRIER_TIMEOUT = 8u   /* persistent kernel: a grid barrier exceeded its spin limit */
+};
+
+/* Fields for mpm_read_state. */
+enum {
+    MPM_F_X = 0,        /* float [3][N_env], original particle order */
+    MPM_F_V = 1,        /* float [3][N_env] */
+    MPM_F_C = 2,        /* float [9][N_env] */
+    MPM_F_F = 3,        /* float [9][N_env] */
+    MPM_F_GRID_M = 4,   /* float [n^3], node (i,j,k) at (i*n+j)*n+k: mass of the last P2G */
+    MPM_F_GRID_MV = 5,  /* float [3][n^3]: momentum of the last P2G */
+    MPM_F_GRID_V = 6,   /* float [3][n^3]: velocity after the last grid operation */
+    MPM_F_STATUS = 7,   /* uint32 [1]: sticky MPM_FLAG_* bits of the environment */
+    MPM_F_TOOL_T = 8,   /* double [max_tools][3]: current tool positions */
+    MPM_F_STEP = 9      /* int32 [1]: substeps taken by the environment */
+};
+
+enum { MPM_TOOL_CAPSULE = 0 };
+enum { MPM_CONTACT_SLIP = 0, MPM_CONTACT_STICKY = 1 };
+enum { MPM_STAGE_P2G = 0, MPM_STAGE_GRID = 1, MPM_STAGE_G2P = 2 };
+
+/* Tunables (mpm_set_option).  Every setting gives the same results up to
+ * the order of floating-point accumulation. */
+enum {
+    MPM_OPT_SCHEME = 0,       /* MPM_SCHEME_* */
+    MPM_OPT_SORT_EVERY = 1,   /* counting-sort particles by grid brick every k substeps (>= 1) */
+    MPM_OPT_BLOCK = 2,        /* threads per workgroup of the tiled particle kernels: 64, 128, 256 */
+    MPM_OPT_GRAPH = 3,        /* 1: mpm_substep replays an internally captured hipGraph */
+    MPM_OPT_PERSISTENT = 4,   /* 1: one persistent kernel per call with grid barriers */
+    MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
+    MPM_OPT_ITEM = 6          /* tiled scheme: max particles per work item, multiple of 64 in [64, 4096] */
+};
+enum {
+    MPM_SCHEME_DIRECT = 0,    /* one thread per particle, global float atomics, dense grid pass */
+    MPM_SCHEME_TILED = 1      /* brick-sorted particles, LDS tiles, fused G2P+P2G, active bricks */
+};
+
+typedef struct {
+    int32_t n_envs;              /* >= 1 */
+    const int32_t *n_particles;  /* host [n_envs], each >= 1 */
+    const int32_t *grid_n;       /* host [n_envs], multiple of 4, 8 <= n <= 512 */
+    float dt;                    /* substep length (s), > 0 */
+    float gravity[3];            /* m/s^2 */
+    int32_t bound;               /* boundary band width in nodes (sticky), >= 0 */
+    int32_t max_tools;           /* tool slots per environment, 0..8 */
+    int32_t checkpoint_every;    /* adjoint: state checkpoint interval (substeps), >= 1 */
+    int32_t max_tape_substeps;   /* adjoint: longest recordable tape; 0 disables the adjoint */
+    const float *x0, *v0, *C0, *F0;  /* device SoA as above; copied by mpm_create */
+    const float *material;       /* device [n_envs][4] = {E, nu, rho, V0}; read at every substep,
+                                    so the caller may change it between calls (graph-safe) */
+} mpm_desc;
+
+typedef struct {
+    int32_t shape;      /* MPM_TOOL_CAPSULE: segment [-half_len, half_len] on the tool-frame x axis */
+    int32_t contact;    /* MPM_CONTACT_SLIP (Coulomb friction) or MPM_CONTACT_STICKY */
+    float radius;       /* capsule radius (m), > 0 */
+    float half_len;     /* half segment length (m), >= 0 */
+    float friction;     /* Coulomb coefficient, >= 0 (slip only) */
+    float theta;        /* contact threshold: contact iff distance < theta (Sec. III-C) */
+    float R[9];         /* world-from-tool rotation, row-major */
+    float T0[3];        /* world position of the tool origin now */
+} mpm_tool;
+
+/* Adjoint inputs and outputs.  All pointers are device memory; particle
+ * arrays use the original particle order and the SoA layout above. */
+typedef struct {
+    const float *xbar, *vbar, *Cbar, *Fbar;  /* adjoints of the final state (NULL = 0) */
+    float *xbar0, *vbar0, *Cbar0, *Fbar0;    /* out: adjoints of the state n substeps earlier (NULL = skip) */
+    double *gE, *gnu;                        /* out [n_envs]: dL/dE, dL/dnu (NULL = skip) */
+    double *gu;                              /* out [n_envs][max_tools][n][3]: dL/du of each substep's tool velocity */
+    double *gT;                              /* out [n_envs][max_tools][3]: dL/dT of the tool positions n substeps earlier */
+} mpm_adjoint_io;
+
+/* Bytes of device workspace a context with this description needs.  Returns 0
+ * for an invalid description (mpm_create then reports why). */
+size_t mpm_workspace_size(const mpm_desc *desc);
+
+/* Create a context: validates desc, carves the caller's workspace (device
+ * memory of at least mpm_workspace_size(desc) bytes, 256-byte aligned, owned
+ * by the caller and kept alive until mpm_destroy), copies the initial state
+ * and clears the grids on `stream`.  Tools start unset.  On success *out owns
+ * a host object released by mpm_destroy. */
+mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_bytes, void *stream,
+                      mpm_ctx **out);
+
+/* Release the host object.  NULL is a no-op.  Does not touch the workspace. */
+void mpm_destroy(mpm_ctx *ctx);
+
+/* Set tool slot `tool` of environment `env` (Sec. III-C): shape, contact
+ * mode, pose.  u is a caller-owned device array [n_traj][3] of tool
+ * velocities; substep k after this call uses u[min(k, n_traj-1)] as the tool
+ * velocity v_co and then advances the position, T <- T + dt u (FP64).  u is
+ * read at every substep, so the caller may rewrite it between calls.
+ * n_traj >= 1.  Passing tool == NULL clears the slot. */
+mpm_status mpm_set_tool(mpm_ctx *ctx, int32_t env, int32_t tool, const mpm_tool *desc,
+                        const float *u, int32_t n_traj);
+
+/* Set a tunable (MPM_OPT_*).  Takes effect at the next substep call. */
+mpm_status mpm_set_option(mpm_ctx *ctx, int32_t option, int32_t value);
+
+/* Advance every environment by n_substeps >= 1 substeps on `stream`.
+ * record_tape != 0 starts a new adjoint tape at the current state and
+ * records these substeps (n_substeps <= max_tape_substeps).  Never
+ * synchronises. */
+mpm_status mpm_substep(mpm_ctx *ctx, int32_t n_substeps, int32_t record_tape, void *stream);
+
+/* Run one stage of a substep in isolation, with the same kernels as
+ * mpm_substep's direct scheme: P2G, then GRID, then G2P make one substep.
+ * For inspection and per-stage checking; not for throughput. */
+mpm_status mpm_run_stage(mpm_ctx *ctx, int32_t stage, void *stream);
+
+/* Reverse the last n_substeps recorded substeps (1 <= n <= tape length):
+ * given adjoints of the current state, produce adjoints of the state n
+ * substeps earlier and the parameter / tool gradients.  Restores tape
+ * checkpoints and recomputes forward segments internally; the forward state
+ * of the context is left as it was.  Returns MPM_E_STATE without a tape of
+ * at least n substeps.  Never synchronises. */
+mpm_status mpm_substep_adjoint(mpm_ctx *ctx, int32_t n_substeps, const mpm_adjoint_io *io,
+                               void *stream);
+
+/* Copy one field of environment env into dst (dst_bytes must equal the
+ * field's size).  dst_on_device != 0: dst is device memory and the copy is
+ * asynchronous on `stream`; otherwise dst is host memory and the call waits
+ * for `stream`.  Particle fields come back in the original particle order. */
+mpm_status mpm_read_state(mpm_ctx *ctx, int32_t env, int32_t field, void *dst, size_t dst_bytes,
+                          int32_t dst_on_device, void *stream);
+
+/* Message of the last failed call on ctx (or of the last failed mpm_create /
+ * mpm_workspace_size when ctx is NULL). Never NULL. */
+const char *mpm_last_error(const mpm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,154 @@
+// Counting sort of particles by grid brick (4x4x4 cells of the stencil base)
+// and the work-item list of the tiled scheme.  All kernels, no host sync.
+//
+//   1. k_brick_count: brick of each particle; rank within the brick by an
+//      atomic counter (histogram).
+//   2. scan of (count, items) per brick, items = ceil(count / P).
+//   3. k_make_items: (brick, first slot, count) per item, brick-major order.
+//   4. k_sort_scatter: move particle state into its sorted slot.
+#include "mpm_tiled.h"
+
+namespace mpm {
+
+__device__ __forceinline__ int particle_brick(const EnvDev &e, float x0, float x1, float x2)
+{
+    int b[3];
+    float xs[3] = {x0, x1, x2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // clamped in floating point (NaN -> 0): frozen particles go to an edge brick
+        float t = floorf(fminf(fmaxf(xs[a] * e.inv_dx - 0.5f, 0.0f), (float)(e.n - 3)));
+        b[a] = ((int)t) >> 2;
+    }
+    return e.bofs + (b[0] * e.nb + b[1]) * e.nb + b[2];
+}
+
+__global__ __launch_bounds__(256) void k_brick_count(Dev d, SortBuf s)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.ntot) return;
+    const EnvDev e = d.env[env_of_particle(d, q)];
+    const int N = d.ntot;
+    int b = particle_brick(e, d.x[q], d.x[N + q], d.x[2 * N + q]);
+    s.key[q] = b;
+    s.rank[q] = atomicAdd(&s.count[b].x, 1);
+}
+
+// Block-wide exclusive scan of int2 over 256 threads x 4 elements.
+constexpr int SCAN_T = 256, SCAN_E = 4, SCAN_CHUNK = SCAN_T * SCAN_E;
+
+__device__ __forceinline__ int2 add2(int2 a, int2 b) { return make_int2(a.x + b.x, a.y + b.y); }
+
+__device__ int2 block_exclusive_scan(int2 v, int2 *sh, int2 &total)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int2 a = t >= off ? sh[t - off] : make_int2(0, 0);
+        __syncthreads();
+        sh[t] = add2(sh[t], a);
+        __syncthreads();
+    }
+    int2 incl = sh[t];
+    total = sh[SCAN_T - 1];
+    __syncthreads();
+    return make_int2(incl.x - v.x, incl.y - v.y);
+}
+
+// Per brick: items = ceil(count / P); local exclusive scan per chunk.
+__global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int nb, int P)
+{
+    __shared__ int2 sh[SCAN_T];
+    int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_E;
+    int2 v[SCAN_E], sum = make_int2(0, 0);
+#pragma unroll
+    for (int i = 0; i < SCAN_E; ++i) {
+        int k = base + i;
+        int c = k < nb ? s.count[k].x : 0;
+        v[i] = make_int2(c, (c + P - 1) / P);
+        sum = add2(sum, v[i]);
+    }
+    int2 total;
+    int2 ex = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+    for (int i = 0; i < SCAN_E; ++i) {
+        int k = base + i;
+        if (k < nb) s.offset[k] = ex;
+        ex = add2(ex, v[i]);
+    }
+    if (threadIdx.x == 0) s.chunk_sum[blockIdx.x] = total;
+}
+
+// Scan of the chunk sums in one block; writes totals (particles, items).
+__global__ __launch_bounds__(SCAN_T) void k_scan_chunks(SortBuf s, int nchunks)
+{
+    __shared__ int2 sh[SCAN_T];
+    int2 carry = make_int2(0, 0);
+    for (int c0 = 0; c0 < nchunks; c0 += SCAN_T) {
+        int k = c0 + threadIdx.x;
+        int2 v = k < nchunks ? s.chunk_sum[k] : make_int2(0, 0);
+        int2 total;
+        int2 ex = block_exclusive_scan(v, sh, total);
+        if (k < nchunks) s.chunk_sum[k] = add2(ex, carry);
+        carry = add2(carry, total);
+    }
+    if (threadIdx.x == 0) *s.totals = carry;
+}
+
+// Add chunk prefixes; write the items of each brick.
+__global__ __launch_bounds__(256) void k_make_items(SortBuf s, int nb, int P)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    int2 o = add2(s.offset[k], s.chunk_sum[k / SCAN_CHUNK]);
+    s.offset[k] = o;
+    int c = s.count[k].x;
+    for (int j = 0, first = o.x; first < o.x + c; ++j, first += P) {
+        int cnt = o.x + c - first;
+        s.items[o.y + j] = make_int4(k, first, cnt < P ? cnt : P, 0);
+    }
+}
+
+// Move each particle to its slot; full = 1 also moves v and C.
+__global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, ParticleBuf dst, int full)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.ntot) return;
+    const int N = d.ntot;
+    int to = s.offset[s.key[q]].x + s.rank[q];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst.x[(size_t)c * N + to] = d.x[(size_t)c * N + q];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst.F[(size_t)c * N + to] = d.F[(size_t)c * N + q];
+    dst.pid[to] = d.pid[q];
+    if (full) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst.v[(size_t)c * N + to] = d.v[(size_t)c * N + q];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dst.C[(size_t)c * N + to] = d.C[(size_t)c * N + q];
+    }
+}
+
+__global__ void k_zero_counts(SortBuf s, int nb)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x)
+        s.count[k] = make_int2(0, 0);
+}
+
+void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
+                 hipStream_t st)
+{
+    int nblk = (total_bricks + 255) / 256;
+    hipLaunchKernelGGL(k_zero_counts, dim3(nblk < 4096 ? nblk : 4096), dim3(256), 0, st, s, total_bricks);
+    hipLaunchKernelGGL(k_brick_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
+    int nchunks = (total_bricks + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, total_bricks, P);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
+    hipLaunchKernelGGL(k_make_items, dim3(nblk), dim3(256), 0, st, s, total_bricks, P);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
+}
+
+size_t sort_chunk_count(int total_bricks) { return (total_bricks + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+
+}  // namespace mpm

@@ -1,0 +1,60 @@
+// Tiled scheme: brick-sorted particles, LDS node tiles, fused G2P + P2G,
+// node-brick work lists for the grid operation.
+#pragma once
+#include "mpm_kernels.h"
+
+namespace mpm {
+
+// Sort scratch and the resulting work items.
+struct SortBuf {
+    int2 *count;       // [total_bricks] (count, -)
+    int2 *offset;      // [total_bricks] (first slot, first item)
+    int2 *chunk_sum;   // [chunks]
+    int2 *totals;      // [1] (particles, items)
+    int32_t *key;      // [ntot] brick of each particle
+    int32_t *rank;     // [ntot] rank within the brick
+    int4 *items;       // [max_items] (brick, first slot, count, -)
+};
+
+struct ParticleBuf {
+    float *x, *v, *C, *F;
+    int32_t *pid;
+};
+
+// Active node bricks: flag per brick, compact list and its length.
+struct ActiveBuf {
+    int32_t *flag;     // [total_bricks]
+    int32_t *list;     // [total_bricks]
+    int32_t *count;    // [1]
+    int32_t *done;     // [1] finished-block counter of the grid kernel
+    const int32_t *env_bofs;  // [n_envs + 1]
+};
+
+// Tile geometry: brick of 4^3 cells plus a one-cell margin on each side and
+// the 2-node stencil reach: 8 nodes per axis.
+constexpr int TILE = 8;
+constexpr int TILE_NODES = TILE * TILE * TILE;
+
+struct TiledArgs {
+    const float *xin, *vin, *Cin, *Fin;   // particle input (sorted slots)
+    const int32_t *pidin;
+    float *xout, *vout, *Cout, *Fout;     // particle output (tail: all; fused: x, F)
+    int32_t *pidout;                      // copied when pidin != pidout
+    const int4 *items;
+    const int2 *totals;                   // .y = number of items
+    ActiveBuf act;
+};
+
+void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
+                 hipStream_t st);
+size_t sort_chunk_count(int total_bricks);
+
+void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_grid_active(const Dev &d, const ActiveBuf &a, int nblocks, hipStream_t st);
+// Persistent workgroup count for the tiled particle kernels at this block
+// size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
+int tiled_workgroups(int block);
+
+}  // namespace mpm

@@ -54,6 +54,11 @@ class Env:
     V0: float
     tools: List[Tool] = field(default_factory=list)
 
+    def __post_init__(self):
+        # scalar inputs are FP32 values, like the arrays
+        for k in ("E", "nu", "rho", "V0"):
+            setattr(self, k, float(np.float32(getattr(self, k))))
+
     @property
     def N(self) -> int:
         return int(self.x.shape[0])
@@ -68,6 +73,10 @@ class Scene:
     gravity: tuple = (0.0, -9.8, 0.0)
     bound: int = 3
     extra: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        self.dt = float(np.float32(self.dt))
+        self.gravity = tuple(float(np.float32(g)) for g in self.gravity)
 
     @property
     def n_particles(self) -> int:
@@ -193,8 +202,7 @@ def batched_scene(seed: int = 4, n_envs: int = 256, substeps: int = 200,
         s = rng.uniform(0.05, 0.2)
         u = s * _unit((rng.uniform(-0.3, 0.3), -1.0, rng.uniform(-0.3, 0.3)))
         tool = capsule_tool(T0=(0.5, y0 + 0.12, 0.5), u=u, friction=0.3)
-        envs.append(Env(n=n, x=x, v=v, C=C, F=F, E=float(np.float32(E)), nu=float(np.float32(nu)),
-                        rho=1e3, V0=0.5 * 0.1 * 0.5 / N, tools=[tool]))
+        envs.append(Env(n=n, x=x, v=v, C=C, F=F, E=E, nu=nu, rho=1e3, V0=0.5 * 0.1 * 0.5 / N, tools=[tool]))
     return Scene(f"batched-{n_envs}", envs, dt=5e-5, substeps=substeps)
 
 

@@ -1,0 +1,159 @@
+"""Python face of the library: a ``Sim`` that owns one C context.
+
+torch provides the device memory (workspace, initial state, material table,
+tool trajectories, gradient buffers) and the stream; the C ABI does the rest.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _soa(arrays, comps):
+    """Concatenate per-env AoS float32 arrays into one [comps][Ntot] array."""
+    return np.ascontiguousarray(np.concatenate([np.asarray(a, np.float32).reshape(-1, comps) for a in arrays], 0).T)
+
+
+class Sim:
+    """All environments of a scene in one context on one GPU."""
+
+    def __init__(self, scene, device="cuda", max_tape: int = 0, checkpoint_every: int = 20,
+                 options: Optional[Dict[int, int]] = None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (there is no CPU path)")
+        self.lib = L.load()
+        self.scene = scene
+        self.device = torch.device(device)
+        envs = scene.envs
+        self.n_envs = len(envs)
+        self.max_tools = max([len(e.tools) for e in envs], default=0)
+        self.np = np.array([e.N for e in envs], np.int32)
+        self.gn = np.array([e.n for e in envs], np.int32)
+        self.pofs = np.concatenate([[0], np.cumsum(self.np)]).astype(np.int64)
+        dev = self.device
+        t = lambda a: torch.from_numpy(a).to(dev)
+        self._x0 = t(_soa([e.x for e in envs], 3))
+        self._v0 = t(_soa([e.v for e in envs], 3))
+        self._C0 = t(_soa([e.C for e in envs], 9))
+        self._F0 = t(_soa([e.F for e in envs], 9))
+        self.material = t(np.array([[e.E, e.nu, e.rho, e.V0] for e in envs], np.float32))
+        self._np_c = (ct.c_int32 * self.n_envs)(*self.np.tolist())
+        self._gn_c = (ct.c_int32 * self.n_envs)(*self.gn.tolist())
+        self.desc = L.MpmDesc(
+            n_envs=self.n_envs, n_particles=self._np_c, grid_n=self._gn_c, dt=float(scene.dt),
+            gravity=(ct.c_float * 3)(*scene.gravity), bound=int(scene.bound), max_tools=self.max_tools,
+            checkpoint_every=int(checkpoint_every), max_tape_substeps=int(max_tape),
+            x0=self._x0.data_ptr(), v0=self._v0.data_ptr(), C0=self._C0.data_ptr(), F0=self._F0.data_ptr(),
+            material=self.material.data_ptr())
+        size = self.lib.mpm_workspace_size(ct.byref(self.desc))
+        if size == 0:
+            raise L.MpmError(L.MPM_E_ARG, self.lib.mpm_last_error(None).decode())
+        self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.ctx = ct.c_void_p()
+        L.check(self.lib.mpm_create(ct.byref(self.desc), ct.c_void_p(aligned), size, _stream_ptr(stream),
+                                    ct.byref(self.ctx)))
+        self.traj = {}
+        for e, env in enumerate(envs):
+            for k, tool in enumerate(env.tools):
+                self.set_tool(e, k, tool)
+        for opt, val in (options or {}).items():
+            self.set_option(opt, val)
+
+    # ------------------------------------------------------------------ control
+    def set_tool(self, env, slot, tool, traj=None):
+        u = torch.from_numpy(np.ascontiguousarray(np.asarray(tool.traj if traj is None else traj,
+                                                             np.float32))).to(self.device)
+        self.traj[(env, slot)] = u
+        td = L.MpmTool(shape=L.TOOL_CAPSULE, contact=int(tool.contact), radius=tool.radius,
+                       half_len=tool.half_len, friction=tool.friction, theta=tool.theta,
+                       R=(ct.c_float * 9)(*np.asarray(tool.R, np.float32).reshape(-1).tolist()),
+                       T0=(ct.c_float * 3)(*np.asarray(tool.T0, np.float32).tolist()))
+        L.check(self.lib.mpm_set_tool(self.ctx, env, slot, ct.byref(td), ct.c_void_p(u.data_ptr()), u.shape[0]),
+                self.ctx)
+
+    def set_option(self, option, value):
+        L.check(self.lib.mpm_set_option(self.ctx, int(option), int(value)), self.ctx)
+
+    def step(self, n=1, record_tape=False, stream=None):
+        L.check(self.lib.mpm_substep(self.ctx, int(n), 1 if record_tape else 0, _stream_ptr(stream)), self.ctx)
+
+    def stage(self, stage, stream=None):
+        L.check(self.lib.mpm_run_stage(self.ctx, int(stage), _stream_ptr(stream)), self.ctx)
+
+    # ------------------------------------------------------------------ reads
+    _PCOMPS = {L.F_X: 3, L.F_V: 3, L.F_C: 9, L.F_F: 9}
+    _GCOMPS = {L.F_GRID_M: 1, L.F_GRID_MV: 3, L.F_GRID_V: 3}
+
+    def read(self, field, env=0, device=True):
+        """A field of one environment as a torch tensor ([comps][N] particles,
+        [comps][n^3] grid), on the device unless device=False (numpy)."""
+        if field in self._PCOMPS:
+            shape = (self._PCOMPS[field], int(self.np[env]))
+        elif field in self._GCOMPS:
+            shape = (self._GCOMPS[field], int(self.gn[env]) ** 3)
+        elif field == L.F_STATUS:
+            out = np.zeros(1, np.uint32)
+            L.check(self.lib.mpm_read_state(self.ctx, env, field, out.ctypes.data_as(ct.c_void_p), 4, 0,
+                                            _stream_ptr()), self.ctx)
+            return int(out[0])
+        elif field == L.F_STEP:
+            out = np.zeros(1, np.int32)
+            L.check(self.lib.mpm_read_state(self.ctx, env, field, out.ctypes.data_as(ct.c_void_p), 4, 0,
+                                            _stream_ptr()), self.ctx)
+            return int(out[0])
+        elif field == L.F_TOOL_T:
+            out = np.zeros((max(1, self.max_tools), 3), np.float64)
+            L.check(self.lib.mpm_read_state(self.ctx, env, field, out.ctypes.data_as(ct.c_void_p), out.nbytes, 0,
+                                            _stream_ptr()), self.ctx)
+            return out[:self.max_tools]
+        else:
+            raise ValueError(field)
+        if device:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+            L.check(self.lib.mpm_read_state(self.ctx, env, field, ct.c_void_p(out.data_ptr()), out.numel() * 4, 1,
+                                            _stream_ptr()), self.ctx)
+            return out
+        out = np.empty(shape, np.float32)
+        L.check(self.lib.mpm_read_state(self.ctx, env, field, out.ctypes.data_as(ct.c_void_p), out.nbytes, 0,
+                                        _stream_ptr()), self.ctx)
+        return out
+
+    def particles(self, env=0):
+        """(x (N,3), v (N,3), C (N,3,3), F (N,3,3)) numpy float32, original order."""
+        x = self.read(L.F_X, env, device=False).T
+        v = self.read(L.F_V, env, device=False).T
+        C = self.read(L.F_C, env, device=False).T.reshape(-1, 3, 3)
+        F = self.read(L.F_F, env, device=False).T.reshape(-1, 3, 3)
+        return x, v, C, F
+
+    def grid(self, env=0):
+        """(m (n,n,n), mv (n,n,n,3), v (n,n,n,3)) numpy float32."""
+        n = int(self.gn[env])
+        m = self.read(L.F_GRID_M, env, device=False).reshape(n, n, n)
+        mv = self.read(L.F_GRID_MV, env, device=False).reshape(3, n, n, n).transpose(1, 2, 3, 0)
+        v = self.read(L.F_GRID_V, env, device=False).reshape(3, n, n, n).transpose(1, 2, 3, 0)
+        return m, mv, v
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            torch.cuda.synchronize()
+            self.lib.mpm_destroy(self.ctx)
+            self.ctx = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

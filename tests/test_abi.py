@@ -1,0 +1,80 @@
+"""The C-ABI library loads, exports every function include/mpm.h declares,
+and validates descriptions on the host (no GPU needed for these calls)."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2402_01181_amd import _lib
+    return _lib
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("mpm_create", "mpm_set_tool", "mpm_substep", "mpm_substep_adjoint", "mpm_read_state"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = ct.CDLL(L.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) == set(L.EXPORTS)
+
+
+def _desc(L, n_envs=1, np_=(100,), gn=(32,), dt=1e-4, bound=3, max_tools=1, tape=0, ck=1):
+    keep = []
+    npc = (ct.c_int32 * n_envs)(*np_)
+    gnc = (ct.c_int32 * n_envs)(*gn)
+    keep += [npc, gnc]
+    d = L.MpmDesc(n_envs=n_envs, n_particles=npc, grid_n=gnc, dt=dt, gravity=(ct.c_float * 3)(0, -9.8, 0),
+                  bound=bound, max_tools=max_tools, checkpoint_every=ck, max_tape_substeps=tape,
+                  x0=1, v0=1, C0=1, F0=1, material=1)
+    return d, keep
+
+
+def test_workspace_size_and_validation(L):
+    lib = L.load()
+    d, keep = _desc(L)
+    s1 = lib.mpm_workspace_size(ct.byref(d))
+    assert s1 > 0 and s1 % 256 == 0
+    # more particles or a bigger grid need more workspace
+    d2, k2 = _desc(L, np_=(1000,), gn=(64,))
+    assert lib.mpm_workspace_size(ct.byref(d2)) > s1
+    bad = [dict(gn=(30,)), dict(gn=(4,)), dict(np_=(0,)), dict(dt=0.0), dict(dt=float("nan")),
+           dict(bound=-1), dict(bound=16), dict(max_tools=9), dict(tape=-1), dict(tape=10, ck=0)]
+    for kw in bad:
+        db, kb = _desc(L, **kw)
+        assert lib.mpm_workspace_size(ct.byref(db)) == 0, kw
+        assert len(lib.mpm_last_error(None)) > 0
+    assert lib.mpm_workspace_size(None) == 0
+
+
+def test_create_rejects_bad_arguments_without_touching_the_device(L):
+    lib = L.load()
+    d, keep = _desc(L)
+    out = ct.c_void_p()
+    assert lib.mpm_create(None, None, 0, None, ct.byref(out)) == L.MPM_E_ARG
+    assert lib.mpm_create(ct.byref(d), None, 0, None, ct.byref(out)) == L.MPM_E_WORKSPACE
+    assert lib.mpm_create(ct.byref(d), ct.c_void_p(256), 16, None, ct.byref(out)) == L.MPM_E_WORKSPACE
+    assert lib.mpm_create(ct.byref(d), ct.c_void_p(257), 1 << 30, None, ct.byref(out)) == L.MPM_E_WORKSPACE
+    assert out.value is None
+    lib.mpm_destroy(None)
+    assert b"" != lib.mpm_last_error(None)
+    assert lib.mpm_substep(None, 1, 0, None) == L.MPM_E_ARG
+    assert lib.mpm_read_state(None, 0, 0, None, 0, 0, None) == L.MPM_E_ARG
+    assert lib.mpm_set_option(None, 0, 0) == L.MPM_E_ARG

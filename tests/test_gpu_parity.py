@@ -1,0 +1,176 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Per stage and per substep the GPU starts from its own FP32 state and the
+oracle from the same values promoted to FP64 (teacher forcing); errors use the
+metric in parity.py against the per-substep tolerance 1e-5.  Free-running
+runs are held to 1e-3 of the domain in particle position.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_01181_amd import scenes
+from parity import FLOORS, TOL_DRIFT, TOL_SUBSTEP, oracle_state_from_gpu, oracle_sim_like, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU")
+    from paper_2402_01181_amd import _lib
+    from paper_2402_01181_amd.sim import Sim
+    return Sim, _lib
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _scheme(L, name):
+    return {"direct": L.SCHEME_DIRECT, "tiled": L.SCHEME_TILED}[name]
+
+
+def _perturbed_cube(seed=1):
+    sc = scenes.cube_scene(seed=seed)
+    scenes.perturbed_state(np.random.default_rng(seed + 100), sc.envs[0], v_scale=0.05, C_scale=1.0,
+                           F_scale=0.01)
+    return sc
+
+
+def _compare_particles(orc_state, gpu_sim, env=0, tol=TOL_SUBSTEP, what=""):
+    x, v, C, F = gpu_sim.particles(env)
+    ex = rel_err(x, orc_state.x, FLOORS["x"])
+    ev = rel_err(v, orc_state.v, FLOORS["v"])
+    eF = rel_err(F, orc_state.F, FLOORS["F"])
+    eC = rel_err(C, orc_state.C, max(1.0, np.abs(orc_state.C).max()))
+    _say(f"  {what} err x={ex:.2e} v={ev:.2e} F={eF:.2e} C={eC:.2e}")
+    assert ex <= tol and ev <= tol and eF <= tol, (what, ex, ev, eF)
+    assert eC <= 1e-4, (what, eC)
+    return ex, ev, eF
+
+
+def test_stage_parity_cube(gpu, orc):
+    Sim, L = gpu
+    _say("stage parity: cube 8192 particles, 32^3, perturbed state")
+    sc = _perturbed_cube()
+    sim = Sim(sc)
+    o = oracle_sim_like(orc, sc)
+    o.state = oracle_state_from_gpu(orc, sim)
+    sim.stage(L.STAGE_P2G)
+    gm, gmv = o.p2g()
+    m, mv, _ = sim.grid()
+    em = rel_err(m, gm, 0.0)
+    emv = rel_err(mv, gmv, 1e-2 * gm.max())
+    _say(f"  P2G err m={em:.2e} mv={emv:.2e}")
+    assert em <= TOL_SUBSTEP and emv <= TOL_SUBSTEP
+    assert abs(m.astype(np.float64).sum() - gm.sum()) <= 1e-6 * gm.sum()    # mass conservation on the GPU
+    sim.stage(L.STAGE_GRID)
+    gv = o.grid_update(gm, gmv)
+    _, _, v = sim.grid()
+    ev = rel_err(v, gv, FLOORS["v"])
+    _say(f"  GRID err v={ev:.2e}")
+    assert ev <= TOL_SUBSTEP
+    sim.stage(L.STAGE_G2P)
+    o.g2p(gv)
+    _compare_particles(o.state, sim, what="G2P")
+    assert sim.read(L.F_STATUS) == 0
+
+
+@pytest.mark.parametrize("scheme", ["direct", "tiled"])
+def test_substep_parity_slab_with_tool(gpu, orc, scheme):
+    Sim, L = gpu
+    for contact in (scenes.CONTACT_SLIP, scenes.CONTACT_STICKY):
+        _say(f"substep parity ({scheme}): small slab 4000 particles, 32^3, contact={contact}")
+        sc = scenes.small_slab_scene(seed=23, n_particles=4000, n=32, substeps=30, contact=contact,
+                                     u=(0.05, -0.5, 0.0))
+        sc.envs[0].tools[0].T0 = (sc.envs[0].tools[0].T0 - np.array([0, 0.012, 0])).astype(np.float32)
+        sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme), L.OPT_SORT_EVERY: 4})
+        o = oracle_sim_like(orc, sc)
+        worst = 0.0
+        for s in range(sc.substeps):
+            o.state = oracle_state_from_gpu(orc, sim)
+            o.T[0] = sim.read(L.F_TOOL_T)[0]
+            o.s = s
+            o.run(1)
+            sim.step(1)
+            worst = max(worst, max(_compare_particles(o.state, sim, what=f"substep {s}")))
+        np.testing.assert_allclose(sim.read(L.F_TOOL_T)[0], o.T[0], rtol=1e-12)
+        assert sim.read(L.F_STEP) == sc.substeps
+        _say(f"  worst {worst:.2e}")
+
+
+@pytest.mark.parametrize("scheme", ["direct", "tiled"])
+def test_free_running_cube_50(gpu, orc, scheme):
+    Sim, L = gpu
+    _say(f"free running ({scheme}): cube 8192 particles, 50 substeps in one call, sort every 8")
+    sc = scenes.cube_scene(seed=1, substeps=50)
+    sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme), L.OPT_SORT_EVERY: 8})
+    sim.step(sc.substeps)
+    o = oracle_sim_like(orc, sc).run(sc.substeps)
+    x, v, C, F = sim.particles()
+    err = np.abs(x - o.state.x).max()
+    _say(f"  max |dx| = {err:.2e}")
+    assert err <= TOL_DRIFT
+    assert sim.read(L.F_STATUS) == 0
+
+
+@pytest.mark.parametrize("scheme", ["direct", "tiled"])
+def test_slab_30k_one_substep_full_size(gpu, orc, scheme):
+    Sim, L = gpu
+    _say(f"slab 30K, 64^3 ({scheme}): teacher-forced substeps at full size")
+    sc = scenes.slab_scene(seed=2, substeps=5)
+    scenes.perturbed_state(np.random.default_rng(5), sc.envs[0], v_scale=0.02, C_scale=0.5, F_scale=0.005)
+    sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme)})
+    o = oracle_sim_like(orc, sc)
+    for s in range(3):
+        o.state = oracle_state_from_gpu(orc, sim)
+        o.T[0] = sim.read(L.F_TOOL_T)[0]
+        o.s = s
+        o.run(1)
+        sim.step(1)
+        _compare_particles(o.state, sim, what=f"substep {s}")
+
+
+@pytest.mark.parametrize("scheme", ["direct", "tiled"])
+def test_status_flags_and_read_errors(gpu, orc, scheme):
+    Sim, L = gpu
+    _say(f"status flags ({scheme})")
+    sc = scenes.small_slab_scene(seed=3, n_particles=500, n=32, substeps=1)
+    env = sc.envs[0]
+    env.x[0] = [0.01, 0.5, 0.5]          # stencil leaves the grid
+    env.F[1] = np.diag([1.0, 1.0, -0.5]).astype(np.float32)   # inverted
+    sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme)})
+    sim.step(3)
+    st = sim.read(L.F_STATUS)
+    assert st & L.FLAG_OUT_OF_DOMAIN and st & L.FLAG_INVERTED
+    x, v, C, F = sim.particles()
+    np.testing.assert_array_equal(x[0], env.x[0])                # frozen particle
+    import ctypes as ct
+    buf = np.zeros(3, np.float32)
+    assert sim.lib.mpm_read_state(sim.ctx, 0, L.F_X, buf.ctypes.data_as(ct.c_void_p), 12, 0, None) == L.MPM_E_ARG
+    assert sim.lib.mpm_read_state(sim.ctx, 5, L.F_X, buf.ctypes.data_as(ct.c_void_p), 12, 0, None) == L.MPM_E_ARG
+    assert sim.lib.mpm_set_tool(sim.ctx, 0, 3, None, None, 0) == L.MPM_E_ARG
+
+
+def test_tiled_matches_direct_long_run(gpu, orc):
+    """Cross-check of the two schemes (different accumulation orders) on the
+    30K slab with the tool pushing: 200 substeps, several sorts, mid-call."""
+    Sim, L = gpu
+    _say("tiled vs direct: slab 30K, 200 substeps")
+    sc = scenes.slab_scene(seed=2, substeps=200)
+    a = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_DIRECT})
+    b = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 16})
+    a.step(120)
+    a.step(80)
+    b.step(120)
+    b.step(80)
+    xa, va, Ca, Fa = a.particles()
+    xb, vb, Cb, Fb = b.particles()
+    ex = np.abs(xa - xb).max()
+    ev = rel_err(vb, va, FLOORS["v"])
+    _say(f"  max |dx| = {ex:.2e}, v err = {ev:.2e}")
+    assert ex <= 1e-5 and ev <= 1e-3
+    assert a.read(L.F_STATUS) == 0 and b.read(L.F_STATUS) == 0
+    np.testing.assert_allclose(a.read(L.F_TOOL_T), b.read(L.F_TOOL_T), rtol=0, atol=0)
