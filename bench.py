@@ -1,0 +1,193 @@
+"""Throughput benchmark of the MLS-MPM substep on one MI355X.
+
+A step is one substep of every particle (P2G, grid operation, G2P, F update).
+Default workload: the 30K-particle tissue slab on a 64^3 grid pushed by a
+capsule tool (dt 5e-5, E 1e4, nu 0.35), the configuration the headline
+particle-substeps/s is quoted on.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config slab|large|cube|batched]
+
+Timing: W untimed substeps, then K substeps bracketed by device syncs and
+hipEvents on the stream the library launches on.  A second pass of the same
+length with the library's event timer on gives each kernel's average launch
+duration; the dominant kernel's roofline uses that duration.  The CPU baseline
+is the FP64 oracle (serial C) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic bytes (FP32 state that must cross HBM per substep):
+#   per particle: read + write x (12 B) and F (36 B) = 96 B
+#   per active grid node: P2G writes (m, mv) 16 B, the grid operation reads
+#   them (16 B) and writes v (12 B), G2P reads v (12 B) = 56 B
+# The fused G2P+P2G kernel alone moves 96 B per particle + 28 B per active node.
+BYTES_PER_PARTICLE = 96
+BYTES_PER_NODE_SUBSTEP = 56
+BYTES_PER_NODE_FUSED = 28
+BYTES_PER_NODE_GRID = 28
+
+
+def active_nodes(x: np.ndarray, n: int) -> int:
+    """Distinct grid nodes inside the 3x3x3 stencils of the particles."""
+    base = np.floor(x.astype(np.float64) * n - 0.5).astype(np.int64)
+    o = np.array([(a, b, c) for a in range(3) for b in range(3) for c in range(3)])
+    nodes = (base[:, None, :] + o[None, :, :]).reshape(-1, 3)
+    key = (nodes[:, 0] * n + nodes[:, 1]) * n + nodes[:, 2]
+    return int(np.unique(key).size)
+
+
+def make_scene(name: str):
+    from paper_2402_01181_amd import scenes
+    if name == "slab":
+        return scenes.slab_scene(), "tissue slab 30,000 particles, 64^3 grid, capsule push 0.2 m/s, slip, 1,000 substeps"
+    if name == "large":
+        return scenes.large_slab_scene(), "large slab 1,048,576 particles, 128^3 grid, sticky capsule pull, 500 substeps"
+    if name == "cube":
+        return scenes.cube_scene(), "cube 8,192 particles, 32^3 grid, no tool, 50 substeps"
+    if name == "batched":
+        return scenes.batched_scene(), "256 environments, 5K-50K particles each, 32^3/64^3 grids, 200 substeps"
+    raise SystemExit(f"unknown config {name}")
+
+
+def cpu_baseline(scene, substeps: int):
+    """The FP64 oracle as it stands, serial, on the first `substeps` substeps of
+    environment 0 of the same scene."""
+    from oracle import oracle
+    oracle.lib()
+    env = scene.envs[0]
+    sim = oracle.Sim(env, scene.dt, gravity=scene.gravity, bound=scene.bound)
+    t0 = time.perf_counter()
+    sim.run(substeps)
+    dt = time.perf_counter() - t0
+    return {"value": env.N * substeps / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"environment 0 ({env.N} particles, {env.n}^3 grid), first {substeps} substeps, "
+                      f"FP64 serial C, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--config", default="slab")
+    ap.add_argument("--scheme", default="tiled", choices=["tiled", "direct"])
+    ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--item", type=int, default=None)
+    ap.add_argument("--graph", type=int, default=None)
+    ap.add_argument("--cpu-substeps", type=int, default=None,
+                    help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2402_01181_amd import _lib as L
+    from paper_2402_01181_amd.sim import Sim
+
+    scene, workload = make_scene(args.config)
+    opts = {L.OPT_SCHEME: L.SCHEME_TILED if args.scheme == "tiled" else L.SCHEME_DIRECT}
+    if args.sort_every: opts[L.OPT_SORT_EVERY] = args.sort_every
+    if args.block: opts[L.OPT_BLOCK] = args.block
+    if args.item: opts[L.OPT_ITEM] = args.item
+    if args.graph is not None: opts[L.OPT_GRAPH] = args.graph
+    sim = Sim(scene, options=opts)
+    N = scene.n_particles
+    K, W = args.steps, args.warmup
+
+    print(f"# bench: {workload}; N={N}; warmup {W}, timed {K} substeps", file=sys.stderr, flush=True)
+    if W:
+        sim.step(W)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = N * K / (ms * 1e-3)
+    print(f"# timed: {ms:.2f} ms, {value:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+
+    status = [sim.read(L.F_STATUS, e) for e in range(sim.n_envs)]
+    x_final = [sim.read(L.F_X, e, device=False).T for e in range(sim.n_envs)]
+    nodes = sum(active_nodes(x, int(sim.gn[e])) for e, x in enumerate(x_final))
+
+    roofline, kernels = None, {}
+    if not args.no_profile_pass and not (args.graph or 0):
+        sim.profile(True)
+        sim.step(K)
+        torch.cuda.synchronize()
+        sim.profile(False)
+        rep = sim.profile_report()
+        kernels = {k: {"avg_us": 1e3 * t / n, "launches": n, "total_ms": t} for k, (t, n) in rep.items()}
+        dom = max(rep, key=lambda k: rep[k][0])
+        t_ms, n_launch = rep[dom]
+        avg_s = t_ms / n_launch * 1e-3
+        if dom.startswith("fused"):
+            per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_FUSED
+        elif dom.startswith("grid"):
+            per_launch = nodes * BYTES_PER_NODE_GRID
+        else:
+            per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
+        achieved = per_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
+        print(f"# kernels: " + ", ".join(f"{k} {v['avg_us']:.2f}us x{v['launches']}" for k, v in kernels.items()),
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        default_cpu = {"slab": 600, "large": 15, "cube": 50, "batched": 300}
+        cpu = cpu_baseline(scene, args.cpu_substeps or default_cpu.get(args.config, 50))
+        print(f"# cpu baseline: {cpu['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "particle-substeps/sec",
+        "value": value,
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded particles in a box, analytic capsule tool)",
+        "config": {"workload": workload, "config": args.config, "particles": N,
+                   "grid": [int(g) for g in sim.gn[:4]], "envs": sim.n_envs, "substeps_timed": K,
+                   "scheme": args.scheme, "active_nodes": nodes,
+                   "algorithmic_bytes_per_substep": N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "status": status if any(status) else 0,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

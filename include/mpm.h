@@ -183,6 +183,18 @@ mpm_status mpm_substep_adjoint(mpm_ctx *ctx, int32_t n_substeps, const mpm_adjoi
 mpm_status mpm_read_state(mpm_ctx *ctx, int32_t env, int32_t field, void *dst, size_t dst_bytes,
                           int32_t dst_on_device, void *stream);
 
+/* Built-in kernel timer.  enable != 0 starts recording: every kernel the
+ * library launches on a context is bracketed by two hipEvents on its own
+ * stream (adds a little host overhead; not available with MPM_OPT_GRAPH).
+ * enable == 0 stops and keeps the totals.  Starting again clears them. */
+mpm_status mpm_profile(mpm_ctx *ctx, int32_t enable);
+
+/* Totals of kernel kind `kind` (0 <= kind < number of kinds; MPM_E_ARG past
+ * the end): its name, summed event time in ms and launch count.  Waits for
+ * the recorded events. */
+mpm_status mpm_profile_read(mpm_ctx *ctx, int32_t kind, const char **name, double *total_ms,
+                            int64_t *launches);
+
 /* Message of the last failed call on ctx (or of the last failed mpm_create /
  * mpm_workspace_size when ctx is NULL). Never NULL. */
 const char *mpm_last_error(const mpm_ctx *ctx);

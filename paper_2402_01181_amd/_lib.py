@@ -24,7 +24,8 @@ OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT
 SCHEME_DIRECT, SCHEME_TILED = 0, 1
 
 EXPORTS = ["mpm_workspace_size", "mpm_create", "mpm_destroy", "mpm_set_tool", "mpm_set_option",
-           "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error"]
+           "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error",
+           "mpm_profile", "mpm_profile_read"]
 
 
 class MpmDesc(ct.Structure):
@@ -85,6 +86,11 @@ def load(path: str = LIB_PATH):
     L.mpm_substep_adjoint.restype = i32
     L.mpm_read_state.argtypes = [vp, i32, i32, vp, ct.c_size_t, i32, vp]
     L.mpm_read_state.restype = i32
+    L.mpm_profile.argtypes = [vp, i32]
+    L.mpm_profile.restype = i32
+    L.mpm_profile_read.argtypes = [vp, i32, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_double),
+                                   ct.POINTER(ct.c_int64)]
+    L.mpm_profile_read.restype = i32
     L.mpm_last_error.argtypes = [vp]
     L.mpm_last_error.restype = ct.c_char_p
     _lib = L

@@ -32,6 +32,7 @@ struct Shape {
     int n_envs, max_tools, ntot;
     int64_t total_nodes;
     int32_t total_bricks;
+    int max_tape, ck;
 };
 
 // One description of the workspace layout, used both to size and to carve it.
@@ -65,11 +66,44 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.max_items = (int64_t)s.total_bricks + s.ntot / 64 + 1;
     c.sort.items = cv.take<int4>(c.max_items);
     c.act.flag = cv.take<int32_t>(s.total_bricks);
-    c.act.list = cv.take<int32_t>(s.total_bricks);
-    c.act.count = cv.take<int32_t>(1);
-    c.act.done = cv.take<int32_t>(1);
+    c.act.list = cv.take<int32_t>((size_t)2 * s.total_bricks);
+    c.act.count = cv.take<int32_t>(2);
+    c.act.stride = s.total_bricks;
     c.env_bofs = cv.take<int32_t>(s.n_envs + 1);
     c.act.env_bofs = c.env_bofs;
+    // adjoint tape
+    if (s.max_tape > 0) {
+        const size_t st24 = (size_t)24 * s.ntot;
+        const size_t slots = (size_t)s.n_envs * std::max(1, s.max_tools);
+        const int k = s.ck;
+        auto &T = c.tape;
+        T.n_ckpt = (s.max_tape + k - 1) / k + 1;
+        T.ckpt_state = cv.take<float>(st24 * T.n_ckpt);
+        T.ckpt_tools = cv.take<ToolDev>(slots * T.n_ckpt);
+        T.ckpt_step = cv.take<int32_t>((size_t)s.n_envs * T.n_ckpt);
+        T.seg_state = cv.take<float>(st24 * k);
+        T.seg_tools = cv.take<ToolDev>(slots * k);
+        T.seg_P = cv.take<float4>((size_t)s.total_nodes * k);
+        T.seg_V = cv.take<float4>((size_t)s.total_nodes * k);
+        T.seg_dec = cv.take<ContactCode>((size_t)s.total_nodes * k);
+        T.work = cv.take<float>(st24);
+        T.work_tools = cv.take<ToolDev>(slots);
+        T.work_step = cv.take<int32_t>(s.n_envs);
+        T.work_status = cv.take<uint32_t>(s.n_envs);
+        T.adj_state = cv.take<float>(st24);
+        T.adj.xb = T.adj_state;
+        T.adj.vb = T.adj_state ? T.adj_state + (size_t)3 * s.ntot : nullptr;
+        T.adj.Cb = T.adj_state ? T.adj_state + (size_t)6 * s.ntot : nullptr;
+        T.adj.Fb = T.adj_state ? T.adj_state + (size_t)15 * s.ntot : nullptr;
+        T.adj.gVb = cv.take<float4>(s.total_nodes);
+        T.adj.gPb = cv.take<float4>(s.total_nodes);
+        const size_t ng = slots * s.max_tape * 3;
+        T.adj.ubar = cv.take<double>(ng);
+        T.adj.Tbar = cv.take<double>(ng);
+        T.adj.mubar = cv.take<double>(s.n_envs);
+        T.adj.lambar = cv.take<double>(s.n_envs);
+        T.adj.max_tape = s.max_tape;
+    }
 }
 
 // Every device buffer the kernels use must have been carved.
@@ -78,9 +112,17 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.F, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.F, c.alt.pid, c.sort.count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.list, c.act.count, c.act.done, c.env_bofs, c.act.env_bofs};
+                       c.act.list, c.act.count, c.env_bofs, c.act.env_bofs};
     for (const void *q : p)
         if (!q) return false;
+    if (c.max_tape > 0) {
+        const auto &T = c.tape;
+        const void *t[] = {T.ckpt_state, T.ckpt_tools, T.ckpt_step, T.seg_state, T.seg_tools, T.seg_P, T.seg_V,
+                           T.seg_dec, T.work, T.work_tools, T.work_step, T.work_status, T.adj_state, T.adj.gVb,
+                           T.adj.gPb, T.adj.ubar, T.adj.Tbar, T.adj.mubar, T.adj.lambar};
+        for (const void *q : t)
+            if (!q) return false;
+    }
     return true;
 }
 
@@ -111,6 +153,8 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
     if (bricks > (1ll << 30)) { why = "too many grid bricks"; return false; }
     s.n_envs = d->n_envs;
     s.max_tools = d->max_tools;
+    s.max_tape = d->max_tape_substeps;
+    s.ck = d->max_tape_substeps > 0 ? std::min(d->checkpoint_every, d->max_tape_substeps) : 1;
     s.ntot = (int)ntot;
     s.total_nodes = nodes;
     s.total_bricks = (int32_t)bricks;
@@ -140,21 +184,62 @@ mpm_status check_launch(mpm_ctx *c, const char *what)
     return MPM_OK;
 }
 
+// Built-in profiler: when on, each launch is bracketed by two events on its
+// stream; mpm_profile_read() resolves them.
+hipEvent_t prof_event(mpm_ctx *c)
+{
+    Profiler &P = c->prof;
+    if (P.used == P.pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        P.pool.push_back(e);
+    }
+    return P.pool[P.used++];
+}
+
+template <class F>
+void timed(mpm_ctx *c, hipStream_t st, int kind, F &&launch)
+{
+    if (!c->prof.on) { launch(); return; }
+    size_t i0 = c->prof.used;
+    hipEvent_t a = prof_event(c), b = prof_event(c);
+    if (!a || !b) { launch(); return; }
+    (void)hipEventRecord(a, st);
+    launch();
+    (void)hipEventRecord(b, st);
+    c->prof.marks.emplace_back(kind, i0);
+}
+
+void prof_resolve(mpm_ctx *c)
+{
+    Profiler &P = c->prof;
+    for (auto &m : P.marks) {
+        float ms = 0.f;
+        if (hipEventSynchronize(P.pool[m.second + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, P.pool[m.second], P.pool[m.second + 1]) == hipSuccess) {
+            P.total_ms[m.first] += ms;
+            P.launches[m.first] += 1;
+        }
+    }
+    P.marks.clear();
+    P.used = 0;
+}
+
 // One substep of the direct scheme.  Leaves the last P2G in the momentum
 // buffer (readable), so the grid is not clean afterwards.
 void substep_direct(mpm_ctx *c, hipStream_t st)
 {
     Dev d = c->dev();
-    launch_fill_f4(c->gP, c->total_nodes, st);
-    launch_p2g_direct(d, st);
-    launch_grid_dense(d, c->env_gofs, c->total_nodes, 0, st);
-    launch_g2p_direct(d, st);
+    timed(c, st, PK_FILL, [&] { launch_fill_f4(c->gP, c->total_nodes, st); });
+    timed(c, st, PK_P2G_DIRECT, [&] { launch_p2g_direct(d, st); });
+    timed(c, st, PK_GRID_DENSE, [&] { launch_grid_dense(d, c->env_gofs, c->total_nodes, 0, st); });
+    timed(c, st, PK_G2P_DIRECT, [&] { launch_g2p_direct(d, st); });
     c->grid_clean = false;
 }
 
 ParticleBuf live(const mpm_ctx *c) { return ParticleBuf{c->x, c->v, c->C, c->F, c->pid}; }
 
-TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf &out)
+TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf &out, int par)
 {
     TiledArgs a{};
     a.xin = in.x; a.vin = in.v; a.Cin = in.C; a.Fin = in.F; a.pidin = in.pid;
@@ -162,13 +247,14 @@ TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf 
     a.items = c->sort.items;
     a.totals = c->sort.totals;
     a.act = c->act;
+    a.par = par;
     return a;
 }
 
 // Sort live particles into the alternate buffers and rebuild the items.
 void sort_into_alt(mpm_ctx *c, hipStream_t st)
 {
-    launch_sort(c->dev(), c->sort, c->total_bricks, c->item, c->alt, 1, st);
+    timed(c, st, PK_SORT, [&] { launch_sort(c->dev(), c->sort, c->total_bricks, c->item, c->alt, 1, st); });
     c->items_valid = true;
     c->items_P = c->item;
     c->since_sort = 0;
@@ -187,7 +273,7 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
 {
     Dev d = c->dev();
     if (!c->grid_clean) {
-        launch_fill_f4(c->gP, c->total_nodes, st);
+        timed(c, st, PK_FILL, [&] { launch_fill_f4(c->gP, c->total_nodes, st); });
         c->grid_clean = true;
     }
     if (c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -197,21 +283,153 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         sort_into_alt(c, st);
         in = c->alt;
     }
-    launch_p2g_tiled(d, tiled_args(c, in, in), c->block, nb, st);
+    // substep i: P2G appends to active list i&1, its grid operation consumes it
+    timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, nb, st); });
     for (int i = 0; i < n; ++i) {
-        launch_grid_active(d, c->act, grid_blocks(c), st);
+        timed(c, st, PK_GRID_ACTIVE, [&] { launch_grid_active(d, c->act, i & 1, grid_blocks(c), st); });
         if (i == n - 1) {
-            launch_g2p_tiled(d, tiled_args(c, in, A), c->block, nb, st);
+            timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, tiled_args(c, in, A, 0), c->block, nb, st); });
         } else {
             if (c->since_sort >= c->sort_every && in.x == A.x) {
                 sort_into_alt(c, st);
                 in = c->alt;
             }
-            launch_fused_tiled(d, tiled_args(c, in, A), c->block, nb, st);
+            timed(c, st, PK_FUSED_TILED, [&] { launch_fused_tiled(d, tiled_args(c, in, A, (i + 1) & 1), c->block, nb, st); });
             in = A;
         }
         c->since_sort += 1;
     }
+}
+
+
+void run_substeps(mpm_ctx *c, int n, hipStream_t st)
+{
+    if (c->scheme == MPM_SCHEME_TILED) substeps_tiled(c, n, st);
+    else for (int i = 0; i < n; ++i) substep_direct(c, st);
+}
+
+// MPM_OPT_GRAPH: replay a captured call of n substeps.  The captured
+// sequence sorts at the start of the call and every sort_every substeps, so it
+// depends only on (n, options); fills needed before it run outside the graph.
+mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
+{
+    if (!c->grid_clean) {
+        launch_fill_f4(c->gP, c->total_nodes, st);
+        c->grid_clean = true;
+    }
+    GraphEntry *ge = nullptr;
+    for (auto &g : c->graphs)
+        if (g.n == n && g.scheme == c->scheme && g.block == c->block && g.item == c->item &&
+            g.sort_every == c->sort_every)
+            ge = &g;
+    if (!ge) {
+        if (c->scheme == MPM_SCHEME_TILED && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
+        if (!c->capture_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        c->items_valid = false;               // force the sort at the start of the captured call
+        hipGraph_t graph = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        run_substeps(c, n, c->capture_stream);
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+        if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        GraphEntry g;
+        g.n = n; g.scheme = c->scheme; g.block = c->block; g.item = c->item; g.sort_every = c->sort_every;
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        g.since_sort_after = c->since_sort;
+        c->graphs.push_back(g);
+        ge = &c->graphs.back();
+    }
+    HIP_TRY(c, hipGraphLaunch(ge->exec, st));
+    if (c->scheme == MPM_SCHEME_TILED) {
+        c->items_valid = true;
+        c->items_P = c->item;
+        c->since_sort = ge->since_sort_after;
+    } else {
+        c->grid_clean = false;
+    }
+    return MPM_OK;
+}
+
+// Kernel view of a [24][ntot] particle block: x(3) v(3) C(9) F(9).
+Dev state_view(const mpm_ctx *c, float *blk)
+{
+    Dev d = c->dev();
+    const size_t N = c->ntot;
+    d.x = blk;
+    d.v = blk + 3 * N;
+    d.C = blk + 6 * N;
+    d.F = blk + 15 * N;
+    d.pid = nullptr;
+    return d;
+}
+
+// Checkpoint k of the tape: live state in original order, tool table, steps.
+void save_checkpoint(mpm_ctx *c, int k, hipStream_t st)
+{
+    auto &T = c->tape;
+    const size_t N = c->ntot;
+    float *dst = T.ckpt_state + (size_t)k * 24 * N;
+    timed(c, st, PK_ADJ_MISC, [&] {
+        launch_unpermute(c->x, c->pid, c->ntot, 3, dst, st);
+        launch_unpermute(c->v, c->pid, c->ntot, 3, dst + 3 * N, st);
+        launch_unpermute(c->C, c->pid, c->ntot, 9, dst + 6 * N, st);
+        launch_unpermute(c->F, c->pid, c->ntot, 9, dst + 15 * N, st);
+        launch_copy_bytes(T.ckpt_tools + (size_t)k * c->tool_slots(), c->tools, sizeof(ToolDev) * c->tool_slots(), st);
+        launch_copy_bytes(T.ckpt_step + (size_t)k * c->n_envs, c->step, sizeof(int32_t) * c->n_envs, st);
+    });
+}
+
+// Recompute substeps [s_begin, s_end) from checkpoint `seg`, keeping each
+// substep's starting state, tool table, grid (m, vhat), node velocities and
+// contact decisions in the segment tape.  Uses the direct-scheme kernels on
+// the tape's own buffers; the live state is not touched.
+void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t st)
+{
+    auto &T = c->tape;
+    const size_t N = c->ntot, slots = c->tool_slots();
+    timed(c, st, PK_ADJ_MISC, [&] {
+        launch_copy_bytes(T.work, T.ckpt_state + (size_t)seg * 24 * N, sizeof(float) * 24 * N, st);
+        launch_copy_bytes(T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots, st);
+        launch_copy_bytes(T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs, st);
+    });
+    for (int j = s_begin; j < s_end; ++j) {
+        const int slot = j - s_begin;
+        Dev d = state_view(c, T.work);
+        d.tools = T.work_tools;
+        d.step = T.work_step;
+        d.status = T.work_status;
+        d.gP = T.seg_P + (size_t)slot * c->total_nodes;
+        d.gV = T.seg_V + (size_t)slot * c->total_nodes;
+        timed(c, st, PK_ADJ_MISC, [&] {
+            launch_copy_bytes(T.seg_state + (size_t)slot * 24 * N, T.work, sizeof(float) * 24 * N, st);
+            launch_copy_bytes(T.seg_tools + (size_t)slot * slots, T.work_tools, sizeof(ToolDev) * slots, st);
+            launch_fill_f4(d.gP, c->total_nodes, st);
+        });
+        timed(c, st, PK_P2G_DIRECT, [&] { launch_p2g_direct(d, st); });
+        timed(c, st, PK_GRID_DENSE, [&] {
+            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, st);
+        });
+        timed(c, st, PK_G2P_DIRECT, [&] { launch_g2p_direct(d, st); });
+    }
+}
+
+// Reverse substep j (tape slot `slot`); window index j - s0.
+void reverse_substep(mpm_ctx *c, int slot, int jw, hipStream_t st)
+{
+    auto &T = c->tape;
+    const size_t N = c->ntot;
+    Dev d = state_view(c, T.seg_state + (size_t)slot * 24 * N);
+    d.gP = T.seg_P + (size_t)slot * c->total_nodes;
+    d.gV = T.seg_V + (size_t)slot * c->total_nodes;
+    d.tools = T.seg_tools + (size_t)slot * c->tool_slots();
+    AdjBuf a = T.adj;
+    a.j = jw;
+    timed(c, st, PK_ADJ_G2P, [&] { launch_adj_g2p(d, a, st); });
+    timed(c, st, PK_ADJ_GRID, [&] {
+        launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
+    });
+    timed(c, st, PK_ADJ_P2G, [&] { launch_adj_p2g(d, a, st); });
 }
 
 }  // namespace
@@ -270,8 +488,8 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         c->bound = desc->bound;
         c->dt = desc->dt;
         for (int a = 0; a < 3; ++a) c->g[a] = desc->gravity[a];
-        c->checkpoint_every = std::max(1, desc->checkpoint_every);
         c->max_tape = desc->max_tape_substeps;
+        c->checkpoint_every = s.ck;
         c->material = desc->material;
         c->stream0 = st;
         c->total_nodes = s.total_nodes;
@@ -337,8 +555,7 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         launch_fill_f4(c->gP, s.total_nodes, st);
         launch_fill_f4(c->gV, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.count), 1, 0u, st);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.done), 1, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.count), 2, 0u, st);
         if ((e2 = hipGetLastError()) != hipSuccess) return cleanup_fail(e2, "init kernels");
         if ((e2 = hipStreamSynchronize(st)) != hipSuccess) return cleanup_fail(e2, "create sync");
         *out = c;
@@ -433,10 +650,29 @@ mpm_status mpm_substep(mpm_ctx *c, int32_t n_substeps, int32_t record_tape, void
 {
     if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
     if (n_substeps < 1) return fail(c, MPM_E_ARG, "n_substeps must be >= 1");
-    if (record_tape) return fail(c, MPM_E_UNSUPPORTED, "adjoint tape not available");
     hipStream_t st = as_stream(stream);
-    if (c->scheme == MPM_SCHEME_TILED) substeps_tiled(c, n_substeps, st);
-    else for (int i = 0; i < n_substeps; ++i) substep_direct(c, st);
+    if (!record_tape) {
+        c->tape.len = 0;   // the tape no longer ends at the current state
+        if (c->use_graph && !c->prof.on) {
+            mpm_status r = run_substeps_graph(c, n_substeps, st);
+            if (r != MPM_OK) return r;
+        } else {
+            run_substeps(c, n_substeps, st);
+        }
+        return check_launch(c, "mpm_substep");
+    }
+    if (c->max_tape == 0) return fail(c, MPM_E_STATE, "context was created without a tape (max_tape_substeps = 0)");
+    if (n_substeps > c->max_tape) return fail(c, MPM_E_ARG, "n_substeps exceeds max_tape_substeps");
+    const int k = c->checkpoint_every;
+    c->tape.len = 0;
+    save_checkpoint(c, 0, st);
+    for (int done = 0; done < n_substeps;) {
+        int m = std::min(k, n_substeps - done);
+        run_substeps(c, m, st);
+        done += m;
+        if (done < n_substeps) save_checkpoint(c, done / k, st);
+    }
+    c->tape.len = n_substeps;
     return check_launch(c, "mpm_substep");
 }
 
@@ -466,8 +702,42 @@ mpm_status mpm_run_stage(mpm_ctx *c, int32_t stage, void *stream)
 mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint_io *io, void *stream)
 {
     if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
-    (void)n_substeps; (void)io; (void)stream;
-    return fail(c, MPM_E_STATE, "no adjoint tape recorded");
+    if (!io) return fail(c, MPM_E_ARG, "io is NULL");
+    if (n_substeps < 1) return fail(c, MPM_E_ARG, "n_substeps must be >= 1");
+    if (c->max_tape == 0 || c->tape.len < n_substeps)
+        return fail(c, MPM_E_STATE, "no recorded tape of at least n_substeps substeps ending at the current state");
+    hipStream_t st = as_stream(stream);
+    auto &T = c->tape;
+    const size_t N = c->ntot;
+    const int k = c->checkpoint_every, len = T.len, s0 = len - n_substeps;
+    // seeds (original order) or zero
+    const float *seeds[4] = {io->xbar, io->vbar, io->Cbar, io->Fbar};
+    float *adj[4] = {T.adj.xb, T.adj.vb, T.adj.Cb, T.adj.Fb};
+    const int comps[4] = {3, 3, 9, 9};
+    timed(c, st, PK_ADJ_MISC, [&] {
+        for (int f = 0; f < 4; ++f) {
+            if (seeds[f]) launch_copy_bytes(adj[f], seeds[f], sizeof(float) * comps[f] * N, st);
+            else launch_fill_u32(reinterpret_cast<uint32_t *>(adj[f]), (int64_t)comps[f] * N, 0u, st);
+        }
+        launch_fill_f4(T.adj.gVb, c->total_nodes, st);
+        const int64_t ng = (int64_t)c->tool_slots() * c->max_tape * 3;
+        launch_fill_f64(T.adj.ubar, ng, st);
+        launch_fill_f64(T.adj.Tbar, ng, st);
+        launch_fill_f64(T.adj.mubar, c->n_envs, st);
+        launch_fill_f64(T.adj.lambar, c->n_envs, st);
+    });
+    for (int seg = (len - 1) / k; seg >= s0 / k; --seg) {
+        const int sb = seg * k, se = std::min(sb + k, len);
+        recompute_segment(c, seg, sb, se, st);
+        for (int j = se - 1; j >= std::max(sb, s0); --j) reverse_substep(c, j - sb, j - s0, st);
+    }
+    timed(c, st, PK_ADJ_MISC, [&] {
+        launch_adj_finish(c->dev(), T.adj, n_substeps, io->gE, io->gnu, io->gu, io->gT, st);
+        float *outs[4] = {io->xbar0, io->vbar0, io->Cbar0, io->Fbar0};
+        for (int f = 0; f < 4; ++f)
+            if (outs[f]) launch_copy_bytes(outs[f], adj[f], sizeof(float) * comps[f] * N, st);
+    });
+    return check_launch(c, "mpm_substep_adjoint");
 }
 
 mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, size_t dst_bytes, int32_t dst_on_device,
@@ -570,6 +840,31 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
         return MPM_OK;
     }
     return fail(c, MPM_E_ARG, "unknown field");
+}
+
+mpm_status mpm_profile(mpm_ctx *c, int32_t enable)
+{
+    if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
+    if (enable && c->use_graph) return fail(c, MPM_E_STATE, "profiling is not available with the graph option");
+    if (!enable && c->prof.on) prof_resolve(c);
+    if (enable && !c->prof.on) {
+        for (int k = 0; k < PK_COUNT; ++k) { c->prof.total_ms[k] = 0.0; c->prof.launches[k] = 0; }
+        c->prof.marks.clear();
+        c->prof.used = 0;
+    }
+    c->prof.on = enable != 0;
+    return MPM_OK;
+}
+
+mpm_status mpm_profile_read(mpm_ctx *c, int32_t kind, const char **name, double *total_ms, int64_t *launches)
+{
+    if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
+    if (kind < 0 || kind >= PK_COUNT) return fail(c, MPM_E_ARG, "kind out of range");
+    if (c->prof.on) prof_resolve(c);
+    if (name) *name = PROF_NAMES[kind];
+    if (total_ms) *total_ms = c->prof.total_ms[kind];
+    if (launches) *launches = c->prof.launches[kind];
+    return MPM_OK;
 }
 
 const char *mpm_last_error(const mpm_ctx *c)

@@ -1,0 +1,485 @@
+// Reverse-mode substep (adjoint of P2G, the grid operation, G2P and the F
+// update), run over a tape recorded by a forward recompute.
+//
+// Per reverse substep j, with the adjoints of the state after substep j:
+//   k_adj_g2p : F update, advection and G2P reversed; scatters the adjoint of
+//               the node velocities (27 nodes x 3 floats per particle).
+//   k_adj_grid: grid operation reversed node by node, using the contact
+//               decisions the tape recorded; yields adjoints of (m, mv) and
+//               the tool-velocity / tool-position gradients.
+//   k_adj_p2g : P2G and the Neo-Hookean stress reversed; gathers the node
+//               adjoints and accumulates dL/dmu, dL/dlambda.
+// The last three also give the adjoints of the state before substep j.
+#include "mpm_adjoint.h"
+
+namespace mpm {
+
+// Grid pass of a tape recompute: like the dense grid operation, but it
+// writes (m, vhat) back into P, the final velocity into V and the contact
+// decision of each node.
+__global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gofs, int64_t total_nodes,
+                                                   ContactCode *dec)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_nodes) return;
+    int lo = 0, hi = d.n_envs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (gload(env_gofs + mid) <= g) lo = mid; else hi = mid - 1;
+    }
+    const EnvDev e = load_env(d.env + lo);
+    int64_t local = g - e.gofs;
+    int i, j, k;
+    brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
+    float4 P = gload(d.gP + g);
+    ContactRec rec;
+    float3 v = grid_node_velocity(d, e, lo, P, i, j, k, &rec);
+    float3 vh = node_vhat(d, P);
+    gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
+    gstore(d.gP + g, make_float4(P.x, vh.x, vh.y, vh.z));
+    gstore(dec + g, (ContactCode)(rec.tool < 0 || rec.branch == 0 ? -1 : rec.tool * 4 + rec.branch));
+}
+
+__device__ __forceinline__ void weight_grads(const Stencil &s, float dw[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float f = s.fx[a];
+        dw[a][0] = -(1.5f - f);
+        dw[a][1] = -2.0f * (f - 1.0f);
+        dw[a][2] = f - 0.5f;
+    }
+}
+
+// Reverse of G2P + advection + F update for one particle.
+__global__ __launch_bounds__(256) void k_adj_g2p(Dev d, AdjBuf a)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.ntot) return;
+    const int N = d.ntot;
+    int env = env_of_particle(d, q);
+    const EnvDev e = load_env(d.env + env);
+    float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+    Stencil s;
+    make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
+    if (s.outside) return;   // frozen particle: state and adjoints pass through
+    float dw[3][3];
+    weight_grads(s, dw);
+    // forward C' from the tape's node velocities
+    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float4 Vn[27];
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2) {
+                int n = (o0 * 3 + o1) * 3 + o2;
+                Vn[n] = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
+                float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                float q0 = o0 - s.fx[0], q1 = o1 - s.fx[1], q2 = o2 - s.fx[2];
+                float wx = w * Vn[n].x, wy = w * Vn[n].y, wz = w * Vn[n].z;
+                B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
+                B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
+                B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
+            }
+    const float cs = 4.0f * e.inv_dx;
+    float Cn[9], F[9], Fb[9], Cb[9], xb[3], vb[3];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        Cn[c] = cs * B[c];
+        F[c] = gload(d.F + (size_t)c * N + q);
+        Fb[c] = gload(a.Fb + (size_t)c * N + q);
+        Cb[c] = gload(a.Cb + (size_t)c * N + q);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xb[c] = gload(a.xb + (size_t)c * N + q);
+        vb[c] = gload(a.vb + (size_t)c * N + q);
+    }
+    // F' = (I + dt C') F:  Fbar <- (I + dt C')^T Fbar',  Cbar' += dt Fbar' F^T
+    float Fbn[9], Cbt[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * (Cn[r] * Fb[c] + Cn[3 + r] * Fb[3 + c] + Cn[6 + r] * Fb[6 + c]);
+            Cbt[3 * r + c] = Cb[3 * r + c] + d.dt * (Fb[3 * r] * F[3 * c] + Fb[3 * r + 1] * F[3 * c + 1] + Fb[3 * r + 2] * F[3 * c + 2]);
+        }
+    // x' = x + dt v'
+    float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
+    float Bb[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Bb[c] = cs * Cbt[c];
+    float fxb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2) {
+                int n = (o0 * 3 + o1) * 3 + o2;
+                float q0 = o0 - s.fx[0], q1 = o1 - s.fx[1], q2 = o2 - s.fx[2];
+                float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                float g0 = vbt[0] + Bb[0] * q0 + Bb[1] * q1 + Bb[2] * q2;
+                float g1 = vbt[1] + Bb[3] * q0 + Bb[4] * q1 + Bb[5] * q2;
+                float g2 = vbt[2] + Bb[6] * q0 + Bb[7] * q1 + Bb[8] * q2;
+                float *gv = reinterpret_cast<float *>(a.gVb + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
+                gatomic_add(gv + 0, w * g0);
+                gatomic_add(gv + 1, w * g1);
+                gatomic_add(gv + 2, w * g2);
+                const float4 V = Vn[n];
+                float wb = V.x * g0 + V.y * g1 + V.z * g2;
+                // qbar = w Bbar^T V; q = o - fx
+                float qb0 = w * (Bb[0] * V.x + Bb[3] * V.y + Bb[6] * V.z);
+                float qb1 = w * (Bb[1] * V.x + Bb[4] * V.y + Bb[7] * V.z);
+                float qb2 = w * (Bb[2] * V.x + Bb[5] * V.y + Bb[8] * V.z);
+                fxb[0] += -qb0 + wb * dw[0][o0] * s.w[1][o1] * s.w[2][o2];
+                fxb[1] += -qb1 + wb * s.w[0][o0] * dw[1][o1] * s.w[2][o2];
+                fxb[2] += -qb2 + wb * s.w[0][o0] * s.w[1][o1] * dw[2][o2];
+            }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        gstore(a.xb + (size_t)c * N + q, xb[c] + e.inv_dx * fxb[c]);
+        gstore(a.vb + (size_t)c * N + q, 0.0f);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        gstore(a.Fb + (size_t)c * N + q, Fbn[c]);
+        gstore(a.Cb + (size_t)c * N + q, 0.0f);
+    }
+}
+
+// Reverse of the grid operation at one node with mass; vb is the adjoint of
+// the node's final velocity.  Returns the adjoint of vhat and adds the
+// contact tool's velocity / position adjoints.
+__device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, int env, float3 vh, int i, int j, int k,
+                                               ContactCode code, float3 vb, int &tool, float3 &ub, float3 &Tb)
+{
+    tool = -1;
+    ub = make_float3(0.f, 0.f, 0.f);
+    Tb = make_float3(0.f, 0.f, 0.f);
+    if (boundary_node(e, i, j, k)) return make_float3(0.f, 0.f, 0.f);
+    if (code < 0) return vb;
+    const int t = code >> 2, branch = code & 3;
+    const ToolDev &T = d.tools[(size_t)env * d.max_tools + t];
+    tool = t;
+    ub = vb;                                   // v = v_rel' + u
+    if (branch == 2) return make_float3(0.f, 0.f, 0.f);
+    // friction branch: v = s v_t + u with s = 1 + mu vn/|vt|
+    CapsuleHit h = capsule_hit(T, i * e.dx, j * e.dx, k * e.dx);
+    float3 u = tool_velocity(T);
+    float3 n = h.n;
+    float r0 = vh.x - u.x, r1 = vh.y - u.y, r2 = vh.z - u.z;
+    float vn = r0 * n.x + r1 * n.y + r2 * n.z;
+    float t0 = r0 - vn * n.x, t1 = r1 - vn * n.y, t2 = r2 - vn * n.z;
+    float nt = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+    float s = 1.0f + T.friction * vn / nt;
+    float sb = vb.x * t0 + vb.y * t1 + vb.z * t2;
+    float tb0 = s * vb.x, tb1 = s * vb.y, tb2 = s * vb.z;
+    float vnb = sb * T.friction / nt;
+    float ntb = -sb * T.friction * vn / (nt * nt);
+    tb0 += ntb * t0 / nt; tb1 += ntb * t1 / nt; tb2 += ntb * t2 / nt;
+    vnb -= tb0 * n.x + tb1 * n.y + tb2 * n.z;
+    float rb0 = tb0 + vnb * n.x, rb1 = tb1 + vnb * n.y, rb2 = tb2 + vnb * n.z;
+    float nb0 = -vn * tb0 + vnb * r0, nb1 = -vn * tb1 + vnb * r1, nb2 = -vn * tb2 + vnb * r2;
+    ub.x -= rb0; ub.y -= rb1; ub.z -= rb2;
+    if (h.len >= 1e-12f) {
+        // n = R l, l = q/|q|, q = x_ref - clamp(x_ref.x) e_x, x_ref = R^T (x - T)
+        float lb0 = T.R[0] * nb0 + T.R[3] * nb1 + T.R[6] * nb2;
+        float lb1 = T.R[1] * nb0 + T.R[4] * nb1 + T.R[7] * nb2;
+        float lb2 = T.R[2] * nb0 + T.R[5] * nb1 + T.R[8] * nb2;
+        float dl = lb0 * h.l[0] + lb1 * h.l[1] + lb2 * h.l[2];
+        float qb0 = (lb0 - dl * h.l[0]) / h.len, qb1 = (lb1 - dl * h.l[1]) / h.len, qb2 = (lb2 - dl * h.l[2]) / h.len;
+        float xr0 = h.interior ? 0.0f : qb0;
+        Tb.x = -(T.R[0] * xr0 + T.R[1] * qb1 + T.R[2] * qb2);
+        Tb.y = -(T.R[3] * xr0 + T.R[4] * qb1 + T.R[5] * qb2);
+        Tb.z = -(T.R[6] * xr0 + T.R[7] * qb1 + T.R[8] * qb2);
+    }
+    return make_float3(rb0, rb1, rb2);
+}
+
+__global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs, int64_t total_nodes,
+                                                  const ContactCode *dec, AdjBuf a)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_nodes) return;
+    float4 vb4 = gload(a.gVb + g);
+    gstore(a.gVb + g, make_float4(0.f, 0.f, 0.f, 0.f));      // ready for the next reverse substep
+    float4 P = gload(d.gP + g);                                // (m, vhat)
+    if (!(P.x > 0.0f)) {
+        gstore(a.gPb + g, make_float4(0.f, 0.f, 0.f, 0.f));
+        return;
+    }
+    int lo = 0, hi = d.n_envs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (gload(env_gofs + mid) <= g) lo = mid; else hi = mid - 1;
+    }
+    const EnvDev e = load_env(d.env + lo);
+    int64_t local = g - e.gofs;
+    int i, j, k;
+    brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
+    int tool;
+    float3 ub, Tb;
+    float3 vh = make_float3(P.y, P.z, P.w);
+    float3 vhb = node_adjoint(d, e, lo, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z), tool, ub, Tb);
+    if (tool >= 0) {
+        size_t o = (((size_t)lo * d.max_tools + tool) * a.max_tape + a.j) * 3;
+        gatomic_add(a.ubar + o + 0, (double)ub.x);
+        gatomic_add(a.ubar + o + 1, (double)ub.y);
+        gatomic_add(a.ubar + o + 2, (double)ub.z);
+        gatomic_add(a.Tbar + o + 0, (double)Tb.x);
+        gatomic_add(a.Tbar + o + 1, (double)Tb.y);
+        gatomic_add(a.Tbar + o + 2, (double)Tb.z);
+    }
+    // vhat = P/m + dt g:  Pbar = vhbar/m,  mbar = -vhbar . (P/m) / m
+    float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
+    float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
+    gstore(a.gPb + g, make_float4(mb, vhb.x / P.x, vhb.y / P.x, vhb.z / P.x));
+}
+
+// Sum per environment over a wavefront, then one double atomic per wave.
+__device__ __forceinline__ void wave_env_add(double *dst, int env, double v, bool active)
+{
+    int env0 = __shfl(env, 0);
+    bool uniform = __all(!active || env == env0);
+    if (uniform) {
+        double s = active ? v : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((threadIdx.x & 63) == 0 && __any(active)) gatomic_add(dst + env0, s);
+    } else if (active) {
+        gatomic_add(dst + env, v);
+    }
+}
+
+// Reverse of P2G and of the stress for one particle.
+__global__ __launch_bounds__(256) void k_adj_p2g(Dev d, AdjBuf a)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = d.ntot;
+    bool active = q < N;
+    int env = 0;
+    double mub = 0.0, lamb = 0.0;
+    if (active) {
+        env = env_of_particle(d, q);
+        const EnvDev e = load_env(d.env + env);
+        float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+        Stencil s;
+        make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
+        if (!s.outside) {
+            const float *mat = d.material + 4 * env;
+            float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
+            float mu, lam;
+            lame(E, nu, mu, lam);
+            const float m = rho * V0;
+            const float kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
+            float F[9], C[9], v[3], tau[9], A[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                F[c] = gload(d.F + (size_t)c * N + q);
+                C[c] = gload(d.C + (size_t)c * N + q);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = gload(d.v + (size_t)c * N + q);
+            bool inverted = kirchhoff(F, mu, lam, tau);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
+            float dw[3][3];
+            weight_grads(s, dw);
+            float vbp[3] = {0.f, 0.f, 0.f}, Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float fxb[3] = {0.f, 0.f, 0.f};
+            const float dx = e.dx;
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+                for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                    for (int o2 = 0; o2 < 3; ++o2) {
+                        float4 Pb = gload(a.gPb + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
+                        float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                        float d0 = (o0 - s.fx[0]) * dx, d1 = (o1 - s.fx[1]) * dx, d2 = (o2 - s.fx[2]) * dx;
+                        vbp[0] += m * w * Pb.y; vbp[1] += m * w * Pb.z; vbp[2] += m * w * Pb.w;
+                        float wy = w * Pb.y, wz = w * Pb.z, ww = w * Pb.w;
+                        Ab[0] += wy * d0; Ab[1] += wy * d1; Ab[2] += wy * d2;
+                        Ab[3] += wz * d0; Ab[4] += wz * d1; Ab[5] += wz * d2;
+                        Ab[6] += ww * d0; Ab[7] += ww * d1; Ab[8] += ww * d2;
+                        float c0 = m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2;
+                        float c1 = m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2;
+                        float c2 = m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2;
+                        float wb = m * Pb.x + Pb.y * c0 + Pb.z * c1 + Pb.w * c2;
+                        // dpos = q dx, q = o - fx:  fxbar -= dx * w A^T Pbar
+                        float db0 = w * (A[0] * Pb.y + A[3] * Pb.z + A[6] * Pb.w);
+                        float db1 = w * (A[1] * Pb.y + A[4] * Pb.z + A[7] * Pb.w);
+                        float db2 = w * (A[2] * Pb.y + A[5] * Pb.z + A[8] * Pb.w);
+                        fxb[0] += -dx * db0 + wb * dw[0][o0] * s.w[1][o1] * s.w[2][o2];
+                        fxb[1] += -dx * db1 + wb * s.w[0][o0] * dw[1][o1] * s.w[2][o2];
+                        fxb[2] += -dx * db2 + wb * s.w[0][o0] * s.w[1][o1] * dw[2][o2];
+                    }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float* px = a.xb + (size_t)c * N + q;
+                gstore(px, gload(px) + e.inv_dx * fxb[c]);
+                float* pv = a.vb + (size_t)c * N + q;
+                gstore(pv, gload(pv) + vbp[c]);
+            }
+            float taub[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                float* pc = a.Cb + (size_t)c * N + q;
+                gstore(pc, gload(pc) + m * Ab[c]);
+                taub[c] = kf * Ab[c];
+            }
+            // tau = mu (F F^T - I) + lam ln J I
+            float Fb[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    Fb[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
+                                          (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
+            double trt = (double)taub[0] + taub[4] + taub[8];
+            double J = det3d(F);
+            double lnJ = log(inverted ? J_MIN : J);
+            if (!inverted) {
+                // F^-T = cof(F) / J
+                double ci[9] = {(double)F[4] * F[8] - (double)F[5] * F[7], -((double)F[3] * F[8] - (double)F[5] * F[6]),
+                                (double)F[3] * F[7] - (double)F[4] * F[6], -((double)F[1] * F[8] - (double)F[2] * F[7]),
+                                (double)F[0] * F[8] - (double)F[2] * F[6], -((double)F[0] * F[7] - (double)F[1] * F[6]),
+                                (double)F[1] * F[5] - (double)F[2] * F[4], -((double)F[0] * F[5] - (double)F[2] * F[3]),
+                                (double)F[0] * F[4] - (double)F[1] * F[3]};
+                double sc = (double)lam * trt / J;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) Fb[c] += (float)(sc * ci[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                float* pf = a.Fb + (size_t)c * N + q;
+                gstore(pf, gload(pf) + Fb[c]);
+            }
+            // dL/dmu = taubar : (F F^T - I),  dL/dlambda = tr(taubar) ln J
+            double ff = 0.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double G = (double)F[3 * r] * F[3 * c] + (double)F[3 * r + 1] * F[3 * c + 1] +
+                               (double)F[3 * r + 2] * F[3 * c + 2] - (r == c ? 1.0 : 0.0);
+                    ff += (double)taub[3 * r + c] * G;
+                }
+            mub = ff;
+            lamb = trt * lnJ;
+        }
+    }
+    wave_env_add(a.mubar, env, mub, active);
+    wave_env_add(a.lambar, env, lamb, active);
+}
+
+// Chain the per-substep tool gradients through T_{s+1} = T_s + dt u_s and
+// the Lame parameters through (E, nu).  One thread per (env, tool).
+__global__ void k_adj_finish(Dev d, AdjBuf a, int n, double *gE, double *gnu, double *gu, double *gT)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int nt = d.max_tools > 0 ? d.max_tools : 1;
+    if (t >= d.n_envs * nt) return;
+    int env = t / nt, tool = t % nt;
+    if (d.max_tools > 0) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int j = n - 1; j >= 0; --j) {
+            size_t o = (((size_t)env * d.max_tools + tool) * a.max_tape + j) * 3;
+            size_t oo = (((size_t)env * d.max_tools + tool) * n + j) * 3;
+            for (int c = 0; c < 3; ++c) {
+                if (gu) gstore(gu + oo + c, gload(a.ubar + o + c) + (double)d.dt * acc[c]);
+                acc[c] += gload(a.Tbar + o + c);
+            }
+        }
+        if (gT)
+            for (int c = 0; c < 3; ++c) gstore(gT + ((size_t)env * d.max_tools + tool) * 3 + c, acc[c]);
+    }
+    if (tool == 0) {
+        double E = gload(d.material + 4 * env), nu = gload(d.material + 4 * env + 1);
+        double mub = gload(a.mubar + env), lamb = gload(a.lambar + env);
+        double dmu_dE = 1.0 / (2.0 * (1.0 + nu)), dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+        double dlam_dE = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        double dlam_dnu = E * (1.0 + 2.0 * nu * nu) / ((1.0 + nu) * (1.0 + nu) * (1.0 - 2.0 * nu) * (1.0 - 2.0 * nu));
+        if (gE) gstore(gE + env, mub * dmu_dE + lamb * dlam_dE);
+        if (gnu) gstore(gnu + env, mub * dmu_dnu + lamb * dlam_dnu);
+    }
+}
+
+// dst[c][pid[q]] = src[c][q]  (slot order -> original order)
+__global__ void k_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ntot) return;
+    int o = gload(pid + q);
+    for (int c = 0; c < comps; ++c) gstore(dst + (size_t)c * ntot + o, gload(src + (size_t)c * ntot + q));
+}
+
+__global__ void k_copy_words(uint32_t *dst, const uint32_t *src, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        gstore(dst + i, gload(src + i));
+}
+
+__global__ void k_fill_f64(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        gstore(p + i, 0.0);
+}
+
+static unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grid_tape, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
+                       total_nodes, dec);
+}
+
+void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_g2p, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
+}
+
+void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
+                     const AdjBuf &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_grid, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
+                       total_nodes, dec, a);
+}
+
+void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_p2g, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
+}
+
+void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
+                       hipStream_t st)
+{
+    int nt = d.n_envs * (d.max_tools > 0 ? d.max_tools : 1);
+    hipLaunchKernelGGL(k_adj_finish, dim3((nt + 255) / 256), dim3(256), 0, st, d, a, n, gE, gnu, gu, gT);
+}
+
+void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unpermute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, pid, ntot, comps, dst);
+}
+
+void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    size_t n = bytes / 4;
+    hipLaunchKernelGGL(k_copy_words, dim3(blocks_for((int64_t)n)), dim3(256), 0, st, static_cast<uint32_t *>(dst),
+                       static_cast<const uint32_t *>(src), n);
+}
+
+void launch_fill_f64(double *p, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n)), dim3(256), 0, st, p, n);
+}
+
+}  // namespace mpm

@@ -13,7 +13,7 @@ __global__ __launch_bounds__(256) void k_p2g_direct(Dev d)
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.ntot) return;
     int env = env_of_particle(d, q);
-    const EnvDev e = d.env[env];
+    const EnvDev e = load_env(d.env + env);
     const int N = d.ntot;
     float x0 = d.x[q], x1 = d.x[N + q], x2 = d.x[2 * N + q];
     Stencil s;
@@ -46,10 +46,10 @@ __global__ __launch_bounds__(256) void k_p2g_direct(Dev d)
                 float p1 = mv1 + A[3] * d0 + A[4] * d1 + A[5] * d2;
                 float p2 = mv2 + A[6] * d0 + A[7] * d1 + A[8] * d2;
                 float *g = reinterpret_cast<float *>(d.gP + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
-                atomicAdd(g + 0, w * m);
-                atomicAdd(g + 1, w * p0);
-                atomicAdd(g + 2, w * p1);
-                atomicAdd(g + 3, w * p2);
+                gatomic_add(g + 0, w * m);
+                gatomic_add(g + 1, w * p0);
+                gatomic_add(g + 2, w * p1);
+                gatomic_add(g + 3, w * p2);
             }
 }
 
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_grid_dense(Dev d, const int64_t *env_go
         int mid = (lo + hi + 1) >> 1;
         if (env_gofs[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    const EnvDev e = d.env[lo];
+    const EnvDev e = load_env(d.env + lo);
     int64_t local = g - e.gofs;
     int i, j, k;
     brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
     advance_tools(d, q);
     if (q >= d.ntot) return;
     int env = env_of_particle(d, q);
-    const EnvDev e = d.env[env];
+    const EnvDev e = load_env(d.env + env);
     const int N = d.ntot;
     float x0 = d.x[q], x1 = d.x[N + q], x2 = d.x[2 * N + q];
     Stencil s;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
             for (int o2 = 0; o2 < 3; ++o2) {
                 float d0 = (o0 - s.fx[0]), d1 = (o1 - s.fx[1]), d2 = (o2 - s.fx[2]);
                 float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
-                float4 V = d.gV[node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2)];
+                float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
                 float wx = w * V.x, wy = w * V.y, wz = w * V.z;
                 vp0 += wx; vp1 += wy; vp2 += wz;
                 B[0] += wx * d0; B[1] += wx * d1; B[2] += wx * d2;

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_brick_count(Dev d, SortBuf s)
 {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.ntot) return;
-    const EnvDev e = d.env[env_of_particle(d, q)];
+    const EnvDev e = load_env(d.env + env_of_particle(d, q));
     const int N = d.ntot;
     int b = particle_brick(e, d.x[q], d.x[N + q], d.x[2 * N + q]);
     s.key[q] = b;

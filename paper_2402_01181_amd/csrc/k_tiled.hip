@@ -37,7 +37,7 @@ __device__ __forceinline__ int env_of_brick(const int32_t *env_bofs, int n_envs,
     int lo = 0, hi = n_envs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (env_bofs[mid] <= b) lo = mid; else hi = mid - 1;
+        if (gload(env_bofs + mid) <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -46,7 +46,7 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const ActiveBuf &act, in
 {
     Tile t;
     t.env = env_of_brick(act.env_bofs, d.n_envs, brick);
-    e = d.env[t.env];
+    e = load_env(d.env + t.env);
     int lb = brick - e.bofs;
     t.bk = lb % e.nb;
     int r = lb / e.nb;
@@ -69,22 +69,22 @@ __device__ __forceinline__ void item_range(int nitems, int &first, int &stride, 
     stride = G / NXCD;
 }
 
-__device__ __forceinline__ void mark_brick(const ActiveBuf &act, int b)
+__device__ __forceinline__ void mark_brick(const ActiveBuf &act, int par, int b)
 {
-    if (atomicCAS(act.flag + b, 0, 1) == 0) {
-        int slot = atomicAdd(act.count, 1);
-        act.list[slot] = b;
+    if (gatomic_cas(act.flag + b, 0, 1)) {
+        int slot = gatomic_add(act.count + par, 1);
+        gstore(act.list + (size_t)par * act.stride + slot, b);
     }
 }
 
 // Mark every node brick a stencil with base b touches (global fallback path).
-__device__ __forceinline__ void mark_stencil_bricks(const ActiveBuf &act, const EnvDev &e, const int b[3])
+__device__ __forceinline__ void mark_stencil_bricks(const ActiveBuf &act, int par, const EnvDev &e, const int b[3])
 {
     int lo0 = b[0] >> 2, hi0 = (b[0] + 2) >> 2, lo1 = b[1] >> 2, hi1 = (b[1] + 2) >> 2;
     int lo2 = b[2] >> 2, hi2 = (b[2] + 2) >> 2;
     for (int i = lo0; i <= hi0; ++i)
         for (int j = lo1; j <= hi1; ++j)
-            for (int k = lo2; k <= hi2; ++k) mark_brick(act, e.bofs + (i * e.nb + j) * e.nb + k);
+            for (int k = lo2; k <= hi2; ++k) mark_brick(act, par, e.bofs + (i * e.nb + j) * e.nb + k);
 }
 
 __device__ __forceinline__ void advance_end_of_substep(const Dev &d)
@@ -124,7 +124,7 @@ __device__ __forceinline__ void g2p_accumulate(const Dev &d, const EnvDev &e, co
                     int li = lds_index(l0 + o0, l1 + o1, l2 + o2);
                     V0 = tvx[li]; V1 = tvy[li]; V2 = tvz[li];
                 } else {
-                    float4 V = d.gV[node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2)];
+                    float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
                     V0 = V.x; V1 = V.y; V2 = V.z;
                 }
                 float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
@@ -163,7 +163,7 @@ __device__ __forceinline__ bool stencil_in_tile(const Tile &t, const Stencil &s,
     return l0 >= 0 && l1 >= 0 && l2 >= 0 && l0 <= TILE - 3 && l1 <= TILE - 3 && l2 <= TILE - 3;
 }
 
-__device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &act, const EnvDev &e,
+__device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &act, int par, const EnvDev &e,
                                                  const Stencil &s, float m, const float A[9], const float v[3])
 {
     for (int o0 = 0; o0 < 3; ++o0)
@@ -172,12 +172,12 @@ __device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &
                 float pm, p0, p1, p2;
                 p2g_weights(e, s, m, A, v, o0, o1, o2, pm, p0, p1, p2);
                 float *g = reinterpret_cast<float *>(d.gP + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
-                atomicAdd(g + 0, pm);
-                atomicAdd(g + 1, p0);
-                atomicAdd(g + 2, p1);
-                atomicAdd(g + 3, p2);
+                gatomic_add(g + 0, pm);
+                gatomic_add(g + 1, p0);
+                gatomic_add(g + 2, p1);
+                gatomic_add(g + 3, p2);
             }
-    mark_stencil_bricks(act, e, s.b);
+    mark_stencil_bricks(act, par, e, s.b);
 }
 
 // A = -dt V0 (4/dx^2) tau(F) + m C   (MLS force folded into the affine term)
@@ -185,12 +185,13 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
                                                    const float C[9], float A[9], float &m)
 {
     const float *mat = d.material + 4 * env;
+    float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
     float mu, lam;
-    lame(mat[0], mat[1], mu, lam);
-    m = mat[2] * mat[3];
+    lame(E, nu, mu, lam);
+    m = rho * V0;
     float tau[9];
     if (kirchhoff(F, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
-    const float k = -d.dt * mat[3] * 4.0f * e.inv_dx * e.inv_dx;
+    const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
 #pragma unroll
     for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * C[c];
 }
@@ -208,11 +209,11 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
     __shared__ int touched;
 
     const int N = d.ntot, T = blockDim.x, tid = threadIdx.x;
-    const int nitems = a.totals->y;
+    const int nitems = gload(a.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
     for (int it = first; it < end; it += stride) {
-        const int4 item = a.items[it];
+        const int4 item = gload(a.items + it);
         EnvDev e;
         const Tile t = make_tile(d, a.act, item.x, e);
         // stage the tile
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
             if (G2P) {
                 int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                 float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n) V = d.gV[node_id(e, i, j, k)];
+                if (i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
                 tvx[li] = V.x; tvy[li] = V.y; tvz[li] = V.z;
             }
         }
@@ -231,10 +232,10 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
         __syncthreads();
 
         for (int p = item.y + tid; p < item.y + item.z; p += T) {
-            float x[3] = {a.xin[p], a.xin[N + p], a.xin[2 * N + p]};
+            float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
             float F[9], v[3], C[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) F[c] = a.Fin[(size_t)c * N + p];
+            for (int c = 0; c < 9; ++c) F[c] = gload(a.Fin + (size_t)c * N + p);
             Stencil s;
             make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s);
             bool frozen = stencil_outside(s, e.n);
@@ -243,11 +244,17 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                 set_flag(d.status, t.env, MPM_FLAG_OUT_OF_DOMAIN);
                 if (a.xout != a.xin) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { a.xout[(size_t)c * N + p] = x[c]; a.vout[(size_t)c * N + p] = a.vin[(size_t)c * N + p]; }
+                    for (int c = 0; c < 3; ++c) {
+                        gstore(a.xout + (size_t)c * N + p, x[c]);
+                        gstore(a.vout + (size_t)c * N + p, gload(a.vin + (size_t)c * N + p));
+                    }
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) { a.Fout[(size_t)c * N + p] = F[c]; a.Cout[(size_t)c * N + p] = a.Cin[(size_t)c * N + p]; }
+                    for (int c = 0; c < 9; ++c) {
+                        gstore(a.Fout + (size_t)c * N + p, F[c]);
+                        gstore(a.Cout + (size_t)c * N + p, gload(a.Cin + (size_t)c * N + p));
+                    }
                 }
-                if (a.pidout != a.pidin) a.pidout[p] = a.pidin[p];
+                if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
                 continue;
             }
             if (G2P) {
@@ -272,9 +279,9 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                     set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
             } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = a.vin[(size_t)c * N + p];
+                for (int c = 0; c < 3; ++c) v[c] = gload(a.vin + (size_t)c * N + p);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) C[c] = a.Cin[(size_t)c * N + p];
+                for (int c = 0; c < 9; ++c) C[c] = gload(a.Cin + (size_t)c * N + p);
             }
             bool write_vc = MODE == 2;
             if (P2G) {
@@ -304,22 +311,22 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                                     atomicAdd(&tpz[li], p2);
                                 }
                     } else {
-                        p2g_particle_global(d, a.act, e, s2, m, A, v);
+                        p2g_particle_global(d, a.act, a.par, e, s2, m, A, v);
                     }
                 }
             }
             if (G2P) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a.xout[(size_t)c * N + p] = x[c];
+                for (int c = 0; c < 3; ++c) gstore(a.xout + (size_t)c * N + p, x[c]);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) a.Fout[(size_t)c * N + p] = F[c];
+                for (int c = 0; c < 9; ++c) gstore(a.Fout + (size_t)c * N + p, F[c]);
                 if (write_vc) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) a.vout[(size_t)c * N + p] = v[c];
+                    for (int c = 0; c < 3; ++c) gstore(a.vout + (size_t)c * N + p, v[c]);
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) a.Cout[(size_t)c * N + p] = C[c];
+                    for (int c = 0; c < 9; ++c) gstore(a.Cout + (size_t)c * N + p, C[c]);
                 }
-                if (a.pidout != a.pidin) a.pidout[p] = a.pidin[p];
+                if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
             }
         }
 
@@ -333,10 +340,11 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                 if (pm != 0.f) {
                     int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                     float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
-                    atomicAdd(g + 0, pm);
-                    atomicAdd(g + 1, tpx[li]);
-                    atomicAdd(g + 2, tpy[li]);
-                    atomicAdd(g + 3, tpz[li]);
+                    float q0 = tpx[li], q1 = tpy[li], q2 = tpz[li];
+                    gatomic_add(g + 0, pm);
+                    gatomic_add(g + 1, q0);
+                    gatomic_add(g + 2, q1);
+                    gatomic_add(g + 3, q2);
                     int bit = (((i >> 2) - t.bi + 1) * 3 + ((j >> 2) - t.bj + 1)) * 3 + ((k >> 2) - t.bk + 1);
                     atomicOr(&touched, 1 << bit);
                 }
@@ -344,45 +352,39 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
             __syncthreads();
             if (tid < 27 && ((touched >> tid) & 1)) {
                 int bi = t.bi - 1 + tid / 9, bj = t.bj - 1 + (tid / 3) % 3, bk = t.bk - 1 + tid % 3;
-                mark_brick(a.act, e.bofs + (bi * e.nb + bj) * e.nb + bk);
+                mark_brick(a.act, a.par, e.bofs + (bi * e.nb + bj) * e.nb + bk);
             }
         }
         __syncthreads();
     }
     if (G2P) advance_end_of_substep(d);
+    // the tail ends a call: both active lists start empty at the next head
+    if (MODE == 2 && blockIdx.x == 0 && tid < 2) gstore(a.act.count + tid, 0);
 }
 
-// Grid operation over the active node bricks: one wavefront per 4^3 brick.
-// Writes V, clears P and the brick's flag; the last workgroup to finish
-// resets the list for the next P2G.
-__global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a)
+// Grid operation over the active node bricks of list `par`: one wavefront
+// per 4^3 brick.  Writes V, clears P and the brick's flag; clears the other
+// list's count for the next P2G.
+__global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int cnt = *a.count;
+    const int cnt = gload(a.count + par);
+    const int32_t *list = a.list + (size_t)par * a.stride;
     for (int i = blockIdx.x * nw + wave; i < cnt; i += gridDim.x * nw) {
-        int b = a.list[i];
+        int b = gload(list + i);
         int env = env_of_brick(a.env_bofs, d.n_envs, b);
-        const EnvDev e = d.env[env];
+        const EnvDev e = load_env(d.env + env);
         int lb = b - e.bofs;
         int gi, gj, gk;
         brick_local_to_ijk(e, lb, lane, gi, gj, gk);
         int64_t g = e.gofs + (int64_t)lb * 64 + lane;
-        float4 P = d.gP[g];
+        float4 P = gload(d.gP + g);
         float3 v = grid_node_velocity(d, e, env, P, gi, gj, gk, nullptr);
-        d.gV[g] = make_float4(v.x, v.y, v.z, 0.f);
-        d.gP[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane == 0) a.flag[b] = 0;
+        gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
+        gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));
+        if (lane == 0) gstore(a.flag + b, 0);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        int done = atomicAdd(a.done, 1);
-        if (done == (int)gridDim.x - 1) {
-            *a.count = 0;
-            *a.done = 0;
-            __threadfence();
-        }
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.count + (par ^ 1), 0);
 }
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
@@ -413,9 +415,9 @@ int tiled_workgroups(int block)
     return g < NXCD ? NXCD : g;
 }
 
-void launch_grid_active(const Dev &d, const ActiveBuf &a, int nblocks, hipStream_t st)
+void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grid_active, dim3(nblocks), dim3(256), 0, st, d, a);
+    hipLaunchKernelGGL(k_grid_active, dim3(nblocks), dim3(256), 0, st, d, a, par);
 }
 
 }  // namespace mpm

@@ -1,0 +1,36 @@
+// Reverse-mode (adjoint) substep: tape layout and kernel launchers.
+#pragma once
+#include "mpm_tiled.h"
+
+namespace mpm {
+
+// Adjoint state of one reverse pass.  Particle arrays use the original
+// particle order, [comp][ntot].
+struct AdjBuf {
+    float *xb, *vb, *Cb, *Fb;
+    float4 *gVb;        // [total_nodes] adjoint of the node velocity (xyz); kept zero between substeps
+    float4 *gPb;        // [total_nodes] adjoint of (m, mv)
+    double *ubar;       // [n_envs][max_tools][max_tape][3] direct dL/du per substep
+    double *Tbar;       // [n_envs][max_tools][max_tape][3] dL/dT per substep
+    double *mubar;      // [n_envs]
+    double *lambar;     // [n_envs]
+    int max_tape;
+    int j;              // window-relative substep index of the current reverse step
+};
+
+// Contact decision of a node, recorded by the tape's grid pass:
+// -1 no contact / unchanged, else tool * 4 + branch (branch as in ContactRec).
+typedef int8_t ContactCode;
+
+void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, hipStream_t st);
+void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st);
+void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
+                     const AdjBuf &a, hipStream_t st);
+void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st);
+void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
+                       hipStream_t st);
+void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st);
+void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
+void launch_fill_f64(double *p, int64_t n, hipStream_t st);
+
+}  // namespace mpm

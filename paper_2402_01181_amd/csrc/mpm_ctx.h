@@ -4,7 +4,33 @@
 #include <string>
 #include <vector>
 
-#include "mpm_tiled.h"
+#include "mpm_adjoint.h"
+
+// Kernel kinds timed by the built-in profiler (mpm_profile_*).
+enum ProfKind {
+    PK_FILL = 0, PK_P2G_DIRECT, PK_GRID_DENSE, PK_G2P_DIRECT, PK_SORT, PK_P2G_TILED, PK_FUSED_TILED,
+    PK_G2P_TILED, PK_GRID_ACTIVE, PK_ADJ_G2P, PK_ADJ_GRID, PK_ADJ_P2G, PK_ADJ_MISC, PK_COUNT
+};
+static const char *const PROF_NAMES[PK_COUNT] = {
+    "fill", "p2g_direct", "grid_dense", "g2p_direct", "sort", "p2g_tiled", "fused_g2p_p2g_tiled",
+    "g2p_tiled", "grid_active", "adj_g2p", "adj_grid", "adj_p2g", "adj_misc"};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;      // reusable events
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> marks;   // (kind, index of start event; stop = +1)
+    double total_ms[PK_COUNT] = {};
+    long long launches[PK_COUNT] = {};
+};
+
+// One captured call of n substeps (MPM_OPT_GRAPH) and the host-side
+// sequencing state that call leaves behind.
+struct GraphEntry {
+    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0;
+    hipGraphExec_t exec = nullptr;
+    int since_sort_after = 0;
+};
 
 struct mpm_ctx {
     std::string err;
@@ -45,6 +71,37 @@ struct mpm_ctx {
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
     // host mirror of the tool slots
     std::vector<mpm::ToolDev> tools_h;
+    Profiler prof;
+    // adjoint tape (carved only when max_tape > 0)
+    struct Tape {
+        int n_ckpt = 0;
+        float *ckpt_state = nullptr;        // [n_ckpt][24][ntot], original order
+        mpm::ToolDev *ckpt_tools = nullptr; // [n_ckpt][slots]
+        int32_t *ckpt_step = nullptr;       // [n_ckpt][n_envs]
+        float *seg_state = nullptr;         // [k][24][ntot]
+        mpm::ToolDev *seg_tools = nullptr;  // [k][slots]
+        float4 *seg_P = nullptr, *seg_V = nullptr;   // [k][total_nodes]
+        mpm::ContactCode *seg_dec = nullptr;         // [k][total_nodes]
+        float *work = nullptr;              // [24][ntot] recompute state
+        mpm::ToolDev *work_tools = nullptr;
+        int32_t *work_step = nullptr;
+        uint32_t *work_status = nullptr;
+        mpm::AdjBuf adj{};
+        float *adj_state = nullptr;         // [24][ntot] (xb, vb, Cb, Fb)
+        int len = 0;                        // recorded substeps
+    } tape;
+    size_t tool_slots() const { return (size_t)n_envs * (max_tools > 0 ? max_tools : 1); }
+
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
+
+    ~mpm_ctx()
+    {
+        for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+        for (auto &g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
 
     mpm::Dev dev() const
     {

@@ -8,6 +8,79 @@
 
 namespace mpm {
 
+// Global-address-space views of device pointers.  Pointers that reach a
+// kernel inside a struct are generic; casting them makes the compiler emit
+// global_* instead of flat_* memory instructions (flat operations also count
+// against the LDS wait counter and would serialise LDS and global traffic).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+__device__ __forceinline__ void gatomic_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void gatomic_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int gatomic_add(int *p, int v)
+{
+    return __hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool gatomic_cas(int *p, int expected, int desired)
+{
+    return __hip_atomic_compare_exchange_strong(gptr(p), &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *gptr(const_cast<T *>(p));
+}
+
+template <class T>
+__device__ __forceinline__ void gstore(T *p, T v)
+{
+    *gptr(p) = v;
+}
+
+// HIP's vector structs cannot be copied through an address-space-qualified
+// reference; move them as clang vector types.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float4 gload(const float4 *p)
+{
+    v4f r = *(const __attribute__((address_space(1))) v4f *)p;
+    return make_float4(r.x, r.y, r.z, r.w);
+}
+
+__device__ __forceinline__ void gstore(float4 *p, float4 v)
+{
+    v4f r = {v.x, v.y, v.z, v.w};
+    *(__attribute__((address_space(1))) v4f *)p = r;
+}
+
+__device__ __forceinline__ int4 gload(const int4 *p)
+{
+    v4i r = *(const __attribute__((address_space(1))) v4i *)p;
+    return make_int4(r.x, r.y, r.z, r.w);
+}
+
+__device__ __forceinline__ int2 gload(const int2 *p)
+{
+    v2i r = *(const __attribute__((address_space(1))) v2i *)p;
+    return make_int2(r.x, r.y);
+}
+
 constexpr int BRICK = 4;            // grid bricks are 4x4x4 nodes = 64 nodes = one wavefront
 constexpr int BRICK_NODES = 64;
 constexpr int MAX_TOOLS = 8;
@@ -25,6 +98,8 @@ struct EnvDev {
     float dx, inv_dx;
     int32_t pad[2];
 };
+
+static_assert(sizeof(EnvDev) == 48, "EnvDev layout");
 
 // One tool slot; T and k advance on the device once per substep.
 struct ToolDev {
@@ -53,12 +128,22 @@ struct Dev {
     float4 *gP, *gV;
 };
 
+__device__ __forceinline__ EnvDev load_env(const EnvDev *p)
+{
+    int w[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = gload(reinterpret_cast<const int *>(p) + k);
+    EnvDev e;
+    __builtin_memcpy(&e, w, sizeof e);
+    return e;
+}
+
 __device__ __forceinline__ int env_of_particle(const Dev &d, int q)
 {
     int lo = 0, hi = d.n_envs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (d.env_pofs[mid] <= q) lo = mid; else hi = mid - 1;
+        if (gload(d.env_pofs + mid) <= q) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -156,66 +241,95 @@ __device__ __forceinline__ double det3d(const float F[9])
            (double)F[2] * ((double)F[3] * F[7] - (double)F[4] * F[6]);
 }
 
-// Grid operation of one node with mass (Sec. III-B item 2, Sec. III-C):
-// normalise + gravity, z-buffer over the environment's tools (nearest
-// capsule, ties to the lowest slot), contact projection, boundary band.
-// Writes the contact record used by the adjoint when rec != nullptr.
-struct ContactRec {
-    int tool;     // -1: no contact
-    int branch;   // 0 unchanged, 1 friction, 2 tool velocity
-};
-
+// Grid operation of one node (Sec. III-B item 2, Sec. III-C): normalise +
+// gravity, z-buffer over the environment's tools (nearest capsule, ties to
+// the lowest slot), contact projection, then the boundary band has the last
+// word.  The forward and the adjoint take the same FP32 decisions through
+// the helpers below.
 __device__ __forceinline__ float3 tool_velocity(const ToolDev &t)
 {
     int k = t.k < t.n_traj ? t.k : t.n_traj - 1;
     return make_float3(t.u[3 * k], t.u[3 * k + 1], t.u[3 * k + 2]);
 }
 
-// Capsule distance in the tool frame and world-frame unit normal.
-__device__ __forceinline__ float capsule_phi(const ToolDev &t, float px, float py, float pz, float3 &nrm)
+// Capsule distance in the tool frame: q = x_ref - clamp(x_ref.x) e_x,
+// phi = |q| - r; the contact normal is R q/|q| (R e_y on the axis).
+struct CapsuleHit {
+    float phi;
+    float3 n;          // world unit normal
+    float l[3];        // tool-frame unit normal
+    float len;         // |q|
+    bool interior;     // closest segment point strictly inside the segment
+};
+
+__device__ __forceinline__ CapsuleHit capsule_hit(const ToolDev &t, float px, float py, float pz)
 {
+    CapsuleHit h;
     float dx0 = (float)(px - t.T[0]), dx1 = (float)(py - t.T[1]), dx2 = (float)(pz - t.T[2]);
     // x_ref = R^T (x - T)
     float r0 = t.R[0] * dx0 + t.R[3] * dx1 + t.R[6] * dx2;
     float r1 = t.R[1] * dx0 + t.R[4] * dx1 + t.R[7] * dx2;
     float r2 = t.R[2] * dx0 + t.R[5] * dx1 + t.R[8] * dx2;
     float c = fminf(fmaxf(r0, -t.half_len), t.half_len);
+    h.interior = r0 >= -t.half_len && r0 <= t.half_len;
     float q0 = r0 - c;
-    float len = sqrtf(q0 * q0 + r1 * r1 + r2 * r2);
-    float l0, l1, l2;
-    if (len < 1e-12f) { l0 = 0.f; l1 = 1.f; l2 = 0.f; }
-    else { float il = 1.0f / len; l0 = q0 * il; l1 = r1 * il; l2 = r2 * il; }
-    nrm.x = t.R[0] * l0 + t.R[1] * l1 + t.R[2] * l2;
-    nrm.y = t.R[3] * l0 + t.R[4] * l1 + t.R[5] * l2;
-    nrm.z = t.R[6] * l0 + t.R[7] * l1 + t.R[8] * l2;
-    return len - t.radius;
+    h.len = sqrtf(q0 * q0 + r1 * r1 + r2 * r2);
+    if (h.len < 1e-12f) { h.l[0] = 0.f; h.l[1] = 1.f; h.l[2] = 0.f; }
+    else { float il = 1.0f / h.len; h.l[0] = q0 * il; h.l[1] = r1 * il; h.l[2] = r2 * il; }
+    h.n.x = t.R[0] * h.l[0] + t.R[1] * h.l[1] + t.R[2] * h.l[2];
+    h.n.y = t.R[3] * h.l[0] + t.R[4] * h.l[1] + t.R[5] * h.l[2];
+    h.n.z = t.R[6] * h.l[0] + t.R[7] * h.l[1] + t.R[8] * h.l[2];
+    h.phi = h.len - t.radius;
+    return h;
+}
+
+// Which tool (if any) a node touches: nearest active capsule with phi < theta.
+__device__ __forceinline__ int select_tool(const ToolDev *tl, int max_tools, float px, float py, float pz,
+                                           CapsuleHit &hit)
+{
+    float best = INFINITY;
+    int bt = -1;
+    for (int t = 0; t < max_tools; ++t) {
+        if (!tl[t].active) continue;
+        CapsuleHit h = capsule_hit(tl[t], px, py, pz);
+        if (h.phi < best) { best = h.phi; bt = t; hit = h; }
+    }
+    if (bt >= 0 && !(best < tl[bt].theta)) bt = -1;
+    return bt;
+}
+
+__device__ __forceinline__ bool boundary_node(const EnvDev &e, int i, int j, int k)
+{
+    return i < e.bound || j < e.bound || k < e.bound || i >= e.n - e.bound || j >= e.n - e.bound ||
+           k >= e.n - e.bound;
+}
+
+// Contact branch: 0 unchanged, 1 Coulomb friction (v_rel' = s v_t, s > 0),
+// 2 node takes the tool velocity.
+struct ContactRec {
+    int tool;     // -1: no contact
+    int branch;
+};
+
+// Node velocity after normalisation and gravity (zero for an empty node).
+__device__ __forceinline__ float3 node_vhat(const Dev &d, float4 P)
+{
+    if (!(P.x > 0.0f)) return make_float3(0.f, 0.f, 0.f);
+    return make_float3(P.y / P.x + d.dt * d.gx, P.z / P.x + d.dt * d.gy, P.w / P.x + d.dt * d.gz);
 }
 
 __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev &e, int env, float4 P, int i,
                                                      int j, int k, ContactRec *rec)
 {
-    float3 v = make_float3(0.f, 0.f, 0.f);
     if (rec) { rec->tool = -1; rec->branch = 0; }
-    if (!(P.x > 0.0f)) return v;
-    v.x = P.y / P.x + d.dt * d.gx;
-    v.y = P.z / P.x + d.dt * d.gy;
-    v.z = P.w / P.x + d.dt * d.gz;
-    bool wall = i < e.bound || j < e.bound || k < e.bound || i >= e.n - e.bound || j >= e.n - e.bound ||
-                k >= e.n - e.bound;
-    if (wall) return make_float3(0.f, 0.f, 0.f);
+    if (!(P.x > 0.0f)) return make_float3(0.f, 0.f, 0.f);
+    float3 v = node_vhat(d, P);
+    if (boundary_node(e, i, j, k)) return make_float3(0.f, 0.f, 0.f);
     if (d.max_tools > 0) {
-        float px = i * e.dx, py = j * e.dx, pz = k * e.dx;
         const ToolDev *tl = d.tools + (size_t)env * d.max_tools;
-        float best = INFINITY;
-        int bt = -1;
-        float3 bn = make_float3(0.f, 1.f, 0.f);
-        for (int t = 0; t < d.max_tools; ++t) {
-            if (!tl[t].active) continue;
-            float3 nrm;
-            float phi = capsule_phi(tl[t], px, py, pz, nrm);
-            if (phi < best) { best = phi; bt = t; bn = nrm; }
-        }
-        if (bt >= 0 && best < tl[bt].theta) {
+        CapsuleHit h;
+        int bt = select_tool(tl, d.max_tools, i * e.dx, j * e.dx, k * e.dx, h);
+        if (bt >= 0) {
             const ToolDev &T = tl[bt];
             float3 u = tool_velocity(T);
             if (rec) rec->tool = bt;
@@ -224,9 +338,9 @@ __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev 
                 if (rec) rec->branch = 2;
             } else {
                 float r0 = v.x - u.x, r1 = v.y - u.y, r2 = v.z - u.z;
-                float vn = r0 * bn.x + r1 * bn.y + r2 * bn.z;
+                float vn = r0 * h.n.x + r1 * h.n.y + r2 * h.n.z;
                 if (vn < 0.0f) {
-                    float t0 = r0 - vn * bn.x, t1 = r1 - vn * bn.y, t2 = r2 - vn * bn.z;
+                    float t0 = r0 - vn * h.n.x, t1 = r1 - vn * h.n.y, t2 = r2 - vn * h.n.z;
                     float nt = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
                     float s = 0.0f;
                     if (nt > 0.0f) s = fmaxf(0.0f, 1.0f + T.friction * vn / nt);
@@ -243,7 +357,7 @@ __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev 
 
 __device__ __forceinline__ void set_flag(uint32_t *status, int env, uint32_t f)
 {
-    atomicOr(status + env, f);
+    __hip_atomic_fetch_or(gptr(status + env), f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace mpm

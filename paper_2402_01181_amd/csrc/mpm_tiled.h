@@ -21,12 +21,15 @@ struct ParticleBuf {
     int32_t *pid;
 };
 
-// Active node bricks: flag per brick, compact list and its length.
+// Active node bricks: flag per brick and two compact lists used alternately
+// (substep parity): P2G appends to list p, the grid operation of that
+// substep consumes list p and clears the count of list p^1, which the next
+// P2G fills.  A call's G2P-only tail clears both counts.
 struct ActiveBuf {
     int32_t *flag;     // [total_bricks]
-    int32_t *list;     // [total_bricks]
-    int32_t *count;    // [1]
-    int32_t *done;     // [1] finished-block counter of the grid kernel
+    int32_t *list;     // [2][total_bricks]
+    int32_t *count;    // [2]
+    int32_t stride;    // total_bricks
     const int32_t *env_bofs;  // [n_envs + 1]
 };
 
@@ -43,6 +46,7 @@ struct TiledArgs {
     const int4 *items;
     const int2 *totals;                   // .y = number of items
     ActiveBuf act;
+    int par;                              // active list this kernel's P2G appends to
 };
 
 void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
@@ -52,7 +56,7 @@ size_t sort_chunk_count(int total_bricks);
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
-void launch_grid_active(const Dev &d, const ActiveBuf &a, int nblocks, hipStream_t st);
+void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
 int tiled_workgroups(int block);

@@ -58,23 +58,38 @@ class Sim:
         size = self.lib.mpm_workspace_size(ct.byref(self.desc))
         if size == 0:
             raise L.MpmError(L.MPM_E_ARG, self.lib.mpm_last_error(None).decode())
+        self.workspace_bytes = size
         self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        self.max_tape = int(max_tape)
+        self.options = dict(options or {})
+        self.traj = {}
+        self.ctx = ct.c_void_p()
+        self._create(stream)
+
+    def _create(self, stream=None):
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
-        self.ctx = ct.c_void_p()
-        L.check(self.lib.mpm_create(ct.byref(self.desc), ct.c_void_p(aligned), size, _stream_ptr(stream),
-                                    ct.byref(self.ctx)))
-        self.traj = {}
-        for e, env in enumerate(envs):
+        L.check(self.lib.mpm_create(ct.byref(self.desc), ct.c_void_p(aligned), self.workspace_bytes,
+                                    _stream_ptr(stream), ct.byref(self.ctx)))
+        for e, env in enumerate(self.scene.envs):
             for k, tool in enumerate(env.tools):
-                self.set_tool(e, k, tool)
-        for opt, val in (options or {}).items():
+                self.set_tool(e, k, tool, traj=self.traj.get((e, k)))
+        for opt, val in self.options.items():
             self.set_option(opt, val)
+
+    def reset(self, stream=None):
+        """Back to the initial state (same workspace, tools at T0, current
+        material table and trajectories)."""
+        self.close()
+        self._create(stream)
 
     # ------------------------------------------------------------------ control
     def set_tool(self, env, slot, tool, traj=None):
-        u = torch.from_numpy(np.ascontiguousarray(np.asarray(tool.traj if traj is None else traj,
-                                                             np.float32))).to(self.device)
+        if isinstance(traj, torch.Tensor):
+            u = traj.detach().to(self.device, torch.float32).contiguous()
+        else:
+            u = torch.from_numpy(np.ascontiguousarray(np.asarray(tool.traj if traj is None else traj,
+                                                                 np.float32))).to(self.device)
         self.traj[(env, slot)] = u
         td = L.MpmTool(shape=L.TOOL_CAPSULE, contact=int(tool.contact), radius=tool.radius,
                        half_len=tool.half_len, friction=tool.friction, theta=tool.theta,
@@ -85,12 +100,65 @@ class Sim:
 
     def set_option(self, option, value):
         L.check(self.lib.mpm_set_option(self.ctx, int(option), int(value)), self.ctx)
+        self.options[int(option)] = int(value)
 
     def step(self, n=1, record_tape=False, stream=None):
         L.check(self.lib.mpm_substep(self.ctx, int(n), 1 if record_tape else 0, _stream_ptr(stream)), self.ctx)
 
     def stage(self, stage, stream=None):
         L.check(self.lib.mpm_run_stage(self.ctx, int(stage), _stream_ptr(stream)), self.ctx)
+
+    def adjoint(self, n, xbar=None, vbar=None, Cbar=None, Fbar=None, stream=None):
+        """Reverse the last n recorded substeps.  Seeds are adjoints of the
+        current state as [comps][Ntot] tensors in the original particle order
+        (environments concatenated); None means zero.  Returns a dict of
+        device tensors: xbar0, vbar0, Cbar0, Fbar0 ([comps][Ntot]), gE, gnu
+        ([n_envs], float64), gu ([n_envs][max_tools][n][3]), gT
+        ([n_envs][max_tools][3])."""
+        N, dev = int(self.pofs[-1]), self.device
+        def seed(a, comps):
+            if a is None:
+                return None
+            t = torch.as_tensor(a, dtype=torch.float32, device=dev).reshape(comps, N).contiguous()
+            return t
+        seeds = [seed(xbar, 3), seed(vbar, 3), seed(Cbar, 9), seed(Fbar, 9)]
+        outs = [torch.empty((c, N), dtype=torch.float32, device=dev) for c in (3, 3, 9, 9)]
+        nt = max(1, self.max_tools)
+        gE = torch.empty(self.n_envs, dtype=torch.float64, device=dev)
+        gnu = torch.empty(self.n_envs, dtype=torch.float64, device=dev)
+        gu = torch.zeros((self.n_envs, nt, n, 3), dtype=torch.float64, device=dev)
+        gT = torch.zeros((self.n_envs, nt, 3), dtype=torch.float64, device=dev)
+        p = lambda t: t.data_ptr() if t is not None else None
+        io = L.MpmAdjointIO(xbar=p(seeds[0]), vbar=p(seeds[1]), Cbar=p(seeds[2]), Fbar=p(seeds[3]),
+                            xbar0=p(outs[0]), vbar0=p(outs[1]), Cbar0=p(outs[2]), Fbar0=p(outs[3]),
+                            gE=p(gE), gnu=p(gnu), gu=p(gu) if self.max_tools else None,
+                            gT=p(gT) if self.max_tools else None)
+        L.check(self.lib.mpm_substep_adjoint(self.ctx, int(n), ct.byref(io), _stream_ptr(stream)), self.ctx)
+        return dict(xbar0=outs[0], vbar0=outs[1], Cbar0=outs[2], Fbar0=outs[3], gE=gE, gnu=gnu,
+                    gu=gu[:, :self.max_tools], gT=gT[:, :self.max_tools])
+
+    def positions(self):
+        """All particle positions, (Ntot, 3) device tensor, original order."""
+        return torch.cat([self.read(L.F_X, e).T for e in range(self.n_envs)], 0)
+
+    def velocities(self):
+        return torch.cat([self.read(L.F_V, e).T for e in range(self.n_envs)], 0)
+
+    def profile(self, enable=True):
+        L.check(self.lib.mpm_profile(self.ctx, 1 if enable else 0), self.ctx)
+
+    def profile_report(self):
+        """{kernel name: (total ms, launches)} of the built-in event timer."""
+        out, k = {}, 0
+        while True:
+            name, ms, n = ct.c_char_p(), ct.c_double(), ct.c_int64()
+            rc = self.lib.mpm_profile_read(self.ctx, k, ct.byref(name), ct.byref(ms), ct.byref(n))
+            if rc != L.MPM_OK:
+                break
+            if n.value:
+                out[name.value.decode()] = (ms.value, n.value)
+            k += 1
+        return out
 
     # ------------------------------------------------------------------ reads
     _PCOMPS = {L.F_X: 3, L.F_V: 3, L.F_C: 9, L.F_F: 9}

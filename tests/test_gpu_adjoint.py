@@ -1,0 +1,174 @@
+"""The GPU adjoint (mpm_substep_adjoint through the C ABI and the autograd
+Function) against the FP64 oracle's adjoint and FP64 central finite
+differences of the oracle.  Gradients are held to 1e-3 relative."""
+import numpy as np
+import pytest
+
+from paper_2402_01181_amd import scenes
+from parity import oracle_sim_like
+
+pytestmark = pytest.mark.gpu
+TOL_GRAD = 1e-3
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU")
+    from paper_2402_01181_amd import _lib
+    from paper_2402_01181_amd.sim import Sim
+    return Sim, _lib, torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def _pressing_scene(seed, N, n, S, contact=scenes.CONTACT_SLIP):
+    sc = scenes.small_slab_scene(seed, N, n=n, substeps=S, contact=contact, u=(0.05, -0.4, 0.02), dt=1e-4)
+    env = sc.envs[0]
+    rng = np.random.default_rng(seed + 1)
+    scenes.perturbed_state(rng, env, v_scale=0.05, C_scale=1.0, F_scale=0.01)
+    env.tools[0].traj = (np.array([0.05, -0.4, 0.02]) + 0.05 * rng.standard_normal((S, 3))).astype(np.float32)
+    env.tools[0].T0 = (env.tools[0].T0 - np.array([0, 0.015, 0])).astype(np.float32)
+    return sc, env
+
+
+@pytest.mark.parametrize("scheme,contact", [("tiled", scenes.CONTACT_SLIP), ("direct", scenes.CONTACT_SLIP),
+                                            ("tiled", scenes.CONTACT_STICKY)])
+def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact):
+    Sim, L, torch = gpu
+    S, N, n, k = 12, 2000, 32, 5
+    _say(f"adjoint vs oracle adjoint: {N} particles, {n}^3, {S} substeps, checkpoints every {k}, {scheme}, contact={contact}")
+    sc, env = _pressing_scene(51 + contact, N, n, S, contact)
+    rng = np.random.default_rng(3)
+    W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
+         rng.standard_normal((N, 3, 3))]
+    sim = Sim(sc, max_tape=S, checkpoint_every=k,
+              options={L.OPT_SCHEME: L.SCHEME_TILED if scheme == "tiled" else L.SCHEME_DIRECT, L.OPT_SORT_EVERY: 3})
+    sim.step(S, record_tape=True)
+    soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
+    g = sim.adjoint(S, soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))
+    o = oracle_sim_like(orc, sc).adjoint(S, *W)
+    assert np.abs(o["gu"]).max() > 0
+    checks = {
+        "xbar0": (g["xbar0"].cpu().numpy().T, o["xbar"].reshape(N, 3)),
+        "vbar0": (g["vbar0"].cpu().numpy().T, o["vbar"].reshape(N, 3)),
+        "Cbar0": (g["Cbar0"].cpu().numpy().T, o["Cbar"].reshape(N, 9)),
+        "Fbar0": (g["Fbar0"].cpu().numpy().T, o["Fbar"].reshape(N, 9)),
+        "gE": (g["gE"].cpu().numpy(), [o["gE"]]),
+        "gnu": (g["gnu"].cpu().numpy(), [o["gnu"]]),
+        "gu": (g["gu"].cpu().numpy()[0, 0], o["gu"][:, 0]),
+        "gT": (g["gT"].cpu().numpy()[0, 0], o["gT0"][0]),
+    }
+    for name, (a, b) in checks.items():
+        e = _rel(a, b)
+        _say(f"  {name}: rel err {e:.2e}")
+        assert e <= TOL_GRAD, (name, e)
+
+
+def test_adjoint_window_shorter_than_tape(gpu, orc):
+    """Reverse only the last 7 of 12 recorded substeps."""
+    Sim, L, torch = gpu
+    S, N, n, k, w = 12, 1500, 32, 4, 7
+    _say(f"adjoint window {w} of {S} substeps")
+    sc, env = _pressing_scene(61, N, n, S)
+    rng = np.random.default_rng(4)
+    Wx = rng.standard_normal((N, 3))
+    sim = Sim(sc, max_tape=S, checkpoint_every=k)
+    sim.step(S, record_tape=True)
+    g = sim.adjoint(w, torch.tensor(Wx.T.copy(), dtype=torch.float32))
+    o = oracle_sim_like(orc, sc)
+    o.run(S - w)
+    # the oracle adjoint restarts at substep S - w from its own FP64 state and tool pose
+    o.traj = np.ascontiguousarray(o.traj[:, S - w:])
+    o.n_traj = o.traj.shape[1]
+    ref = o.adjoint(w, Wx)
+    for name, a, b in (("xbar0", g["xbar0"].cpu().numpy().T, ref["xbar"]), ("gE", g["gE"].cpu().numpy(), [ref["gE"]]),
+                       ("gu", g["gu"].cpu().numpy()[0, 0], ref["gu"][:, 0])):
+        e = _rel(a, b)
+        _say(f"  {name}: rel err {e:.2e}")
+        assert e <= TOL_GRAD, (name, e)
+
+
+def test_autograd_diff_slab_full_size_vs_fd(gpu, orc):
+    """The differentiable workload at full size: 30K particles, 64^3, 200
+    substeps, checkpoints every 20; loss = |centroid - target|^2; gradients
+    with respect to E, nu and the 200 tool velocities against FP64 central
+    differences of the oracle."""
+    Sim, L, torch = gpu
+    from paper_2402_01181_amd.autograd import MPMRollout
+    sc = scenes.diff_scene()
+    env = sc.envs[0]
+    S = sc.substeps
+    target = torch.tensor(sc.extra["target"], dtype=torch.float64)
+    _say(f"autograd rollout: {env.N} particles, {S} substeps, checkpoints every {sc.extra['checkpoint_every']}")
+    sim = Sim(sc, max_tape=S, checkpoint_every=sc.extra["checkpoint_every"])
+    E = torch.tensor([env.E], dtype=torch.float64, requires_grad=True)
+    nu = torch.tensor([env.nu], dtype=torch.float64, requires_grad=True)
+    u = torch.tensor(env.tools[0].traj[None, None], dtype=torch.float64, requires_grad=True)
+    x, v = MPMRollout.apply(E, nu, u, sim, S)
+    loss = ((x.double().mean(0).cpu() - target) ** 2).sum()
+    loss.backward()
+    assert sim.read(L.F_STATUS) == 0
+
+    def oracle_loss(E_=None, nu_=None, traj=None):
+        o = oracle_sim_like(orc, sc)
+        if E_ is not None:
+            o.P.E = E_
+        if nu_ is not None:
+            o.P.nu = nu_
+        if traj is not None:
+            o.traj[0] = traj
+        o.run(S)
+        c = o.state.x.mean(0)
+        return float(((c - sc.extra["target"]) ** 2).sum())
+
+    L0 = oracle_loss()
+    _say(f"  loss gpu {loss.item():.6e} oracle {L0:.6e}")
+    assert abs(loss.item() - L0) <= 1e-3 * L0
+    hE, hnu = 1e-3 * env.E, 1e-6
+    fdE = (oracle_loss(E_=env.E + hE) - oracle_loss(E_=env.E - hE)) / (2 * hE)
+    fdnu = (oracle_loss(nu_=env.nu + hnu) - oracle_loss(nu_=env.nu - hnu)) / (2 * hnu)
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((S, 3))
+    hu = 1e-4
+    traj0 = env.tools[0].traj.astype(np.float64)
+    fdu = (oracle_loss(traj=traj0 + hu * d) - oracle_loss(traj=traj0 - hu * d)) / (2 * hu)
+    gu_dir = float((u.grad[0, 0].numpy() * d).sum())
+    for name, a, b in (("dL/dE", E.grad.item(), fdE), ("dL/dnu", nu.grad.item(), fdnu), ("dL/du . d", gu_dir, fdu)):
+        e = abs(a - b) / max(abs(b), 1e-30)
+        _say(f"  {name}: adjoint {a:.6e} fd {b:.6e} rel {e:.2e}")
+        assert e <= TOL_GRAD, (name, a, b)
+
+
+def test_adjoint_state_errors(gpu, orc):
+    Sim, L, torch = gpu
+    sc = scenes.small_slab_scene(5, 300, n=16, substeps=4)
+    sim = Sim(sc, max_tape=4, checkpoint_every=2)
+    with pytest.raises(L.MpmError) as ei:
+        sim.adjoint(2)
+    assert ei.value.code == L.MPM_E_STATE
+    with pytest.raises(L.MpmError) as ei:
+        sim.step(5, record_tape=True)
+    assert ei.value.code == L.MPM_E_ARG
+    sim.step(3, record_tape=True)
+    with pytest.raises(L.MpmError) as ei:
+        sim.adjoint(4)
+    assert ei.value.code == L.MPM_E_STATE
+    sim.adjoint(3)
+    sim.step(1)                        # stepping on invalidates the tape
+    with pytest.raises(L.MpmError) as ei:
+        sim.adjoint(1)
+    assert ei.value.code == L.MPM_E_STATE
+    nt = Sim(sc)                       # no tape capacity
+    with pytest.raises(L.MpmError) as ei:
+        nt.step(1, record_tape=True)
+    assert ei.value.code == L.MPM_E_STATE
