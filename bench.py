@@ -93,6 +93,9 @@ def main():
                     help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick block/item/sort/graph options by timing first")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,10 +109,21 @@ def main():
 
     scene, workload = make_scene(args.config)
     opts = {L.OPT_SCHEME: L.SCHEME_TILED if args.scheme == "tiled" else L.SCHEME_DIRECT}
+    if args.autotune and args.scheme == "tiled":
+        from paper_2402_01181_amd.autotune import autotune
+        opts.update(autotune(scene, verbose=True))
+        print(f"# autotuned options: {opts}", file=sys.stderr, flush=True)
     if args.sort_every: opts[L.OPT_SORT_EVERY] = args.sort_every
     if args.block: opts[L.OPT_BLOCK] = args.block
     if args.item: opts[L.OPT_ITEM] = args.item
     if args.graph is not None: opts[L.OPT_GRAPH] = args.graph
+    if args.calib_copy_mib:
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     sim = Sim(scene, options=opts)
     N = scene.n_particles
     K, W = args.steps, args.warmup
@@ -134,7 +148,8 @@ def main():
     nodes = sum(active_nodes(x, int(sim.gn[e])) for e, x in enumerate(x_final))
 
     roofline, kernels = None, {}
-    if not args.no_profile_pass and not (args.graph or 0):
+    if not args.no_profile_pass:
+        sim.set_option(L.OPT_GRAPH, 0)   # the event timer brackets eager launches
         sim.profile(True)
         sim.step(K)
         torch.cuda.synchronize()
@@ -178,7 +193,8 @@ def main():
         "data": "synthetic (seeded particles in a box, analytic capsule tool)",
         "config": {"workload": workload, "config": args.config, "particles": N,
                    "grid": [int(g) for g in sim.gn[:4]], "envs": sim.n_envs, "substeps_timed": K,
-                   "scheme": args.scheme, "active_nodes": nodes,
+                   "scheme": args.scheme, "options": {str(k): v for k, v in sim.options.items()},
+                   "active_nodes": nodes,
                    "algorithmic_bytes_per_substep": N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP},
         "roofline": roofline,
         "cpu_baseline": cpu,

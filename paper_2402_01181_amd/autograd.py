@@ -30,7 +30,7 @@ class MPMRollout(torch.autograd.Function):
             x = sim.positions()
             v = sim.velocities()
         ctx.sim, ctx.n = sim, n
-        ctx.dtypes = (E.dtype, nu.dtype, u.dtype)
+        ctx.like = tuple((t.device, t.dtype) for t in (E, nu, u))
         return x, v
 
     @staticmethod
@@ -39,5 +39,5 @@ class MPMRollout(torch.autograd.Function):
         xbar = None if gx is None else gx.detach().to(torch.float32).T.contiguous()
         vbar = None if gv is None else gv.detach().to(torch.float32).T.contiguous()
         g = sim.adjoint(n, xbar=xbar, vbar=vbar)
-        dE, dnu, du = ctx.dtypes
-        return g["gE"].to(dE), g["gnu"].to(dnu), g["gu"].to(du), None, None
+        (dE, tE), (dnu, tnu), (du, tu) = ctx.like
+        return g["gE"].to(dE, tE), g["gnu"].to(dnu, tnu), g["gu"].to(du, tu), None, None

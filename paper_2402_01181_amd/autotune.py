@@ -1,0 +1,93 @@
+"""Autotuner for the tiled scheme's launch shapes.
+
+Searches, in stages, the workgroup size (MPM_OPT_BLOCK), the particles per
+work item (MPM_OPT_ITEM), the sort interval (MPM_OPT_SORT_EVERY) and graph
+replay (MPM_OPT_GRAPH) for a scene, timing short runs with HIP events on the
+stream the library launches on.  Every setting gives the same results up to
+float accumulation order, so the tuner only compares time.  Results are cached
+in a JSON file keyed by device, HIP version and workload shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Optional
+
+import torch
+
+from . import _lib as L
+from .sim import Sim
+
+CACHE = os.environ.get("MPM355_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "mpm355",
+                                                         "autotune.json"))
+
+
+def workload_key(scene) -> str:
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    N = scene.n_particles
+    bucket = 1 << max(0, int(N - 1).bit_length())
+    grids = sorted({e.n for e in scene.envs})
+    return f"{dev}|hip {torch.version.hip}|envs {len(scene.envs)}|N<= {bucket}|grids {grids}"
+
+
+def _time(sim: Sim, substeps: int, warmup: int) -> float:
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    sim.step(substeps)
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / substeps
+
+
+def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = CACHE,
+             blocks=(64, 128, 256), items=(128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
+             graph=(0, 1), verbose: bool = False) -> Dict[int, int]:
+    """Best options {MPM_OPT_*: value} for this scene (tiled scheme)."""
+    key = workload_key(scene)
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        return {int(k): int(v) for k, v in table[key]["options"].items()}
+
+    sim = Sim(scene, options={L.OPT_SCHEME: L.SCHEME_TILED})
+    best = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: 256, L.OPT_ITEM: 512, L.OPT_SORT_EVERY: 16,
+            L.OPT_GRAPH: 0}
+    log: List[dict] = []
+
+    def trial(opts):
+        for k, v in opts.items():
+            sim.set_option(k, v)
+        ms = _time(sim, substeps, warmup)
+        log.append({"options": {str(k): v for k, v in opts.items()}, "ms_per_substep": ms})
+        if verbose:
+            print(f"  autotune {opts} -> {ms * 1e3:.1f} us/substep", flush=True)
+        return ms
+
+    def stage(candidates):
+        nonlocal best
+        scores = []
+        for cand in candidates:
+            opts = dict(best)
+            opts.update(cand)
+            scores.append((trial(opts), opts))
+        best = min(scores, key=lambda t: t[0])[1]
+
+    stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i} for b in blocks for i in items if i >= b])
+    stage([{L.OPT_SORT_EVERY: k} for k in sort_every])
+    stage([{L.OPT_GRAPH: g} for g in graph])
+    sim.close()
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        table[key] = {"options": {str(k): v for k, v in best.items()}, "trials": log}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1)
+        os.replace(tmp, cache)
+    return best

@@ -47,7 +47,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.x = cv.take<float>((size_t)3 * s.ntot);
     c.v = cv.take<float>((size_t)3 * s.ntot);
     c.C = cv.take<float>((size_t)9 * s.ntot);
-    c.F = cv.take<float>((size_t)9 * s.ntot);
+    c.H = cv.take<float>((size_t)9 * s.ntot);
     c.pid = cv.take<int32_t>(s.ntot);
     c.gP = cv.take<float4>(s.total_nodes);
     c.gV = cv.take<float4>(s.total_nodes);
@@ -55,7 +55,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.alt.x = cv.take<float>((size_t)3 * s.ntot);
     c.alt.v = cv.take<float>((size_t)3 * s.ntot);
     c.alt.C = cv.take<float>((size_t)9 * s.ntot);
-    c.alt.F = cv.take<float>((size_t)9 * s.ntot);
+    c.alt.H = cv.take<float>((size_t)9 * s.ntot);
     c.alt.pid = cv.take<int32_t>(s.ntot);
     c.sort.count = cv.take<int2>(s.total_bricks);
     c.sort.offset = cv.take<int2>(s.total_bricks);
@@ -109,8 +109,8 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
 // Every device buffer the kernels use must have been carved.
 bool all_carved(const mpm_ctx &c)
 {
-    const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.F, c.pid,
-                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.F, c.alt.pid, c.sort.count, c.sort.offset,
+    const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
+                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
                        c.act.list, c.act.count, c.env_bofs, c.act.env_bofs};
     for (const void *q : p)
@@ -237,13 +237,13 @@ void substep_direct(mpm_ctx *c, hipStream_t st)
     c->grid_clean = false;
 }
 
-ParticleBuf live(const mpm_ctx *c) { return ParticleBuf{c->x, c->v, c->C, c->F, c->pid}; }
+ParticleBuf live(const mpm_ctx *c) { return ParticleBuf{c->x, c->v, c->C, c->H, c->pid}; }
 
 TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf &out, int par)
 {
     TiledArgs a{};
-    a.xin = in.x; a.vin = in.v; a.Cin = in.C; a.Fin = in.F; a.pidin = in.pid;
-    a.xout = out.x; a.vout = out.v; a.Cout = out.C; a.Fout = out.F; a.pidout = out.pid;
+    a.xin = in.x; a.vin = in.v; a.Cin = in.C; a.Hin = in.H; a.pidin = in.pid;
+    a.xout = out.x; a.vout = out.v; a.Cout = out.C; a.Hout = out.H; a.pidout = out.pid;
     a.items = c->sort.items;
     a.totals = c->sort.totals;
     a.act = c->act;
@@ -359,7 +359,7 @@ Dev state_view(const mpm_ctx *c, float *blk)
     d.x = blk;
     d.v = blk + 3 * N;
     d.C = blk + 6 * N;
-    d.F = blk + 15 * N;
+    d.H = blk + 15 * N;
     d.pid = nullptr;
     return d;
 }
@@ -374,7 +374,7 @@ void save_checkpoint(mpm_ctx *c, int k, hipStream_t st)
         launch_unpermute(c->x, c->pid, c->ntot, 3, dst, st);
         launch_unpermute(c->v, c->pid, c->ntot, 3, dst + 3 * N, st);
         launch_unpermute(c->C, c->pid, c->ntot, 9, dst + 6 * N, st);
-        launch_unpermute(c->F, c->pid, c->ntot, 9, dst + 15 * N, st);
+        launch_unpermute(c->H, c->pid, c->ntot, 9, dst + 15 * N, st);
         launch_copy_bytes(T.ckpt_tools + (size_t)k * c->tool_slots(), c->tools, sizeof(ToolDev) * c->tool_slots(), st);
         launch_copy_bytes(T.ckpt_step + (size_t)k * c->n_envs, c->step, sizeof(int32_t) * c->n_envs, st);
     });
@@ -547,8 +547,9 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         if ((e2 = hipMemcpyAsync(c->x, desc->x0, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e2 = hipMemcpyAsync(c->v, desc->v0, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e2 = hipMemcpyAsync(c->C, desc->C0, 9 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
-            (e2 = hipMemcpyAsync(c->F, desc->F0, 9 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            (e2 = hipMemcpyAsync(c->H, desc->F0, 9 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return cleanup_fail(e2, "copy initial state");
+        launch_add_identity(c->H, s.ntot, s.ntot, -1.0f, st);    // stored as H = F - I
         launch_iota(c->pid, s.ntot, st);
         launch_fill_u32(c->status, s.n_envs, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->step), s.n_envs, 0u, st);
@@ -756,7 +757,7 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
     case MPM_F_X: comps = 3; src = c->x; break;
     case MPM_F_V: comps = 3; src = c->v; break;
     case MPM_F_C: comps = 9; src = c->C; break;
-    case MPM_F_F: comps = 9; src = c->F; break;
+    case MPM_F_F: comps = 9; src = c->H; break;   // returned as F = I + H
     case MPM_F_GRID_M: comps = 1; break;
     case MPM_F_GRID_MV: comps = 3; break;
     case MPM_F_GRID_V: comps = 3; break;
@@ -774,6 +775,7 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
     if (field <= MPM_F_F) {
         if (dst_on_device) {
             launch_read_particles(src, c->pid, c->ntot, c->pofs[env], np, comps, static_cast<float *>(dst), st);
+            if (field == MPM_F_F) launch_add_identity(static_cast<float *>(dst), np, np, 1.0f, st);
             return check_launch(c, "read particles");
         }
         std::vector<float> raw((size_t)comps * np);
@@ -788,6 +790,12 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
             int o = pid[i] - c->pofs[env];
             for (int k = 0; k < comps; ++k) out[(size_t)k * np + o] = raw[(size_t)k * np + i];
         }
+        if (field == MPM_F_F)
+            for (int i = 0; i < np; ++i) {
+                out[i] += 1.0f;
+                out[(size_t)4 * np + i] += 1.0f;
+                out[(size_t)8 * np + i] += 1.0f;
+            }
         return MPM_OK;
     }
     if (field <= MPM_F_GRID_V) {

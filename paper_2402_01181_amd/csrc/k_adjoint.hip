@@ -84,11 +84,11 @@ __global__ __launch_bounds__(256) void k_adj_g2p(Dev d, AdjBuf a)
                 B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
             }
     const float cs = 4.0f * e.inv_dx;
-    float Cn[9], F[9], Fb[9], Cb[9], xb[3], vb[3];
+    float Cn[9], H[9], Fb[9], Cb[9], xb[3], vb[3];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
         Cn[c] = cs * B[c];
-        F[c] = gload(d.F + (size_t)c * N + q);
+        H[c] = gload(d.H + (size_t)c * N + q);
         Fb[c] = gload(a.Fb + (size_t)c * N + q);
         Cb[c] = gload(a.Cb + (size_t)c * N + q);
     }
@@ -97,14 +97,15 @@ __global__ __launch_bounds__(256) void k_adj_g2p(Dev d, AdjBuf a)
         xb[c] = gload(a.xb + (size_t)c * N + q);
         vb[c] = gload(a.vb + (size_t)c * N + q);
     }
-    // F' = (I + dt C') F:  Fbar <- (I + dt C')^T Fbar',  Cbar' += dt Fbar' F^T
+    // F' = (I + dt C') F:  Fbar <- (I + dt C')^T Fbar',  Cbar' += dt Fbar' F^T  (F = I + H)
     float Fbn[9], Cbt[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * (Cn[r] * Fb[c] + Cn[3 + r] * Fb[3 + c] + Cn[6 + r] * Fb[6 + c]);
-            Cbt[3 * r + c] = Cb[3 * r + c] + d.dt * (Fb[3 * r] * F[3 * c] + Fb[3 * r + 1] * F[3 * c + 1] + Fb[3 * r + 2] * F[3 * c + 2]);
+            Cbt[3 * r + c] = Cb[3 * r + c] + d.dt * (Fb[3 * r + c] + Fb[3 * r] * H[3 * c] + Fb[3 * r + 1] * H[3 * c + 1] +
+                                                     Fb[3 * r + 2] * H[3 * c + 2]);
         }
     // x' = x + dt v'
     float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
@@ -275,15 +276,16 @@ __global__ __launch_bounds__(256) void k_adj_p2g(Dev d, AdjBuf a)
             lame(E, nu, mu, lam);
             const float m = rho * V0;
             const float kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
-            float F[9], C[9], v[3], tau[9], A[9];
+            float H[9], F[9], C[9], v[3], tau[9], A[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                F[c] = gload(d.F + (size_t)c * N + q);
+                H[c] = gload(d.H + (size_t)c * N + q);
+                F[c] = H[c] + ((c & 3) == 0 ? 1.0f : 0.0f);
                 C[c] = gload(d.C + (size_t)c * N + q);
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) v[c] = gload(d.v + (size_t)c * N + q);
-            bool inverted = kirchhoff(F, mu, lam, tau);
+            bool inverted = kirchhoff(H, mu, lam, tau);
 #pragma unroll
             for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
             float dw[3][3];
@@ -340,16 +342,17 @@ __global__ __launch_bounds__(256) void k_adj_p2g(Dev d, AdjBuf a)
                     Fb[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
                                           (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
             double trt = (double)taub[0] + taub[4] + taub[8];
-            double J = det3d(F);
-            double lnJ = log(inverted ? J_MIN : J);
+            double jm1 = jm1_of(H);
+            double lnJ = inverted ? log(J_MIN) : log1p(jm1);
             if (!inverted) {
-                // F^-T = cof(F) / J
-                double ci[9] = {(double)F[4] * F[8] - (double)F[5] * F[7], -((double)F[3] * F[8] - (double)F[5] * F[6]),
-                                (double)F[3] * F[7] - (double)F[4] * F[6], -((double)F[1] * F[8] - (double)F[2] * F[7]),
-                                (double)F[0] * F[8] - (double)F[2] * F[6], -((double)F[0] * F[7] - (double)F[1] * F[6]),
-                                (double)F[1] * F[5] - (double)F[2] * F[4], -((double)F[0] * F[5] - (double)F[2] * F[3]),
-                                (double)F[0] * F[4] - (double)F[1] * F[3]};
-                double sc = (double)lam * trt / J;
+                // F^-T = cof(F) / J, F = I + H exactly in FP64
+                double f[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) f[c] = (double)H[c] + ((c & 3) == 0 ? 1.0 : 0.0);
+                double ci[9] = {f[4] * f[8] - f[5] * f[7], -(f[3] * f[8] - f[5] * f[6]), f[3] * f[7] - f[4] * f[6],
+                                -(f[1] * f[8] - f[2] * f[7]), f[0] * f[8] - f[2] * f[6], -(f[0] * f[7] - f[1] * f[6]),
+                                f[1] * f[5] - f[2] * f[4], -(f[0] * f[5] - f[2] * f[3]), f[0] * f[4] - f[1] * f[3]};
+                double sc = (double)lam * trt / (1.0 + jm1);
 #pragma unroll
                 for (int c = 0; c < 9; ++c) Fb[c] += (float)(sc * ci[c]);
             }
@@ -358,14 +361,14 @@ __global__ __launch_bounds__(256) void k_adj_p2g(Dev d, AdjBuf a)
                 float* pf = a.Fb + (size_t)c * N + q;
                 gstore(pf, gload(pf) + Fb[c]);
             }
-            // dL/dmu = taubar : (F F^T - I),  dL/dlambda = tr(taubar) ln J
+            // dL/dmu = taubar : (F F^T - I) = taubar : (H + H^T + H H^T),  dL/dlambda = tr(taubar) ln J
             double ff = 0.0;
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    double G = (double)F[3 * r] * F[3 * c] + (double)F[3 * r + 1] * F[3 * c + 1] +
-                               (double)F[3 * r + 2] * F[3 * c + 2] - (r == c ? 1.0 : 0.0);
+                    double G = (double)H[3 * r + c] + H[3 * c + r] + (double)H[3 * r] * H[3 * c] +
+                               (double)H[3 * r + 1] * H[3 * c + 1] + (double)H[3 * r + 2] * H[3 * c + 2];
                     ff += (double)taub[3 * r + c] * G;
                 }
             mub = ff;

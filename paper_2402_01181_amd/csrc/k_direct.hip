@@ -26,10 +26,10 @@ __global__ __launch_bounds__(256) void k_p2g_direct(Dev d)
     float mu, lam;
     lame(mat[0], mat[1], mu, lam);
     const float V0 = mat[3], m = mat[2] * mat[3];
-    float F[9], tau[9], A[9];
+    float H[9], tau[9], A[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) F[c] = d.F[(size_t)c * N + q];
-    if (kirchhoff(F, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
+    for (int c = 0; c < 9; ++c) H[c] = gload(d.H + (size_t)c * N + q);
+    if (kirchhoff(H, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
     const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
 #pragma unroll
     for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * d.C[(size_t)c * N + q];
@@ -91,7 +91,7 @@ __device__ __forceinline__ void advance_tools(const Dev &d, int t)
     }
 }
 
-// G2P (Sec. III-B item 3) + advection + F update (I + dt C) F.
+// G2P (Sec. III-B item 3) + advection + F update (I + dt C) F (kept as H = F - I).
 __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
 {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,15 +130,11 @@ __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
 #pragma unroll
     for (int c = 0; c < 9; ++c) Cn[c] = cs * B[c];
     x0 += d.dt * vp0; x1 += d.dt * vp1; x2 += d.dt * vp2;
-    float F[9], Fn[9];
+    float H[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) F[c] = d.F[(size_t)c * N + q];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            Fn[3 * a + b] = F[3 * a + b] + d.dt * (Cn[3 * a + 0] * F[b] + Cn[3 * a + 1] * F[3 + b] + Cn[3 * a + 2] * F[6 + b]);
-    if (!(det3d(Fn) > J_MIN)) set_flag(d.status, env, MPM_FLAG_INVERTED);
+    for (int c = 0; c < 9; ++c) H[c] = gload(d.H + (size_t)c * N + q);
+    update_h(H, Cn, d.dt);
+    if (inverted_h(H)) set_flag(d.status, env, MPM_FLAG_INVERTED);
     if (!(isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(vp0) && isfinite(vp1) && isfinite(vp2)))
         set_flag(d.status, env, MPM_FLAG_NONFINITE);
     d.x[q] = x0; d.x[N + q] = x1; d.x[2 * N + q] = x2;
@@ -146,7 +142,7 @@ __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
         d.C[(size_t)c * N + q] = Cn[c];
-        d.F[(size_t)c * N + q] = Fn[c];
+        d.H[(size_t)c * N + q] = H[c];
     }
 }
 

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
 #pragma unroll
     for (int c = 0; c < 3; ++c) dst.x[(size_t)c * N + to] = d.x[(size_t)c * N + q];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dst.F[(size_t)c * N + to] = d.F[(size_t)c * N + q];
+    for (int c = 0; c < 9; ++c) dst.H[(size_t)c * N + to] = d.H[(size_t)c * N + q];
     dst.pid[to] = d.pid[q];
     if (full) {
 #pragma unroll

@@ -181,7 +181,7 @@ __device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &
 }
 
 // A = -dt V0 (4/dx^2) tau(F) + m C   (MLS force folded into the affine term)
-__device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e, int env, const float F[9],
+__device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e, int env, const float H[9],
                                                    const float C[9], float A[9], float &m)
 {
     const float *mat = d.material + 4 * env;
@@ -190,15 +190,15 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
     lame(E, nu, mu, lam);
     m = rho * V0;
     float tau[9];
-    if (kirchhoff(F, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
+    if (kirchhoff(H, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
     const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
 #pragma unroll
     for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * C[c];
 }
 
-// MODE 0: P2G only (head of a call; reads x, v, C, F).
-// MODE 1: fused G2P(s) + F update + advection + P2G(s+1) (reads/writes x, F).
-// MODE 2: G2P only (tail of a call; writes x, v, C, F).
+// MODE 0: P2G only (head of a call; reads x, v, C, H).
+// MODE 1: fused G2P(s) + F update + advection + P2G(s+1) (reads/writes x, H).
+// MODE 2: G2P only (tail of a call; writes x, v, C, H).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
 {
@@ -233,9 +233,9 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
 
         for (int p = item.y + tid; p < item.y + item.z; p += T) {
             float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
-            float F[9], v[3], C[9];
+            float H[9], v[3], C[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) F[c] = gload(a.Fin + (size_t)c * N + p);
+            for (int c = 0; c < 9; ++c) H[c] = gload(a.Hin + (size_t)c * N + p);
             Stencil s;
             make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s);
             bool frozen = stencil_outside(s, e.n);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                     }
 #pragma unroll
                     for (int c = 0; c < 9; ++c) {
-                        gstore(a.Fout + (size_t)c * N + p, F[c]);
+                        gstore(a.Hout + (size_t)c * N + p, H[c]);
                         gstore(a.Cout + (size_t)c * N + p, gload(a.Cin + (size_t)c * N + p));
                     }
                 }
@@ -266,15 +266,8 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                 x[0] += d.dt * v[0];
                 x[1] += d.dt * v[1];
                 x[2] += d.dt * v[2];
-                float Fn[9];
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        Fn[3 * r + c] = F[3 * r + c] + d.dt * (C[3 * r + 0] * F[c] + C[3 * r + 1] * F[3 + c] + C[3 * r + 2] * F[6 + c]);
-#pragma unroll
-                for (int c = 0; c < 9; ++c) F[c] = Fn[c];
-                if (!(det3d(F) > J_MIN)) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
+                update_h(H, C, d.dt);
+                if (inverted_h(H)) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
                 if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
                     set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
             } else {
@@ -293,7 +286,7 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
                     write_vc = true;
                 } else {
                     float A[9], m;
-                    affine_with_stress(d, e, t.env, F, C, A, m);
+                    affine_with_stress(d, e, t.env, H, C, A, m);
                     int l0, l1, l2;
                     if (stencil_in_tile(t, s2, l0, l1, l2)) {
 #pragma unroll
@@ -319,7 +312,7 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) gstore(a.xout + (size_t)c * N + p, x[c]);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) gstore(a.Fout + (size_t)c * N + p, F[c]);
+                for (int c = 0; c < 9; ++c) gstore(a.Hout + (size_t)c * N + p, H[c]);
                 if (write_vc) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) gstore(a.vout + (size_t)c * N + p, v[c]);

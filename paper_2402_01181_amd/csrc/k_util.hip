@@ -62,6 +62,15 @@ __global__ void k_read_grid(const float4 *g, int64_t gofs, int n, int comp0, int
     for (int c = 0; c < comps; ++c) dst[(size_t)c * nn + id] = src[comp0 + c];
 }
 
+__global__ void k_add_identity(float *p, int64_t n, int64_t stride, float sign)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        p[i] += sign;
+        p[4 * stride + i] += sign;
+        p[8 * stride + i] += sign;
+    }
+}
+
 static unsigned grid_for(int64_t n, int block = 256)
 {
     int64_t b = (n + block - 1) / block;
@@ -102,6 +111,11 @@ void launch_write_particles(float *dst, const int32_t *pid, int ntot, int pofs, 
 {
     hipLaunchKernelGGL(k_write_particles, dim3((np + 255) / 256), dim3(256), 0, st, dst, pid, ntot, pofs, np,
                        comps, src);
+}
+
+void launch_add_identity(float *p, int64_t n, int64_t stride, float sign, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_identity, dim3(grid_for(n)), dim3(256), 0, st, p, n, stride, sign);
 }
 
 void launch_read_grid(const float4 *g, int64_t gofs, int n, int comp0, int comps, float *dst, hipStream_t st)

@@ -54,7 +54,7 @@ struct mpm_ctx {
     mpm::ToolDev *tools = nullptr;
     uint32_t *status = nullptr;
     int32_t *step = nullptr;
-    float *x = nullptr, *v = nullptr, *C = nullptr, *F = nullptr;
+    float *x = nullptr, *v = nullptr, *C = nullptr, *H = nullptr;   // H = F - I
     int32_t *pid = nullptr;
     float4 *gP = nullptr, *gV = nullptr;
     // tiled scheme
@@ -117,7 +117,7 @@ struct mpm_ctx {
         d.tools = tools;
         d.status = status;
         d.step = step;
-        d.x = x; d.v = v; d.C = C; d.F = F;
+        d.x = x; d.v = v; d.C = C; d.H = H;
         d.pid = pid;
         d.gP = gP; d.gV = gV;
         return d;

@@ -121,8 +121,10 @@ struct Dev {
     ToolDev *tools;           // [n_envs][max_tools]
     uint32_t *status;         // [n_envs]
     int32_t *step;            // [n_envs] substeps taken
-    // particle state, SoA component-major [comp][ntot]
-    float *x, *v, *C, *F;
+    // particle state, SoA component-major [comp][ntot]; the deformation is
+    // stored as the displacement gradient H = F - I, so that small strains
+    // (and J - 1, ln J) keep full FP32 relative precision
+    float *x, *v, *C, *H;
     int32_t *pid;             // original index of the particle held in each slot
     // grid: P = (m, mv) and V = (v, 0) as float4 over all environments
     float4 *gP, *gV;
@@ -204,29 +206,33 @@ __device__ __forceinline__ void lame(float E, float nu, float &mu, float &lam)
     lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
 }
 
-// Neo-Hookean Kirchhoff stress tau = mu (F F^T - I) + lam ln J I, with
-// F F^T - I formed from G = F - I as G + G^T + G G^T to avoid cancellation.
-// J and ln J in FP64.  Returns true if J <= J_MIN (then ln J_MIN is used).
-__device__ __forceinline__ bool kirchhoff(const float F[9], float mu, float lam, float tau[9])
+// J - 1 = det(I + H) - 1 in FP64, expanded so no O(1) terms cancel:
+// tr H + (sum of the principal 2x2 minors of H) + det H.
+__device__ __forceinline__ double jm1_of(const float H[9])
 {
-    double J = (double)F[0] * ((double)F[4] * F[8] - (double)F[5] * F[7]) -
-               (double)F[1] * ((double)F[3] * F[8] - (double)F[5] * F[6]) +
-               (double)F[2] * ((double)F[3] * F[7] - (double)F[4] * F[6]);
-    bool inv = !(J > J_MIN);
-    double lnJ = log(inv ? J_MIN : J);
-    float G[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) G[3 * a + b] = F[3 * a + b] - (a == b ? 1.0f : 0.0f);
+    double h0 = H[0], h1 = H[1], h2 = H[2], h3 = H[3], h4 = H[4], h5 = H[5], h6 = H[6], h7 = H[7], h8 = H[8];
+    double tr = h0 + h4 + h8;
+    double m2 = (h0 * h4 - h1 * h3) + (h0 * h8 - h2 * h6) + (h4 * h8 - h5 * h7);
+    double dt = h0 * (h4 * h8 - h5 * h7) - h1 * (h3 * h8 - h5 * h6) + h2 * (h3 * h7 - h4 * h6);
+    return tr + m2 + dt;
+}
+
+// Neo-Hookean Kirchhoff stress tau = P F^T = mu (F F^T - I) + lam ln J I
+// from H = F - I: F F^T - I = H + H^T + H H^T.  ln J = log1p(J - 1) in FP64.
+// Returns true if J <= J_MIN (then ln J_MIN is used).
+__device__ __forceinline__ bool kirchhoff(const float H[9], float mu, float lam, float tau[9])
+{
+    double jm1 = jm1_of(H);
+    bool inv = !(1.0 + jm1 > J_MIN);
+    double lnJ = inv ? log(J_MIN) : log1p(jm1);
     float p = (float)((double)lam * lnJ);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = a; b < 3; ++b) {
-            float s = G[3 * a + b] + G[3 * b + a];
+            float s = H[3 * a + b] + H[3 * b + a];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) s = fmaf(G[3 * a + c], G[3 * b + c], s);
+            for (int c = 0; c < 3; ++c) s = fmaf(H[3 * a + c], H[3 * b + c], s);
             float t = mu * s + (a == b ? p : 0.0f);
             tau[3 * a + b] = t;
             tau[3 * b + a] = t;
@@ -234,11 +240,19 @@ __device__ __forceinline__ bool kirchhoff(const float F[9], float mu, float lam,
     return inv;
 }
 
-__device__ __forceinline__ double det3d(const float F[9])
+__device__ __forceinline__ bool inverted_h(const float H[9]) { return !(1.0 + jm1_of(H) > J_MIN); }
+
+// H' = H + dt C (I + H): the F update F' = (I + dt C) F written for H.
+__device__ __forceinline__ void update_h(float H[9], const float C[9], float dt)
 {
-    return (double)F[0] * ((double)F[4] * F[8] - (double)F[5] * F[7]) -
-           (double)F[1] * ((double)F[3] * F[8] - (double)F[5] * F[6]) +
-           (double)F[2] * ((double)F[3] * F[7] - (double)F[4] * F[6]);
+    float Hn[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Hn[3 * r + c] = H[3 * r + c] + dt * (C[3 * r + c] + C[3 * r] * H[c] + C[3 * r + 1] * H[3 + c] + C[3 * r + 2] * H[6 + c]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) H[k] = Hn[k];
 }
 
 // Grid operation of one node (Sec. III-B item 2, Sec. III-C): normalise +

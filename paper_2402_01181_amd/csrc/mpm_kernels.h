@@ -18,6 +18,8 @@ void launch_read_particles(const float *src, const int32_t *pid, int ntot, int p
                            float *dst, hipStream_t st);
 void launch_write_particles(float *dst, const int32_t *pid, int ntot, int pofs, int np, int comps,
                             const float *src, hipStream_t st);
+// p[c][i] += sign for the diagonal components c = 0, 4, 8 of a [9][stride] array, i < n.
+void launch_add_identity(float *p, int64_t n, int64_t stride, float sign, hipStream_t st);
 void launch_read_grid(const float4 *g, int64_t gofs, int n, int comp0, int comps, float *dst, hipStream_t st);
 
 }  // namespace mpm

@@ -17,7 +17,7 @@ struct SortBuf {
 };
 
 struct ParticleBuf {
-    float *x, *v, *C, *F;
+    float *x, *v, *C, *H;   // H = F - I
     int32_t *pid;
 };
 
@@ -39,9 +39,9 @@ constexpr int TILE = 8;
 constexpr int TILE_NODES = TILE * TILE * TILE;
 
 struct TiledArgs {
-    const float *xin, *vin, *Cin, *Fin;   // particle input (sorted slots)
+    const float *xin, *vin, *Cin, *Hin;   // particle input (sorted slots); H = F - I
     const int32_t *pidin;
-    float *xout, *vout, *Cout, *Fout;     // particle output (tail: all; fused: x, F)
+    float *xout, *vout, *Cout, *Hout;     // particle output (tail: all; fused: x, H)
     int32_t *pidout;                      // copied when pidin != pidout
     const int4 *items;
     const int2 *totals;                   // .y = number of items

@@ -134,12 +134,25 @@ def test_autograd_diff_slab_full_size_vs_fd(gpu, orc):
     L0 = oracle_loss()
     _say(f"  loss gpu {loss.item():.6e} oracle {L0:.6e}")
     assert abs(loss.item() - L0) <= 1e-3 * L0
-    hE, hnu = 1e-3 * env.E, 1e-6
+    # the oracle's own FP64 adjoint of the same loss
+    o = oracle_sim_like(orc, sc)
+    c0 = None
+    ref = None
+    oo = oracle_sim_like(orc, sc).run(S)
+    c0 = oo.state.x.mean(0)
+    xbar = np.tile(2.0 * (c0 - sc.extra["target"]) / env.N, (env.N, 1))
+    ref = o.adjoint(S, xbar)
+    for name, a, b in (("dL/dE", E.grad.item(), ref["gE"]), ("dL/dnu", nu.grad.item(), ref["gnu"]),
+                       ("dL/du", u.grad[0, 0].numpy(), ref["gu"][:, 0])):
+        e = _rel(a, b)
+        _say(f"  {name} vs oracle adjoint: rel {e:.2e}")
+        assert e <= TOL_GRAD, (name, e)
+    hE, hnu = 1e-3 * env.E, 1e-5
     fdE = (oracle_loss(E_=env.E + hE) - oracle_loss(E_=env.E - hE)) / (2 * hE)
     fdnu = (oracle_loss(nu_=env.nu + hnu) - oracle_loss(nu_=env.nu - hnu)) / (2 * hnu)
     rng = np.random.default_rng(11)
     d = rng.standard_normal((S, 3))
-    hu = 1e-4
+    hu = 1e-6   # small: the tool path moves < 1e-8 m, so no contact decision changes
     traj0 = env.tools[0].traj.astype(np.float64)
     fdu = (oracle_loss(traj=traj0 + hu * d) - oracle_loss(traj=traj0 - hu * d)) / (2 * hu)
     gu_dir = float((u.grad[0, 0].numpy() * d).sum())

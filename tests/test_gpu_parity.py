@@ -198,3 +198,47 @@ def test_graph_replays_match_eager(gpu, orc):
         assert graph.read(L.F_STEP) == 40 * (r + 1)
         np.testing.assert_array_equal(graph.read(L.F_TOOL_T), eager.read(L.F_TOOL_T))
     assert graph.read(L.F_STATUS) == 0
+
+
+def _small_batch(seed=4, n_envs=6):
+    return scenes.batched_scene(seed=seed, n_envs=n_envs, substeps=30, n_min=1500, n_max=5000)
+
+
+def test_batched_matches_single_environments(gpu, orc):
+    """Environments stepped together (one context, shared kernels) give the
+    same trajectories as each environment stepped alone."""
+    Sim, L = gpu
+    sc = _small_batch()
+    _say(f"batched vs single: {len(sc.envs)} envs, grids {[e.n for e in sc.envs]}, N {[e.N for e in sc.envs]}")
+    b = Sim(sc, options={L.OPT_SORT_EVERY: 8})
+    b.step(sc.substeps)
+    for e, env in enumerate(sc.envs):
+        one = scenes.Scene(f"env{e}", [env], dt=sc.dt, substeps=sc.substeps)
+        s = Sim(one, options={L.OPT_SORT_EVERY: 8})
+        s.step(sc.substeps)
+        xb = b.particles(e)[0]
+        xs = s.particles(0)[0]
+        err = np.abs(xb - xs).max()
+        _say(f"  env {e}: max |dx| = {err:.2e}")
+        assert err <= 1e-5
+        np.testing.assert_array_equal(b.read(L.F_TOOL_T, e), s.read(L.F_TOOL_T, 0))
+        assert b.read(L.F_STEP, e) == sc.substeps and b.read(L.F_STATUS, e) == 0
+
+
+def test_batched_teacher_forced_parity(gpu, orc):
+    Sim, L = gpu
+    sc = _small_batch(seed=9, n_envs=5)
+    _say(f"batched teacher-forced parity: {len(sc.envs)} envs")
+    b = Sim(sc)
+    for s in range(3):
+        refs = []
+        for e, env in enumerate(sc.envs):
+            o = orc.Sim(env, dt=sc.dt, gravity=sc.gravity, bound=sc.bound)
+            o.state = oracle_state_from_gpu(orc, b, e)
+            o.T[0] = b.read(L.F_TOOL_T, e)[0]
+            o.s = s
+            o.run(1)
+            refs.append(o.state)
+        b.step(1)
+        for e, ref in enumerate(refs):
+            _compare_particles(ref, b, env=e, what=f"substep {s} env {e}")
