@@ -63,6 +63,61 @@ def make_scene(name: str):
     raise SystemExit(f"unknown config {name}")
 
 
+def _events_ms(torch, fn):
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def measure_forms(torch, L, Sim, opts, batched_steps=40, adj_steps=200):
+    """The other forms of the substep on the same GPU: the batched workload
+    (256 environments) and the differentiable slab (forward with tape +
+    hand adjoint, checkpoints every 20) against its plain forward."""
+    from paper_2402_01181_amd import scenes
+    out = {}
+    bsc = scenes.batched_scene()
+    bs = Sim(bsc, options=opts)
+    bs.step(5)
+    ms = _events_ms(torch, lambda: bs.step(batched_steps))
+    nb = bsc.n_particles
+    x = [bs.read(L.F_X, e, device=False).T for e in range(bs.n_envs)]
+    nodes = sum(active_nodes(xx, int(bs.gn[e])) for e, xx in enumerate(x))
+    bytes_step = nb * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
+    out["batched"] = {"workload": "256 environments, 5K-50K particles each (seeded), 32^3/64^3 grids, own capsules",
+                      "particles": nb, "substeps": batched_steps, "ms_per_substep": ms / batched_steps,
+                      "value": nb * batched_steps / (ms * 1e-3), "unit": "particle-substeps/s",
+                      "algorithmic_GBps": bytes_step / (ms / batched_steps * 1e-3) / 1e9,
+                      "hbm_frac": bytes_step / (ms / batched_steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "status": int(any(bs.read(L.F_STATUS, e) for e in range(bs.n_envs)))}
+    bs.close()
+    del bs
+    dsc = scenes.diff_scene(substeps=adj_steps)
+    ck = dsc.extra["checkpoint_every"]
+    fw = Sim(dsc, options=opts)
+    fw.step(20)
+    ms_f = _events_ms(torch, lambda: fw.step(adj_steps))
+    fw.close()
+    ad = Sim(dsc, max_tape=adj_steps, checkpoint_every=ck, options=opts)
+    N = dsc.n_particles
+    seed = torch.full((3, N), 1.0 / N, device="cuda")
+    def fwd_adj():
+        ad.step(adj_steps, record_tape=True)
+        ad.adjoint(adj_steps, xbar=seed)
+    fwd_adj()
+    ms_fa = _events_ms(torch, fwd_adj)
+    out["forward_adjoint"] = {"workload": f"slab 30,000 particles, 64^3, {adj_steps} substeps, checkpoints every {ck}",
+                              "substeps": adj_steps, "ms_forward": ms_f, "ms_forward_with_tape_plus_adjoint": ms_fa,
+                              "value": N * adj_steps / (ms_fa * 1e-3), "unit": "particle-substeps/s",
+                              "ratio_to_forward": ms_fa / ms_f}
+    ad.close()
+    return out
+
+
 def cpu_baseline(scene, substeps: int):
     """The FP64 oracle as it stands, serial, on the first `substeps` substeps of
     environment 0 of the same scene."""
@@ -94,6 +149,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick block/item/sort/graph options by timing first")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -121,7 +177,7 @@ def main():
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.5, out=b)      # one elementwise kernel: reads and writes the stated MiB
         torch.cuda.synchronize()
         del a, b
     sim = Sim(scene, options=opts)
@@ -172,6 +228,13 @@ def main():
         print(f"# kernels: " + ", ".join(f"{k} {v['avg_us']:.2f}us x{v['launches']}" for k, v in kernels.items()),
               file=sys.stderr, flush=True)
 
+    forms = None
+    if not args.no_forms and args.config == "slab":
+        sim.close()
+        forms = measure_forms(torch, L, Sim, {k: v for k, v in opts.items() if k != L.OPT_GRAPH})
+        for k, v in forms.items():
+            print(f"# form {k}: {v['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         default_cpu = {"slab": 600, "large": 15, "cube": 50, "batched": 300}
@@ -199,6 +262,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "forms": forms,
         "status": status if any(status) else 0,
     }
     print(json.dumps(out), flush=True)

@@ -81,7 +81,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
         T.ckpt_state = cv.take<float>(st24 * T.n_ckpt);
         T.ckpt_tools = cv.take<ToolDev>(slots * T.n_ckpt);
         T.ckpt_step = cv.take<int32_t>((size_t)s.n_envs * T.n_ckpt);
-        T.seg_state = cv.take<float>(st24 * k);
+        T.seg_state = cv.take<float>(st24 * (k + 1));
         T.seg_tools = cv.take<ToolDev>(slots * k);
         T.seg_P = cv.take<float4>((size_t)s.total_nodes * k);
         T.seg_V = cv.take<float4>((size_t)s.total_nodes * k);
@@ -91,6 +91,9 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
         T.work_step = cv.take<int32_t>(s.n_envs);
         T.work_status = cv.take<uint32_t>(s.n_envs);
         T.adj_state = cv.take<float>(st24);
+        T.adj_slot = cv.take<float>(st24);
+        T.perm = cv.take<int32_t>(s.ntot);
+        T.iota = cv.take<int32_t>(s.ntot);
         T.adj.xb = T.adj_state;
         T.adj.vb = T.adj_state ? T.adj_state + (size_t)3 * s.ntot : nullptr;
         T.adj.Cb = T.adj_state ? T.adj_state + (size_t)6 * s.ntot : nullptr;
@@ -119,7 +122,7 @@ bool all_carved(const mpm_ctx &c)
         const auto &T = c.tape;
         const void *t[] = {T.ckpt_state, T.ckpt_tools, T.ckpt_step, T.seg_state, T.seg_tools, T.seg_P, T.seg_V,
                            T.seg_dec, T.work, T.work_tools, T.work_step, T.work_status, T.adj_state, T.adj.gVb,
-                           T.adj.gPb, T.adj.ubar, T.adj.Tbar, T.adj.mubar, T.adj.lambar};
+                           T.adj.gPb, T.adj.ubar, T.adj.Tbar, T.adj.mubar, T.adj.lambar, T.adj_slot, T.perm, T.iota};
         for (const void *q : t)
             if (!q) return false;
     }
@@ -414,6 +417,100 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
     }
 }
 
+// Tape bookkeeping without active-brick lists (the tape's grid passes are dense).
+ActiveBuf tape_act(const mpm_ctx *c)
+{
+    ActiveBuf a = c->act;
+    a.flag = nullptr;
+    a.list = nullptr;
+    a.count = nullptr;
+    return a;
+}
+
+ParticleBuf seg_view(const mpm_ctx *c, int slot)
+{
+    const size_t N = c->ntot;
+    float *b = c->tape.seg_state + (size_t)slot * 24 * N;
+    return ParticleBuf{b, b + 3 * N, b + 6 * N, b + 15 * N, c->tape.perm};
+}
+
+// Tiled recompute of substeps [s_begin, s_end) from checkpoint `seg`: the
+// checkpoint is counting-sorted by brick into tape slot 0 (its permutation
+// kept), then each substep runs the tiled P2G head into its own tape grid,
+// the dense tape grid pass, and the tiled G2P tail writing the next slot.
+void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t st)
+{
+    auto &T = c->tape;
+    const size_t N = c->ntot, slots = c->tool_slots();
+    Dev dc = state_view(c, T.ckpt_state + (size_t)seg * 24 * N);
+    dc.pid = T.iota;
+    timed(c, st, PK_SORT, [&] { launch_sort(dc, c->sort, c->total_bricks, c->item, seg_view(c, 0), 1, st); });
+    c->items_valid = false;   // the live state's work items were overwritten
+    if (c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
+    timed(c, st, PK_ADJ_MISC, [&] {
+        launch_copy_bytes(T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots, st);
+        launch_copy_bytes(T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs, st);
+    });
+    const ActiveBuf ta = tape_act(c);
+    for (int j = s_begin; j < s_end; ++j) {
+        const int slot = j - s_begin;
+        Dev d = c->dev();
+        d.tools = T.work_tools;
+        d.step = T.work_step;
+        d.status = T.work_status;
+        d.gP = T.seg_P + (size_t)slot * c->total_nodes;
+        d.gV = T.seg_V + (size_t)slot * c->total_nodes;
+        ParticleBuf in = seg_view(c, slot), out = seg_view(c, slot + 1);
+        TiledArgs head = tiled_args(c, in, in, 0), tail = tiled_args(c, in, out, 0);
+        head.act = ta;
+        tail.act = ta;
+        timed(c, st, PK_ADJ_MISC, [&] {
+            launch_copy_bytes(T.seg_tools + (size_t)slot * slots, T.work_tools, sizeof(ToolDev) * slots, st);
+            launch_fill_f4(d.gP, c->total_nodes, st);
+        });
+        timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, head, c->block, c->tiled_blocks, st); });
+        timed(c, st, PK_GRID_DENSE, [&] {
+            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, st);
+        });
+        timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, tail, c->block, c->tiled_blocks, st); });
+    }
+}
+
+// Reverse the recomputed segment's substeps [lo, s_end) in its sorted slot
+// order; adjoints are gathered from / scattered back to original order.
+void reverse_segment_tiled(mpm_ctx *c, int s_begin, int lo, int s_end, int s0, hipStream_t st)
+{
+    auto &T = c->tape;
+    const size_t N = c->ntot;
+    timed(c, st, PK_ADJ_MISC, [&] { launch_permute(T.adj_state, T.perm, c->ntot, 24, T.adj_slot, 0, st); });
+    AdjBuf a = T.adj;
+    a.xb = T.adj_slot;
+    a.vb = T.adj_slot + 3 * N;
+    a.Cb = T.adj_slot + 6 * N;
+    a.Fb = T.adj_slot + 15 * N;
+    const ActiveBuf ta = tape_act(c);
+    for (int j = s_end - 1; j >= lo; --j) {
+        const int slot = j - s_begin;
+        ParticleBuf sv = seg_view(c, slot);
+        Dev d = c->dev();
+        d.x = sv.x; d.v = sv.v; d.C = sv.C; d.H = sv.H; d.pid = nullptr;
+        d.gP = T.seg_P + (size_t)slot * c->total_nodes;
+        d.gV = T.seg_V + (size_t)slot * c->total_nodes;
+        d.tools = T.seg_tools + (size_t)slot * c->tool_slots();
+        a.j = j - s0;
+        timed(c, st, PK_ADJ_G2P, [&] {
+            launch_adj_g2p_tiled(d, a, c->sort.items, c->sort.totals, ta, c->block, c->tiled_blocks, st);
+        });
+        timed(c, st, PK_ADJ_GRID, [&] {
+            launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
+        });
+        timed(c, st, PK_ADJ_P2G, [&] {
+            launch_adj_p2g_tiled(d, a, c->sort.items, c->sort.totals, ta, c->block, c->tiled_blocks, st);
+        });
+    }
+    timed(c, st, PK_ADJ_MISC, [&] { launch_permute(T.adj_slot, T.perm, c->ntot, 24, T.adj_state, 1, st); });
+}
+
 // Reverse substep j (tape slot `slot`); window index j - s0.
 void reverse_substep(mpm_ctx *c, int slot, int jw, hipStream_t st)
 {
@@ -551,6 +648,7 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
             return cleanup_fail(e2, "copy initial state");
         launch_add_identity(c->H, s.ntot, s.ntot, -1.0f, st);    // stored as H = F - I
         launch_iota(c->pid, s.ntot, st);
+        if (c->max_tape > 0) launch_iota(c->tape.iota, s.ntot, st);
         launch_fill_u32(c->status, s.n_envs, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->step), s.n_envs, 0u, st);
         launch_fill_f4(c->gP, s.total_nodes, st);
@@ -729,8 +827,13 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
     });
     for (int seg = (len - 1) / k; seg >= s0 / k; --seg) {
         const int sb = seg * k, se = std::min(sb + k, len);
-        recompute_segment(c, seg, sb, se, st);
-        for (int j = se - 1; j >= std::max(sb, s0); --j) reverse_substep(c, j - sb, j - s0, st);
+        if (c->scheme == MPM_SCHEME_TILED) {
+            recompute_segment_tiled(c, seg, sb, se, st);
+            reverse_segment_tiled(c, sb, std::max(sb, s0), se, s0, st);
+        } else {
+            recompute_segment(c, seg, sb, se, st);
+            for (int j = se - 1; j >= std::max(sb, s0); --j) reverse_substep(c, j - sb, j - s0, st);
+        }
     }
     timed(c, st, PK_ADJ_MISC, [&] {
         launch_adj_finish(c->dev(), T.adj, n_substeps, io->gE, io->gnu, io->gu, io->gT, st);

@@ -11,6 +11,7 @@
 //               adjoints and accumulates dL/dmu, dL/dlambda.
 // The last three also give the adjoints of the state before substep j.
 #include "mpm_adjoint.h"
+#include "mpm_tile_util.h"
 
 namespace mpm {
 
@@ -432,6 +433,360 @@ __global__ void k_fill_f64(double *p, int64_t n)
         gstore(p + i, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled reverse kernels: particles in brick-sorted slots (the order a tape
+// segment was recomputed in), one work item per (brick, slot range).
+
+struct AdjTiledArgs {
+    const int4 *items;
+    const int2 *totals;
+    ActiveBuf act;      // env_bofs only (no marking)
+};
+
+// Reverse of G2P + advection + F update.  Pass 1 (lane = particle) forms C'
+// from the tape's node velocities (LDS tile), the particle adjoints and the
+// weight-gradient terms; pass 2 (lane = stencil node) adds
+// w (vbar_t + Bbar q) to per-wavefront tiles, flushed to the node-velocity
+// adjoint with one float atomic per component.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTiledArgs ta)
+{
+    constexpr int T = 64 * W;
+    __shared__ float4 tv[TILE_NODES];
+    __shared__ float4 tp[W * TILE_NODES];
+    __shared__ Payload pay[T];
+    const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, o = lane & 31;
+    const bool node_lane = o < 27;
+    const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
+    const int nitems = gload(ta.totals).y;
+    int first, stride, end;
+    item_range(nitems, first, stride, end);
+    for (int it = first; it < end; it += stride) {
+        const int4 item = gload(ta.items + it);
+        EnvDev e;
+        const Tile t = make_tile(d, ta.act, item.x, e);
+        for (int n = tid; n < TILE_NODES; n += T) {
+            int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
+            for (int w = 0; w < W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
+            tv[n] = V;
+        }
+        __syncthreads();
+        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
+            const int q = chunk + tid;
+            int bits = 0;
+            if (q < item.y + item.z) {
+                float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+                Stencil s;
+                make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
+                if (!s.outside) {
+                    int l0, l1, l2;
+                    const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
+                    float dw[3][3];
+                    weight_grads(s, dw);
+                    float4 Vn[27];
+                    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int a0 = 0; a0 < 3; ++a0)
+#pragma unroll
+                        for (int a1 = 0; a1 < 3; ++a1)
+#pragma unroll
+                            for (int a2 = 0; a2 < 3; ++a2) {
+                                int n = (a0 * 3 + a1) * 3 + a2;
+                                Vn[n] = in_tile ? tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
+                                                : gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
+                                float wx = w * Vn[n].x, wy = w * Vn[n].y, wz = w * Vn[n].z;
+                                B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
+                                B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
+                                B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
+                            }
+                    const float cs = 4.0f * e.inv_dx;
+                    float Cn[9], H[9], Fb[9], Cb[9], xb[3], vb[3];
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        Cn[c] = cs * B[c];
+                        H[c] = gload(d.H + (size_t)c * N + q);
+                        Fb[c] = gload(a.Fb + (size_t)c * N + q);
+                        Cb[c] = gload(a.Cb + (size_t)c * N + q);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xb[c] = gload(a.xb + (size_t)c * N + q);
+                        vb[c] = gload(a.vb + (size_t)c * N + q);
+                    }
+                    float Fbn[9], Bb[9];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * (Cn[r] * Fb[c] + Cn[3 + r] * Fb[3 + c] + Cn[6 + r] * Fb[6 + c]);
+                            float cbt = Cb[3 * r + c] + d.dt * (Fb[3 * r + c] + Fb[3 * r] * H[3 * c] + Fb[3 * r + 1] * H[3 * c + 1] +
+                                                                Fb[3 * r + 2] * H[3 * c + 2]);
+                            Bb[3 * r + c] = cs * cbt;
+                        }
+                    float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
+                    float fxb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int a0 = 0; a0 < 3; ++a0)
+#pragma unroll
+                        for (int a1 = 0; a1 < 3; ++a1)
+#pragma unroll
+                            for (int a2 = 0; a2 < 3; ++a2) {
+                                int n = (a0 * 3 + a1) * 3 + a2;
+                                float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
+                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                float g0 = vbt[0] + Bb[0] * q0 + Bb[1] * q1 + Bb[2] * q2;
+                                float g1 = vbt[1] + Bb[3] * q0 + Bb[4] * q1 + Bb[5] * q2;
+                                float g2 = vbt[2] + Bb[6] * q0 + Bb[7] * q1 + Bb[8] * q2;
+                                const float4 V = Vn[n];
+                                float wb = V.x * g0 + V.y * g1 + V.z * g2;
+                                float qb0 = w * (Bb[0] * V.x + Bb[3] * V.y + Bb[6] * V.z);
+                                float qb1 = w * (Bb[1] * V.x + Bb[4] * V.y + Bb[7] * V.z);
+                                float qb2 = w * (Bb[2] * V.x + Bb[5] * V.y + Bb[8] * V.z);
+                                fxb[0] += -qb0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                fxb[1] += -qb1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
+                                fxb[2] += -qb2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
+                            }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        gstore(a.xb + (size_t)c * N + q, xb[c] + e.inv_dx * fxb[c]);
+                        gstore(a.vb + (size_t)c * N + q, 0.0f);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        gstore(a.Fb + (size_t)c * N + q, Fbn[c]);
+                        gstore(a.Cb + (size_t)c * N + q, 0.0f);
+                    }
+                    // node contributions w (vbar_t + Bbar q), the same form as P2G's w (m v + A q)
+                    bits = PAY_VALID | (in_tile ? PAY_IN_TILE : 0);
+                    Payload &P = pay[tid];
+                    P.f_m = make_float4(s.fx[0], s.fx[1], s.fx[2], 0.f);
+                    P.mv_bits = make_float4(vbt[0], vbt[1], vbt[2], __int_as_float(bits));
+                    P.a0 = make_float4(Bb[0], Bb[1], Bb[2], __int_as_float(s.b[0]));
+                    P.a1 = make_float4(Bb[3], Bb[4], Bb[5], __int_as_float(s.b[1]));
+                    P.a2 = make_float4(Bb[6], Bb[7], Bb[8], __int_as_float(s.b[2]));
+                }
+            }
+            if (!bits) pay[tid].mv_bits.w = __int_as_float(0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float4 *mytile = tp + wave * TILE_NODES;
+            for (int r = 0; r < 32; ++r) {
+                const Payload &P = pay[wave * 64 + half * 32 + r];
+                const int pb = __float_as_int(P.mv_bits.w);
+                const bool act = node_lane && (pb & PAY_VALID);
+                float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                int l = -1, b0 = 0, b1 = 0, b2 = 0;
+                if (act) {
+                    const float4 fm = P.f_m, g = P.mv_bits, A0 = P.a0, A1 = P.a1, A2 = P.a2;
+                    b0 = __float_as_int(A0.w); b1 = __float_as_int(A1.w); b2 = __float_as_int(A2.w);
+                    const float q0 = o0 - fm.x, q1 = o1 - fm.y, q2 = o2 - fm.z;
+                    const float w = bspline2(q0) * bspline2(q1) * bspline2(q2);
+                    c4.y = w * (g.x + A0.x * q0 + A0.y * q1 + A0.z * q2);
+                    c4.z = w * (g.y + A1.x * q0 + A1.y * q1 + A1.z * q2);
+                    c4.w = w * (g.z + A2.x * q0 + A2.y * q1 + A2.z * q2);
+                    c4.x = 1.0f;   // marks the node as touched
+                    if (pb & PAY_IN_TILE)
+                        l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (half == h && l >= 0) {
+                        float4 old = mytile[l];
+                        mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                if (act && l < 0) {
+                    float *g = reinterpret_cast<float *>(a.gVb + node_id(e, b0 + o0, b1 + o1, b2 + o2));
+                    gatomic_add(g + 0, c4.y);
+                    gatomic_add(g + 1, c4.z);
+                    gatomic_add(g + 2, c4.w);
+                }
+            }
+            __syncthreads();
+        }
+        for (int n = tid; n < TILE_NODES; n += T) {
+            float4 sum = tp[n];
+#pragma unroll
+            for (int w = 1; w < W; ++w) {
+                float4 q4 = tp[w * TILE_NODES + n];
+                sum.x += q4.x; sum.y += q4.y; sum.z += q4.z; sum.w += q4.w;
+            }
+            if (sum.x != 0.f) {
+                int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
+                float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
+                gatomic_add(g + 0, sum.y);
+                gatomic_add(g + 1, sum.z);
+                gatomic_add(g + 2, sum.w);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Reverse of P2G and of the stress, gathering the node adjoints (m, mv)bar
+// of the item's tile from LDS.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTiledArgs ta)
+{
+    constexpr int T = 64 * W;
+    __shared__ float4 tb[TILE_NODES];
+    const int N = d.ntot, tid = threadIdx.x;
+    const int nitems = gload(ta.totals).y;
+    int first, stride, end;
+    item_range(nitems, first, stride, end);
+    for (int it = first; it < end; it += stride) {
+        const int4 item = gload(ta.items + it);
+        EnvDev e;
+        const Tile t = make_tile(d, ta.act, item.x, e);
+        for (int n = tid; n < TILE_NODES; n += T) {
+            int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
+            float4 Pb = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < e.n && j < e.n && k < e.n) Pb = gload(a.gPb + node_id(e, i, j, k));
+            tb[n] = Pb;
+        }
+        __syncthreads();
+        const float *mat = d.material + 4 * t.env;
+        const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
+        float mu, lam;
+        lame(E, nu, mu, lam);
+        const float m = rho * V0;
+        const float kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
+        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
+            const int q = chunk + tid;
+            bool active = q < item.y + item.z;
+            double mub = 0.0, lamb = 0.0;
+            if (active) {
+                float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+                Stencil s;
+                make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
+                if (!s.outside) {
+                    int l0, l1, l2;
+                    const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
+                    float H[9], F[9], C[9], v[3], tau[9], A[9];
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        H[c] = gload(d.H + (size_t)c * N + q);
+                        F[c] = H[c] + ((c & 3) == 0 ? 1.0f : 0.0f);
+                        C[c] = gload(d.C + (size_t)c * N + q);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[c] = gload(d.v + (size_t)c * N + q);
+                    bool inverted = kirchhoff(H, mu, lam, tau);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
+                    float dw[3][3];
+                    weight_grads(s, dw);
+                    float vbp[3] = {0.f, 0.f, 0.f}, Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    float fxb[3] = {0.f, 0.f, 0.f};
+                    const float dx = e.dx;
+#pragma unroll
+                    for (int a0 = 0; a0 < 3; ++a0)
+#pragma unroll
+                        for (int a1 = 0; a1 < 3; ++a1)
+#pragma unroll
+                            for (int a2 = 0; a2 < 3; ++a2) {
+                                float4 Pb = in_tile ? tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
+                                                    : gload(a.gPb + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                float d0 = (a0 - s.fx[0]) * dx, d1 = (a1 - s.fx[1]) * dx, d2 = (a2 - s.fx[2]) * dx;
+                                vbp[0] += m * w * Pb.y; vbp[1] += m * w * Pb.z; vbp[2] += m * w * Pb.w;
+                                float wy = w * Pb.y, wz = w * Pb.z, ww = w * Pb.w;
+                                Ab[0] += wy * d0; Ab[1] += wy * d1; Ab[2] += wy * d2;
+                                Ab[3] += wz * d0; Ab[4] += wz * d1; Ab[5] += wz * d2;
+                                Ab[6] += ww * d0; Ab[7] += ww * d1; Ab[8] += ww * d2;
+                                float c0 = m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2;
+                                float c1 = m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2;
+                                float c2 = m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2;
+                                float wb = m * Pb.x + Pb.y * c0 + Pb.z * c1 + Pb.w * c2;
+                                float db0 = w * (A[0] * Pb.y + A[3] * Pb.z + A[6] * Pb.w);
+                                float db1 = w * (A[1] * Pb.y + A[4] * Pb.z + A[7] * Pb.w);
+                                float db2 = w * (A[2] * Pb.y + A[5] * Pb.z + A[8] * Pb.w);
+                                fxb[0] += -dx * db0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                fxb[1] += -dx * db1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
+                                fxb[2] += -dx * db2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
+                            }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float *px = a.xb + (size_t)c * N + q;
+                        gstore(px, gload(px) + e.inv_dx * fxb[c]);
+                        float *pv = a.vb + (size_t)c * N + q;
+                        gstore(pv, gload(pv) + vbp[c]);
+                    }
+                    float taub[9];
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        float *pc = a.Cb + (size_t)c * N + q;
+                        gstore(pc, gload(pc) + m * Ab[c]);
+                        taub[c] = kf * Ab[c];
+                    }
+                    float Fb[9];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            Fb[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
+                                                  (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
+                    double trt = (double)taub[0] + taub[4] + taub[8];
+                    double jm1 = jm1_of(H);
+                    double lnJ = inverted ? log(J_MIN) : log1p(jm1);
+                    if (!inverted) {
+                        double f[9];
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) f[c] = (double)H[c] + ((c & 3) == 0 ? 1.0 : 0.0);
+                        double ci[9] = {f[4] * f[8] - f[5] * f[7], -(f[3] * f[8] - f[5] * f[6]), f[3] * f[7] - f[4] * f[6],
+                                        -(f[1] * f[8] - f[2] * f[7]), f[0] * f[8] - f[2] * f[6], -(f[0] * f[7] - f[1] * f[6]),
+                                        f[1] * f[5] - f[2] * f[4], -(f[0] * f[5] - f[2] * f[3]), f[0] * f[4] - f[1] * f[3]};
+                        double sc = (double)lam * trt / (1.0 + jm1);
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) Fb[c] += (float)(sc * ci[c]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        float *pf = a.Fb + (size_t)c * N + q;
+                        gstore(pf, gload(pf) + Fb[c]);
+                    }
+                    double ff = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double G = (double)H[3 * r + c] + H[3 * c + r] + (double)H[3 * r] * H[3 * c] +
+                                       (double)H[3 * r + 1] * H[3 * c + 1] + (double)H[3 * r + 2] * H[3 * c + 2];
+                            ff += (double)taub[3 * r + c] * G;
+                        }
+                    mub = ff;
+                    lamb = trt * lnJ;
+                }
+            }
+            // every particle of an item belongs to the tile's environment
+            wave_env_add(a.mubar, t.env, mub, active);
+            wave_env_add(a.lambar, t.env, lamb, active);
+        }
+        __syncthreads();
+    }
+}
+
+// dst[c][q] = src[c][perm[q]] (gather into slot order) or the reverse scatter.
+__global__ void k_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ntot) return;
+    int o = gload(perm + q);
+    for (int c = 0; c < comps; ++c) {
+        if (scatter) gstore(dst + (size_t)c * ntot + o, gload(src + (size_t)c * ntot + q));
+        else gstore(dst + (size_t)c * ntot + q, gload(src + (size_t)c * ntot + o));
+    }
+}
+
 static unsigned blocks_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -466,6 +821,30 @@ void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double 
 {
     int nt = d.n_envs * (d.max_tools > 0 ? d.max_tools : 1);
     hipLaunchKernelGGL(k_adj_finish, dim3((nt + 255) / 256), dim3(256), 0, st, d, a, n, gE, gnu, gu, gT);
+}
+
+void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+                          const ActiveBuf &act, int block, int nblocks, hipStream_t st)
+{
+    AdjTiledArgs ta{items, totals, act};
+    if (block == 64) hipLaunchKernelGGL((k_adj_g2p_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
+    else if (block == 128) hipLaunchKernelGGL((k_adj_g2p_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
+    else hipLaunchKernelGGL((k_adj_g2p_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
+}
+
+void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+                          const ActiveBuf &act, int block, int nblocks, hipStream_t st)
+{
+    AdjTiledArgs ta{items, totals, act};
+    if (block == 64) hipLaunchKernelGGL((k_adj_p2g_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
+    else if (block == 128) hipLaunchKernelGGL((k_adj_p2g_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
+    else hipLaunchKernelGGL((k_adj_p2g_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
+}
+
+void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_permute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, perm, ntot, comps, dst, scatter);
 }
 
 void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st)

@@ -1,91 +1,22 @@
 // Tiled scheme kernels.
 //
 // Particles are sorted by the 4x4x4-cell brick of their stencil base; a work
-// item is (brick, slot range).  For each item a workgroup stages an 8^3 node
-// tile (the brick's 6^3 stencil reach plus one cell of drift margin on each
-// side) in LDS:
+// item is (brick, slot range).  For each item a workgroup stages the 6^3
+// nodes the brick's stencils reach in LDS:
 //   - G2P reads node velocities from the tile,
-//   - P2G accumulates mass/momentum into the tile with LDS float atomics and
-//     flushes each non-empty tile node to the global grid with one float
-//     atomic per component,
+//   - P2G accumulates mass/momentum into per-wavefront tiles and flushes each
+//     non-empty tile node to the global grid with one float atomic per
+//     component,
 // so global atomics scale with tile nodes, not with particles x 27.  A
-// particle whose stencil has drifted out of the tile since the last sort
-// uses global memory directly (rare; correct either way).
+// particle whose stencil has drifted out of its sort-time brick uses global
+// memory directly (rare between sorts; correct either way).
 //
 // Workgroups are persistent over the item list; workgroup w runs on XCD
 // w % 8 and walks a contiguous eighth of the (spatially ordered) items, so
 // neighbouring tiles, which share halo nodes, stay in one XCD's L2.
-#include "mpm_tiled.h"
+#include "mpm_tile_util.h"
 
 namespace mpm {
-
-constexpr int NXCD = 8;
-// Padded LDS strides for the 8^3 tile: node (a,b,c) -> a*73 + b*9 + c
-// spreads the i-, j- and k-neighbours over different banks.
-constexpr int LS_I = 73, LS_J = 9, TILE_LDS = 7 * LS_I + 7 * LS_J + 7 + 1;
-
-__device__ __forceinline__ int lds_index(int a, int b, int c) { return a * LS_I + b * LS_J + c; }
-
-struct Tile {
-    int env;
-    int bi, bj, bk;   // brick coordinates
-    int o[3];         // node coordinates of tile corner (0,0,0) = 4*brick - 1
-};
-
-__device__ __forceinline__ int env_of_brick(const int32_t *env_bofs, int n_envs, int b)
-{
-    int lo = 0, hi = n_envs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (gload(env_bofs + mid) <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ Tile make_tile(const Dev &d, const ActiveBuf &act, int brick, EnvDev &e)
-{
-    Tile t;
-    t.env = env_of_brick(act.env_bofs, d.n_envs, brick);
-    e = load_env(d.env + t.env);
-    int lb = brick - e.bofs;
-    t.bk = lb % e.nb;
-    int r = lb / e.nb;
-    t.bj = r % e.nb;
-    t.bi = r / e.nb;
-    t.o[0] = 4 * t.bi - 1;
-    t.o[1] = 4 * t.bj - 1;
-    t.o[2] = 4 * t.bk - 1;
-    return t;
-}
-
-// Item walk: contiguous eighth of the list per XCD.
-__device__ __forceinline__ void item_range(int nitems, int &first, int &stride, int &end)
-{
-    int G = gridDim.x;               // multiple of NXCD
-    int x = blockIdx.x % NXCD, r = blockIdx.x / NXCD;
-    int per = (nitems + NXCD - 1) / NXCD;
-    first = x * per + r;
-    end = min(nitems, (x + 1) * per);
-    stride = G / NXCD;
-}
-
-__device__ __forceinline__ void mark_brick(const ActiveBuf &act, int par, int b)
-{
-    if (gatomic_cas(act.flag + b, 0, 1)) {
-        int slot = gatomic_add(act.count + par, 1);
-        gstore(act.list + (size_t)par * act.stride + slot, b);
-    }
-}
-
-// Mark every node brick a stencil with base b touches (global fallback path).
-__device__ __forceinline__ void mark_stencil_bricks(const ActiveBuf &act, int par, const EnvDev &e, const int b[3])
-{
-    int lo0 = b[0] >> 2, hi0 = (b[0] + 2) >> 2, lo1 = b[1] >> 2, hi1 = (b[1] + 2) >> 2;
-    int lo2 = b[2] >> 2, hi2 = (b[2] + 2) >> 2;
-    for (int i = lo0; i <= hi0; ++i)
-        for (int j = lo1; j <= hi1; ++j)
-            for (int k = lo2; k <= hi2; ++k) mark_brick(act, par, e.bofs + (i * e.nb + j) * e.nb + k);
-}
 
 __device__ __forceinline__ void advance_end_of_substep(const Dev &d)
 {
@@ -121,7 +52,7 @@ __device__ __forceinline__ void g2p_accumulate(const Dev &d, const EnvDev &e, co
             for (int o2 = 0; o2 < 3; ++o2) {
                 float V0, V1, V2;
                 if (FROM_TILE) {
-                    int li = lds_index(l0 + o0, l1 + o1, l2 + o2);
+                    int li = ((l0 + o0) * TILE + l1 + o1) * TILE + l2 + o2;
                     V0 = tvx[li]; V1 = tvy[li]; V2 = tvz[li];
                 } else {
                     float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
@@ -155,13 +86,6 @@ __device__ __forceinline__ void p2g_weights(const EnvDev &e, const Stencil &s, f
     pm = w * m;
 }
 
-__device__ __forceinline__ bool stencil_in_tile(const Tile &t, const Stencil &s, int &l0, int &l1, int &l2)
-{
-    l0 = s.b[0] - t.o[0];
-    l1 = s.b[1] - t.o[1];
-    l2 = s.b[2] - t.o[2];
-    return l0 >= 0 && l1 >= 0 && l2 >= 0 && l0 <= TILE - 3 && l1 <= TILE - 3 && l2 <= TILE - 3;
-}
 
 __device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &act, int par, const EnvDev &e,
                                                  const Stencil &s, float m, const float A[9], const float v[3])
@@ -199,152 +123,235 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
 // MODE 0: P2G only (head of a call; reads x, v, C, H).
 // MODE 1: fused G2P(s) + F update + advection + P2G(s+1) (reads/writes x, H).
 // MODE 2: G2P only (tail of a call; writes x, v, C, H).
-template <int MODE>
-__global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
+//
+// W wavefronts per workgroup.  Pass 1 (lane = particle): G2P from the LDS
+// velocity tile, F update, advection, stress and the P2G payload.  Pass 2
+// (lane = stencil node): each wavefront walks its 64 payloads two at a time,
+// lanes 0-26 on one particle's 27 nodes and lanes 32-58 on another's, and adds
+// the contributions to its own LDS tile with plain read-modify-write; the two
+// half-waves' updates are issued one after the other so none is lost.  (LDS
+// float atomics run at about 1/3 lane per clock per CU on this chip, far
+// below plain LDS traffic.)  The W tiles are summed and flushed to the global
+// grid with one float atomic per component per non-empty node.
+template <int MODE, int W>
+__global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1;
-    __shared__ float tm[P2G ? TILE_LDS : 1], tpx[P2G ? TILE_LDS : 1], tpy[P2G ? TILE_LDS : 1],
-        tpz[P2G ? TILE_LDS : 1];
-    __shared__ float tvx[G2P ? TILE_LDS : 1], tvy[G2P ? TILE_LDS : 1], tvz[G2P ? TILE_LDS : 1];
+    constexpr int T = 64 * W;
+    __shared__ float4 tv[G2P ? TILE_NODES : 1];          // node velocities
+    __shared__ float4 tp[P2G ? W * TILE_NODES : 1];      // per-wave (m, mv) tiles
+    __shared__ Payload pay[P2G ? T : 1];
     __shared__ int touched;
 
-    const int N = d.ntot, T = blockDim.x, tid = threadIdx.x;
+    const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = gload(a.totals).y;
+    // node-pass lane roles: half-wave h takes the particle 32 h + r of each pair r
+    const int half = lane >> 5, o = lane & 31;
+    const bool node_lane = o < 27;
+    const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
     int first, stride, end;
     item_range(nitems, first, stride, end);
     for (int it = first; it < end; it += stride) {
         const int4 item = gload(a.items + it);
         EnvDev e;
         const Tile t = make_tile(d, a.act, item.x, e);
-        // stage the tile
         for (int n = tid; n < TILE_NODES; n += T) {
-            int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
-            int li = lds_index(la, lb, lc);
-            if (P2G) { tm[li] = 0.f; tpx[li] = 0.f; tpy[li] = 0.f; tpz[li] = 0.f; }
+            int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
+            if (P2G)
+                for (int w = 0; w < W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (G2P) {
                 int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                 float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
-                tvx[li] = V.x; tvy[li] = V.y; tvz[li] = V.z;
+                if (i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
+                tv[n] = V;
             }
         }
         if (tid == 0) touched = 0;
         __syncthreads();
 
-        for (int p = item.y + tid; p < item.y + item.z; p += T) {
-            float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
-            float H[9], v[3], C[9];
+        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
+            // ---- pass 1: lane = particle
+            const int p = chunk + tid;
+            int bits = 0;
+            if (p < item.y + item.z) {
+                float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
+                float H[9], v[3], C[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) H[c] = gload(a.Hin + (size_t)c * N + p);
-            Stencil s;
-            make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s);
-            bool frozen = stencil_outside(s, e.n);
-            if (frozen) {
-                // out of the domain: state unchanged, no transfers
-                set_flag(d.status, t.env, MPM_FLAG_OUT_OF_DOMAIN);
-                if (a.xout != a.xin) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        gstore(a.xout + (size_t)c * N + p, x[c]);
-                        gstore(a.vout + (size_t)c * N + p, gload(a.vin + (size_t)c * N + p));
-                    }
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        gstore(a.Hout + (size_t)c * N + p, H[c]);
-                        gstore(a.Cout + (size_t)c * N + p, gload(a.Cin + (size_t)c * N + p));
-                    }
-                }
-                if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
-                continue;
-            }
-            if (G2P) {
-                int l0, l1, l2;
-                if (stencil_in_tile(t, s, l0, l1, l2))
-                    g2p_accumulate<true>(d, e, s, l0, l1, l2, tvx, tvy, tvz, v, C);
-                else
-                    g2p_accumulate<false>(d, e, s, 0, 0, 0, tvx, tvy, tvz, v, C);
-                x[0] += d.dt * v[0];
-                x[1] += d.dt * v[1];
-                x[2] += d.dt * v[2];
-                update_h(H, C, d.dt);
-                if (inverted_h(H)) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
-                if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
-                    set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = gload(a.vin + (size_t)c * N + p);
-#pragma unroll
-                for (int c = 0; c < 9; ++c) C[c] = gload(a.Cin + (size_t)c * N + p);
-            }
-            bool write_vc = MODE == 2;
-            if (P2G) {
-                Stencil s2;
-                if (G2P) make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s2); else s2 = s;
-                if (stencil_outside(s2, e.n)) {
-                    // leaves the domain now: freeze with this G2P's v, C
+                for (int c = 0; c < 9; ++c) H[c] = gload(a.Hin + (size_t)c * N + p);
+                Stencil s;
+                make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s);
+                if (s.outside) {
+                    // out of the domain: state unchanged, no transfers
                     set_flag(d.status, t.env, MPM_FLAG_OUT_OF_DOMAIN);
-                    write_vc = true;
+                    if (a.xout != a.xin) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            gstore(a.xout + (size_t)c * N + p, x[c]);
+                            gstore(a.vout + (size_t)c * N + p, gload(a.vin + (size_t)c * N + p));
+                        }
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) {
+                            gstore(a.Hout + (size_t)c * N + p, H[c]);
+                            gstore(a.Cout + (size_t)c * N + p, gload(a.Cin + (size_t)c * N + p));
+                        }
+                    }
+                    if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
                 } else {
-                    float A[9], m;
-                    affine_with_stress(d, e, t.env, H, C, A, m);
-                    int l0, l1, l2;
-                    if (stencil_in_tile(t, s2, l0, l1, l2)) {
+                    if (G2P) {
+                        int l0, l1, l2;
+                        if (stencil_in_tile(t, s, l0, l1, l2)) {
+                            float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                            v[0] = v[1] = v[2] = 0.f;
 #pragma unroll
-                        for (int o0 = 0; o0 < 3; ++o0)
+                            for (int a0 = 0; a0 < 3; ++a0)
 #pragma unroll
-                            for (int o1 = 0; o1 < 3; ++o1)
+                                for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-                                for (int o2 = 0; o2 < 3; ++o2) {
-                                    float pm, p0, p1, p2;
-                                    p2g_weights(e, s2, m, A, v, o0, o1, o2, pm, p0, p1, p2);
-                                    int li = lds_index(l0 + o0, l1 + o1, l2 + o2);
-                                    atomicAdd(&tm[li], pm);
-                                    atomicAdd(&tpx[li], p0);
-                                    atomicAdd(&tpy[li], p1);
-                                    atomicAdd(&tpz[li], p2);
-                                }
+                                    for (int a2 = 0; a2 < 3; ++a2) {
+                                        float4 V = tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2];
+                                        float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
+                                        float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                        float wx = w * V.x, wy = w * V.y, wz = w * V.z;
+                                        v[0] += wx; v[1] += wy; v[2] += wz;
+                                        B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
+                                        B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
+                                        B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
+                                    }
+                            const float cs = 4.0f * e.inv_dx;
+#pragma unroll
+                            for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
+                        } else {
+                            g2p_accumulate<false>(d, e, s, 0, 0, 0, nullptr, nullptr, nullptr, v, C);
+                        }
+                        x[0] += d.dt * v[0];
+                        x[1] += d.dt * v[1];
+                        x[2] += d.dt * v[2];
+                        update_h(H, C, d.dt);
+                        if (inverted_h(H)) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
+                        if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) &&
+                              isfinite(v[1]) && isfinite(v[2])))
+                            set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
                     } else {
-                        p2g_particle_global(d, a.act, a.par, e, s2, m, A, v);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) v[c] = gload(a.vin + (size_t)c * N + p);
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) C[c] = gload(a.Cin + (size_t)c * N + p);
+                    }
+                    bool write_vc = MODE == 2;
+                    if (P2G) {
+                        Stencil s2;
+                        if (G2P) make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s2); else s2 = s;
+                        if (s2.outside) {
+                            // leaves the domain now: freeze with this G2P's v, C
+                            set_flag(d.status, t.env, MPM_FLAG_OUT_OF_DOMAIN);
+                            write_vc = true;
+                        } else {
+                            float A[9], m;
+                            affine_with_stress(d, e, t.env, H, C, A, m);
+                            int l0, l1, l2;
+                            bits = PAY_VALID | (stencil_in_tile(t, s2, l0, l1, l2) ? PAY_IN_TILE : 0);
+                            Payload &P = pay[tid];
+                            P.f_m = make_float4(s2.fx[0], s2.fx[1], s2.fx[2], m);
+                            P.mv_bits = make_float4(m * v[0], m * v[1], m * v[2], __int_as_float(bits));
+                            P.a0 = make_float4(A[0] * e.dx, A[1] * e.dx, A[2] * e.dx, __int_as_float(s2.b[0]));
+                            P.a1 = make_float4(A[3] * e.dx, A[4] * e.dx, A[5] * e.dx, __int_as_float(s2.b[1]));
+                            P.a2 = make_float4(A[6] * e.dx, A[7] * e.dx, A[8] * e.dx, __int_as_float(s2.b[2]));
+                        }
+                    }
+                    if (G2P) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) gstore(a.xout + (size_t)c * N + p, x[c]);
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) gstore(a.Hout + (size_t)c * N + p, H[c]);
+                        if (write_vc) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) gstore(a.vout + (size_t)c * N + p, v[c]);
+#pragma unroll
+                            for (int c = 0; c < 9; ++c) gstore(a.Cout + (size_t)c * N + p, C[c]);
+                        }
+                        if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
                     }
                 }
             }
-            if (G2P) {
+            if (P2G) {
+                if (!bits) pay[tid].mv_bits.w = __int_as_float(0);
+                // payloads are read by other lanes of this wavefront only
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // ---- pass 2: lane = stencil node, two particles per step
+                float4 *mytile = tp + wave * TILE_NODES;
+                for (int r = 0; r < 32; ++r) {
+                    const Payload &P = pay[wave * 64 + half * 32 + r];
+                    const int pb = __float_as_int(P.mv_bits.w);
+                    const bool act = node_lane && (pb & PAY_VALID);
+                    float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    int l = -1, b0 = 0, b1 = 0, b2 = 0;
+                    if (act) {
+                        const float4 fm = P.f_m, mv = P.mv_bits, A0 = P.a0, A1 = P.a1, A2 = P.a2;
+                        b0 = __float_as_int(A0.w); b1 = __float_as_int(A1.w); b2 = __float_as_int(A2.w);
+                        const float q0 = o0 - fm.x, q1 = o1 - fm.y, q2 = o2 - fm.z;
+                        const float w = bspline2(q0) * bspline2(q1) * bspline2(q2);
+                        c4.x = w * fm.w;
+                        c4.y = w * (mv.x + A0.x * q0 + A0.y * q1 + A0.z * q2);
+                        c4.z = w * (mv.y + A1.x * q0 + A1.y * q1 + A1.z * q2);
+                        c4.w = w * (mv.z + A2.x * q0 + A2.y * q1 + A2.z * q2);
+                        if (pb & PAY_IN_TILE)
+                            l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
+                    }
+                    // half-wave 0 updates its nodes, then half-wave 1 (their nodes may coincide)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gstore(a.xout + (size_t)c * N + p, x[c]);
-#pragma unroll
-                for (int c = 0; c < 9; ++c) gstore(a.Hout + (size_t)c * N + p, H[c]);
-                if (write_vc) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) gstore(a.vout + (size_t)c * N + p, v[c]);
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) gstore(a.Cout + (size_t)c * N + p, C[c]);
+                    for (int h = 0; h < 2; ++h) {
+                        if (half == h && l >= 0) {
+                            float4 old = mytile[l];
+                            mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    if (act && l < 0) {
+                        // stencil outside the tile: straight to the global grid
+                        float *g = reinterpret_cast<float *>(d.gP + node_id(e, b0 + o0, b1 + o1, b2 + o2));
+                        gatomic_add(g + 0, c4.x);
+                        gatomic_add(g + 1, c4.y);
+                        gatomic_add(g + 2, c4.z);
+                        gatomic_add(g + 3, c4.w);
+                        if (o == 0) {
+                            int bb[3] = {b0, b1, b2};
+                            mark_stencil_bricks(a.act, a.par, e, bb);
+                        }
+                    }
                 }
-                if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
             }
+            if (P2G) __syncthreads();   // payload slots are rewritten by the next chunk
         }
 
         if (P2G) {
             __syncthreads();
-            // flush non-empty tile nodes; remember which node bricks were hit
+            // sum the wave tiles, flush non-empty nodes, remember the node bricks hit
             for (int n = tid; n < TILE_NODES; n += T) {
-                int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
-                int li = lds_index(la, lb, lc);
-                float pm = tm[li];
-                if (pm != 0.f) {
+                float4 sum = tp[n];
+#pragma unroll
+                for (int w = 1; w < W; ++w) {
+                    float4 q = tp[w * TILE_NODES + n];
+                    sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
+                }
+                if (sum.x != 0.f) {
+                    int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
                     int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                     float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
-                    float q0 = tpx[li], q1 = tpy[li], q2 = tpz[li];
-                    gatomic_add(g + 0, pm);
-                    gatomic_add(g + 1, q0);
-                    gatomic_add(g + 2, q1);
-                    gatomic_add(g + 3, q2);
-                    int bit = (((i >> 2) - t.bi + 1) * 3 + ((j >> 2) - t.bj + 1)) * 3 + ((k >> 2) - t.bk + 1);
+                    gatomic_add(g + 0, sum.x);
+                    gatomic_add(g + 1, sum.y);
+                    gatomic_add(g + 2, sum.z);
+                    gatomic_add(g + 3, sum.w);
+                    int bit = (((i >> 2) - t.bi) * 2 + ((j >> 2) - t.bj)) * 2 + ((k >> 2) - t.bk);
                     atomicOr(&touched, 1 << bit);
                 }
             }
             __syncthreads();
-            if (tid < 27 && ((touched >> tid) & 1)) {
-                int bi = t.bi - 1 + tid / 9, bj = t.bj - 1 + (tid / 3) % 3, bk = t.bk - 1 + tid % 3;
+            if (tid < 8 && ((touched >> tid) & 1)) {
+                int bi = t.bi + (tid >> 2), bj = t.bj + ((tid >> 1) & 1), bk = t.bk + (tid & 1);
                 mark_brick(a.act, a.par, e.bofs + (bi * e.nb + bj) * e.nb + bk);
             }
         }
@@ -352,7 +359,7 @@ __global__ __launch_bounds__(256) void k_tiled(Dev d, TiledArgs a)
     }
     if (G2P) advance_end_of_substep(d);
     // the tail ends a call: both active lists start empty at the next head
-    if (MODE == 2 && blockIdx.x == 0 && tid < 2) gstore(a.act.count + tid, 0);
+    if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.count) gstore(a.act.count + tid, 0);
 }
 
 // Grid operation over the active node bricks of list `par`: one wavefront
@@ -380,19 +387,27 @@ __global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par
     if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.count + (par ^ 1), 0);
 }
 
+template <int MODE>
+static void launch_mode(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
+{
+    if (block == 64) hipLaunchKernelGGL((k_tiled<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
+    else if (block == 128) hipLaunchKernelGGL((k_tiled<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
+    else hipLaunchKernelGGL((k_tiled<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);
+}
+
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tiled<0>, dim3(nblocks), dim3(block), 0, st, d, a);
+    launch_mode<0>(d, a, block, nblocks, st);
 }
 
 void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tiled<1>, dim3(nblocks), dim3(block), 0, st, d, a);
+    launch_mode<1>(d, a, block, nblocks, st);
 }
 
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tiled<2>, dim3(nblocks), dim3(block), 0, st, d, a);
+    launch_mode<2>(d, a, block, nblocks, st);
 }
 
 int tiled_workgroups(int block)
@@ -402,7 +417,11 @@ int tiled_workgroups(int block)
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
     }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1>, block, 0) != hipSuccess || per < 1) per = 1;
+    hipError_t e;
+    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 1>, 64, 0);
+    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 2>, 128, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 4>, 256, 0);
+    if (e != hipSuccess || per < 1) per = 1;
     int g = per * cus;
     g -= g % NXCD;
     return g < NXCD ? NXCD : g;

@@ -29,6 +29,13 @@ void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes,
 void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st);
 void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
                        hipStream_t st);
+void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+                          const ActiveBuf &act, int block, int nblocks, hipStream_t st);
+void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+                          const ActiveBuf &act, int block, int nblocks, hipStream_t st);
+// scatter == 0: dst[c][q] = src[c][perm[q]]; scatter != 0: dst[c][perm[q]] = src[c][q]
+void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter,
+                    hipStream_t st);
 void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st);
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
 void launch_fill_f64(double *p, int64_t n, hipStream_t st);

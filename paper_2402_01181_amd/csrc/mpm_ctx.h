@@ -78,7 +78,7 @@ struct mpm_ctx {
         float *ckpt_state = nullptr;        // [n_ckpt][24][ntot], original order
         mpm::ToolDev *ckpt_tools = nullptr; // [n_ckpt][slots]
         int32_t *ckpt_step = nullptr;       // [n_ckpt][n_envs]
-        float *seg_state = nullptr;         // [k][24][ntot]
+        float *seg_state = nullptr;         // [k + 1][24][ntot] state at each substep start
         mpm::ToolDev *seg_tools = nullptr;  // [k][slots]
         float4 *seg_P = nullptr, *seg_V = nullptr;   // [k][total_nodes]
         mpm::ContactCode *seg_dec = nullptr;         // [k][total_nodes]
@@ -87,7 +87,10 @@ struct mpm_ctx {
         int32_t *work_step = nullptr;
         uint32_t *work_status = nullptr;
         mpm::AdjBuf adj{};
-        float *adj_state = nullptr;         // [24][ntot] (xb, vb, Cb, Fb)
+        float *adj_state = nullptr;         // [24][ntot] (xb, vb, Cb, Fb), original order
+        float *adj_slot = nullptr;          // [24][ntot] the same in a segment's sorted slot order
+        int32_t *perm = nullptr;            // [ntot] sorted slot -> original index of the current segment
+        int32_t *iota = nullptr;            // [ntot] identity
         int len = 0;                        // recorded substeps
     } tape;
     size_t tool_slots() const { return (size_t)n_envs * (max_tools > 0 ? max_tools : 1); }

@@ -33,9 +33,9 @@ struct ActiveBuf {
     const int32_t *env_bofs;  // [n_envs + 1]
 };
 
-// Tile geometry: brick of 4^3 cells plus a one-cell margin on each side and
-// the 2-node stencil reach: 8 nodes per axis.
-constexpr int TILE = 8;
+// Tile geometry: the nodes reached by the stencils of a brick of 4^3 cells
+// (bases 4B..4B+3, offsets 0..2): 6 nodes per axis.
+constexpr int TILE = 6;
 constexpr int TILE_NODES = TILE * TILE * TILE;
 
 struct TiledArgs {
