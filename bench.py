@@ -118,6 +118,29 @@ def measure_forms(torch, L, Sim, opts, batched_steps=40, adj_steps=200):
     return out
 
 
+def stored_traffic(config: str, kernel: str, options) -> float | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when there is none or the kernels or options differ from the ones
+    the counters were taken with."""
+    from paper_2402_01181_amd.build import source_hash
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_hash():
+        return None
+    from paper_2402_01181_amd import _lib as L
+    shape = (L.OPT_SCHEME, L.OPT_SORT_EVERY, L.OPT_BLOCK, L.OPT_ITEM, L.OPT_PERSISTENT)
+    mine = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in options.items()}}
+    theirs = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in t.get("options", {}).items()}}
+    if any(mine[k] != theirs[k] for k in shape):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_dispatch"])
+
+
 def cpu_baseline(scene, substeps: int):
     """The FP64 oracle as it stands, serial, on the first `substeps` substeps of
     environment 0 of the same scene."""
@@ -144,6 +167,7 @@ def main():
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--item", type=int, default=None)
     ap.add_argument("--graph", type=int, default=None)
+    ap.add_argument("--persistent", type=int, default=None)
     ap.add_argument("--cpu-substeps", type=int, default=None,
                     help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -173,6 +197,7 @@ def main():
     if args.block: opts[L.OPT_BLOCK] = args.block
     if args.item: opts[L.OPT_ITEM] = args.item
     if args.graph is not None: opts[L.OPT_GRAPH] = args.graph
+    if args.persistent is not None: opts[L.OPT_PERSISTENT] = args.persistent
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -215,7 +240,11 @@ def main():
         dom = max(rep, key=lambda k: rep[k][0])
         t_ms, n_launch = rep[dom]
         avg_s = t_ms / n_launch * 1e-3
-        if dom.startswith("fused"):
+        if dom.startswith("persistent"):
+            # one launch runs a whole run of substeps between sorts
+            per_launch = (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) * (
+                rep.get("persistent_tiled", (0, 1))[1] and K / rep["persistent_tiled"][1])
+        elif dom.startswith("fused"):
             per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_FUSED
         elif dom.startswith("grid"):
             per_launch = nodes * BYTES_PER_NODE_GRID
@@ -223,7 +252,7 @@ def main():
             per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
         achieved = per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(args.config, dom, sim.options),
                     "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
         print(f"# kernels: " + ", ".join(f"{k} {v['avg_us']:.2f}us x{v['launches']}" for k, v in kernels.items()),
               file=sys.stderr, flush=True)

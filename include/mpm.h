@@ -84,7 +84,9 @@ enum {
     MPM_OPT_SORT_EVERY = 1,   /* counting-sort particles by grid brick every k substeps (>= 1) */
     MPM_OPT_BLOCK = 2,        /* threads per workgroup of the tiled particle kernels: 64, 128, 256 */
     MPM_OPT_GRAPH = 3,        /* 1: mpm_substep replays an internally captured hipGraph */
-    MPM_OPT_PERSISTENT = 4,   /* 1: one persistent kernel per call with grid barriers */
+    MPM_OPT_PERSISTENT = 4,   /* tiled scheme, 1: each run of up to sort_every substeps is one persistent
+                                 kernel (grid operation and particle pass separated by grid barriers with
+                                 a bounded spin; a timeout sets MPM_FLAG_BARRIER_TIMEOUT) */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
     MPM_OPT_ITEM = 6          /* tiled scheme: max particles per work item, multiple of 64 in [64, 4096] */
 };

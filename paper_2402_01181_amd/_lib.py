@@ -22,6 +22,9 @@ CONTACT_SLIP, CONTACT_STICKY = 0, 1
 STAGE_P2G, STAGE_GRID, STAGE_G2P = 0, 1, 2
 OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM = range(7)
 SCHEME_DIRECT, SCHEME_TILED = 0, 1
+# option values a new context starts with
+OPT_DEFAULTS = {OPT_SCHEME: SCHEME_TILED, OPT_SORT_EVERY: 16, OPT_BLOCK: 256, OPT_GRAPH: 0, OPT_PERSISTENT: 0,
+                OPT_ITEM: 512}
 
 EXPORTS = ["mpm_workspace_size", "mpm_create", "mpm_destroy", "mpm_set_tool", "mpm_set_option",
            "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error",

@@ -1,8 +1,9 @@
 """Autotuner for the tiled scheme's launch shapes.
 
 Searches, in stages, the workgroup size (MPM_OPT_BLOCK), the particles per
-work item (MPM_OPT_ITEM), the sort interval (MPM_OPT_SORT_EVERY) and graph
-replay (MPM_OPT_GRAPH) for a scene, timing short runs with HIP events on the
+work item (MPM_OPT_ITEM), the sort interval (MPM_OPT_SORT_EVERY), and the
+persistent kernel (MPM_OPT_PERSISTENT) with or without graph replay
+(MPM_OPT_GRAPH) for a scene, timing short runs with HIP events on the
 stream the library launches on.  Every setting gives the same results up to
 float accumulation order, so the tuner only compares time.  Results are cached
 in a JSON file keyed by device, HIP version and workload shape.
@@ -43,8 +44,8 @@ def _time(sim: Sim, substeps: int, warmup: int) -> float:
 
 
 def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = CACHE,
-             blocks=(64, 128, 256), items=(128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
-             graph=(0, 1), verbose: bool = False) -> Dict[int, int]:
+             blocks=(64, 128, 256), items=(64, 128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
+             graph=(0, 1), persistent=(0, 1), verbose: bool = False) -> Dict[int, int]:
     """Best options {MPM_OPT_*: value} for this scene (tiled scheme)."""
     key = workload_key(scene)
     table = {}
@@ -58,13 +59,17 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
 
     sim = Sim(scene, options={L.OPT_SCHEME: L.SCHEME_TILED})
     best = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: 256, L.OPT_ITEM: 512, L.OPT_SORT_EVERY: 16,
-            L.OPT_GRAPH: 0}
+            L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0}
     log: List[dict] = []
 
     def trial(opts):
         for k, v in opts.items():
             sim.set_option(k, v)
         ms = _time(sim, substeps, warmup)
+        if any(sim.read(L.F_STATUS, e) for e in range(sim.n_envs)):
+            # a flagged run (e.g. a barrier timeout) is not a candidate; start over
+            ms = float("inf")
+            sim.reset()
         log.append({"options": {str(k): v for k, v in opts.items()}, "ms_per_substep": ms})
         if verbose:
             print(f"  autotune {opts} -> {ms * 1e3:.1f} us/substep", flush=True)
@@ -81,7 +86,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
 
     stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i} for b in blocks for i in items if i >= b])
     stage([{L.OPT_SORT_EVERY: k} for k in sort_every])
-    stage([{L.OPT_GRAPH: g} for g in graph])
+    stage([{L.OPT_PERSISTENT: p, L.OPT_GRAPH: g} for p in persistent for g in graph])
     sim.close()
     if cache:
         os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -38,6 +38,20 @@ def _compile(src: str) -> str:
     return obj
 
 
+def source_hash() -> str:
+    """SHA-256 over the HIP sources, their headers and the public header, in
+    name order: identifies the kernels a stored profile was taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")))
+    files.append(os.path.join(INCLUDE, "mpm.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))

@@ -71,6 +71,8 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.act.stride = s.total_bricks;
     c.env_bofs = cv.take<int32_t>(s.n_envs + 1);
     c.act.env_bofs = c.env_bofs;
+    c.barrier.count = cv.take<unsigned>(1);
+    c.barrier.gen = cv.take<unsigned>(1);
     // adjoint tape
     if (s.max_tape > 0) {
         const size_t st24 = (size_t)24 * s.ntot;
@@ -115,7 +117,7 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.list, c.act.count, c.env_bofs, c.act.env_bofs};
+                       c.act.list, c.act.count, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
     for (const void *q : p)
         if (!q) return false;
     if (c.max_tape > 0) {
@@ -288,6 +290,30 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
     }
     // substep i: P2G appends to active list i&1, its grid operation consumes it
     timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, nb, st); });
+    if (c->persistent) {
+        if (c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
+        const int pb = c->persistent_blocks;
+        if (pb > 0) {
+            // runs of up to sort_every substeps, one persistent launch each, sorts in between
+            for (int done = 0; done < n;) {
+                if (done > 0) {
+                    sort_into_alt(c, st);
+                    in = c->alt;
+                }
+                const int m = std::min(n - done, c->sort_every);
+                const int tail = done + m == n;
+                TiledArgs first = tiled_args(c, in, A, 0), rest = tiled_args(c, A, A, 0);
+                timed(c, st, PK_FILL, [&] { launch_fill_u32(c->barrier.count, 1, 0u, st); });
+                timed(c, st, PK_PERSISTENT, [&] {
+                    launch_persistent(d, first, rest, m, done & 1, tail, c->barrier, c->spin_limit, c->block, pb, st);
+                });
+                in = A;
+                done += m;
+                c->since_sort = m;
+            }
+            return;
+        }
+    }
     for (int i = 0; i < n; ++i) {
         timed(c, st, PK_GRID_ACTIVE, [&] { launch_grid_active(d, c->act, i & 1, grid_blocks(c), st); });
         if (i == n - 1) {
@@ -323,7 +349,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
     GraphEntry *ge = nullptr;
     for (auto &g : c->graphs)
         if (g.n == n && g.scheme == c->scheme && g.block == c->block && g.item == c->item &&
-            g.sort_every == c->sort_every)
+            g.sort_every == c->sort_every && g.persistent == c->persistent)
             ge = &g;
     if (!ge) {
         if (c->scheme == MPM_SCHEME_TILED && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -336,6 +362,8 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
         if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         GraphEntry g;
         g.n = n; g.scheme = c->scheme; g.block = c->block; g.item = c->item; g.sort_every = c->sort_every;
+        g.persistent = c->persistent;
+        if (c->persistent && c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -655,6 +683,8 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         launch_fill_f4(c->gV, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.count), 2, 0u, st);
+        launch_fill_u32(c->barrier.count, 1, 0u, st);
+        launch_fill_u32(c->barrier.gen, 1, 0u, st);
         if ((e2 = hipGetLastError()) != hipSuccess) return cleanup_fail(e2, "init kernels");
         if ((e2 = hipStreamSynchronize(st)) != hipSuccess) return cleanup_fail(e2, "create sync");
         *out = c;
@@ -724,6 +754,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         if (value != 64 && value != 128 && value != 256) return fail(c, MPM_E_ARG, "block must be 64, 128 or 256");
         c->block = value;
         c->tiled_blocks = 0;
+        c->persistent_blocks = -1;
         return MPM_OK;
     case MPM_OPT_ITEM:
         if (value < 64 || value > 4096 || value % 64) return fail(c, MPM_E_ARG, "item size must be a multiple of 64 in [64, 4096]");
@@ -733,8 +764,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         c->use_graph = value != 0;
         return MPM_OK;
     case MPM_OPT_PERSISTENT:
-        if (value) return fail(c, MPM_E_UNSUPPORTED, "persistent kernel not available");
-        c->persistent = 0;
+        c->persistent = value != 0;
         return MPM_OK;
     case MPM_OPT_SPIN_LIMIT:
         if (value < 1) return fail(c, MPM_E_ARG, "spin limit must be > 0");

@@ -453,7 +453,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
 {
     constexpr int T = 64 * W;
     __shared__ float4 tv[TILE_NODES];
-    __shared__ float4 tp[W * TILE_NODES];
+    __shared__ float4 tp[2 * W * TILE_NODES];
     __shared__ Payload pay[T];
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int half = lane >> 5, o = lane & 31;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
         const Tile t = make_tile(d, ta.act, item.x, e);
         for (int n = tid; n < TILE_NODES; n += T) {
             int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
-            for (int w = 0; w < W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int w = 0; w < 2 * W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
             float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
             if (i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
             tv[n] = V;
@@ -575,9 +575,10 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float4 *mytile = tp + wave * TILE_NODES;
-            for (int r = 0; r < 32; ++r) {
-                const Payload &P = pay[wave * 64 + half * 32 + r];
+            float4 *mytile = tp + (2 * wave + half) * TILE_NODES;
+            const int n_w = min(64, max(0, item.y + item.z - (chunk + wave * 64)));
+            for (int r = 0; 2 * r < n_w; ++r) {
+                const Payload &P = pay[wave * 64 + 2 * r + half];
                 const int pb = __float_as_int(P.mv_bits.w);
                 const bool act = node_lane && (pb & PAY_VALID);
                 float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -594,15 +595,9 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
                     if (pb & PAY_IN_TILE)
                         l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
                 }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    if (half == h && l >= 0) {
-                        float4 old = mytile[l];
-                        mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (l >= 0) {
+                    float4 old = mytile[l];
+                    mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
                 }
                 if (act && l < 0) {
                     float *g = reinterpret_cast<float *>(a.gVb + node_id(e, b0 + o0, b1 + o1, b2 + o2));
@@ -616,7 +611,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
         for (int n = tid; n < TILE_NODES; n += T) {
             float4 sum = tp[n];
 #pragma unroll
-            for (int w = 1; w < W; ++w) {
+            for (int w = 1; w < 2 * W; ++w) {
                 float4 q4 = tp[w * TILE_NODES + n];
                 sum.x += q4.x; sum.y += q4.y; sum.z += q4.z; sum.w += q4.w;
             }

@@ -23,15 +23,34 @@ __device__ __forceinline__ int particle_brick(const EnvDev &e, float x0, float x
     return e.bofs + (b[0] * e.nb + b[1]) * e.nb + b[2];
 }
 
+// Brick key and rank of each particle.  Particles arrive mostly in brick
+// order (from the previous sort), so a wavefront holds few distinct bricks:
+// the lanes of one brick take their ranks from a single counter increment
+// made by the lowest of them.
 __global__ __launch_bounds__(256) void k_brick_count(Dev d, SortBuf s)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.ntot) return;
-    const EnvDev e = load_env(d.env + env_of_particle(d, q));
+    const int q = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+    const bool valid = q < d.ntot;
     const int N = d.ntot;
-    int b = particle_brick(e, d.x[q], d.x[N + q], d.x[2 * N + q]);
-    s.key[q] = b;
-    s.rank[q] = atomicAdd(&s.count[b].x, 1);
+    int b = -1;
+    if (valid) {
+        const EnvDev e = load_env(d.env + env_of_particle(d, q));
+        b = particle_brick(e, gload(d.x + q), gload(d.x + N + q), gload(d.x + 2 * N + q));
+        gstore(s.key + q, b);
+    }
+    unsigned long long pending = __ballot(valid);
+    int rank = 0;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int kb = __shfl(b, leader);
+        const unsigned long long same = __ballot(valid && b == kb);
+        int base = 0;
+        if (lane == leader) base = gatomic_add(&s.count[kb].x, (int)__popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane) & 1ull) rank = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    if (valid) gstore(s.rank + q, rank);
 }
 
 // Block-wide exclusive scan of int2 over 256 threads x 4 elements.

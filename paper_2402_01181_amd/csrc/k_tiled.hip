@@ -126,26 +126,33 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
 //
 // W wavefronts per workgroup.  Pass 1 (lane = particle): G2P from the LDS
 // velocity tile, F update, advection, stress and the P2G payload.  Pass 2
-// (lane = stencil node): each wavefront walks its 64 payloads two at a time,
-// lanes 0-26 on one particle's 27 nodes and lanes 32-58 on another's, and adds
-// the contributions to its own LDS tile with plain read-modify-write; the two
-// half-waves' updates are issued one after the other so none is lost.  (LDS
-// float atomics run at about 1/3 lane per clock per CU on this chip, far
-// below plain LDS traffic.)  The W tiles are summed and flushed to the global
-// grid with one float atomic per component per non-empty node.
+// (lane = stencil node): each wavefront walks its payloads two at a time,
+// lanes 0-26 on particle 2r's 27 nodes and lanes 32-58 on particle 2r+1's,
+// and each half-wave adds its contributions to its own LDS tile with plain
+// read-modify-write (its 27 lanes touch 27 distinct nodes).  LDS float
+// atomics run at about 1/3 lane per clock per CU on this chip, far below
+// plain LDS traffic.  The 2W tiles are summed and flushed to the global grid
+// with one float atomic per component per non-empty node.
+template <int W>
+struct TiledShared {
+    float4 tv[TILE_NODES];            // node velocities
+    float4 tp[2 * W * TILE_NODES];    // per-half-wave (m, mv) tiles
+    Payload pay[64 * W];
+    int touched;
+};
+
 template <int MODE, int W>
-__global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
+__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W> &sh)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1;
     constexpr int T = 64 * W;
-    __shared__ float4 tv[G2P ? TILE_NODES : 1];          // node velocities
-    __shared__ float4 tp[P2G ? W * TILE_NODES : 1];      // per-wave (m, mv) tiles
-    __shared__ Payload pay[P2G ? T : 1];
-    __shared__ int touched;
+    float4 *tv = sh.tv, *tp = sh.tp;
+    Payload *pay = sh.pay;
+    int &touched = sh.touched;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = gload(a.totals).y;
-    // node-pass lane roles: half-wave h takes the particle 32 h + r of each pair r
+    // node-pass lane roles: half-wave h takes particle 2 r + h of pair r, lane o < 27 one stencil node
     const int half = lane >> 5, o = lane & 31;
     const bool node_lane = o < 27;
     const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
         for (int n = tid; n < TILE_NODES; n += T) {
             int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
             if (P2G)
-                for (int w = 0; w < W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int w = 0; w < 2 * W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (G2P) {
                 int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                 float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -280,9 +287,10 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // ---- pass 2: lane = stencil node, two particles per step
-                float4 *mytile = tp + wave * TILE_NODES;
-                for (int r = 0; r < 32; ++r) {
-                    const Payload &P = pay[wave * 64 + half * 32 + r];
+                float4 *mytile = tp + (2 * wave + half) * TILE_NODES;
+                const int n_w = min(64, max(0, item.y + item.z - (chunk + wave * 64)));
+                for (int r = 0; 2 * r < n_w; ++r) {
+                    const Payload &P = pay[wave * 64 + 2 * r + half];
                     const int pb = __float_as_int(P.mv_bits.w);
                     const bool act = node_lane && (pb & PAY_VALID);
                     float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -299,16 +307,10 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
                         if (pb & PAY_IN_TILE)
                             l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
                     }
-                    // half-wave 0 updates its nodes, then half-wave 1 (their nodes may coincide)
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (half == h && l >= 0) {
-                            float4 old = mytile[l];
-                            mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
+                    if (l >= 0) {
+                        float4 old = mytile[l];
+                        mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
                     }
                     if (act && l < 0) {
                         // stencil outside the tile: straight to the global grid
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
             for (int n = tid; n < TILE_NODES; n += T) {
                 float4 sum = tp[n];
 #pragma unroll
-                for (int w = 1; w < W; ++w) {
+                for (int w = 1; w < 2 * W; ++w) {
                     float4 q = tp[w * TILE_NODES + n];
                     sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
                 }
@@ -362,10 +364,17 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
     if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.count) gstore(a.act.count + tid, 0);
 }
 
+template <int MODE, int W>
+__global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
+{
+    __shared__ TiledShared<W> sh;
+    tiled_body<MODE, W>(d, a, sh);
+}
+
 // Grid operation over the active node bricks of list `par`: one wavefront
 // per 4^3 brick.  Writes V, clears P and the brick's flag; clears the other
 // list's count for the next P2G.
-__global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par)
+__device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int cnt = gload(a.count + par);
@@ -385,6 +394,66 @@ __global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par
         if (lane == 0) gstore(a.flag + b, 0);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.count + (par ^ 1), 0);
+}
+
+__global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par)
+{
+    grid_active_body(d, a, par);
+}
+
+// Grid-wide barrier for the persistent kernel: arrival counter plus a
+// generation word, agent-scope release/acquire around it, and a bounded spin.
+// Returns false (and the caller exits) if the spin limit is reached, which
+// happens only if not every workgroup is resident.
+__device__ __forceinline__ bool grid_sync(const GridBarrier &b, int spin_limit, int &ok_shared)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned g = __hip_atomic_load(gptr(b.gen), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned arrived = __hip_atomic_fetch_add(gptr(b.count), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        int ok = 1;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(gptr(b.count), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gptr(b.gen), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(gptr(b.gen), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins > spin_limit) { ok = 0; break; }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        ok_shared = ok;
+    }
+    __syncthreads();
+    return ok_shared != 0;
+}
+
+// Persistent form: for m substeps, the grid operation over the active list
+// and then the fused particle pass (or, for the last substep of a call, the
+// G2P-only tail), separated by grid barriers.  `first` reads the particles
+// from the sort destination, `rest` from the live buffers.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_persistent(Dev d, TiledArgs first, TiledArgs rest, int m, int par0,
+                                                       int tail_last, GridBarrier bar, int spin_limit)
+{
+    __shared__ TiledShared<W> sh;
+    __shared__ int ok;
+    if (threadIdx.x == 0) ok = 1;
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+        const int par = (par0 + i) & 1;
+        grid_active_body(d, first.act, par);
+        if (!grid_sync(bar, spin_limit, ok)) break;
+        TiledArgs a = i == 0 ? first : rest;
+        a.par = par ^ 1;
+        if (i == m - 1 && tail_last) tiled_body<2, W>(d, a, sh);
+        else tiled_body<1, W>(d, a, sh);
+        if (!grid_sync(bar, spin_limit, ok)) break;
+    }
+    if (!ok && threadIdx.x == 0)
+        for (int e = 0; e < d.n_envs; ++e) set_flag(d.status, e, MPM_FLAG_BARRIER_TIMEOUT);
 }
 
 template <int MODE>
@@ -408,6 +477,34 @@ void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
     launch_mode<2>(d, a, block, nblocks, st);
+}
+
+void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, int m, int par0, int tail_last,
+                       const GridBarrier &bar, int spin_limit, int block, int nblocks, hipStream_t st)
+{
+    if (block == 64)
+        hipLaunchKernelGGL((k_persistent<1>), dim3(nblocks), dim3(64), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+    else if (block == 128)
+        hipLaunchKernelGGL((k_persistent<2>), dim3(nblocks), dim3(128), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+    else
+        hipLaunchKernelGGL((k_persistent<4>), dim3(nblocks), dim3(256), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+}
+
+int persistent_workgroups(int block)
+{
+    int dev = 0, cus = 256, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
+    }
+    hipError_t e;
+    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<1>, 64, 0);
+    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<2>, 128, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<4>, 256, 0);
+    if (e != hipSuccess || per < 1) return 0;
+    int g = per * cus;
+    g -= g % NXCD;
+    return g;
 }
 
 int tiled_workgroups(int block)

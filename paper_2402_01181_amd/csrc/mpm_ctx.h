@@ -9,11 +9,13 @@
 // Kernel kinds timed by the built-in profiler (mpm_profile_*).
 enum ProfKind {
     PK_FILL = 0, PK_P2G_DIRECT, PK_GRID_DENSE, PK_G2P_DIRECT, PK_SORT, PK_P2G_TILED, PK_FUSED_TILED,
-    PK_G2P_TILED, PK_GRID_ACTIVE, PK_ADJ_G2P, PK_ADJ_GRID, PK_ADJ_P2G, PK_ADJ_MISC, PK_COUNT
+    PK_G2P_TILED, PK_GRID_ACTIVE, PK_ADJ_G2P, PK_ADJ_GRID, PK_ADJ_P2G, PK_ADJ_MISC, PK_PERSISTENT,
+    PK_COUNT
 };
 static const char *const PROF_NAMES[PK_COUNT] = {
     "fill", "p2g_direct", "grid_dense", "g2p_direct", "sort", "p2g_tiled", "fused_g2p_p2g_tiled",
-    "g2p_tiled", "grid_active", "adj_g2p", "adj_grid", "adj_p2g", "adj_misc"};
+    "g2p_tiled", "grid_active", "adj_g2p", "adj_grid", "adj_p2g", "adj_misc",
+    "persistent_tiled"};
 
 struct Profiler {
     bool on = false;
@@ -27,7 +29,7 @@ struct Profiler {
 // One captured call of n substeps (MPM_OPT_GRAPH) and the host-side
 // sequencing state that call leaves behind.
 struct GraphEntry {
-    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0;
+    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0;
     hipGraphExec_t exec = nullptr;
     int since_sort_after = 0;
 };
@@ -46,7 +48,7 @@ struct mpm_ctx {
     hipStream_t stream0 = nullptr;
     // options
     int scheme = MPM_SCHEME_TILED, sort_every = 16, block = 256, item = 512, use_graph = 0, persistent = 0;
-    int spin_limit = 1 << 26;
+    int spin_limit = 1 << 22;
     // device buffers carved from the caller's workspace
     mpm::EnvDev *env = nullptr;
     int32_t *env_pofs = nullptr;
@@ -69,6 +71,8 @@ struct mpm_ctx {
     int items_P = 0;
     int since_sort = 0;
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
+    int persistent_blocks = -1;      // co-resident workgroups of the persistent kernel (0: unavailable)
+    mpm::GridBarrier barrier{};
     // host mirror of the tool slots
     std::vector<mpm::ToolDev> tools_h;
     Profiler prof;

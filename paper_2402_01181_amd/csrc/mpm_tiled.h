@@ -49,6 +49,12 @@ struct TiledArgs {
     int par;                              // active list this kernel's P2G appends to
 };
 
+// Grid-wide barrier state of the persistent kernel (reset before each launch).
+struct GridBarrier {
+    unsigned *count;
+    unsigned *gen;
+};
+
 void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
                  hipStream_t st);
 size_t sort_chunk_count(int total_bricks);
@@ -60,5 +66,11 @@ void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, 
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
 int tiled_workgroups(int block);
+// Persistent kernel: m substeps of (grid operation, fused particle pass), the
+// last one a G2P-only tail if tail_last; nblocks must not exceed
+// persistent_workgroups(block) (all workgroups co-resident), 0 if unknown.
+void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, int m, int par0, int tail_last,
+                       const GridBarrier &bar, int spin_limit, int block, int nblocks, hipStream_t st);
+int persistent_workgroups(int block);
 
 }  // namespace mpm

@@ -242,3 +242,50 @@ def test_batched_teacher_forced_parity(gpu, orc):
         b.step(1)
         for e, ref in enumerate(refs):
             _compare_particles(ref, b, env=e, what=f"substep {s} env {e}")
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_persistent_matches_eager(gpu, orc, use_graph):
+    """MPM_OPT_PERSISTENT: runs of up to sort_every substeps in one kernel with
+    grid barriers; 3 calls of 40 substeps (runs of 16, 16, 8) against the
+    same calls launched per phase.  No barrier may time out."""
+    Sim, L = gpu
+    _say(f"persistent (graph={use_graph}) vs eager: slab 30K, 3 x 40 substeps")
+    sc = scenes.slab_scene(seed=3, substeps=120)
+    opts = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 16}
+    eager = Sim(sc, options=dict(opts))
+    pers = Sim(sc, options={**opts, L.OPT_PERSISTENT: 1, L.OPT_GRAPH: use_graph})
+    for r in range(3):
+        eager.step(40)
+        pers.step(40)
+        assert pers.read(L.F_STATUS) == 0, "barrier timeout or other status flag"
+        xe, ve, _, Fe = eager.particles()
+        xp, vp, _, Fp = pers.particles()
+        ex = np.abs(xe - xp).max()
+        ev = rel_err(vp, ve, FLOORS["v"])
+        eF = rel_err(Fp, Fe, FLOORS["F"])
+        _say(f"  call {r}: max |dx| = {ex:.2e}, v err = {ev:.2e}, F err = {eF:.2e}")
+        assert ex <= 1e-5 and ev <= 1e-3 and eF <= 1e-3
+        assert pers.read(L.F_STEP) == 40 * (r + 1)
+        np.testing.assert_array_equal(pers.read(L.F_TOOL_T), eager.read(L.F_TOOL_T))
+
+
+def test_persistent_batched_and_single_substeps(gpu, orc):
+    """Persistent form on a batch of environments, with calls of 1, 7 and
+    22 substeps (a run of one substep, runs ending in the G2P tail)."""
+    Sim, L = gpu
+    sc = _small_batch(seed=5, n_envs=6)
+    _say(f"persistent batched: {len(sc.envs)} envs, calls 1, 7, 22")
+    eager = Sim(sc, options={L.OPT_SORT_EVERY: 8})
+    pers = Sim(sc, options={L.OPT_SORT_EVERY: 8, L.OPT_PERSISTENT: 1})
+    for n in (1, 7, 22):
+        eager.step(n)
+        pers.step(n)
+    for e in range(len(sc.envs)):
+        xe = eager.particles(e)[0]
+        xp = pers.particles(e)[0]
+        err = np.abs(xe - xp).max()
+        _say(f"  env {e}: max |dx| = {err:.2e}")
+        assert err <= 1e-5
+        assert pers.read(L.F_STATUS, e) == 0 and pers.read(L.F_STEP, e) == 30
+        np.testing.assert_array_equal(pers.read(L.F_TOOL_T, e), eager.read(L.F_TOOL_T, e))
