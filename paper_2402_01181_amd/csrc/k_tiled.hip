@@ -120,6 +120,72 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
     for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * C[c];
 }
 
+// Per-particle P2G inputs handed from the particle pass to the node pass of
+// the same wavefront (64 bytes, four LDS vector reads): fx and a packed key,
+// m v, and A dx row by row.  The particle mass is uniform per environment.
+struct Payload4 {
+    float4 fk;         // fx0, fx1, fx2, key
+    float4 q1;         // m v, A00
+    float4 q2;         // A01, A02, A10, A11
+    float4 q3;         // A12, A20, A21, A22
+};
+// key: bit 0 valid; bit 1 stencil inside the tile, then bits 2.. hold the
+// tile index of the stencil base; otherwise bits 2-11, 12-21, 22-31 hold the
+// absolute base (grids are at most 512 nodes per axis).
+constexpr int KEY_VALID = 1, KEY_IN_TILE = 2;
+
+__device__ __forceinline__ int key_in_tile(int l0, int l1, int l2)
+{
+    return KEY_VALID | KEY_IN_TILE | (((l0 * TILE + l1) * TILE + l2) << 2);
+}
+__device__ __forceinline__ int key_global(const int b[3])
+{
+    return KEY_VALID | (b[0] << 2) | (b[1] << 12) | (b[2] << 22);
+}
+
+// Node brick (bi + di, bj + dj, bk + dk), di, dj, dk in {-1, 0, 1}, as a bit
+// of the 27-bit touched mask of a tile.
+__device__ __forceinline__ int touched_bit(int di, int dj, int dk) { return 1 << (((di + 1) * 3 + dj + 1) * 3 + dk + 1); }
+
+// FP32 J - 1 from H (terms of order |H|, |H|^2, |H|^3: nothing cancels).
+__device__ __forceinline__ float jm1_f(const float H[9])
+{
+    float tr = H[0] + H[4] + H[8];
+    float m2 = fmaf(H[0], H[4], -H[1] * H[3]) + fmaf(H[0], H[8], -H[2] * H[6]) + fmaf(H[4], H[8], -H[5] * H[7]);
+    float c0 = fmaf(H[4], H[8], -H[5] * H[7]), c1 = fmaf(H[3], H[8], -H[5] * H[6]), c2 = fmaf(H[3], H[7], -H[4] * H[6]);
+    float dt = fmaf(H[0], c0, fmaf(-H[1], c1, H[2] * c2));
+    return tr + m2 + dt;
+}
+
+// J <= J_MIN?  Decided in FP64 whenever the FP32 value is within reach of
+// the threshold.
+__device__ __forceinline__ bool inverted_f(const float H[9], float jm1)
+{
+    if (jm1 > -0.999f) return false;
+    return inverted_h(H);
+}
+
+// A = -dt V0 (4/dx^2) tau(F) + m C with tau = mu (H + H^T + H H^T) + lam ln J I
+// (the MLS force folded into the affine term); ln J = log1p(J - 1).
+__device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, const float H[9], float jm1,
+                                                bool inv, const float C[9], float mu, float lam, float m, float V0,
+                                                float A[9])
+{
+    const float p = lam * (inv ? -13.815510557964274f : log1pf(jm1));   // ln J_MIN = ln 1e-6
+    const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            float s = H[3 * a + b] + H[3 * b + a];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s = fmaf(H[3 * a + c], H[3 * b + c], s);
+            float t = k * (mu * s + (a == b ? p : 0.0f));
+            A[3 * a + b] = fmaf(m, C[3 * a + b], t);
+            if (a != b) A[3 * b + a] = fmaf(m, C[3 * b + a], t);
+        }
+}
+
 // MODE 0: P2G only (head of a call; reads x, v, C, H).
 // MODE 1: fused G2P(s) + F update + advection + P2G(s+1) (reads/writes x, H).
 // MODE 2: G2P only (tail of a call; writes x, v, C, H).
@@ -137,8 +203,8 @@ template <int W>
 struct TiledShared {
     float4 tv[TILE_NODES];            // node velocities
     float4 tp[2 * W * TILE_NODES];    // per-half-wave (m, mv) tiles
-    Payload pay[64 * W];
-    int touched;
+    Payload4 pay[64 * W];
+    int touched;                      // node bricks around the tile that received mass (27 bits)
 };
 
 template <int MODE, int W>
@@ -147,7 +213,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1;
     constexpr int T = 64 * W;
     float4 *tv = sh.tv, *tp = sh.tp;
-    Payload *pay = sh.pay;
+    Payload4 *pay = sh.pay;
     int &touched = sh.touched;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -156,12 +222,32 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     const int half = lane >> 5, o = lane & 31;
     const bool node_lane = o < 27;
     const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
+    const int lo = (o0 * TILE + o1) * TILE + o2;
+    // quadratic B-spline of node offset o_a as alpha (fx - c)^2 + gamma (fx in [0.5, 1.5))
+    float wc[3], wa[3], wg[3];
+    {
+        const int oo[3] = {o0, o1, o2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            wc[k] = 1.5f - 0.5f * oo[k];
+            wa[k] = oo[k] == 1 ? -1.0f : 0.5f;
+            wg[k] = oo[k] == 1 ? 0.75f : 0.0f;
+        }
+    }
     int first, stride, end;
     item_range(nitems, first, stride, end);
     for (int it = first; it < end; it += stride) {
         const int4 item = gload(a.items + it);
         EnvDev e;
         const Tile t = make_tile(d, a.act, item.x, e);
+        float mu = 0.f, lam = 0.f, m = 0.f, V0 = 0.f;
+        if (P2G) {
+            const float *mat = d.material + 4 * t.env;
+            const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2);
+            V0 = gload(mat + 3);
+            lame(E, nu, mu, lam);
+            m = rho * V0;
+        }
         for (int n = tid; n < TILE_NODES; n += T) {
             int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
             if (P2G)
@@ -179,7 +265,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
             // ---- pass 1: lane = particle
             const int p = chunk + tid;
-            int bits = 0;
+            int key = 0;
             if (p < item.y + item.z) {
                 float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
                 float H[9], v[3], C[9];
@@ -204,26 +290,41 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     }
                     if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
                 } else {
+                    float jm1 = 0.f;
+                    bool inv = false;
                     if (G2P) {
                         int l0, l1, l2;
                         if (stencil_in_tile(t, s, l0, l1, l2)) {
+                            // v = sum w V, B = sum w V (o - fx)^T, summed over o2 first
+                            float q[3][3], w2q[3];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                q[0][k] = k - s.fx[0]; q[1][k] = k - s.fx[1]; q[2][k] = k - s.fx[2];
+                                w2q[k] = s.w[2][k] * q[2][k];
+                            }
                             float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                             v[0] = v[1] = v[2] = 0.f;
+                            const float4 *tb = tv + (l0 * TILE + l1) * TILE + l2;
 #pragma unroll
                             for (int a0 = 0; a0 < 3; ++a0)
 #pragma unroll
-                                for (int a1 = 0; a1 < 3; ++a1)
+                                for (int a1 = 0; a1 < 3; ++a1) {
+                                    float sx = 0.f, sy = 0.f, sz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
 #pragma unroll
                                     for (int a2 = 0; a2 < 3; ++a2) {
-                                        float4 V = tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2];
-                                        float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
-                                        float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                        float wx = w * V.x, wy = w * V.y, wz = w * V.z;
-                                        v[0] += wx; v[1] += wy; v[2] += wz;
-                                        B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
-                                        B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
-                                        B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
+                                        const float4 V = tb[(a0 * TILE + a1) * TILE + a2];
+                                        const float w2 = s.w[2][a2];
+                                        sx = fmaf(w2, V.x, sx); sy = fmaf(w2, V.y, sy); sz = fmaf(w2, V.z, sz);
+                                        ux = fmaf(w2q[a2], V.x, ux); uy = fmaf(w2q[a2], V.y, uy);
+                                        uz = fmaf(w2q[a2], V.z, uz);
                                     }
+                                    const float ww = s.w[0][a0] * s.w[1][a1];
+                                    const float w0q = ww * q[0][a0], w1q = ww * q[1][a1];
+                                    v[0] = fmaf(ww, sx, v[0]); v[1] = fmaf(ww, sy, v[1]); v[2] = fmaf(ww, sz, v[2]);
+                                    B[0] = fmaf(w0q, sx, B[0]); B[1] = fmaf(w1q, sx, B[1]); B[2] = fmaf(ww, ux, B[2]);
+                                    B[3] = fmaf(w0q, sy, B[3]); B[4] = fmaf(w1q, sy, B[4]); B[5] = fmaf(ww, uy, B[5]);
+                                    B[6] = fmaf(w0q, sz, B[6]); B[7] = fmaf(w1q, sz, B[7]); B[8] = fmaf(ww, uz, B[8]);
+                                }
                             const float cs = 4.0f * e.inv_dx;
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
@@ -234,7 +335,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                         x[1] += d.dt * v[1];
                         x[2] += d.dt * v[2];
                         update_h(H, C, d.dt);
-                        if (inverted_h(H)) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
+                        jm1 = jm1_f(H);
+                        inv = inverted_f(H, jm1);
+                        if (inv) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
                         if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) &&
                               isfinite(v[1]) && isfinite(v[2])))
                             set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
@@ -243,6 +346,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                         for (int c = 0; c < 3; ++c) v[c] = gload(a.vin + (size_t)c * N + p);
 #pragma unroll
                         for (int c = 0; c < 9; ++c) C[c] = gload(a.Cin + (size_t)c * N + p);
+                        jm1 = jm1_f(H);
+                        inv = inverted_f(H, jm1);
+                        if (inv) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
                     }
                     bool write_vc = MODE == 2;
                     if (P2G) {
@@ -253,16 +359,15 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                             set_flag(d.status, t.env, MPM_FLAG_OUT_OF_DOMAIN);
                             write_vc = true;
                         } else {
-                            float A[9], m;
-                            affine_with_stress(d, e, t.env, H, C, A, m);
+                            float A[9];
+                            affine_stress_f(d, e, H, jm1, inv, C, mu, lam, m, V0, A);
                             int l0, l1, l2;
-                            bits = PAY_VALID | (stencil_in_tile(t, s2, l0, l1, l2) ? PAY_IN_TILE : 0);
-                            Payload &P = pay[tid];
-                            P.f_m = make_float4(s2.fx[0], s2.fx[1], s2.fx[2], m);
-                            P.mv_bits = make_float4(m * v[0], m * v[1], m * v[2], __int_as_float(bits));
-                            P.a0 = make_float4(A[0] * e.dx, A[1] * e.dx, A[2] * e.dx, __int_as_float(s2.b[0]));
-                            P.a1 = make_float4(A[3] * e.dx, A[4] * e.dx, A[5] * e.dx, __int_as_float(s2.b[1]));
-                            P.a2 = make_float4(A[6] * e.dx, A[7] * e.dx, A[8] * e.dx, __int_as_float(s2.b[2]));
+                            key = stencil_in_tile(t, s2, l0, l1, l2) ? key_in_tile(l0, l1, l2) : key_global(s2.b);
+                            Payload4 &P = pay[tid];
+                            P.fk = make_float4(s2.fx[0], s2.fx[1], s2.fx[2], __int_as_float(key));
+                            P.q1 = make_float4(m * v[0], m * v[1], m * v[2], A[0] * e.dx);
+                            P.q2 = make_float4(A[1] * e.dx, A[2] * e.dx, A[3] * e.dx, A[4] * e.dx);
+                            P.q3 = make_float4(A[5] * e.dx, A[6] * e.dx, A[7] * e.dx, A[8] * e.dx);
                         }
                     }
                     if (G2P) {
@@ -281,7 +386,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 }
             }
             if (P2G) {
-                if (!bits) pay[tid].mv_bits.w = __int_as_float(0);
+                if (!key) pay[tid].fk.w = __int_as_float(0);
                 // payloads are read by other lanes of this wavefront only
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -290,39 +395,39 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 float4 *mytile = tp + (2 * wave + half) * TILE_NODES;
                 const int n_w = min(64, max(0, item.y + item.z - (chunk + wave * 64)));
                 for (int r = 0; 2 * r < n_w; ++r) {
-                    const Payload &P = pay[wave * 64 + 2 * r + half];
-                    const int pb = __float_as_int(P.mv_bits.w);
-                    const bool act = node_lane && (pb & PAY_VALID);
-                    float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    int l = -1, b0 = 0, b1 = 0, b2 = 0;
-                    if (act) {
-                        const float4 fm = P.f_m, mv = P.mv_bits, A0 = P.a0, A1 = P.a1, A2 = P.a2;
-                        b0 = __float_as_int(A0.w); b1 = __float_as_int(A1.w); b2 = __float_as_int(A2.w);
-                        const float q0 = o0 - fm.x, q1 = o1 - fm.y, q2 = o2 - fm.z;
-                        const float w = bspline2(q0) * bspline2(q1) * bspline2(q2);
-                        c4.x = w * fm.w;
-                        c4.y = w * (mv.x + A0.x * q0 + A0.y * q1 + A0.z * q2);
-                        c4.z = w * (mv.y + A1.x * q0 + A1.y * q1 + A1.z * q2);
-                        c4.w = w * (mv.z + A2.x * q0 + A2.y * q1 + A2.z * q2);
-                        if (pb & PAY_IN_TILE)
-                            l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
-                    }
-                    // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
-                    if (l >= 0) {
+                    const Payload4 &P = pay[wave * 64 + 2 * r + half];
+                    const float4 fk = P.fk;
+                    const int pk = __float_as_int(fk.w);
+                    if (!node_lane || !(pk & KEY_VALID)) continue;
+                    const float4 q1 = P.q1, q2 = P.q2, q3 = P.q3;
+                    const float t0 = fk.x - wc[0], t1 = fk.y - wc[1], t2 = fk.z - wc[2];
+                    const float w = fmaf(wa[0], t0 * t0, wg[0]) * fmaf(wa[1], t1 * t1, wg[1]) *
+                                    fmaf(wa[2], t2 * t2, wg[2]);
+                    const float d0 = o0 - fk.x, d1 = o1 - fk.y, d2 = o2 - fk.z;
+                    float4 c4;
+                    c4.x = w * m;
+                    c4.y = w * fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
+                    c4.z = w * fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
+                    c4.w = w * fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
+                    if (pk & KEY_IN_TILE) {
+                        // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
+                        const int l = (pk >> 2) + lo;
                         float4 old = mytile[l];
                         mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
-                    }
-                    if (act && l < 0) {
+                    } else {
                         // stencil outside the tile: straight to the global grid
-                        float *g = reinterpret_cast<float *>(d.gP + node_id(e, b0 + o0, b1 + o1, b2 + o2));
+                        const int b0 = (pk >> 2) & 1023, b1 = (pk >> 12) & 1023, b2 = (pk >> 22) & 1023;
+                        const int i = b0 + o0, j = b1 + o1, k = b2 + o2;
+                        float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
                         gatomic_add(g + 0, c4.x);
                         gatomic_add(g + 1, c4.y);
                         gatomic_add(g + 2, c4.z);
                         gatomic_add(g + 3, c4.w);
-                        if (o == 0) {
-                            int bb[3] = {b0, b1, b2};
-                            mark_stencil_bricks(a.act, a.par, e, bb);
-                        }
+                        const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
+                        if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1)
+                            atomicOr(&touched, touched_bit(di, dj, dk));
+                        else
+                            mark_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
                     }
                 }
             }
@@ -330,7 +435,6 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
 
         if (P2G) {
-            __syncthreads();
             // sum the wave tiles, flush non-empty nodes, remember the node bricks hit
             for (int n = tid; n < TILE_NODES; n += T) {
                 float4 sum = tp[n];
@@ -347,13 +451,12 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     gatomic_add(g + 1, sum.y);
                     gatomic_add(g + 2, sum.z);
                     gatomic_add(g + 3, sum.w);
-                    int bit = (((i >> 2) - t.bi) * 2 + ((j >> 2) - t.bj)) * 2 + ((k >> 2) - t.bk);
-                    atomicOr(&touched, 1 << bit);
+                    atomicOr(&touched, touched_bit((i >> 2) - t.bi, (j >> 2) - t.bj, (k >> 2) - t.bk));
                 }
             }
             __syncthreads();
-            if (tid < 8 && ((touched >> tid) & 1)) {
-                int bi = t.bi + (tid >> 2), bj = t.bj + ((tid >> 1) & 1), bk = t.bk + (tid & 1);
+            if (tid < 27 && ((touched >> tid) & 1)) {
+                const int bi = t.bi + tid / 9 - 1, bj = t.bj + (tid / 3) % 3 - 1, bk = t.bk + tid % 3 - 1;
                 mark_brick(a.act, a.par, e.bofs + (bi * e.nb + bj) * e.nb + bk);
             }
         }
