@@ -88,7 +88,7 @@ enum {
                                  kernel (grid operation and particle pass separated by grid barriers with
                                  a bounded spin; a timeout sets MPM_FLAG_BARRIER_TIMEOUT) */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
-    MPM_OPT_ITEM = 6          /* tiled scheme: max particles per work item, multiple of 64 in [64, 4096] */
+    MPM_OPT_ITEM = 6          /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
 };
 enum {
     MPM_SCHEME_DIRECT = 0,    /* one thread per particle, global float atomics, dense grid pass */
@@ -98,7 +98,8 @@ enum {
 typedef struct {
     int32_t n_envs;              /* >= 1 */
     const int32_t *n_particles;  /* host [n_envs], each >= 1 */
-    const int32_t *grid_n;       /* host [n_envs], multiple of 4, 8 <= n <= 512 */
+    const int32_t *grid_n;       /* host [n_envs], multiple of 4, 8 <= n <= 512; at most 2^30 nodes and
+                                    2^30 particles over all environments */
     float dt;                    /* substep length (s), > 0 */
     float gravity[3];            /* m/s^2 */
     int32_t bound;               /* boundary band width in nodes (sticky), >= 0 */

@@ -44,7 +44,7 @@ def _time(sim: Sim, substeps: int, warmup: int) -> float:
 
 
 def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = CACHE,
-             blocks=(64, 128, 256), items=(64, 128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
+             blocks=(64, 128, 256), items=(32, 64, 128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
              graph=(0, 1), persistent=(0, 1), verbose: bool = False) -> Dict[int, int]:
     """Best options {MPM_OPT_*: value} for this scene (tiled scheme)."""
     key = workload_key(scene)
@@ -84,7 +84,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
             scores.append((trial(opts), opts))
         best = min(scores, key=lambda t: t[0])[1]
 
-    stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i} for b in blocks for i in items if i >= b])
+    stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i} for b in blocks for i in items])
     stage([{L.OPT_SORT_EVERY: k} for k in sort_every])
     stage([{L.OPT_PERSISTENT: p, L.OPT_GRAPH: g} for p in persistent for g in graph])
     sim.close()

@@ -57,13 +57,14 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.alt.C = cv.take<float>((size_t)9 * s.ntot);
     c.alt.H = cv.take<float>((size_t)9 * s.ntot);
     c.alt.pid = cv.take<int32_t>(s.ntot);
-    c.sort.count = cv.take<int2>(s.total_bricks);
-    c.sort.offset = cv.take<int2>(s.total_bricks);
-    c.sort.chunk_sum = cv.take<int2>(sort_chunk_count(s.total_bricks));
+    c.sort.count = cv.take<int32_t>((size_t)s.total_bricks * 64);
+    c.sort.brick_count = cv.take<int32_t>(s.total_bricks);
+    c.sort.offset = cv.take<int2>((size_t)s.total_bricks * 64);
+    c.sort.chunk_sum = cv.take<int2>(sort_chunk_count((int64_t)s.total_bricks * 64));
     c.sort.totals = cv.take<int2>(1);
     c.sort.key = cv.take<int32_t>(s.ntot);
     c.sort.rank = cv.take<int32_t>(s.ntot);
-    c.max_items = (int64_t)s.total_bricks + s.ntot / 64 + 1;
+    c.max_items = (int64_t)s.total_bricks + s.ntot / 16 + 1;   // items of >= 16 particles
     c.sort.items = cv.take<int4>(c.max_items);
     c.act.flag = cv.take<int32_t>(s.total_bricks);
     c.act.list = cv.take<int32_t>((size_t)2 * s.total_bricks);
@@ -115,7 +116,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
 bool all_carved(const mpm_ctx &c)
 {
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
-                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.offset,
+                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
                        c.act.list, c.act.count, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
     for (const void *q : p)
@@ -155,7 +156,7 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
         bricks += (int64_t)(n / 4) * (n / 4) * (n / 4);
     }
     if (ntot > (1ll << 30)) { why = "too many particles (max 2^30)"; return false; }
-    if (bricks > (1ll << 30)) { why = "too many grid bricks"; return false; }
+    if (nodes > (1ll << 30)) { why = "too many grid nodes (max 2^30 over all environments)"; return false; }
     s.n_envs = d->n_envs;
     s.max_tools = d->max_tools;
     s.max_tape = d->max_tape_substeps;
@@ -757,7 +758,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         c->persistent_blocks = -1;
         return MPM_OK;
     case MPM_OPT_ITEM:
-        if (value < 64 || value > 4096 || value % 64) return fail(c, MPM_E_ARG, "item size must be a multiple of 64 in [64, 4096]");
+        if (value < 16 || value > 4096 || value % 16) return fail(c, MPM_E_ARG, "item size must be a multiple of 16 in [16, 4096]");
         c->item = value;
         return MPM_OK;
     case MPM_OPT_GRAPH:

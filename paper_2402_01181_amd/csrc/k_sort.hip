@@ -1,56 +1,68 @@
-// Counting sort of particles by grid brick (4x4x4 cells of the stencil base)
-// and the work-item list of the tiled scheme.  All kernels, no host sync.
+// Counting sort of particles by the cell of their stencil base, cells
+// numbered brick-major (so each 4x4x4-cell brick is contiguous and grouped
+// by cell inside), and the work-item list of the tiled scheme.  All kernels,
+// no host sync.
 //
-//   1. k_brick_count: brick of each particle; rank within the brick by an
-//      atomic counter (histogram).
-//   2. scan of (count, items) per brick, items = ceil(count / P).
+//   1. k_cell_count: cell of each particle; rank within the cell by an
+//      atomic counter (histogram), and particles per brick.
+//   2. scan of (particles, items) per cell, a brick's items = ceil(count / P)
+//      counted at its first cell.
 //   3. k_make_items: (brick, first slot, count) per item, brick-major order.
 //   4. k_sort_scatter: move particle state into its sorted slot.
 #include "mpm_tiled.h"
 
 namespace mpm {
 
-__device__ __forceinline__ int particle_brick(const EnvDev &e, float x0, float x1, float x2)
+// Cell key of a particle: brick-major number of the cell holding its
+// stencil base, clamped in floating point (NaN -> 0) so frozen particles go
+// to an edge cell.
+__device__ __forceinline__ int particle_cell(const EnvDev &e, float x0, float x1, float x2)
 {
-    int b[3];
+    int t[3];
     float xs[3] = {x0, x1, x2};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        // clamped in floating point (NaN -> 0): frozen particles go to an edge brick
-        float t = floorf(fminf(fmaxf(xs[a] * e.inv_dx - 0.5f, 0.0f), (float)(e.n - 3)));
-        b[a] = ((int)t) >> 2;
-    }
-    return e.bofs + (b[0] * e.nb + b[1]) * e.nb + b[2];
+    for (int a = 0; a < 3; ++a) t[a] = (int)floorf(fminf(fmaxf(xs[a] * e.inv_dx - 0.5f, 0.0f), (float)(e.n - 3)));
+    const int brick = e.bofs + ((t[0] >> 2) * e.nb + (t[1] >> 2)) * e.nb + (t[2] >> 2);
+    return brick * 64 + ((t[0] & 3) * 4 + (t[1] & 3)) * 4 + (t[2] & 3);
 }
 
-// Brick key and rank of each particle.  Particles arrive mostly in brick
-// order (from the previous sort), so a wavefront holds few distinct bricks:
-// the lanes of one brick take their ranks from a single counter increment
-// made by the lowest of them.
-__global__ __launch_bounds__(256) void k_brick_count(Dev d, SortBuf s)
+// Cell key and rank of each particle, and the particle count of every cell
+// and brick.  Particles arrive mostly in cell order (from the previous sort),
+// so a wavefront holds few distinct cells and bricks: the lanes of one cell
+// (brick) take their ranks from a single increment made by the lowest of them.
+__global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
     const bool valid = q < d.ntot;
     const int N = d.ntot;
-    int b = -1;
+    int key = -1;
     if (valid) {
         const EnvDev e = load_env(d.env + env_of_particle(d, q));
-        b = particle_brick(e, gload(d.x + q), gload(d.x + N + q), gload(d.x + 2 * N + q));
-        gstore(s.key + q, b);
+        key = particle_cell(e, gload(d.x + q), gload(d.x + N + q), gload(d.x + 2 * N + q));
+        gstore(s.key + q, key);
     }
+    const unsigned long long lower = (1ull << lane) - 1ull;
     unsigned long long pending = __ballot(valid);
     int rank = 0;
     while (pending) {
         const int leader = __builtin_ctzll(pending);
-        const int kb = __shfl(b, leader);
-        const unsigned long long same = __ballot(valid && b == kb);
+        const int kc = __shfl(key, leader);
+        const unsigned long long same = __ballot(valid && key == kc);
         int base = 0;
-        if (lane == leader) base = gatomic_add(&s.count[kb].x, (int)__popcll(same));
+        if (lane == leader) base = gatomic_add(s.count + kc, (int)__popcll(same));
         base = __shfl(base, leader);
-        if ((same >> lane) & 1ull) rank = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        if ((same >> lane) & 1ull) rank = base + (int)__popcll(same & lower);
         pending &= ~same;
     }
     if (valid) gstore(s.rank + q, rank);
+    const int brick = key >> 6;
+    pending = __ballot(valid);
+    while (pending) {
+        const int kb = __shfl(brick, __builtin_ctzll(pending));
+        const unsigned long long same = __ballot(valid && brick == kb);
+        if (lane == __builtin_ctzll(pending)) gatomic_add(s.brick_count + kb, (int)__popcll(same));
+        pending &= ~same;
+    }
 }
 
 // Block-wide exclusive scan of int2 over 256 threads x 4 elements.
@@ -75,8 +87,9 @@ __device__ int2 block_exclusive_scan(int2 v, int2 *sh, int2 &total)
     return make_int2(incl.x - v.x, incl.y - v.y);
 }
 
-// Per brick: items = ceil(count / P); local exclusive scan per chunk.
-__global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int nb, int P)
+// Per cell: (particles, items), the brick's items ceil(count / P) counted at
+// its first cell; local exclusive scan per chunk of cells.
+__global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int ncells, int P)
 {
     __shared__ int2 sh[SCAN_T];
     int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_E;
@@ -84,8 +97,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int nb, int P)
 #pragma unroll
     for (int i = 0; i < SCAN_E; ++i) {
         int k = base + i;
-        int c = k < nb ? s.count[k].x : 0;
-        v[i] = make_int2(c, (c + P - 1) / P);
+        int c = k < ncells ? gload(s.count + k) : 0;
+        int bc = (k < ncells && (k & 63) == 0) ? gload(s.brick_count + (k >> 6)) : 0;
+        v[i] = make_int2(c, (bc + P - 1) / P);
         sum = add2(sum, v[i]);
     }
     int2 total;
@@ -93,7 +107,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int nb, int P)
 #pragma unroll
     for (int i = 0; i < SCAN_E; ++i) {
         int k = base + i;
-        if (k < nb) s.offset[k] = ex;
+        if (k < ncells) s.offset[k] = ex;
         ex = add2(ex, v[i]);
     }
     if (threadIdx.x == 0) s.chunk_sum[blockIdx.x] = total;
@@ -115,14 +129,14 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_chunks(SortBuf s, int nchunks)
     if (threadIdx.x == 0) *s.totals = carry;
 }
 
-// Add chunk prefixes; write the items of each brick.
+// Write the items of each brick.
 __global__ __launch_bounds__(256) void k_make_items(SortBuf s, int nb, int P)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nb) return;
-    int2 o = add2(s.offset[k], s.chunk_sum[k / SCAN_CHUNK]);
-    s.offset[k] = o;
-    int c = s.count[k].x;
+    const int64_t c0 = (int64_t)k * 64;
+    int2 o = add2(s.offset[c0], s.chunk_sum[c0 / SCAN_CHUNK]);
+    int c = gload(s.brick_count + k);
     for (int j = 0, first = o.x; first < o.x + c; ++j, first += P) {
         int cnt = o.x + c - first;
         s.items[o.y + j] = make_int4(k, first, cnt < P ? cnt : P, 0);
@@ -135,7 +149,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.ntot) return;
     const int N = d.ntot;
-    int to = s.offset[s.key[q]].x + s.rank[q];
+    const int key = s.key[q];
+    int to = s.offset[key].x + s.chunk_sum[key / SCAN_CHUNK].x + s.rank[q];
 #pragma unroll
     for (int c = 0; c < 3; ++c) dst.x[(size_t)c * N + to] = d.x[(size_t)c * N + q];
 #pragma unroll
@@ -151,23 +166,28 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
 
 __global__ void k_zero_counts(SortBuf s, int nb)
 {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x)
-        s.count[k] = make_int2(0, 0);
+    const int64_t ncells = (int64_t)nb * 64;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncells; k += (int64_t)gridDim.x * blockDim.x) {
+        s.count[k] = 0;
+        if (k < nb) s.brick_count[k] = 0;
+    }
 }
 
 void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
                  hipStream_t st)
 {
-    int nblk = (total_bricks + 255) / 256;
-    hipLaunchKernelGGL(k_zero_counts, dim3(nblk < 4096 ? nblk : 4096), dim3(256), 0, st, s, total_bricks);
-    hipLaunchKernelGGL(k_brick_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
-    int nchunks = (total_bricks + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, total_bricks, P);
+    const int nblk = (total_bricks + 255) / 256;
+    const int ncells = total_bricks * 64;
+    const int zblk = (ncells + 255) / 256;
+    hipLaunchKernelGGL(k_zero_counts, dim3(zblk < 8192 ? zblk : 8192), dim3(256), 0, st, s, total_bricks);
+    hipLaunchKernelGGL(k_cell_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
+    int nchunks = (ncells + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, ncells, P);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
     hipLaunchKernelGGL(k_make_items, dim3(nblk), dim3(256), 0, st, s, total_bricks, P);
     hipLaunchKernelGGL(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
 }
 
-size_t sort_chunk_count(int total_bricks) { return (total_bricks + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+size_t sort_chunk_count(int64_t ncells) { return (size_t)((ncells + SCAN_CHUNK - 1) / SCAN_CHUNK); }
 
 }  // namespace mpm

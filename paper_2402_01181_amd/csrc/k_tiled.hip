@@ -192,10 +192,12 @@ __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, c
 //
 // W wavefronts per workgroup.  Pass 1 (lane = particle): G2P from the LDS
 // velocity tile, F update, advection, stress and the P2G payload.  Pass 2
-// (lane = stencil node): each wavefront walks its payloads two at a time,
-// lanes 0-26 on particle 2r's 27 nodes and lanes 32-58 on particle 2r+1's,
-// and each half-wave adds its contributions to its own LDS tile with plain
-// read-modify-write (its 27 lanes touch 27 distinct nodes).  LDS float
+// (lane = stencil node): the chunk's payloads are split into 2W contiguous
+// runs, one per half-wave; lanes 0-26 of a half-wave take one particle's 27
+// nodes per step, sum the contributions of consecutive particles with the
+// same stencil (the sort groups particles by cell) in registers, and add
+// each sum to the half-wave's own LDS tile with plain read-modify-write
+// (27 lanes, 27 distinct nodes).  LDS float
 // atomics run at about 1/3 lane per clock per CU on this chip, far below
 // plain LDS traffic.  The 2W tiles are summed and flushed to the global grid
 // with one float atomic per component per non-empty node.
@@ -218,7 +220,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = gload(a.totals).y;
-    // node-pass lane roles: half-wave h takes particle 2 r + h of pair r, lane o < 27 one stencil node
+    // node-pass lane roles: lane o < 27 of each half-wave takes one stencil node
     const int half = lane >> 5, o = lane & 31;
     const bool node_lane = o < 27;
     const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
@@ -387,15 +389,20 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             }
             if (P2G) {
                 if (!key) pay[tid].fk.w = __int_as_float(0);
-                // payloads are read by other lanes of this wavefront only
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // ---- pass 2: lane = stencil node, two particles per step
-                float4 *mytile = tp + (2 * wave + half) * TILE_NODES;
-                const int n_w = min(64, max(0, item.y + item.z - (chunk + wave * 64)));
-                for (int r = 0; 2 * r < n_w; ++r) {
-                    const Payload4 &P = pay[wave * 64 + 2 * r + half];
+                __syncthreads();
+                // ---- pass 2: lane = stencil node; the chunk's particles are split into 2W
+                // contiguous runs, one per half-wave
+                const int hw = 2 * wave + half;
+                float4 *mytile = tp + hw * TILE_NODES;
+                const int n_c = min(T, item.y + item.z - chunk);
+                const int per = (n_c + 2 * W - 1) / (2 * W);
+                const int r_end = min(n_c, (hw + 1) * per);
+                // particles are cell-ordered, so consecutive ones usually share the stencil:
+                // sum a run in registers and add it to the tile when the stencil changes
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                int cur = -1;
+                for (int r = hw * per; r < r_end; ++r) {
+                    const Payload4 &P = pay[r];
                     const float4 fk = P.fk;
                     const int pk = __float_as_int(fk.w);
                     if (!node_lane || !(pk & KEY_VALID)) continue;
@@ -412,8 +419,16 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     if (pk & KEY_IN_TILE) {
                         // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
                         const int l = (pk >> 2) + lo;
-                        float4 old = mytile[l];
-                        mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
+                        if (l == cur) {
+                            acc.x += c4.x; acc.y += c4.y; acc.z += c4.z; acc.w += c4.w;
+                        } else {
+                            if (cur >= 0) {
+                                float4 old = mytile[cur];
+                                mytile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
+                            }
+                            acc = c4;
+                            cur = l;
+                        }
                     } else {
                         // stencil outside the tile: straight to the global grid
                         const int b0 = (pk >> 2) & 1023, b1 = (pk >> 12) & 1023, b2 = (pk >> 22) & 1023;
@@ -429,6 +444,10 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                         else
                             mark_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
                     }
+                }
+                if (cur >= 0) {
+                    float4 old = mytile[cur];
+                    mytile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
                 }
             }
             if (P2G) __syncthreads();   // payload slots are rewritten by the next chunk

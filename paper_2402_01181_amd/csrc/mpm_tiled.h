@@ -6,14 +6,18 @@
 namespace mpm {
 
 // Sort scratch and the resulting work items.
+// Counting sort by cell of the stencil base, cells numbered brick-major
+// (brick * 64 + cell within the 4^3-cell brick): particles of one brick are
+// contiguous, and within it grouped by cell.
 struct SortBuf {
-    int2 *count;       // [total_bricks] (count, -)
-    int2 *offset;      // [total_bricks] (first slot, first item)
-    int2 *chunk_sum;   // [chunks]
-    int2 *totals;      // [1] (particles, items)
-    int32_t *key;      // [ntot] brick of each particle
-    int32_t *rank;     // [ntot] rank within the brick
-    int4 *items;       // [max_items] (brick, first slot, count, -)
+    int32_t *count;        // [total_bricks * 64] particles per cell
+    int32_t *brick_count;  // [total_bricks] particles per brick
+    int2 *offset;          // [total_bricks * 64] (first slot, first item) before the chunk prefix
+    int2 *chunk_sum;       // [chunks] exclusive prefix of each scan chunk
+    int2 *totals;          // [1] (particles, items)
+    int32_t *key;          // [ntot] cell of each particle
+    int32_t *rank;         // [ntot] rank within the cell
+    int4 *items;           // [max_items] (brick, first slot, count, -)
 };
 
 struct ParticleBuf {
@@ -57,7 +61,7 @@ struct GridBarrier {
 
 void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
                  hipStream_t st);
-size_t sort_chunk_count(int total_bricks);
+size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
