@@ -7,6 +7,10 @@ particle-substeps/s is quoted on.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--config slab|large|cube|batched]
 
+Launch options (workgroup size, particles per work item, sort interval,
+graph replay, persistent kernel) come from the autotuner unless
+--no-autotune is given; explicit flags override them.
+
 Timing: W untimed substeps, then K substeps bracketed by device syncs and
 hipEvents on the stream the library launches on.  A second pass of the same
 length with the library's event timer on gives each kernel's average launch
@@ -74,14 +78,19 @@ def _events_ms(torch, fn):
     return a.elapsed_time(b)
 
 
-def measure_forms(torch, L, Sim, opts, batched_steps=40, adj_steps=200):
+def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200):
     """The other forms of the substep on the same GPU: the batched workload
-    (256 environments) and the differentiable slab (forward with tape +
-    hand adjoint, checkpoints every 20) against its plain forward."""
+    (256 environments, launch options tuned for it when `tune`) and the
+    differentiable slab (forward with tape + hand adjoint, checkpoints every
+    20) against its plain forward with the slab's options."""
     from paper_2402_01181_amd import scenes
     out = {}
     bsc = scenes.batched_scene()
-    bs = Sim(bsc, options=opts)
+    bopts = dict(opts)
+    if tune:
+        from paper_2402_01181_amd.autotune import autotune
+        bopts.update(autotune(bsc))
+    bs = Sim(bsc, options=bopts)
     bs.step(5)
     ms = _events_ms(torch, lambda: bs.step(batched_steps))
     nb = bsc.n_particles
@@ -93,6 +102,7 @@ def measure_forms(torch, L, Sim, opts, batched_steps=40, adj_steps=200):
                       "value": nb * batched_steps / (ms * 1e-3), "unit": "particle-substeps/s",
                       "algorithmic_GBps": bytes_step / (ms / batched_steps * 1e-3) / 1e9,
                       "hbm_frac": bytes_step / (ms / batched_steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "options": {str(k): v for k, v in bopts.items()},
                       "status": int(any(bs.read(L.F_STATUS, e) for e in range(bs.n_envs)))}
     bs.close()
     del bs
@@ -172,7 +182,8 @@ def main():
                     help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="pick block/item/sort/graph options by timing first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (launch options: library defaults plus the flags given)")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
@@ -189,9 +200,10 @@ def main():
 
     scene, workload = make_scene(args.config)
     opts = {L.OPT_SCHEME: L.SCHEME_TILED if args.scheme == "tiled" else L.SCHEME_DIRECT}
-    if args.autotune and args.scheme == "tiled":
+    tune = not args.no_autotune and args.scheme == "tiled"
+    if tune:
         from paper_2402_01181_amd.autotune import autotune
-        opts.update(autotune(scene, verbose=True))
+        opts.update(autotune(scene, verbose=False))
         print(f"# autotuned options: {opts}", file=sys.stderr, flush=True)
     if args.sort_every: opts[L.OPT_SORT_EVERY] = args.sort_every
     if args.block: opts[L.OPT_BLOCK] = args.block
@@ -260,7 +272,7 @@ def main():
     forms = None
     if not args.no_forms and args.config == "slab":
         sim.close()
-        forms = measure_forms(torch, L, Sim, {k: v for k, v in opts.items() if k != L.OPT_GRAPH})
+        forms = measure_forms(torch, L, Sim, {k: v for k, v in opts.items() if k != L.OPT_GRAPH}, tune)
         for k, v in forms.items():
             print(f"# form {k}: {v['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
 

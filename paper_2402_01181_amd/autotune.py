@@ -89,10 +89,13 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
     stage([{L.OPT_PERSISTENT: p, L.OPT_GRAPH: g} for p in persistent for g in graph])
     sim.close()
     if cache:
-        os.makedirs(os.path.dirname(cache), exist_ok=True)
         table[key] = {"options": {str(k): v for k, v in best.items()}, "trials": log}
-        tmp = cache + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(table, f, indent=1)
-        os.replace(tmp, cache)
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1)
+            os.replace(tmp, cache)
+        except OSError:
+            pass   # an unwritable cache only costs re-tuning next time
     return best

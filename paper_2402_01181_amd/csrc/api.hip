@@ -67,9 +67,11 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.max_items = (int64_t)s.total_bricks + s.ntot / 16 + 1;   // items of >= 16 particles
     c.sort.items = cv.take<int4>(c.max_items);
     c.act.flag = cv.take<int32_t>(s.total_bricks);
-    c.act.list = cv.take<int32_t>((size_t)2 * s.total_bricks);
-    c.act.count = cv.take<int32_t>(2);
-    c.act.stride = s.total_bricks;
+    c.act.slist = cv.take<int32_t>(s.total_bricks);
+    c.act.scount = cv.take<int32_t>(1);
+    c.act.dlist = cv.take<int32_t>((size_t)2 * s.total_bricks);
+    c.act.dcount = cv.take<int32_t>(2);
+    c.act.nbricks = s.total_bricks;
     c.env_bofs = cv.take<int32_t>(s.n_envs + 1);
     c.act.env_bofs = c.env_bofs;
     c.barrier.count = cv.take<unsigned>(1);
@@ -118,7 +120,7 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.list, c.act.count, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
+                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
     for (const void *q : p)
         if (!q) return false;
     if (c.max_tape > 0) {
@@ -210,6 +212,15 @@ void timed(mpm_ctx *c, hipStream_t st, int kind, F &&launch)
     size_t i0 = c->prof.used;
     hipEvent_t a = prof_event(c), b = prof_event(c);
     if (!a || !b) { launch(); return; }
+    if (PROF_SINGLE_KERNEL[kind]) {
+        // the kernel itself records its start and end
+        launch_timer = LaunchTimer{a, b, false};
+        launch();
+        const bool used = launch_timer.used;
+        launch_timer = LaunchTimer{};
+        if (used) c->prof.marks.emplace_back(kind, i0);
+        return;
+    }
     (void)hipEventRecord(a, st);
     launch();
     (void)hipEventRecord(b, st);
@@ -260,7 +271,7 @@ TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf 
 // Sort live particles into the alternate buffers and rebuild the items.
 void sort_into_alt(mpm_ctx *c, hipStream_t st)
 {
-    timed(c, st, PK_SORT, [&] { launch_sort(c->dev(), c->sort, c->total_bricks, c->item, c->alt, 1, st); });
+    timed(c, st, PK_SORT, [&] { launch_sort(c->dev(), c->sort, c->act, c->total_bricks, c->item, c->alt, 1, st); });
     c->items_valid = true;
     c->items_P = c->item;
     c->since_sort = 0;
@@ -289,7 +300,7 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         sort_into_alt(c, st);
         in = c->alt;
     }
-    // substep i: P2G appends to active list i&1, its grid operation consumes it
+    // substep i: P2G lists far bricks in dynamic list i&1, its grid operation consumes it
     timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, nb, st); });
     if (c->persistent) {
         if (c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
@@ -446,13 +457,11 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
     }
 }
 
-// Tape bookkeeping without active-brick lists (the tape's grid passes are dense).
+// Tape bookkeeping without active-brick flags (the tape's grid passes are dense).
 ActiveBuf tape_act(const mpm_ctx *c)
 {
     ActiveBuf a = c->act;
     a.flag = nullptr;
-    a.list = nullptr;
-    a.count = nullptr;
     return a;
 }
 
@@ -473,7 +482,7 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
     const size_t N = c->ntot, slots = c->tool_slots();
     Dev dc = state_view(c, T.ckpt_state + (size_t)seg * 24 * N);
     dc.pid = T.iota;
-    timed(c, st, PK_SORT, [&] { launch_sort(dc, c->sort, c->total_bricks, c->item, seg_view(c, 0), 1, st); });
+    timed(c, st, PK_SORT, [&] { launch_sort(dc, c->sort, tape_act(c), c->total_bricks, c->item, seg_view(c, 0), 1, st); });
     c->items_valid = false;   // the live state's work items were overwritten
     if (c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
     timed(c, st, PK_ADJ_MISC, [&] {
@@ -683,7 +692,8 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         launch_fill_f4(c->gP, s.total_nodes, st);
         launch_fill_f4(c->gV, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.count), 2, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.scount), 1, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.dcount), 2, 0u, st);
         launch_fill_u32(c->barrier.count, 1, 0u, st);
         launch_fill_u32(c->barrier.gen, 1, 0u, st);
         if ((e2 = hipGetLastError()) != hipSuccess) return cleanup_fail(e2, "init kernels");

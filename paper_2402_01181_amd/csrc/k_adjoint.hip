@@ -790,73 +790,73 @@ static unsigned blocks_for(int64_t n)
 
 void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grid_tape, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
+    launch_k(k_grid_tape, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
                        total_nodes, dec);
 }
 
 void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adj_g2p, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
+    launch_k(k_adj_g2p, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
 }
 
 void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
                      const AdjBuf &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adj_grid, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
+    launch_k(k_adj_grid, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
                        total_nodes, dec, a);
 }
 
 void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adj_p2g, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
+    launch_k(k_adj_p2g, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
 }
 
 void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
                        hipStream_t st)
 {
     int nt = d.n_envs * (d.max_tools > 0 ? d.max_tools : 1);
-    hipLaunchKernelGGL(k_adj_finish, dim3((nt + 255) / 256), dim3(256), 0, st, d, a, n, gE, gnu, gu, gT);
+    launch_k(k_adj_finish, dim3((nt + 255) / 256), dim3(256), 0, st, d, a, n, gE, gnu, gu, gT);
 }
 
 void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st)
 {
     AdjTiledArgs ta{items, totals, act};
-    if (block == 64) hipLaunchKernelGGL((k_adj_g2p_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
-    else if (block == 128) hipLaunchKernelGGL((k_adj_g2p_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
-    else hipLaunchKernelGGL((k_adj_g2p_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
+    if (block == 64) launch_k((k_adj_g2p_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
+    else if (block == 128) launch_k((k_adj_g2p_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
+    else launch_k((k_adj_g2p_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
 }
 
 void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st)
 {
     AdjTiledArgs ta{items, totals, act};
-    if (block == 64) hipLaunchKernelGGL((k_adj_p2g_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
-    else if (block == 128) hipLaunchKernelGGL((k_adj_p2g_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
-    else hipLaunchKernelGGL((k_adj_p2g_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
+    if (block == 64) launch_k((k_adj_p2g_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
+    else if (block == 128) launch_k((k_adj_p2g_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
+    else launch_k((k_adj_p2g_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
 }
 
 void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter,
                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_permute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, perm, ntot, comps, dst, scatter);
+    launch_k(k_permute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, perm, ntot, comps, dst, scatter);
 }
 
 void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_unpermute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, pid, ntot, comps, dst);
+    launch_k(k_unpermute, dim3((ntot + 255) / 256), dim3(256), 0, st, src, pid, ntot, comps, dst);
 }
 
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
 {
     size_t n = bytes / 4;
-    hipLaunchKernelGGL(k_copy_words, dim3(blocks_for((int64_t)n)), dim3(256), 0, st, static_cast<uint32_t *>(dst),
+    launch_k(k_copy_words, dim3(blocks_for((int64_t)n)), dim3(256), 0, st, static_cast<uint32_t *>(dst),
                        static_cast<const uint32_t *>(src), n);
 }
 
 void launch_fill_f64(double *p, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n)), dim3(256), 0, st, p, n);
+    launch_k(k_fill_f64, dim3(blocks_for(n)), dim3(256), 0, st, p, n);
 }
 
 }  // namespace mpm

@@ -148,12 +148,12 @@ __global__ __launch_bounds__(256) void k_g2p_direct(Dev d)
 
 void launch_p2g_direct(const Dev &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_p2g_direct, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d);
+    launch_k(k_p2g_direct, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d);
 }
 
 void launch_grid_dense(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, int zero_P, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grid_dense, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
+    launch_k(k_grid_dense, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
                        total_nodes, zero_P);
 }
 
@@ -162,7 +162,7 @@ void launch_g2p_direct(const Dev &d, hipStream_t st)
     int n = d.ntot;
     if (n < d.n_envs * d.max_tools) n = d.n_envs * d.max_tools;
     if (n < d.n_envs) n = d.n_envs;
-    hipLaunchKernelGGL(k_g2p_direct, dim3((n + 255) / 256), dim3(256), 0, st, d);
+    launch_k(k_g2p_direct, dim3((n + 255) / 256), dim3(256), 0, st, d);
 }
 
 }  // namespace mpm

@@ -9,7 +9,7 @@
 //      counted at its first cell.
 //   3. k_make_items: (brick, first slot, count) per item, brick-major order.
 //   4. k_sort_scatter: move particle state into its sorted slot.
-#include "mpm_tiled.h"
+#include "mpm_tile_util.h"
 
 namespace mpm {
 
@@ -164,8 +164,32 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
     }
 }
 
-__global__ void k_zero_counts(SortBuf s, int nb)
+// Drop the previous static brick list (its flags).
+__global__ void k_static_clear(ActiveBuf act)
 {
+    const int n = gload(act.scount);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        gstore(act.flag + gload(act.slist + i), 0);
+}
+
+// New static brick list: the 27-brick neighbourhood (within its environment's
+// grid) of every occupied particle brick; one lane per (brick, neighbour).
+__global__ __launch_bounds__(256) void k_static_build(Dev d, SortBuf s, ActiveBuf act)
+{
+    const int b = blockIdx.x * 8 + (threadIdx.x >> 5), o = threadIdx.x & 31;
+    if (b >= act.nbricks || o >= 27 || gload(s.brick_count + b) == 0) return;
+    const EnvDev e = load_env(d.env + env_of_brick(act.env_bofs, d.n_envs, b));
+    const int lb = b - e.bofs;
+    const int bi = lb / (e.nb * e.nb) + o / 9 - 1, bj = (lb / e.nb) % e.nb + (o / 3) % 3 - 1,
+              bk = lb % e.nb + o % 3 - 1;
+    if (bi < 0 || bj < 0 || bk < 0 || bi >= e.nb || bj >= e.nb || bk >= e.nb) return;
+    const int x = e.bofs + (bi * e.nb + bj) * e.nb + bk;
+    if (gatomic_cas(act.flag + x, 0, 1)) gstore(act.slist + gatomic_add(act.scount, 1), x);
+}
+
+__global__ void k_zero_counts(SortBuf s, ActiveBuf act, int nb)
+{
+    if (act.flag && blockIdx.x == 0 && threadIdx.x == 0) gstore(act.scount, 0);
     const int64_t ncells = (int64_t)nb * 64;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncells; k += (int64_t)gridDim.x * blockDim.x) {
         s.count[k] = 0;
@@ -173,19 +197,21 @@ __global__ void k_zero_counts(SortBuf s, int nb)
     }
 }
 
-void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
-                 hipStream_t st)
+void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
+                 const ParticleBuf &dst, int full, hipStream_t st)
 {
     const int nblk = (total_bricks + 255) / 256;
     const int ncells = total_bricks * 64;
     const int zblk = (ncells + 255) / 256;
-    hipLaunchKernelGGL(k_zero_counts, dim3(zblk < 8192 ? zblk : 8192), dim3(256), 0, st, s, total_bricks);
-    hipLaunchKernelGGL(k_cell_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
+    if (act.flag) launch_k(k_static_clear, dim3(nblk < 1024 ? nblk : 1024), dim3(256), 0, st, act);
+    launch_k(k_zero_counts, dim3(zblk < 8192 ? zblk : 8192), dim3(256), 0, st, s, act, total_bricks);
+    launch_k(k_cell_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
+    if (act.flag) launch_k(k_static_build, dim3((total_bricks + 7) / 8), dim3(256), 0, st, d, s, act);
     int nchunks = (ncells + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, ncells, P);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
-    hipLaunchKernelGGL(k_make_items, dim3(nblk), dim3(256), 0, st, s, total_bricks, P);
-    hipLaunchKernelGGL(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
+    launch_k(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, ncells, P);
+    launch_k(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
+    launch_k(k_make_items, dim3(nblk), dim3(256), 0, st, s, total_bricks, P);
+    launch_k(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
 }
 
 size_t sort_chunk_count(int64_t ncells) { return (size_t)((ncells + SCAN_CHUNK - 1) / SCAN_CHUNK); }

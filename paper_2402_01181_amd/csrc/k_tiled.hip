@@ -87,23 +87,6 @@ __device__ __forceinline__ void p2g_weights(const EnvDev &e, const Stencil &s, f
 }
 
 
-__device__ __noinline__ void p2g_particle_global(const Dev &d, const ActiveBuf &act, int par, const EnvDev &e,
-                                                 const Stencil &s, float m, const float A[9], const float v[3])
-{
-    for (int o0 = 0; o0 < 3; ++o0)
-        for (int o1 = 0; o1 < 3; ++o1)
-            for (int o2 = 0; o2 < 3; ++o2) {
-                float pm, p0, p1, p2;
-                p2g_weights(e, s, m, A, v, o0, o1, o2, pm, p0, p1, p2);
-                float *g = reinterpret_cast<float *>(d.gP + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
-                gatomic_add(g + 0, pm);
-                gatomic_add(g + 1, p0);
-                gatomic_add(g + 2, p1);
-                gatomic_add(g + 3, p2);
-            }
-    mark_stencil_bricks(act, par, e, s.b);
-}
-
 // A = -dt V0 (4/dx^2) tau(F) + m C   (MLS force folded into the affine term)
 __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e, int env, const float H[9],
                                                    const float C[9], float A[9], float &m)
@@ -142,10 +125,6 @@ __device__ __forceinline__ int key_global(const int b[3])
 {
     return KEY_VALID | (b[0] << 2) | (b[1] << 12) | (b[2] << 22);
 }
-
-// Node brick (bi + di, bj + dj, bk + dk), di, dj, dk in {-1, 0, 1}, as a bit
-// of the 27-bit touched mask of a tile.
-__device__ __forceinline__ int touched_bit(int di, int dj, int dk) { return 1 << (((di + 1) * 3 + dj + 1) * 3 + dk + 1); }
 
 // FP32 J - 1 from H (terms of order |H|, |H|^2, |H|^3: nothing cancels).
 __device__ __forceinline__ float jm1_f(const float H[9])
@@ -206,7 +185,6 @@ struct TiledShared {
     float4 tv[TILE_NODES];            // node velocities
     float4 tp[2 * W * TILE_NODES];    // per-half-wave (m, mv) tiles
     Payload4 pay[64 * W];
-    int touched;                      // node bricks around the tile that received mass (27 bits)
 };
 
 template <int MODE, int W>
@@ -216,7 +194,6 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     constexpr int T = 64 * W;
     float4 *tv = sh.tv, *tp = sh.tp;
     Payload4 *pay = sh.pay;
-    int &touched = sh.touched;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = gload(a.totals).y;
@@ -242,6 +219,20 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         const int4 item = gload(a.items + it);
         EnvDev e;
         const Tile t = make_tile(d, a.act, item.x, e);
+        const int item_end = item.y + item.z;
+        // position and deformation of this lane's particle in the next chunk, loaded
+        // ahead so the loads overlap the tile set-up (first chunk) or the node pass
+        float px[3], pH[9];
+        auto prefetch = [&](int chunk) {
+            const int p = chunk + tid;
+            if (p < item_end) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) px[c] = gload(a.xin + (size_t)c * N + p);
+#pragma unroll
+                for (int c = 0; c < 9; ++c) pH[c] = gload(a.Hin + (size_t)c * N + p);
+            }
+        };
+        prefetch(item.y);
         float mu = 0.f, lam = 0.f, m = 0.f, V0 = 0.f;
         if (P2G) {
             const float *mat = d.material + 4 * t.env;
@@ -261,18 +252,17 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 tv[n] = V;
             }
         }
-        if (tid == 0) touched = 0;
         __syncthreads();
 
-        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
+        for (int chunk = item.y; chunk < item_end; chunk += T) {
             // ---- pass 1: lane = particle
             const int p = chunk + tid;
             int key = 0;
-            if (p < item.y + item.z) {
-                float x[3] = {gload(a.xin + p), gload(a.xin + N + p), gload(a.xin + 2 * N + p)};
+            if (p < item_end) {
+                float x[3] = {px[0], px[1], px[2]};
                 float H[9], v[3], C[9];
 #pragma unroll
-                for (int c = 0; c < 9; ++c) H[c] = gload(a.Hin + (size_t)c * N + p);
+                for (int c = 0; c < 9; ++c) H[c] = pH[c];
                 Stencil s;
                 make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s);
                 if (s.outside) {
@@ -387,6 +377,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     }
                 }
             }
+            if (chunk + T < item_end) prefetch(chunk + T);
             if (P2G) {
                 if (!key) pay[tid].fk.w = __int_as_float(0);
                 __syncthreads();
@@ -394,7 +385,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 // contiguous runs, one per half-wave
                 const int hw = 2 * wave + half;
                 float4 *mytile = tp + hw * TILE_NODES;
-                const int n_c = min(T, item.y + item.z - chunk);
+                const int n_c = min(T, item_end - chunk);
                 const int per = (n_c + 2 * W - 1) / (2 * W);
                 const int r_end = min(n_c, (hw + 1) * per);
                 // particles are cell-ordered, so consecutive ones usually share the stencil:
@@ -439,10 +430,8 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                         gatomic_add(g + 2, c4.z);
                         gatomic_add(g + 3, c4.w);
                         const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
-                        if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1)
-                            atomicOr(&touched, touched_bit(di, dj, dk));
-                        else
-                            mark_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
+                        if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1)
+                            mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
                     }
                 }
                 if (cur >= 0) {
@@ -454,7 +443,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
 
         if (P2G) {
-            // sum the wave tiles, flush non-empty nodes, remember the node bricks hit
+            // sum the wave tiles and flush the non-empty nodes (their bricks are in the static list)
             for (int n = tid; n < TILE_NODES; n += T) {
                 float4 sum = tp[n];
 #pragma unroll
@@ -470,20 +459,14 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     gatomic_add(g + 1, sum.y);
                     gatomic_add(g + 2, sum.z);
                     gatomic_add(g + 3, sum.w);
-                    atomicOr(&touched, touched_bit((i >> 2) - t.bi, (j >> 2) - t.bj, (k >> 2) - t.bk));
                 }
-            }
-            __syncthreads();
-            if (tid < 27 && ((touched >> tid) & 1)) {
-                const int bi = t.bi + tid / 9 - 1, bj = t.bj + (tid / 3) % 3 - 1, bk = t.bk + tid % 3 - 1;
-                mark_brick(a.act, a.par, e.bofs + (bi * e.nb + bj) * e.nb + bk);
             }
         }
         __syncthreads();
     }
     if (G2P) advance_end_of_substep(d);
-    // the tail ends a call: both active lists start empty at the next head
-    if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.count) gstore(a.act.count + tid, 0);
+    // the tail ends a call: both dynamic lists start empty at the next head
+    if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.dcount) gstore(a.act.dcount + tid, 0);
 }
 
 template <int MODE, int W>
@@ -493,16 +476,17 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
     tiled_body<MODE, W>(d, a, sh);
 }
 
-// Grid operation over the active node bricks of list `par`: one wavefront
-// per 4^3 brick.  Writes V, clears P and the brick's flag; clears the other
-// list's count for the next P2G.
+// Grid operation over the static brick list and dynamic list `par`: one
+// wavefront per 4^3 brick.  Writes V and clears P; clears the flags of the
+// dynamic bricks, and the other dynamic list's count for the next P2G.
 __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int cnt = gload(a.count + par);
-    const int32_t *list = a.list + (size_t)par * a.stride;
-    for (int i = blockIdx.x * nw + wave; i < cnt; i += gridDim.x * nw) {
-        int b = gload(list + i);
+    const int ns = gload(a.scount), nd = gload(a.dcount + par);
+    const int32_t *dl = a.dlist + (size_t)par * a.nbricks;
+    for (int i = blockIdx.x * nw + wave; i < ns + nd; i += gridDim.x * nw) {
+        const bool dyn = i >= ns;
+        const int b = dyn ? gload(dl + (i - ns)) : gload(a.slist + i);
         int env = env_of_brick(a.env_bofs, d.n_envs, b);
         const EnvDev e = load_env(d.env + env);
         int lb = b - e.bofs;
@@ -513,9 +497,9 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         float3 v = grid_node_velocity(d, e, env, P, gi, gj, gk, nullptr);
         gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
         gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));
-        if (lane == 0) gstore(a.flag + b, 0);
+        if (dyn && lane == 0) gstore(a.flag + b, 0);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.count + (par ^ 1), 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.dcount + (par ^ 1), 0);
 }
 
 __global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par)
@@ -552,7 +536,7 @@ __device__ __forceinline__ bool grid_sync(const GridBarrier &b, int spin_limit, 
     return ok_shared != 0;
 }
 
-// Persistent form: for m substeps, the grid operation over the active list
+// Persistent form: for m substeps, the grid operation over the listed bricks
 // and then the fused particle pass (or, for the last substep of a call, the
 // G2P-only tail), separated by grid barriers.  `first` reads the particles
 // from the sort destination, `rest` from the live buffers.
@@ -581,9 +565,9 @@ __global__ __launch_bounds__(64 * W) void k_persistent(Dev d, TiledArgs first, T
 template <int MODE>
 static void launch_mode(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    if (block == 64) hipLaunchKernelGGL((k_tiled<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
-    else if (block == 128) hipLaunchKernelGGL((k_tiled<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
-    else hipLaunchKernelGGL((k_tiled<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);
+    if (block == 64) launch_k((k_tiled<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
+    else if (block == 128) launch_k((k_tiled<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
+    else launch_k((k_tiled<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);
 }
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
@@ -605,11 +589,11 @@ void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &re
                        const GridBarrier &bar, int spin_limit, int block, int nblocks, hipStream_t st)
 {
     if (block == 64)
-        hipLaunchKernelGGL((k_persistent<1>), dim3(nblocks), dim3(64), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<1>), dim3(nblocks), dim3(64), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
     else if (block == 128)
-        hipLaunchKernelGGL((k_persistent<2>), dim3(nblocks), dim3(128), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<2>), dim3(nblocks), dim3(128), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
     else
-        hipLaunchKernelGGL((k_persistent<4>), dim3(nblocks), dim3(256), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<4>), dim3(nblocks), dim3(256), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
 }
 
 int persistent_workgroups(int block)
@@ -648,7 +632,7 @@ int tiled_workgroups(int block)
 
 void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grid_active, dim3(nblocks), dim3(256), 0, st, d, a, par);
+    launch_k(k_grid_active, dim3(nblocks), dim3(256), 0, st, d, a, par);
 }
 
 }  // namespace mpm

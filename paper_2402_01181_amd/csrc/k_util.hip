@@ -4,6 +4,8 @@
 
 namespace mpm {
 
+thread_local LaunchTimer launch_timer;
+
 __global__ void k_fill_f4(float4 *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -81,47 +83,47 @@ static unsigned grid_for(int64_t n, int block = 256)
 
 void launch_fill_f4(float4 *p, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+    launch_k(k_fill_f4, dim3(grid_for(n)), dim3(256), 0, st, p, n);
 }
 
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, st, p, n, value);
+    launch_k(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, st, p, n, value);
 }
 
 void launch_iota(int32_t *p, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+    launch_k(k_iota, dim3(grid_for(n)), dim3(256), 0, st, p, n);
 }
 
 void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
+    launch_k(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
 }
 
 void launch_read_particles(const float *src, const int32_t *pid, int ntot, int pofs, int np, int comps,
                            float *dst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_read_particles, dim3((np + 255) / 256), dim3(256), 0, st, src, pid, ntot, pofs, np,
+    launch_k(k_read_particles, dim3((np + 255) / 256), dim3(256), 0, st, src, pid, ntot, pofs, np,
                        comps, dst);
 }
 
 void launch_write_particles(float *dst, const int32_t *pid, int ntot, int pofs, int np, int comps,
                             const float *src, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_write_particles, dim3((np + 255) / 256), dim3(256), 0, st, dst, pid, ntot, pofs, np,
+    launch_k(k_write_particles, dim3((np + 255) / 256), dim3(256), 0, st, dst, pid, ntot, pofs, np,
                        comps, src);
 }
 
 void launch_add_identity(float *p, int64_t n, int64_t stride, float sign, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_add_identity, dim3(grid_for(n)), dim3(256), 0, st, p, n, stride, sign);
+    launch_k(k_add_identity, dim3(grid_for(n)), dim3(256), 0, st, p, n, stride, sign);
 }
 
 void launch_read_grid(const float4 *g, int64_t gofs, int n, int comp0, int comps, float *dst, hipStream_t st)
 {
     int64_t nn = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_read_grid, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g, gofs, n, comp0,
+    launch_k(k_read_grid, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g, gofs, n, comp0,
                        comps, dst);
 }
 

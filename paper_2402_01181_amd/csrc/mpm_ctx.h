@@ -16,6 +16,12 @@ static const char *const PROF_NAMES[PK_COUNT] = {
     "fill", "p2g_direct", "grid_dense", "g2p_direct", "sort", "p2g_tiled", "fused_g2p_p2g_tiled",
     "g2p_tiled", "grid_active", "adj_g2p", "adj_grid", "adj_p2g", "adj_misc",
     "persistent_tiled"};
+// Kinds launched as one kernel: timed by the kernel's own start/end events;
+// the others by events recorded around their launches.
+static const bool PROF_SINGLE_KERNEL[PK_COUNT] = {
+    true, true, true, true, false, true, true,
+    true, true, true, true, true, false,
+    true};
 
 struct Profiler {
     bool on = false;

@@ -51,23 +51,15 @@ __device__ __forceinline__ void item_range(int nitems, int &first, int &stride, 
     stride = G / NXCD;
 }
 
-__device__ __forceinline__ void mark_brick(const ActiveBuf &act, int par, int b)
+// A stencil reached brick b outside the static neighbourhood of the
+// particle's sort-time brick: list b once for the next grid operation.
+__device__ __forceinline__ void mark_far_brick(const ActiveBuf &act, int par, int b)
 {
-    if (!act.flag) return;   // no active-brick bookkeeping (tape recompute)
-    if (gatomic_cas(act.flag + b, 0, 1)) {
-        int slot = gatomic_add(act.count + par, 1);
-        gstore(act.list + (size_t)par * act.stride + slot, b);
+    if (!act.flag) return;   // no bookkeeping (tape recompute)
+    if (gatomic_cas(act.flag + b, 0, 2)) {
+        int slot = gatomic_add(act.dcount + par, 1);
+        gstore(act.dlist + (size_t)par * act.nbricks + slot, b);
     }
-}
-
-// Mark every node brick a stencil with base b touches (global fallback path).
-__device__ __forceinline__ void mark_stencil_bricks(const ActiveBuf &act, int par, const EnvDev &e, const int b[3])
-{
-    int lo0 = b[0] >> 2, hi0 = (b[0] + 2) >> 2, lo1 = b[1] >> 2, hi1 = (b[1] + 2) >> 2;
-    int lo2 = b[2] >> 2, hi2 = (b[2] + 2) >> 2;
-    for (int i = lo0; i <= hi0; ++i)
-        for (int j = lo1; j <= hi1; ++j)
-            for (int k = lo2; k <= hi2; ++k) mark_brick(act, par, e.bofs + (i * e.nb + j) * e.nb + k);
 }
 
 __device__ __forceinline__ bool stencil_in_tile(const Tile &t, const Stencil &s, int &l0, int &l1, int &l2)

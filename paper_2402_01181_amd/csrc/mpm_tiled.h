@@ -29,12 +29,20 @@ struct ParticleBuf {
 // (substep parity): P2G appends to list p, the grid operation of that
 // substep consumes list p and clears the count of list p^1, which the next
 // P2G fills.  A call's G2P-only tail clears both counts.
+// Node bricks the grid operation visits.  The static list, rebuilt at every
+// sort, holds the 27-brick neighbourhood of every occupied particle brick: all
+// nodes a particle can reach while its stencil base stays within one cell of
+// its sort-time brick.  A particle that has drifted further lists the bricks
+// it reaches in a dynamic list (two, alternating with substep parity) that
+// the next grid operation consumes and clears.
 struct ActiveBuf {
-    int32_t *flag;     // [total_bricks]
-    int32_t *list;     // [2][total_bricks]
-    int32_t *count;    // [2]
-    int32_t stride;    // total_bricks
-    const int32_t *env_bofs;  // [n_envs + 1]
+    int32_t *flag;            // [nbricks] 0 unlisted, 1 static, 2 dynamic; nullptr: no bookkeeping
+    int32_t *slist;           // [nbricks] static list
+    int32_t *scount;          // [1]
+    int32_t *dlist;           // [2][nbricks] dynamic lists
+    int32_t *dcount;          // [2]
+    const int32_t *env_bofs;  // [n_envs + 1] first brick of each environment
+    int32_t nbricks;          // total bricks over all environments
 };
 
 // Tile geometry: the nodes reached by the stencils of a brick of 4^3 cells
@@ -50,7 +58,7 @@ struct TiledArgs {
     const int4 *items;
     const int2 *totals;                   // .y = number of items
     ActiveBuf act;
-    int par;                              // active list this kernel's P2G appends to
+    int par;                              // dynamic list this kernel's P2G appends to
 };
 
 // Grid-wide barrier state of the persistent kernel (reset before each launch).
@@ -59,8 +67,9 @@ struct GridBarrier {
     unsigned *gen;
 };
 
-void launch_sort(const Dev &d, const SortBuf &s, int total_bricks, int P, const ParticleBuf &dst, int full,
-                 hipStream_t st);
+// act.flag == nullptr: the static brick list is left as it is.
+void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
+                 const ParticleBuf &dst, int full, hipStream_t st);
 size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
