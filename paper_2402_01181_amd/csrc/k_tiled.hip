@@ -103,6 +103,12 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
     for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * C[c];
 }
 
+// Component c of a [comp][N] particle array: a uniform base pointer, so a
+// particle access is that base plus a 32-bit lane offset (one address form,
+// no per-lane 64-bit arithmetic).
+template <class T>
+__device__ __forceinline__ T *comp(T *base, int c, int N) { return base + (size_t)c * N; }
+
 // Per-particle P2G inputs handed from the particle pass to the node pass of
 // the same wavefront (64 bytes, four LDS vector reads): fx and a packed key,
 // m v, and A dx row by row.  The particle mass is uniform per environment.
@@ -227,9 +233,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             const int p = chunk + tid;
             if (p < item_end) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) px[c] = gload(a.xin + (size_t)c * N + p);
+                for (int c = 0; c < 3; ++c) px[c] = gload(comp(a.xin, c, N) + (uint32_t)p);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) pH[c] = gload(a.Hin + (size_t)c * N + p);
+                for (int c = 0; c < 9; ++c) pH[c] = gload(comp(a.Hin, c, N) + (uint32_t)p);
             }
         };
         prefetch(item.y);
@@ -271,16 +277,16 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     if (a.xout != a.xin) {
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            gstore(a.xout + (size_t)c * N + p, x[c]);
-                            gstore(a.vout + (size_t)c * N + p, gload(a.vin + (size_t)c * N + p));
+                            gstore(comp(a.xout, c, N) + (uint32_t)p, x[c]);
+                            gstore(comp(a.vout, c, N) + (uint32_t)p, gload(comp(a.vin, c, N) + (uint32_t)p));
                         }
 #pragma unroll
                         for (int c = 0; c < 9; ++c) {
-                            gstore(a.Hout + (size_t)c * N + p, H[c]);
-                            gstore(a.Cout + (size_t)c * N + p, gload(a.Cin + (size_t)c * N + p));
+                            gstore(comp(a.Hout, c, N) + (uint32_t)p, H[c]);
+                            gstore(comp(a.Cout, c, N) + (uint32_t)p, gload(comp(a.Cin, c, N) + (uint32_t)p));
                         }
                     }
-                    if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
+                    if (a.pidout != a.pidin) gstore(a.pidout + (uint32_t)p, gload(a.pidin + (uint32_t)p));
                 } else {
                     float jm1 = 0.f;
                     bool inv = false;
@@ -335,9 +341,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                             set_flag(d.status, t.env, MPM_FLAG_NONFINITE);
                     } else {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) v[c] = gload(a.vin + (size_t)c * N + p);
+                        for (int c = 0; c < 3; ++c) v[c] = gload(comp(a.vin, c, N) + (uint32_t)p);
 #pragma unroll
-                        for (int c = 0; c < 9; ++c) C[c] = gload(a.Cin + (size_t)c * N + p);
+                        for (int c = 0; c < 9; ++c) C[c] = gload(comp(a.Cin, c, N) + (uint32_t)p);
                         jm1 = jm1_f(H);
                         inv = inverted_f(H, jm1);
                         if (inv) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
@@ -364,16 +370,16 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     }
                     if (G2P) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) gstore(a.xout + (size_t)c * N + p, x[c]);
+                        for (int c = 0; c < 3; ++c) gstore(comp(a.xout, c, N) + (uint32_t)p, x[c]);
 #pragma unroll
-                        for (int c = 0; c < 9; ++c) gstore(a.Hout + (size_t)c * N + p, H[c]);
+                        for (int c = 0; c < 9; ++c) gstore(comp(a.Hout, c, N) + (uint32_t)p, H[c]);
                         if (write_vc) {
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) gstore(a.vout + (size_t)c * N + p, v[c]);
+                            for (int c = 0; c < 3; ++c) gstore(comp(a.vout, c, N) + (uint32_t)p, v[c]);
 #pragma unroll
-                            for (int c = 0; c < 9; ++c) gstore(a.Cout + (size_t)c * N + p, C[c]);
+                            for (int c = 0; c < 9; ++c) gstore(comp(a.Cout, c, N) + (uint32_t)p, C[c]);
                         }
-                        if (a.pidout != a.pidin) gstore(a.pidout + p, gload(a.pidin + p));
+                        if (a.pidout != a.pidin) gstore(a.pidout + (uint32_t)p, gload(a.pidin + (uint32_t)p));
                     }
                 }
             }
@@ -392,12 +398,10 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 // sum a run in registers and add it to the tile when the stencil changes
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                 int cur = -1;
-                for (int r = hw * per; r < r_end; ++r) {
+                for (int r = hw * per; node_lane && r < r_end; ++r) {
                     const Payload4 &P = pay[r];
-                    const float4 fk = P.fk;
+                    const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
                     const int pk = __float_as_int(fk.w);
-                    if (!node_lane || !(pk & KEY_VALID)) continue;
-                    const float4 q1 = P.q1, q2 = P.q2, q3 = P.q3;
                     const float t0 = fk.x - wc[0], t1 = fk.y - wc[1], t2 = fk.z - wc[2];
                     const float w = fmaf(wa[0], t0 * t0, wg[0]) * fmaf(wa[1], t1 * t1, wg[1]) *
                                     fmaf(wa[2], t2 * t2, wg[2]);
@@ -407,19 +411,19 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     c4.y = w * fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
                     c4.z = w * fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
                     c4.w = w * fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
+                    if (!(pk & KEY_VALID)) continue;
                     if (pk & KEY_IN_TILE) {
                         // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
                         const int l = (pk >> 2) + lo;
-                        if (l == cur) {
-                            acc.x += c4.x; acc.y += c4.y; acc.z += c4.z; acc.w += c4.w;
-                        } else {
+                        if (l != cur) {
                             if (cur >= 0) {
                                 float4 old = mytile[cur];
                                 mytile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
                             }
-                            acc = c4;
+                            acc = make_float4(0.f, 0.f, 0.f, 0.f);
                             cur = l;
                         }
+                        acc.x += c4.x; acc.y += c4.y; acc.z += c4.z; acc.w += c4.w;
                     } else {
                         // stencil outside the tile: straight to the global grid
                         const int b0 = (pk >> 2) & 1023, b1 = (pk >> 12) & 1023, b2 = (pk >> 22) & 1023;
