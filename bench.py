@@ -278,7 +278,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        default_cpu = {"slab": 600, "large": 15, "cube": 50, "batched": 300}
+        default_cpu = {"slab": 1500, "large": 40, "cube": 200, "batched": 600}
         cpu = cpu_baseline(scene, args.cpu_substeps or default_cpu.get(args.config, 50))
         print(f"# cpu baseline: {cpu['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
 

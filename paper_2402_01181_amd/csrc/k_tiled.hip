@@ -486,11 +486,16 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int stride = gridDim.x * nw;
+    int i = blockIdx.x * nw + wave;
+    // the first static entry is loaded together with the counts (used only if i < ns)
+    int bs = i < a.nbricks ? gload(a.slist + i) : 0;
     const int ns = gload(a.scount), nd = gload(a.dcount + par);
     const int32_t *dl = a.dlist + (size_t)par * a.nbricks;
-    for (int i = blockIdx.x * nw + wave; i < ns + nd; i += gridDim.x * nw) {
+    for (; i < ns + nd; i += stride) {
         const bool dyn = i >= ns;
-        const int b = dyn ? gload(dl + (i - ns)) : gload(a.slist + i);
+        const int b = dyn ? gload(dl + (i - ns)) : bs;
+        if (i + stride < a.nbricks) bs = gload(a.slist + i + stride);
         int env = env_of_brick(a.env_bofs, d.n_envs, b);
         const EnvDev e = load_env(d.env + env);
         int lb = b - e.bofs;

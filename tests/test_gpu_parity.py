@@ -289,3 +289,43 @@ def test_persistent_batched_and_single_substeps(gpu, orc):
         assert err <= 1e-5
         assert pers.read(L.F_STATUS, e) == 0 and pers.read(L.F_STEP, e) == 30
         np.testing.assert_array_equal(pers.read(L.F_TOOL_T, e), eager.read(L.F_TOOL_T, e))
+
+
+def _drift_scene(substeps=150):
+    """A block translating rigidly at ~4.5 m/s with no gravity, far from the
+    walls: in 150 substeps of 1e-4 s it moves ~2.9 cells of the 64^3 grid."""
+    rng = np.random.default_rng(7)
+    x = scenes.box_uniform(rng, 6000, (0.30, 0.30, 0.30), (0.45, 0.45, 0.45))
+    v, C, F = scenes._rest_state(x)
+    u = np.array([3.0, -2.0, 2.5], np.float32)
+    v[:] = u
+    env = scenes.Env(n=64, x=x, v=v, C=C, F=F, E=1e4, nu=0.3, rho=1e3, V0=0.15 ** 3 / x.shape[0])
+    return scenes.Scene("drift", [env], dt=1e-4, substeps=substeps, gravity=(0.0, 0.0, 0.0)), u
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_far_drift_between_sorts(gpu, orc, persistent):
+    """Particles that move several cells past their sort-time brick (one sort
+    for the whole run) reach bricks outside the static brick list; the
+    dynamic lists must carry them.  Rigid translation has a closed form
+    (x = x0 + S dt u, v = u, F = I) and the direct scheme keeps no lists."""
+    Sim, L = gpu
+    sc, u = _drift_scene()
+    S = sc.substeps
+    _say(f"far drift: 6000 particles, {S} substeps, one sort, persistent={persistent}")
+    tiled = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 1000, L.OPT_PERSISTENT: persistent})
+    direct = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_DIRECT})
+    tiled.step(S)
+    direct.step(S)
+    xt, vt, Ct, Ft = tiled.particles()
+    xd, _, _, _ = direct.particles()
+    x_exact = sc.envs[0].x.astype(np.float64) + S * float(np.float32(sc.dt)) * u.astype(np.float64)
+    moved = np.abs(xt - sc.envs[0].x).max() * 64
+    ex = np.abs(xt - x_exact).max()
+    ev = np.abs(vt - u).max()
+    eF = np.abs(Ft - np.eye(3)).max()
+    etd = np.abs(xt - xd).max()
+    _say(f"  moved {moved:.2f} cells; |x - exact| {ex:.2e}, |v - u| {ev:.2e}, |F - I| {eF:.2e}, |tiled - direct| {etd:.2e}")
+    assert moved > 2.5
+    assert ex <= 2e-5 and ev <= 1e-4 and eF <= 1e-5 and etd <= 1e-5
+    assert tiled.read(L.F_STATUS) == 0 and tiled.read(L.F_STEP) == S
