@@ -451,7 +451,8 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
         });
         timed(c, st, PK_P2G_DIRECT, [&] { launch_p2g_direct(d, st); });
         timed(c, st, PK_GRID_DENSE, [&] {
-            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, st);
+            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, nullptr, 0,
+                             nullptr, st);
         });
         timed(c, st, PK_G2P_DIRECT, [&] { launch_g2p_direct(d, st); });
     }
@@ -490,27 +491,43 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
         launch_copy_bytes(T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs, st);
     });
     const ActiveBuf ta = tape_act(c);
-    for (int j = s_begin; j < s_end; ++j) {
-        const int slot = j - s_begin;
+    // substep j: grid pass on slot j's P, then G2P(j) into slot j + 1 fused with P2G(j + 1)
+    // into slot j + 1's P (the last substep: G2P only)
+    auto slot_dev = [&](int slot) {
         Dev d = c->dev();
         d.tools = T.work_tools;
         d.step = T.work_step;
         d.status = T.work_status;
         d.gP = T.seg_P + (size_t)slot * c->total_nodes;
         d.gV = T.seg_V + (size_t)slot * c->total_nodes;
-        ParticleBuf in = seg_view(c, slot), out = seg_view(c, slot + 1);
-        TiledArgs head = tiled_args(c, in, in, 0), tail = tiled_args(c, in, out, 0);
+        return d;
+    };
+    {
+        Dev d = slot_dev(0);
+        ParticleBuf in = seg_view(c, 0);
+        TiledArgs head = tiled_args(c, in, in, 0);
         head.act = ta;
-        tail.act = ta;
-        timed(c, st, PK_ADJ_MISC, [&] {
-            launch_copy_bytes(T.seg_tools + (size_t)slot * slots, T.work_tools, sizeof(ToolDev) * slots, st);
-            launch_fill_f4(d.gP, c->total_nodes, st);
-        });
+        timed(c, st, PK_FILL, [&] { launch_fill_f4(d.gP, c->total_nodes, st); });
         timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, head, c->block, c->tiled_blocks, st); });
+    }
+    for (int j = s_begin; j < s_end; ++j) {
+        const int slot = j - s_begin;
+        const bool last = j + 1 == s_end;
+        Dev d = slot_dev(slot);
+        // the grid pass also snapshots the tool table and zeroes the next substep's P
+        float4 *next_P = last ? nullptr : T.seg_P + (size_t)(slot + 1) * c->total_nodes;
         timed(c, st, PK_GRID_DENSE, [&] {
-            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, st);
+            launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes,
+                             T.seg_tools + (size_t)slot * slots, (int)slots, next_P, st);
         });
-        timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, tail, c->block, c->tiled_blocks, st); });
+        TiledArgs step = tiled_args(c, seg_view(c, slot), seg_view(c, slot + 1), 0);
+        step.act = ta;
+        if (last) {
+            timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, step, c->block, c->tiled_blocks, st); });
+        } else {
+            d.gP = next_P;
+            timed(c, st, PK_FUSED_TILED, [&] { launch_fused_full_tiled(d, step, c->block, c->tiled_blocks, st); });
+        }
     }
 }
 

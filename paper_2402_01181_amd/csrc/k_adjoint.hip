@@ -19,10 +19,12 @@ namespace mpm {
 // writes (m, vhat) back into P, the final velocity into V and the contact
 // decision of each node.
 __global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gofs, int64_t total_nodes,
-                                                   ContactCode *dec)
+                                                   ContactCode *dec, ToolDev *snap, int slots, float4 *next_P)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (snap && g < slots) snap[g] = d.tools[g];   // slots <= 8 * n_envs < total_nodes
     if (g >= total_nodes) return;
+    if (next_P) gstore(next_P + g, make_float4(0.f, 0.f, 0.f, 0.f));
     int lo = 0, hi = d.n_envs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -454,16 +456,16 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
     constexpr int T = 64 * W;
     __shared__ float4 tv[TILE_NODES];
     __shared__ float4 tp[2 * W * TILE_NODES];
-    __shared__ Payload pay[T];
+    __shared__ Payload4 pay[T];
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int half = lane >> 5, o = lane & 31;
-    const bool node_lane = o < 27;
-    const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
+    const int hw = 2 * wave + (lane >> 5);
+    const NodeLane nl = node_lane_of(lane);
     const int nitems = gload(ta.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
     for (int it = first; it < end; it += stride) {
         const int4 item = gload(ta.items + it);
+        const int item_end = item.y + item.z;
         EnvDev e;
         const Tile t = make_tile(d, ta.act, item.x, e);
         for (int n = tid; n < TILE_NODES; n += T) {
@@ -474,138 +476,117 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
             tv[n] = V;
         }
         __syncthreads();
-        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
+        for (int chunk = item.y; chunk < item_end; chunk += T) {
             const int q = chunk + tid;
-            int bits = 0;
-            if (q < item.y + item.z) {
-                float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+            int key = 0;
+            if (q < item_end) {
+                const uint32_t uq = (uint32_t)q;
+                float x0 = gload(d.x + uq), x1 = gload(d.x + N + uq), x2 = gload(d.x + 2 * N + uq);
                 Stencil s;
                 make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
                 if (!s.outside) {
                     int l0, l1, l2;
                     const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
+                    // node velocity of stencil node (a0, a1, a2)
+                    auto Vat = [&](int a0, int a1, int a2) -> float4 {
+                        return in_tile ? tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
+                                       : gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                    };
                     float dw[3][3];
                     weight_grads(s, dw);
-                    float4 Vn[27];
-                    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int a0 = 0; a0 < 3; ++a0)
-#pragma unroll
-                        for (int a1 = 0; a1 < 3; ++a1)
-#pragma unroll
-                            for (int a2 = 0; a2 < 3; ++a2) {
-                                int n = (a0 * 3 + a1) * 3 + a2;
-                                Vn[n] = in_tile ? tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
-                                                : gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
-                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
-                                float wx = w * Vn[n].x, wy = w * Vn[n].y, wz = w * Vn[n].z;
-                                B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
-                                B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
-                                B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
-                            }
+                    // the particle's adjoint state first: Bbar and vbar_t do not depend on the
+                    // recomputed C, so one pass over the stencil serves C and the x adjoint
                     const float cs = 4.0f * e.inv_dx;
-                    float Cn[9], H[9], Fb[9], Cb[9], xb[3], vb[3];
+                    float H[9], Fb[9], Cb[9], xb[3], vb[3];
 #pragma unroll
                     for (int c = 0; c < 9; ++c) {
-                        Cn[c] = cs * B[c];
-                        H[c] = gload(d.H + (size_t)c * N + q);
-                        Fb[c] = gload(a.Fb + (size_t)c * N + q);
-                        Cb[c] = gload(a.Cb + (size_t)c * N + q);
+                        H[c] = gload(d.H + (size_t)c * N + uq);
+                        Fb[c] = gload(a.Fb + (size_t)c * N + uq);
+                        Cb[c] = gload(a.Cb + (size_t)c * N + uq);
                     }
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        xb[c] = gload(a.xb + (size_t)c * N + q);
-                        vb[c] = gload(a.vb + (size_t)c * N + q);
+                        xb[c] = gload(a.xb + (size_t)c * N + uq);
+                        vb[c] = gload(a.vb + (size_t)c * N + uq);
                     }
-                    float Fbn[9], Bb[9];
+                    float Bb[9];
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * (Cn[r] * Fb[c] + Cn[3 + r] * Fb[3 + c] + Cn[6 + r] * Fb[6 + c]);
                             float cbt = Cb[3 * r + c] + d.dt * (Fb[3 * r + c] + Fb[3 * r] * H[3 * c] + Fb[3 * r + 1] * H[3 * c + 1] +
                                                                 Fb[3 * r + 2] * H[3 * c + 2]);
                             Bb[3 * r + c] = cs * cbt;
                         }
-                    float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
+                    const float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
+                    // one pass: B = sum w V q^T (the recomputed C = (4/dx) B) and the x adjoint
+                    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     float fxb[3] = {0.f, 0.f, 0.f};
+                    auto stencil_pass = [&](auto Vat) {
 #pragma unroll
-                    for (int a0 = 0; a0 < 3; ++a0)
+                        for (int a0 = 0; a0 < 3; ++a0) {
+                            const float w0 = s.w[0][a0], d0w = dw[0][a0];
+                            const float q0 = a0 - s.fx[0];
 #pragma unroll
-                        for (int a1 = 0; a1 < 3; ++a1)
+                            for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-                            for (int a2 = 0; a2 < 3; ++a2) {
-                                int n = (a0 * 3 + a1) * 3 + a2;
-                                float q0 = a0 - s.fx[0], q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
-                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                float g0 = vbt[0] + Bb[0] * q0 + Bb[1] * q1 + Bb[2] * q2;
-                                float g1 = vbt[1] + Bb[3] * q0 + Bb[4] * q1 + Bb[5] * q2;
-                                float g2 = vbt[2] + Bb[6] * q0 + Bb[7] * q1 + Bb[8] * q2;
-                                const float4 V = Vn[n];
-                                float wb = V.x * g0 + V.y * g1 + V.z * g2;
-                                float qb0 = w * (Bb[0] * V.x + Bb[3] * V.y + Bb[6] * V.z);
-                                float qb1 = w * (Bb[1] * V.x + Bb[4] * V.y + Bb[7] * V.z);
-                                float qb2 = w * (Bb[2] * V.x + Bb[5] * V.y + Bb[8] * V.z);
-                                fxb[0] += -qb0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                fxb[1] += -qb1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
-                                fxb[2] += -qb2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
-                            }
+                                for (int a2 = 0; a2 < 3; ++a2) {
+                                    const float q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
+                                    const float w12 = s.w[1][a1] * s.w[2][a2];
+                                    const float w = w0 * w12;
+                                    const float4 V = Vat(a0, a1, a2);
+                                    const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
+                                    B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
+                                    B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
+                                    B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
+                                    const float g0 = vbt[0] + Bb[0] * q0 + Bb[1] * q1 + Bb[2] * q2;
+                                    const float g1 = vbt[1] + Bb[3] * q0 + Bb[4] * q1 + Bb[5] * q2;
+                                    const float g2 = vbt[2] + Bb[6] * q0 + Bb[7] * q1 + Bb[8] * q2;
+                                    const float wb = V.x * g0 + V.y * g1 + V.z * g2;
+                                    fxb[0] += -(Bb[0] * wx + Bb[3] * wy + Bb[6] * wz) + wb * d0w * w12;
+                                    fxb[1] += -(Bb[1] * wx + Bb[4] * wy + Bb[7] * wz) + wb * w0 * dw[1][a1] * s.w[2][a2];
+                                    fxb[2] += -(Bb[2] * wx + Bb[5] * wy + Bb[8] * wz) + wb * w0 * s.w[1][a1] * dw[2][a2];
+                                }
+                        }
+                    };
+                    if (in_tile)
+                        stencil_pass([&](int a0, int a1, int a2) { return tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
+                    else
+                        stencil_pass([&](int a0, int a1, int a2) {
+                            return gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                        });
+                    float Fbn[9];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * cs * (B[r] * Fb[c] + B[3 + r] * Fb[3 + c] + B[6 + r] * Fb[6 + c]);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        gstore(a.xb + (size_t)c * N + q, xb[c] + e.inv_dx * fxb[c]);
-                        gstore(a.vb + (size_t)c * N + q, 0.0f);
+                        gstore(a.xb + (size_t)c * N + uq, xb[c] + e.inv_dx * fxb[c]);
+                        gstore(a.vb + (size_t)c * N + uq, 0.0f);
                     }
 #pragma unroll
                     for (int c = 0; c < 9; ++c) {
-                        gstore(a.Fb + (size_t)c * N + q, Fbn[c]);
-                        gstore(a.Cb + (size_t)c * N + q, 0.0f);
+                        gstore(a.Fb + (size_t)c * N + uq, Fbn[c]);
+                        gstore(a.Cb + (size_t)c * N + uq, 0.0f);
                     }
-                    // node contributions w (vbar_t + Bbar q), the same form as P2G's w (m v + A q)
-                    bits = PAY_VALID | (in_tile ? PAY_IN_TILE : 0);
-                    Payload &P = pay[tid];
-                    P.f_m = make_float4(s.fx[0], s.fx[1], s.fx[2], 0.f);
-                    P.mv_bits = make_float4(vbt[0], vbt[1], vbt[2], __int_as_float(bits));
-                    P.a0 = make_float4(Bb[0], Bb[1], Bb[2], __int_as_float(s.b[0]));
-                    P.a1 = make_float4(Bb[3], Bb[4], Bb[5], __int_as_float(s.b[1]));
-                    P.a2 = make_float4(Bb[6], Bb[7], Bb[8], __int_as_float(s.b[2]));
+                    // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q)
+                    key = in_tile ? key_in_tile(l0, l1, l2) : key_global(s.b);
+                    store_payload(pay[tid], s.fx, key, vbt, Bb);
                 }
             }
-            if (!bits) pay[tid].mv_bits.w = __int_as_float(0);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float4 *mytile = tp + (2 * wave + half) * TILE_NODES;
-            const int n_w = min(64, max(0, item.y + item.z - (chunk + wave * 64)));
-            for (int r = 0; 2 * r < n_w; ++r) {
-                const Payload &P = pay[wave * 64 + 2 * r + half];
-                const int pb = __float_as_int(P.mv_bits.w);
-                const bool act = node_lane && (pb & PAY_VALID);
-                float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                int l = -1, b0 = 0, b1 = 0, b2 = 0;
-                if (act) {
-                    const float4 fm = P.f_m, g = P.mv_bits, A0 = P.a0, A1 = P.a1, A2 = P.a2;
-                    b0 = __float_as_int(A0.w); b1 = __float_as_int(A1.w); b2 = __float_as_int(A2.w);
-                    const float q0 = o0 - fm.x, q1 = o1 - fm.y, q2 = o2 - fm.z;
-                    const float w = bspline2(q0) * bspline2(q1) * bspline2(q2);
-                    c4.y = w * (g.x + A0.x * q0 + A0.y * q1 + A0.z * q2);
-                    c4.z = w * (g.y + A1.x * q0 + A1.y * q1 + A1.z * q2);
-                    c4.w = w * (g.z + A2.x * q0 + A2.y * q1 + A2.z * q2);
-                    c4.x = 1.0f;   // marks the node as touched
-                    if (pb & PAY_IN_TILE)
-                        l = ((b0 - t.o[0] + o0) * TILE + (b1 - t.o[1] + o1)) * TILE + (b2 - t.o[2] + o2);
-                }
-                if (l >= 0) {
-                    float4 old = mytile[l];
-                    mytile[l] = make_float4(old.x + c4.x, old.y + c4.y, old.z + c4.z, old.w + c4.w);
-                }
-                if (act && l < 0) {
-                    float *g = reinterpret_cast<float *>(a.gVb + node_id(e, b0 + o0, b1 + o1, b2 + o2));
-                    gatomic_add(g + 0, c4.y);
-                    gatomic_add(g + 1, c4.z);
-                    gatomic_add(g + 2, c4.w);
-                }
-            }
+            if (!key) pay[tid].fk.w = __int_as_float(0);
+            __syncthreads();
+            int r0, r1;
+            half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
+            // .x sums the weights (the flush skips nodes no particle reached)
+            node_pass(pay, r0, r1, tp + hw * TILE_NODES, nl, 1.0f, [&](const float4 &c4, int i, int j, int k) {
+                float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
+                gatomic_add(g + 0, c4.y);
+                gatomic_add(g + 1, c4.z);
+                gatomic_add(g + 2, c4.w);
+            });
             __syncthreads();
         }
         for (int n = tid; n < TILE_NODES; n += T) {
@@ -683,32 +664,39 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
                     float vbp[3] = {0.f, 0.f, 0.f}, Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     float fxb[3] = {0.f, 0.f, 0.f};
                     const float dx = e.dx;
+                    auto stencil_pass = [&](auto Pat) {
 #pragma unroll
-                    for (int a0 = 0; a0 < 3; ++a0)
+                        for (int a0 = 0; a0 < 3; ++a0)
 #pragma unroll
-                        for (int a1 = 0; a1 < 3; ++a1)
+                            for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-                            for (int a2 = 0; a2 < 3; ++a2) {
-                                float4 Pb = in_tile ? tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
-                                                    : gload(a.gPb + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
-                                float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                float d0 = (a0 - s.fx[0]) * dx, d1 = (a1 - s.fx[1]) * dx, d2 = (a2 - s.fx[2]) * dx;
-                                vbp[0] += m * w * Pb.y; vbp[1] += m * w * Pb.z; vbp[2] += m * w * Pb.w;
-                                float wy = w * Pb.y, wz = w * Pb.z, ww = w * Pb.w;
-                                Ab[0] += wy * d0; Ab[1] += wy * d1; Ab[2] += wy * d2;
-                                Ab[3] += wz * d0; Ab[4] += wz * d1; Ab[5] += wz * d2;
-                                Ab[6] += ww * d0; Ab[7] += ww * d1; Ab[8] += ww * d2;
-                                float c0 = m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2;
-                                float c1 = m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2;
-                                float c2 = m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2;
-                                float wb = m * Pb.x + Pb.y * c0 + Pb.z * c1 + Pb.w * c2;
-                                float db0 = w * (A[0] * Pb.y + A[3] * Pb.z + A[6] * Pb.w);
-                                float db1 = w * (A[1] * Pb.y + A[4] * Pb.z + A[7] * Pb.w);
-                                float db2 = w * (A[2] * Pb.y + A[5] * Pb.z + A[8] * Pb.w);
-                                fxb[0] += -dx * db0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                fxb[1] += -dx * db1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
-                                fxb[2] += -dx * db2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
-                            }
+                                for (int a2 = 0; a2 < 3; ++a2) {
+                                    const float4 Pb = Pat(a0, a1, a2);
+                                    float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                    float d0 = (a0 - s.fx[0]) * dx, d1 = (a1 - s.fx[1]) * dx, d2 = (a2 - s.fx[2]) * dx;
+                                    vbp[0] += m * w * Pb.y; vbp[1] += m * w * Pb.z; vbp[2] += m * w * Pb.w;
+                                    float wy = w * Pb.y, wz = w * Pb.z, ww = w * Pb.w;
+                                    Ab[0] += wy * d0; Ab[1] += wy * d1; Ab[2] += wy * d2;
+                                    Ab[3] += wz * d0; Ab[4] += wz * d1; Ab[5] += wz * d2;
+                                    Ab[6] += ww * d0; Ab[7] += ww * d1; Ab[8] += ww * d2;
+                                    float c0 = m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2;
+                                    float c1 = m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2;
+                                    float c2 = m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2;
+                                    float wb = m * Pb.x + Pb.y * c0 + Pb.z * c1 + Pb.w * c2;
+                                    float db0 = w * (A[0] * Pb.y + A[3] * Pb.z + A[6] * Pb.w);
+                                    float db1 = w * (A[1] * Pb.y + A[4] * Pb.z + A[7] * Pb.w);
+                                    float db2 = w * (A[2] * Pb.y + A[5] * Pb.z + A[8] * Pb.w);
+                                    fxb[0] += -dx * db0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
+                                    fxb[1] += -dx * db1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
+                                    fxb[2] += -dx * db2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
+                                }
+                    };
+                    if (in_tile)
+                        stencil_pass([&](int a0, int a1, int a2) { return tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
+                    else
+                        stencil_pass([&](int a0, int a1, int a2) {
+                            return gload(a.gPb + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                        });
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         float *px = a.xb + (size_t)c * N + q;
@@ -788,10 +776,11 @@ static unsigned blocks_for(int64_t n)
     return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
-void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, hipStream_t st)
+void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, ToolDev *snap,
+                      int slots, float4 *next_P, hipStream_t st)
 {
     launch_k(k_grid_tape, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
-                       total_nodes, dec);
+                       total_nodes, dec, snap, slots, next_P);
 }
 
 void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)

@@ -109,29 +109,6 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
 template <class T>
 __device__ __forceinline__ T *comp(T *base, int c, int N) { return base + (size_t)c * N; }
 
-// Per-particle P2G inputs handed from the particle pass to the node pass of
-// the same wavefront (64 bytes, four LDS vector reads): fx and a packed key,
-// m v, and A dx row by row.  The particle mass is uniform per environment.
-struct Payload4 {
-    float4 fk;         // fx0, fx1, fx2, key
-    float4 q1;         // m v, A00
-    float4 q2;         // A01, A02, A10, A11
-    float4 q3;         // A12, A20, A21, A22
-};
-// key: bit 0 valid; bit 1 stencil inside the tile, then bits 2.. hold the
-// tile index of the stencil base; otherwise bits 2-11, 12-21, 22-31 hold the
-// absolute base (grids are at most 512 nodes per axis).
-constexpr int KEY_VALID = 1, KEY_IN_TILE = 2;
-
-__device__ __forceinline__ int key_in_tile(int l0, int l1, int l2)
-{
-    return KEY_VALID | KEY_IN_TILE | (((l0 * TILE + l1) * TILE + l2) << 2);
-}
-__device__ __forceinline__ int key_global(const int b[3])
-{
-    return KEY_VALID | (b[0] << 2) | (b[1] << 12) | (b[2] << 22);
-}
-
 // FP32 J - 1 from H (terms of order |H|, |H|^2, |H|^3: nothing cancels).
 __device__ __forceinline__ float jm1_f(const float H[9])
 {
@@ -174,6 +151,8 @@ __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, c
 // MODE 0: P2G only (head of a call; reads x, v, C, H).
 // MODE 1: fused G2P(s) + F update + advection + P2G(s+1) (reads/writes x, H).
 // MODE 2: G2P only (tail of a call; writes x, v, C, H).
+// MODE 3: as MODE 1, also writing v and C (tape recompute: every substep's
+//         full state is kept).
 //
 // W wavefronts per workgroup.  Pass 1 (lane = particle): G2P from the LDS
 // velocity tile, F update, advection, stress and the P2G payload.  Pass 2
@@ -196,29 +175,15 @@ struct TiledShared {
 template <int MODE, int W>
 __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W> &sh)
 {
-    constexpr bool G2P = MODE >= 1, P2G = MODE <= 1;
+    constexpr bool G2P = MODE >= 1, P2G = MODE <= 1 || MODE == 3;
     constexpr int T = 64 * W;
     float4 *tv = sh.tv, *tp = sh.tp;
     Payload4 *pay = sh.pay;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = gload(a.totals).y;
-    // node-pass lane roles: lane o < 27 of each half-wave takes one stencil node
-    const int half = lane >> 5, o = lane & 31;
-    const bool node_lane = o < 27;
-    const int o0 = o / 9, o1 = (o / 3) % 3, o2 = o % 3;
-    const int lo = (o0 * TILE + o1) * TILE + o2;
-    // quadratic B-spline of node offset o_a as alpha (fx - c)^2 + gamma (fx in [0.5, 1.5))
-    float wc[3], wa[3], wg[3];
-    {
-        const int oo[3] = {o0, o1, o2};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            wc[k] = 1.5f - 0.5f * oo[k];
-            wa[k] = oo[k] == 1 ? -1.0f : 0.5f;
-            wg[k] = oo[k] == 1 ? 0.75f : 0.0f;
-        }
-    }
+    const int hw = 2 * wave + (lane >> 5);   // half-wave index
+    const NodeLane nl = node_lane_of(lane);
     int first, stride, end;
     item_range(nitems, first, stride, end);
     for (int it = first; it < end; it += stride) {
@@ -348,7 +313,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                         inv = inverted_f(H, jm1);
                         if (inv) set_flag(d.status, t.env, MPM_FLAG_INVERTED);
                     }
-                    bool write_vc = MODE == 2;
+                    bool write_vc = MODE >= 2;
                     if (P2G) {
                         Stencil s2;
                         if (G2P) make_stencil(x[0], x[1], x[2], e.inv_dx, e.n, s2); else s2 = s;
@@ -361,11 +326,10 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                             affine_stress_f(d, e, H, jm1, inv, C, mu, lam, m, V0, A);
                             int l0, l1, l2;
                             key = stencil_in_tile(t, s2, l0, l1, l2) ? key_in_tile(l0, l1, l2) : key_global(s2.b);
-                            Payload4 &P = pay[tid];
-                            P.fk = make_float4(s2.fx[0], s2.fx[1], s2.fx[2], __int_as_float(key));
-                            P.q1 = make_float4(m * v[0], m * v[1], m * v[2], A[0] * e.dx);
-                            P.q2 = make_float4(A[1] * e.dx, A[2] * e.dx, A[3] * e.dx, A[4] * e.dx);
-                            P.q3 = make_float4(A[5] * e.dx, A[6] * e.dx, A[7] * e.dx, A[8] * e.dx);
+                            const float mv[3] = {m * v[0], m * v[1], m * v[2]};
+#pragma unroll
+                            for (int c = 0; c < 9; ++c) A[c] *= e.dx;
+                            store_payload(pay[tid], s2.fx, key, mv, A);
                         }
                     }
                     if (G2P) {
@@ -387,61 +351,20 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             if (P2G) {
                 if (!key) pay[tid].fk.w = __int_as_float(0);
                 __syncthreads();
-                // ---- pass 2: lane = stencil node; the chunk's particles are split into 2W
-                // contiguous runs, one per half-wave
-                const int hw = 2 * wave + half;
-                float4 *mytile = tp + hw * TILE_NODES;
-                const int n_c = min(T, item_end - chunk);
-                const int per = (n_c + 2 * W - 1) / (2 * W);
-                const int r_end = min(n_c, (hw + 1) * per);
-                // particles are cell-ordered, so consecutive ones usually share the stencil:
-                // sum a run in registers and add it to the tile when the stencil changes
-                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                int cur = -1;
-                for (int r = hw * per; node_lane && r < r_end; ++r) {
-                    const Payload4 &P = pay[r];
-                    const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
-                    const int pk = __float_as_int(fk.w);
-                    const float t0 = fk.x - wc[0], t1 = fk.y - wc[1], t2 = fk.z - wc[2];
-                    const float w = fmaf(wa[0], t0 * t0, wg[0]) * fmaf(wa[1], t1 * t1, wg[1]) *
-                                    fmaf(wa[2], t2 * t2, wg[2]);
-                    const float d0 = o0 - fk.x, d1 = o1 - fk.y, d2 = o2 - fk.z;
-                    float4 c4;
-                    c4.x = w * m;
-                    c4.y = w * fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
-                    c4.z = w * fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
-                    c4.w = w * fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
-                    if (!(pk & KEY_VALID)) continue;
-                    if (pk & KEY_IN_TILE) {
-                        // each half-wave owns a tile; its 27 lanes hit 27 distinct nodes
-                        const int l = (pk >> 2) + lo;
-                        if (l != cur) {
-                            if (cur >= 0) {
-                                float4 old = mytile[cur];
-                                mytile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
-                            }
-                            acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                            cur = l;
-                        }
-                        acc.x += c4.x; acc.y += c4.y; acc.z += c4.z; acc.w += c4.w;
-                    } else {
-                        // stencil outside the tile: straight to the global grid
-                        const int b0 = (pk >> 2) & 1023, b1 = (pk >> 12) & 1023, b2 = (pk >> 22) & 1023;
-                        const int i = b0 + o0, j = b1 + o1, k = b2 + o2;
-                        float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
-                        gatomic_add(g + 0, c4.x);
-                        gatomic_add(g + 1, c4.y);
-                        gatomic_add(g + 2, c4.z);
-                        gatomic_add(g + 3, c4.w);
-                        const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
-                        if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1)
-                            mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
-                    }
-                }
-                if (cur >= 0) {
-                    float4 old = mytile[cur];
-                    mytile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
-                }
+                // ---- pass 2: lane = stencil node, the chunk split into 2W contiguous runs
+                int r0, r1;
+                half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
+                node_pass(pay, r0, r1, tp + hw * TILE_NODES, nl, m, [&](const float4 &c4, int i, int j, int k) {
+                    // stencil outside the tile: straight to the global grid
+                    float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
+                    gatomic_add(g + 0, c4.x);
+                    gatomic_add(g + 1, c4.y);
+                    gatomic_add(g + 2, c4.z);
+                    gatomic_add(g + 3, c4.w);
+                    const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
+                    if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1)
+                        mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
+                });
             }
             if (P2G) __syncthreads();   // payload slots are rewritten by the next chunk
         }
@@ -592,6 +515,11 @@ void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
     launch_mode<2>(d, a, block, nblocks, st);
+}
+
+void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
+{
+    launch_mode<3>(d, a, block, nblocks, st);
 }
 
 void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, int m, int par0, int tail_last,

@@ -22,7 +22,11 @@ struct AdjBuf {
 // -1 no contact / unchanged, else tool * 4 + branch (branch as in ContactRec).
 typedef int8_t ContactCode;
 
-void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, hipStream_t st);
+// Dense grid pass of the tape: V, (m, v-hat) and the contact decision of every node.  With
+// snap != nullptr the tool table (slots entries) is copied there; with
+// next_P != nullptr that grid is zeroed (the next substep's P2G target).
+void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, ToolDev *snap,
+                      int slots, float4 *next_P, hipStream_t st);
 void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st);
 void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
                      const AdjBuf &a, hipStream_t st);

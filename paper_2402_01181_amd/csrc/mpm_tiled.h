@@ -75,6 +75,8 @@ size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+// fused G2P + P2G that also writes v and C (d.gV: this substep's grid, d.gP: the next one's)
+void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
