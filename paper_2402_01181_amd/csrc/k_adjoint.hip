@@ -440,9 +440,9 @@ __global__ void k_fill_f64(double *p, int64_t n)
 // segment was recomputed in), one work item per (brick, slot range).
 
 struct AdjTiledArgs {
-    const int4 *items;
+    const int4 *items;  // (brick, first slot, count, environment)
     const int2 *totals;
-    ActiveBuf act;      // env_bofs only (no marking)
+    ActiveBuf act;      // unused by the reverse kernels (no marking)
 };
 
 // Reverse of G2P + advection + F update.  Pass 1 (lane = particle) forms C'
@@ -463,11 +463,13 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
     const int nitems = gload(ta.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
+    int4 next = first < end ? gload(ta.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
-        const int4 item = gload(ta.items + it);
+        const int4 item = next;   // loaded one iteration ahead
+        if (it + stride < end) next = gload(ta.items + it + stride);
         const int item_end = item.y + item.z;
         EnvDev e;
-        const Tile t = make_tile(d, ta.act, item.x, e);
+        const Tile t = make_tile(d, item, e);
         for (int n = tid; n < TILE_NODES; n += T) {
             int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
             for (int w = 0; w < 2 * W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -619,10 +621,12 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
     const int nitems = gload(ta.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
+    int4 next = first < end ? gload(ta.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
-        const int4 item = gload(ta.items + it);
+        const int4 item = next;   // loaded one iteration ahead
+        if (it + stride < end) next = gload(ta.items + it + stride);
         EnvDev e;
-        const Tile t = make_tile(d, ta.act, item.x, e);
+        const Tile t = make_tile(d, item, e);
         for (int n = tid; n < TILE_NODES; n += T) {
             int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
             float4 Pb = make_float4(0.f, 0.f, 0.f, 0.f);

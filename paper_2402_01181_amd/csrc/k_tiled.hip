@@ -181,15 +181,17 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     Payload4 *pay = sh.pay;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nitems = gload(a.totals).y;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
     const NodeLane nl = node_lane_of(lane);
+    const int nitems = gload(a.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
+    int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
-        const int4 item = gload(a.items + it);
+        const int4 item = next;   // loaded one iteration ahead
+        if (it + stride < end) next = gload(a.items + it + stride);
         EnvDev e;
-        const Tile t = make_tile(d, a.act, item.x, e);
+        const Tile t = make_tile(d, item, e);
         const int item_end = item.y + item.z;
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass

@@ -24,12 +24,13 @@ __device__ __forceinline__ int env_of_brick(const int32_t *env_bofs, int n_envs,
     return lo;
 }
 
-__device__ __forceinline__ Tile make_tile(const Dev &d, const ActiveBuf &act, int brick, EnvDev &e)
+// Tile of work item (brick, first slot, count, environment).
+__device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev &e)
 {
     Tile t;
-    t.env = env_of_brick(act.env_bofs, d.n_envs, brick);
+    t.env = item.w;
     e = load_env(d.env + t.env);
-    int lb = brick - e.bofs;
+    int lb = item.x - e.bofs;
     t.bk = lb % e.nb;
     int r = lb / e.nb;
     t.bj = r % e.nb;
@@ -40,12 +41,15 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const ActiveBuf &act, in
     return t;
 }
 
-// Item walk: contiguous eighth of the list per XCD.
+// Item walk: workgroup x + NXCD r runs on XCD x (workgroups are dealt to the
+// XCDs round-robin) and takes every (G / NXCD)-th item, from its r-th on, of
+// the contiguous eighth of the (spatially ordered) item list that belongs to
+// XCD x, so neighbouring tiles, which share halo nodes, meet in one L2.
 __device__ __forceinline__ void item_range(int nitems, int &first, int &stride, int &end)
 {
-    int G = gridDim.x;               // multiple of NXCD
-    int x = blockIdx.x % NXCD, r = blockIdx.x / NXCD;
-    int per = (nitems + NXCD - 1) / NXCD;
+    const int G = gridDim.x;         // multiple of NXCD
+    const int x = blockIdx.x % NXCD, r = blockIdx.x / NXCD;
+    const int per = (nitems + NXCD - 1) / NXCD;
     first = x * per + r;
     end = min(nitems, (x + 1) * per);
     stride = G / NXCD;

@@ -17,7 +17,7 @@ struct SortBuf {
     int2 *totals;          // [1] (particles, items)
     int32_t *key;          // [ntot] cell of each particle
     int32_t *rank;         // [ntot] rank within the cell
-    int4 *items;           // [max_items] (brick, first slot, count, -)
+    int4 *items;           // [max_items] (brick, first slot, count, environment)
 };
 
 struct ParticleBuf {
@@ -55,7 +55,7 @@ struct TiledArgs {
     const int32_t *pidin;
     float *xout, *vout, *Cout, *Hout;     // particle output (tail: all; fused: x, H)
     int32_t *pidout;                      // copied when pidin != pidout
-    const int4 *items;
+    const int4 *items;                    // (brick, first slot, count, environment)
     const int2 *totals;                   // .y = number of items
     ActiveBuf act;
     int par;                              // dynamic list this kernel's P2G appends to
@@ -67,7 +67,7 @@ struct GridBarrier {
     unsigned *gen;
 };
 
-// act.flag == nullptr: the static brick list is left as it is.
+// act.flag == nullptr: the static brick list is left as it is (act.env_bofs is always used).
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
                  const ParticleBuf &dst, int full, hipStream_t st);
 size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
