@@ -329,3 +329,60 @@ def test_far_drift_between_sorts(gpu, orc, persistent):
     assert moved > 2.5
     assert ex <= 2e-5 and ev <= 1e-4 and eF <= 1e-5 and etd <= 1e-5
     assert tiled.read(L.F_STATUS) == 0 and tiled.read(L.F_STEP) == S
+
+
+def _ragged_scene(seed=11):
+    """Three small environments of ragged sizes: one particle on an 8^3 grid,
+    17 particles on a 12^3 grid, 300 in a cube on a 16^3 grid, all moving."""
+    rng = np.random.default_rng(seed)
+    envs = []
+    for n, N, lo, hi in ((8, 1, 0.45, 0.55), (12, 17, 0.35, 0.65), (16, 300, 0.3, 0.6)):
+        x = scenes.box_uniform(rng, N, (lo,) * 3, (hi,) * 3)
+        v, C, F = scenes._rest_state(x)
+        env = scenes.Env(n=n, x=x, v=v, C=C, F=F, E=3e3, nu=0.3, rho=1e3, V0=(hi - lo) ** 3 / N)
+        scenes.perturbed_state(rng, env, v_scale=0.2, C_scale=1.0, F_scale=0.01)
+        envs.append(env)
+    return scenes.Scene("ragged", envs, dt=1e-4, substeps=20)
+
+
+@pytest.mark.parametrize("block,item", [(64, 16), (256, 4096), (128, 48)])
+def test_ragged_tiny_environments(gpu, orc, block, item):
+    """Edge shapes: a one-particle environment, the smallest grid (8^3), item
+    sizes from 16 to 4096 particles and workgroups of 64 to 256 threads; every
+    environment free-runs 20 substeps against the oracle."""
+    Sim, L = gpu
+    sc = _ragged_scene()
+    _say(f"ragged tiny envs: N {[e.N for e in sc.envs]}, grids {[e.n for e in sc.envs]}, block {block}, item {item}")
+    sim = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: block, L.OPT_ITEM: item, L.OPT_SORT_EVERY: 7})
+    sim.step(13)
+    sim.step(7)
+    for e, env in enumerate(sc.envs):
+        o = orc.Sim(env, dt=sc.dt, gravity=sc.gravity, bound=sc.bound).run(sc.substeps)
+        x, v, C, F = sim.particles(e)
+        ex = np.abs(x - o.state.x).max()
+        ev = rel_err(v, o.state.v, FLOORS["v"])
+        _say(f"  env {e}: |dx| {ex:.2e}, v err {ev:.2e}")
+        assert ex <= 1e-5 and ev <= 1e-4
+        assert sim.read(L.F_STATUS, e) == 0 and sim.read(L.F_STEP, e) == sc.substeps
+
+
+def test_autotune_picks_and_caches(gpu, orc, tmp_path):
+    """The autotuner times its candidates, returns one of them, and a second
+    call is answered from the JSON cache."""
+    Sim, L = gpu
+    from paper_2402_01181_amd.autotune import autotune, workload_key
+    import json
+    sc = scenes.cube_scene(seed=1, substeps=10)
+    cache = str(tmp_path / "tune.json")
+    kw = dict(substeps=8, warmup=2, cache=cache, blocks=(64, 256), items=(64, 512), sort_every=(8, 16),
+              graph=(0, 1), persistent=(0,))
+    best = autotune(sc, **kw)
+    _say(f"autotune cube: {best}")
+    assert best[L.OPT_BLOCK] in (64, 256) and best[L.OPT_ITEM] in (64, 512) and best[L.OPT_SORT_EVERY] in (8, 16)
+    table = json.load(open(cache))
+    entry = table[workload_key(sc)]
+    assert len(entry["trials"]) == 4 + 2 + 2
+    assert autotune(sc, **kw) == best
+    s = Sim(sc, options=best)   # the options are accepted by the library
+    s.step(10)
+    assert s.read(L.F_STATUS) == 0
