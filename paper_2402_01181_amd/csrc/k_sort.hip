@@ -28,8 +28,11 @@ __device__ __forceinline__ int particle_cell(const EnvDev &e, float x0, float x1
 
 // Cell key and rank of each particle, and the particle count of every cell
 // and brick.  Particles arrive mostly in cell order (from the previous sort),
-// so a wavefront holds few distinct cells and bricks: the lanes of one cell
-// (brick) take their ranks from a single increment made by the lowest of them.
+// so a wavefront holds few distinct cells and bricks.  The lanes of one cell
+// are grouped first (ballots, no memory traffic); then the lowest lane of
+// every group adds the group's size to its cell's counter, all groups in one
+// atomic instruction, and each lane's rank is that base plus its position in
+// the group.
 __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
@@ -42,27 +45,35 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s)
         gstore(s.key + q, key);
     }
     const unsigned long long lower = (1ull << lane) - 1ull;
+    const int brick = key >> 6;
+    int leader = lane, pos = 0, size = 0;        // cell group
+    int bleader = lane, bsize = 0;               // brick group
     unsigned long long pending = __ballot(valid);
-    int rank = 0;
     while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int kc = __shfl(key, leader);
+        const int l = __builtin_ctzll(pending);
+        const int kc = __shfl(key, l);
         const unsigned long long same = __ballot(valid && key == kc);
-        int base = 0;
-        if (lane == leader) base = gatomic_add(s.count + kc, (int)__popcll(same));
-        base = __shfl(base, leader);
-        if ((same >> lane) & 1ull) rank = base + (int)__popcll(same & lower);
+        if ((same >> lane) & 1ull) {
+            leader = l;
+            pos = (int)__popcll(same & lower);
+        }
+        if (lane == l) size = (int)__popcll(same);
         pending &= ~same;
     }
-    if (valid) gstore(s.rank + q, rank);
-    const int brick = key >> 6;
     pending = __ballot(valid);
     while (pending) {
-        const int kb = __shfl(brick, __builtin_ctzll(pending));
+        const int l = __builtin_ctzll(pending);
+        const int kb = __shfl(brick, l);
         const unsigned long long same = __ballot(valid && brick == kb);
-        if (lane == __builtin_ctzll(pending)) gatomic_add(s.brick_count + kb, (int)__popcll(same));
+        if ((same >> lane) & 1ull) bleader = l;
+        if (lane == l) bsize = (int)__popcll(same);
         pending &= ~same;
     }
+    int base = 0;
+    if (valid && lane == leader) base = gatomic_add(s.count + key, size);
+    if (valid && lane == bleader) gatomic_add(s.brick_count + brick, bsize);
+    base = __shfl(base, leader);
+    if (valid) gstore(s.rank + q, base + pos);
 }
 
 // Block-wide exclusive scan of int2 over 256 threads x 4 elements.
