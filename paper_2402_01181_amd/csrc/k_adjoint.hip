@@ -660,7 +660,10 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
                     }
 #pragma unroll
                     for (int c = 0; c < 3; ++c) v[c] = gload(d.v + (size_t)c * N + q);
-                    bool inverted = kirchhoff(H, mu, lam, tau);
+                    // the forward's FP32 stress (same formulas, same inversion decision)
+                    const float jm1 = jm1_f(H);
+                    const bool inverted = inverted_f(H, jm1);
+                    kirchhoff_f(H, jm1, inverted, mu, lam, tau);
 #pragma unroll
                     for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
                     float dw[3][3];
@@ -722,36 +725,34 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
                         for (int c = 0; c < 3; ++c)
                             Fb[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
                                                   (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
-                    double trt = (double)taub[0] + taub[4] + taub[8];
-                    double jm1 = jm1_of(H);
-                    double lnJ = inverted ? log(J_MIN) : log1p(jm1);
+                    // tau-bar -> F-bar: mu (tau-bar + tau-bar^T) F + lam tr(tau-bar) cof(F) / J
+                    const float trt = taub[0] + taub[4] + taub[8];
+                    const float lnJ = inverted ? -13.815510557964274f : log1pf(jm1);
                     if (!inverted) {
-                        double f[9];
+                        const float ci[9] = {F[4] * F[8] - F[5] * F[7], -(F[3] * F[8] - F[5] * F[6]), F[3] * F[7] - F[4] * F[6],
+                                             -(F[1] * F[8] - F[2] * F[7]), F[0] * F[8] - F[2] * F[6], -(F[0] * F[7] - F[1] * F[6]),
+                                             F[1] * F[5] - F[2] * F[4], -(F[0] * F[5] - F[2] * F[3]), F[0] * F[4] - F[1] * F[3]};
+                        const float sc = lam * trt / (1.0f + jm1);
 #pragma unroll
-                        for (int c = 0; c < 9; ++c) f[c] = (double)H[c] + ((c & 3) == 0 ? 1.0 : 0.0);
-                        double ci[9] = {f[4] * f[8] - f[5] * f[7], -(f[3] * f[8] - f[5] * f[6]), f[3] * f[7] - f[4] * f[6],
-                                        -(f[1] * f[8] - f[2] * f[7]), f[0] * f[8] - f[2] * f[6], -(f[0] * f[7] - f[1] * f[6]),
-                                        f[1] * f[5] - f[2] * f[4], -(f[0] * f[5] - f[2] * f[3]), f[0] * f[4] - f[1] * f[3]};
-                        double sc = (double)lam * trt / (1.0 + jm1);
-#pragma unroll
-                        for (int c = 0; c < 9; ++c) Fb[c] += (float)(sc * ci[c]);
+                        for (int c = 0; c < 9; ++c) Fb[c] = fmaf(sc, ci[c], Fb[c]);
                     }
 #pragma unroll
                     for (int c = 0; c < 9; ++c) {
                         float *pf = a.Fb + (size_t)c * N + q;
                         gstore(pf, gload(pf) + Fb[c]);
                     }
-                    double ff = 0.0;
+                    // dL/dmu and dL/dlam of this particle (summed per environment in FP64)
+                    float ff = 0.0f;
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            double G = (double)H[3 * r + c] + H[3 * c + r] + (double)H[3 * r] * H[3 * c] +
-                                       (double)H[3 * r + 1] * H[3 * c + 1] + (double)H[3 * r + 2] * H[3 * c + 2];
-                            ff += (double)taub[3 * r + c] * G;
+                            const float G = H[3 * r + c] + H[3 * c + r] + H[3 * r] * H[3 * c] + H[3 * r + 1] * H[3 * c + 1] +
+                                            H[3 * r + 2] * H[3 * c + 2];
+                            ff = fmaf(taub[3 * r + c], G, ff);
                         }
                     mub = ff;
-                    lamb = trt * lnJ;
+                    lamb = (double)trt * lnJ;
                 }
             }
             // every particle of an item belongs to the tile's environment

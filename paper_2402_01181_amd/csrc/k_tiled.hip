@@ -109,43 +109,16 @@ __device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e
 template <class T>
 __device__ __forceinline__ T *comp(T *base, int c, int N) { return base + (size_t)c * N; }
 
-// FP32 J - 1 from H (terms of order |H|, |H|^2, |H|^3: nothing cancels).
-__device__ __forceinline__ float jm1_f(const float H[9])
-{
-    float tr = H[0] + H[4] + H[8];
-    float m2 = fmaf(H[0], H[4], -H[1] * H[3]) + fmaf(H[0], H[8], -H[2] * H[6]) + fmaf(H[4], H[8], -H[5] * H[7]);
-    float c0 = fmaf(H[4], H[8], -H[5] * H[7]), c1 = fmaf(H[3], H[8], -H[5] * H[6]), c2 = fmaf(H[3], H[7], -H[4] * H[6]);
-    float dt = fmaf(H[0], c0, fmaf(-H[1], c1, H[2] * c2));
-    return tr + m2 + dt;
-}
-
-// J <= J_MIN?  Decided in FP64 whenever the FP32 value is within reach of
-// the threshold.
-__device__ __forceinline__ bool inverted_f(const float H[9], float jm1)
-{
-    if (jm1 > -0.999f) return false;
-    return inverted_h(H);
-}
-
-// A = -dt V0 (4/dx^2) tau(F) + m C with tau = mu (H + H^T + H H^T) + lam ln J I
-// (the MLS force folded into the affine term); ln J = log1p(J - 1).
+// A = -dt V0 (4/dx^2) tau(F) + m C (the MLS force folded into the affine term).
 __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, const float H[9], float jm1,
                                                 bool inv, const float C[9], float mu, float lam, float m, float V0,
                                                 float A[9])
 {
-    const float p = lam * (inv ? -13.815510557964274f : log1pf(jm1));   // ln J_MIN = ln 1e-6
+    float tau[9];
+    kirchhoff_f(H, jm1, inv, mu, lam, tau);
     const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b) {
-            float s = H[3 * a + b] + H[3 * b + a];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) s = fmaf(H[3 * a + c], H[3 * b + c], s);
-            float t = k * (mu * s + (a == b ? p : 0.0f));
-            A[3 * a + b] = fmaf(m, C[3 * a + b], t);
-            if (a != b) A[3 * b + a] = fmaf(m, C[3 * b + a], t);
-        }
+    for (int c = 0; c < 9; ++c) A[c] = fmaf(m, C[c], k * tau[c]);
 }
 
 // MODE 0: P2G only (head of a call; reads x, v, C, H).

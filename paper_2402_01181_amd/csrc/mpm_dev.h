@@ -243,6 +243,42 @@ __device__ __forceinline__ bool kirchhoff(const float H[9], float mu, float lam,
 
 __device__ __forceinline__ bool inverted_h(const float H[9]) { return !(1.0 + jm1_of(H) > J_MIN); }
 
+// FP32 J - 1 from H (terms of order |H|, |H|^2, |H|^3: nothing cancels).
+__device__ __forceinline__ float jm1_f(const float H[9])
+{
+    float tr = H[0] + H[4] + H[8];
+    float m2 = fmaf(H[0], H[4], -H[1] * H[3]) + fmaf(H[0], H[8], -H[2] * H[6]) + fmaf(H[4], H[8], -H[5] * H[7]);
+    float c0 = fmaf(H[4], H[8], -H[5] * H[7]), c1 = fmaf(H[3], H[8], -H[5] * H[6]), c2 = fmaf(H[3], H[7], -H[4] * H[6]);
+    float dt = fmaf(H[0], c0, fmaf(-H[1], c1, H[2] * c2));
+    return tr + m2 + dt;
+}
+
+// J <= J_MIN?  Decided in FP64 whenever the FP32 value is within reach of
+// the threshold.
+__device__ __forceinline__ bool inverted_f(const float H[9], float jm1)
+{
+    if (jm1 > -0.999f) return false;
+    return inverted_h(H);
+}
+
+// Neo-Hookean Kirchhoff stress tau = mu (H + H^T + H H^T) + lam ln J I in
+// FP32 from J - 1 (see jm1_f); ln J = log1p(J - 1), or ln J_MIN when inverted.
+__device__ __forceinline__ void kirchhoff_f(const float H[9], float jm1, bool inv, float mu, float lam, float tau[9])
+{
+    const float p = lam * (inv ? -13.815510557964274f : log1pf(jm1));   // ln J_MIN = ln 1e-6
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            float s = H[3 * a + b] + H[3 * b + a];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s = fmaf(H[3 * a + c], H[3 * b + c], s);
+            const float t = mu * s + (a == b ? p : 0.0f);
+            tau[3 * a + b] = t;
+            tau[3 * b + a] = t;
+        }
+}
+
 // H' = H + dt C (I + H): the F update F' = (I + dt C) F written for H.
 __device__ __forceinline__ void update_h(float H[9], const float C[9], float dt)
 {
