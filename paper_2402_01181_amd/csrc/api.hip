@@ -666,6 +666,7 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
             c->pofs[e + 1] = c->pofs[e] + c->np[e];
             c->gofs[e + 1] = c->gofs[e] + (int64_t)n * n * n;
             c->bofs[e + 1] = c->bofs[e] + (n / 4) * (n / 4) * (n / 4);
+            // n = 4 nb, so gofs = 64 bofs for every environment (the grid kernel relies on it)
             EnvDev &E = envh[e];
             memset(&E, 0, sizeof E);
             E.n = n;

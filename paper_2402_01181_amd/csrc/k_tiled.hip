@@ -394,13 +394,15 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         const bool dyn = i >= ns;
         const int b = dyn ? gload(dl + (i - ns)) : bs;
         if (i + stride < a.nbricks) bs = gload(a.slist + i + stride);
+        // environments' grids are consecutive brick-major slices, so node l of brick b is
+        // node 64 b + l of the whole grid: P is loaded without waiting for the environment
+        const int64_t g = (int64_t)b * BRICK_NODES + lane;
+        float4 P = gload(d.gP + g);
         int env = env_of_brick(a.env_bofs, d.n_envs, b);
         const EnvDev e = load_env(d.env + env);
         int lb = b - e.bofs;
         int gi, gj, gk;
         brick_local_to_ijk(e, lb, lane, gi, gj, gk);
-        int64_t g = e.gofs + (int64_t)lb * 64 + lane;
-        float4 P = gload(d.gP + g);
         float3 v = grid_node_velocity(d, e, env, P, gi, gj, gk, nullptr);
         gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
         gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));
