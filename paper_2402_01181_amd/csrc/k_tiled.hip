@@ -1,10 +1,10 @@
 // Tiled scheme kernels.
 //
-// Particles are sorted by the 4x4x4-cell brick of their stencil base; a work
-// item is (brick, slot range).  For each item a workgroup stages the 6^3
-// nodes the brick's stencils reach in LDS:
+// Particles are sorted by the cell of their stencil base, brick-major; a work
+// item is (brick, slot range, environment).  For each item a workgroup stages
+// the 6^3 nodes the brick's stencils reach in LDS:
 //   - G2P reads node velocities from the tile,
-//   - P2G accumulates mass/momentum into per-wavefront tiles and flushes each
+//   - P2G accumulates mass/momentum into per-half-wave tiles and flushes each
 //     non-empty tile node to the global grid with one float atomic per
 //     component,
 // so global atomics scale with tile nodes, not with particles x 27.  A
@@ -34,13 +34,9 @@ __device__ __forceinline__ void advance_end_of_substep(const Dev &d)
     }
 }
 
-// G2P of one particle: velocity and the affine matrix
-// C = (4/dx) sum w v (o - fx), from the LDS tile or, when the stencil is
-// outside the tile, from global memory.
-template <bool FROM_TILE>
-__device__ __forceinline__ void g2p_accumulate(const Dev &d, const EnvDev &e, const Stencil &s, int l0, int l1,
-                                               int l2, const float *tvx, const float *tvy, const float *tvz,
-                                               float vp[3], float Cn[9])
+// G2P of one particle whose stencil is outside the item's tile (drift since
+// the sort): velocity and C = (4/dx) sum w v (o - fx)^T from global memory.
+__device__ __forceinline__ void g2p_global(const Dev &d, const EnvDev &e, const Stencil &s, float vp[3], float Cn[9])
 {
     float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     vp[0] = vp[1] = vp[2] = 0.f;
@@ -50,17 +46,10 @@ __device__ __forceinline__ void g2p_accumulate(const Dev &d, const EnvDev &e, co
         for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
             for (int o2 = 0; o2 < 3; ++o2) {
-                float V0, V1, V2;
-                if (FROM_TILE) {
-                    int li = ((l0 + o0) * TILE + l1 + o1) * TILE + l2 + o2;
-                    V0 = tvx[li]; V1 = tvy[li]; V2 = tvz[li];
-                } else {
-                    float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
-                    V0 = V.x; V1 = V.y; V2 = V.z;
-                }
-                float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
-                float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
-                float wx = w * V0, wy = w * V1, wz = w * V2;
+                const float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
+                const float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
+                const float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
                 vp[0] += wx; vp[1] += wy; vp[2] += wz;
                 B[0] += wx * d0; B[1] += wx * d1; B[2] += wx * d2;
                 B[3] += wy * d0; B[4] += wy * d1; B[5] += wy * d2;
@@ -69,38 +58,6 @@ __device__ __forceinline__ void g2p_accumulate(const Dev &d, const EnvDev &e, co
     const float cs = 4.0f * e.inv_dx;
 #pragma unroll
     for (int c = 0; c < 9; ++c) Cn[c] = cs * B[c];
-}
-
-// P2G of one particle into the tile (LDS atomics) or, when its stencil is
-// outside the tile, into the global grid.  The two paths are separate loops
-// so every atomic has a fixed address space.
-__device__ __forceinline__ void p2g_weights(const EnvDev &e, const Stencil &s, float m, const float A[9],
-                                            const float v[3], int o0, int o1, int o2, float &pm, float &p0,
-                                            float &p1, float &p2)
-{
-    float d0 = (o0 - s.fx[0]) * e.dx, d1 = (o1 - s.fx[1]) * e.dx, d2 = (o2 - s.fx[2]) * e.dx;
-    float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
-    p0 = w * (m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2);
-    p1 = w * (m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2);
-    p2 = w * (m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2);
-    pm = w * m;
-}
-
-
-// A = -dt V0 (4/dx^2) tau(F) + m C   (MLS force folded into the affine term)
-__device__ __forceinline__ void affine_with_stress(const Dev &d, const EnvDev &e, int env, const float H[9],
-                                                   const float C[9], float A[9], float &m)
-{
-    const float *mat = d.material + 4 * env;
-    float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
-    float mu, lam;
-    lame(E, nu, mu, lam);
-    m = rho * V0;
-    float tau[9];
-    if (kirchhoff(H, mu, lam, tau)) set_flag(d.status, env, MPM_FLAG_INVERTED);
-    const float k = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A[c] = k * tau[c] + m * C[c];
 }
 
 // Component c of a [comp][N] particle array: a uniform base pointer, so a
@@ -134,10 +91,10 @@ __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, c
 // nodes per step, sum the contributions of consecutive particles with the
 // same stencil (the sort groups particles by cell) in registers, and add
 // each sum to the half-wave's own LDS tile with plain read-modify-write
-// (27 lanes, 27 distinct nodes).  LDS float
-// atomics run at about 1/3 lane per clock per CU on this chip, far below
-// plain LDS traffic.  The 2W tiles are summed and flushed to the global grid
-// with one float atomic per component per non-empty node.
+// (27 lanes, 27 distinct nodes).  LDS float atomics run at about 1/3 lane
+// per clock per CU on this chip, far below plain LDS traffic.  The 2W tiles
+// are summed and flushed to the global grid with one float atomic per
+// component per non-empty node.
 template <int W>
 struct TiledShared {
     float4 tv[TILE_NODES];            // node velocities
@@ -267,7 +224,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
                         } else {
-                            g2p_accumulate<false>(d, e, s, 0, 0, 0, nullptr, nullptr, nullptr, v, C);
+                            g2p_global(d, e, s, v, C);
                         }
                         x[0] += d.dt * v[0];
                         x[1] += d.dt * v[1];

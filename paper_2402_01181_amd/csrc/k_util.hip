@@ -23,12 +23,6 @@ __global__ void k_iota(int32_t *p, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
 }
 
-__global__ void k_copy_f32(float *dst, const float *src, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
 // Particle slot q of environment [pofs, pofs+np) holds original particle
 // pid[q]; write it to dst[c][pid[q] - pofs].
 __global__ void k_read_particles(const float *src, const int32_t *pid, int ntot, int pofs, int np, int comps,
@@ -94,11 +88,6 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t st)
 void launch_iota(int32_t *p, int n, hipStream_t st)
 {
     launch_k(k_iota, dim3(grid_for(n)), dim3(256), 0, st, p, n);
-}
-
-void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t st)
-{
-    launch_k(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
 }
 
 void launch_read_particles(const float *src, const int32_t *pid, int ntot, int pofs, int np, int comps,

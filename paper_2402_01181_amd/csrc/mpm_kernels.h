@@ -13,7 +13,6 @@ void launch_g2p_direct(const Dev &d, hipStream_t st);
 void launch_fill_f4(float4 *p, int64_t n, hipStream_t st);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t st);
 void launch_iota(int32_t *p, int n, hipStream_t st);
-void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t st);
 void launch_read_particles(const float *src, const int32_t *pid, int ntot, int pofs, int np, int comps,
                            float *dst, hipStream_t st);
 void launch_write_particles(float *dst, const int32_t *pid, int ntot, int pofs, int np, int comps,

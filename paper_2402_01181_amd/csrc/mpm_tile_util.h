@@ -1,6 +1,6 @@
 // Device helpers shared by the tiled forward and adjoint kernels: brick
-// tiles, the XCD-aware item walk, active-brick marking and the per-particle
-// payload handed from a particle pass to a node pass.
+// tiles, the XCD-aware item walk, listing of far bricks, and the node pass
+// (a particle pass hands each particle's payload to lanes = stencil nodes).
 #pragma once
 #include "mpm_tiled.h"
 
