@@ -142,7 +142,7 @@ def stored_traffic(config: str, kernel: str, options) -> float | None:
     if t.get("source_sha256") != source_hash():
         return None
     from paper_2402_01181_amd import _lib as L
-    shape = (L.OPT_SCHEME, L.OPT_SORT_EVERY, L.OPT_BLOCK, L.OPT_ITEM, L.OPT_PERSISTENT)
+    shape = (L.OPT_SCHEME, L.OPT_SORT_EVERY, L.OPT_BLOCK, L.OPT_ITEM, L.OPT_PERSISTENT, L.OPT_NODE_SLOTS)
     mine = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in options.items()}}
     theirs = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in t.get("options", {}).items()}}
     if any(mine[k] != theirs[k] for k in shape):
@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--item", type=int, default=None)
     ap.add_argument("--graph", type=int, default=None)
     ap.add_argument("--persistent", type=int, default=None)
+    ap.add_argument("--slots", type=int, default=None, help="node-pass particles per half-wave step (1 or 3)")
     ap.add_argument("--cpu-substeps", type=int, default=None,
                     help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -210,6 +211,7 @@ def main():
     if args.item: opts[L.OPT_ITEM] = args.item
     if args.graph is not None: opts[L.OPT_GRAPH] = args.graph
     if args.persistent is not None: opts[L.OPT_PERSISTENT] = args.persistent
+    if args.slots is not None: opts[L.OPT_NODE_SLOTS] = args.slots
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

@@ -88,7 +88,9 @@ enum {
                                  kernel (grid operation and particle pass separated by grid barriers with
                                  a bounded spin; a timeout sets MPM_FLAG_BARRIER_TIMEOUT) */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
-    MPM_OPT_ITEM = 6          /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
+    MPM_OPT_ITEM = 6,         /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
+    MPM_OPT_NODE_SLOTS = 7    /* tiled scheme: particles per half-wavefront step of the P2G node pass, 1 or 3
+                                 (3: a third of the arithmetic per node, better at many particles per cell) */
 };
 enum {
     MPM_SCHEME_DIRECT = 0,    /* one thread per particle, global float atomics, dense grid pass */

@@ -20,11 +20,11 @@ F_X, F_V, F_C, F_F, F_GRID_M, F_GRID_MV, F_GRID_V, F_STATUS, F_TOOL_T, F_STEP = 
 TOOL_CAPSULE = 0
 CONTACT_SLIP, CONTACT_STICKY = 0, 1
 STAGE_P2G, STAGE_GRID, STAGE_G2P = 0, 1, 2
-OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM = range(7)
+OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM, OPT_NODE_SLOTS = range(8)
 SCHEME_DIRECT, SCHEME_TILED = 0, 1
 # option values a new context starts with
 OPT_DEFAULTS = {OPT_SCHEME: SCHEME_TILED, OPT_SORT_EVERY: 16, OPT_BLOCK: 256, OPT_GRAPH: 0, OPT_PERSISTENT: 0,
-                OPT_ITEM: 512}
+                OPT_ITEM: 512, OPT_NODE_SLOTS: 3}
 
 EXPORTS = ["mpm_workspace_size", "mpm_create", "mpm_destroy", "mpm_set_tool", "mpm_set_option",
            "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error",

@@ -1,7 +1,8 @@
 """Autotuner for the tiled scheme's launch shapes.
 
-Searches, in stages, the workgroup size (MPM_OPT_BLOCK), the particles per
-work item (MPM_OPT_ITEM), the sort interval (MPM_OPT_SORT_EVERY), and the
+Searches, in stages, the workgroup size (MPM_OPT_BLOCK) with the particles per
+work item (MPM_OPT_ITEM) and the node-pass form (MPM_OPT_NODE_SLOTS), the sort
+interval (MPM_OPT_SORT_EVERY), and the
 persistent kernel (MPM_OPT_PERSISTENT) with or without graph replay
 (MPM_OPT_GRAPH) for a scene, timing short runs with HIP events on the
 stream the library launches on.  Every setting gives the same results up to
@@ -45,7 +46,7 @@ def _time(sim: Sim, substeps: int, warmup: int) -> float:
 
 def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = CACHE,
              blocks=(64, 128, 256), items=(32, 64, 128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
-             graph=(0, 1), persistent=(0, 1), verbose: bool = False) -> Dict[int, int]:
+             graph=(0, 1), persistent=(0, 1), slots=(1, 3), verbose: bool = False) -> Dict[int, int]:
     """Best options {MPM_OPT_*: value} for this scene (tiled scheme)."""
     key = workload_key(scene)
     table = {}
@@ -59,7 +60,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
 
     sim = Sim(scene, options={L.OPT_SCHEME: L.SCHEME_TILED})
     best = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: 256, L.OPT_ITEM: 512, L.OPT_SORT_EVERY: 16,
-            L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0}
+            L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0, L.OPT_NODE_SLOTS: 3}
     log: List[dict] = []
 
     def trial(opts):
@@ -84,7 +85,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
             scores.append((trial(opts), opts))
         best = min(scores, key=lambda t: t[0])[1]
 
-    stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i} for b in blocks for i in items])
+    stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i, L.OPT_NODE_SLOTS: n} for b in blocks for i in items for n in slots])
     stage([{L.OPT_SORT_EVERY: k} for k in sort_every])
     stage([{L.OPT_PERSISTENT: p, L.OPT_GRAPH: g} for p in persistent for g in graph])
     sim.close()

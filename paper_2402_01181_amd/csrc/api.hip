@@ -263,6 +263,7 @@ TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf 
     a.xout = out.x; a.vout = out.v; a.Cout = out.C; a.Hout = out.H; a.pidout = out.pid;
     a.items = c->sort.items;
     a.totals = c->sort.totals;
+    a.slots = c->node_slots;
     a.act = c->act;
     a.par = par;
     return a;
@@ -361,7 +362,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
     GraphEntry *ge = nullptr;
     for (auto &g : c->graphs)
         if (g.n == n && g.scheme == c->scheme && g.block == c->block && g.item == c->item &&
-            g.sort_every == c->sort_every && g.persistent == c->persistent)
+            g.sort_every == c->sort_every && g.persistent == c->persistent && g.node_slots == c->node_slots)
             ge = &g;
     if (!ge) {
         if (c->scheme == MPM_SCHEME_TILED && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -375,6 +376,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
         GraphEntry g;
         g.n = n; g.scheme = c->scheme; g.block = c->block; g.item = c->item; g.sort_every = c->sort_every;
         g.persistent = c->persistent;
+        g.node_slots = c->node_slots;
         if (c->persistent && c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -554,7 +556,7 @@ void reverse_segment_tiled(mpm_ctx *c, int s_begin, int lo, int s_end, int s0, h
         d.tools = T.seg_tools + (size_t)slot * c->tool_slots();
         a.j = j - s0;
         timed(c, st, PK_ADJ_G2P, [&] {
-            launch_adj_g2p_tiled(d, a, c->sort.items, c->sort.totals, ta, c->block, c->tiled_blocks, st);
+            launch_adj_g2p_tiled(d, a, c->sort.items, c->sort.totals, c->node_slots, ta, c->block, c->tiled_blocks, st);
         });
         timed(c, st, PK_ADJ_GRID, [&] {
             launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
@@ -788,6 +790,10 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
     case MPM_OPT_ITEM:
         if (value < 16 || value > 4096 || value % 16) return fail(c, MPM_E_ARG, "item size must be a multiple of 16 in [16, 4096]");
         c->item = value;
+        return MPM_OK;
+    case MPM_OPT_NODE_SLOTS:
+        if (value != 1 && value != 3) return fail(c, MPM_E_ARG, "node slots must be 1 or 3");
+        c->node_slots = value;
         return MPM_OK;
     case MPM_OPT_GRAPH:
         c->use_graph = value != 0;

@@ -442,6 +442,7 @@ __global__ void k_fill_f64(double *p, int64_t n)
 struct AdjTiledArgs {
     const int4 *items;  // (brick, first slot, count, environment)
     const int2 *totals;
+    int slots;          // node pass: particles per half-wave step (1 or 3)
     ActiveBuf act;      // unused by the reverse kernels (no marking)
 };
 
@@ -459,7 +460,6 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
     __shared__ Payload4 pay[T];
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);
-    const NodeLane nl = node_lane_of(lane);
     const int nitems = gload(ta.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
             int r0, r1;
             half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
             // .x sums the weights (the flush skips nodes no particle reached)
-            node_pass(pay, r0, r1, tp + hw * TILE_NODES, nl, 1.0f, [&](const float4 &c4, int i, int j, int k) {
+            node_pass(ta.slots, pay, r0, r1, tp + hw * TILE_NODES, lane, 1.0f, [&](const float4 &c4, int i, int j, int k) {
                 float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
                 gatomic_add(g + 0, c4.y);
                 gatomic_add(g + 1, c4.z);
@@ -812,10 +812,10 @@ void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double 
     launch_k(k_adj_finish, dim3((nt + 255) / 256), dim3(256), 0, st, d, a, n, gE, gnu, gu, gT);
 }
 
-void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals, int slots,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st)
 {
-    AdjTiledArgs ta{items, totals, act};
+    AdjTiledArgs ta{items, totals, slots, act};
     if (block == 64) launch_k((k_adj_g2p_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
     else if (block == 128) launch_k((k_adj_g2p_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
     else launch_k((k_adj_g2p_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
@@ -824,7 +824,7 @@ void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, cons
 void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st)
 {
-    AdjTiledArgs ta{items, totals, act};
+    AdjTiledArgs ta{items, totals, 1, act};
     if (block == 64) launch_k((k_adj_p2g_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
     else if (block == 128) launch_k((k_adj_p2g_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
     else launch_k((k_adj_p2g_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);

@@ -112,7 +112,6 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
-    const NodeLane nl = node_lane_of(lane);
     const int nitems = gload(a.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
@@ -286,7 +285,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                 // ---- pass 2: lane = stencil node, the chunk split into 2W contiguous runs
                 int r0, r1;
                 half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
-                node_pass(pay, r0, r1, tp + hw * TILE_NODES, nl, m, [&](const float4 &c4, int i, int j, int k) {
+                node_pass(a.slots, pay, r0, r1, tp + hw * TILE_NODES, lane, m, [&](const float4 &c4, int i, int j, int k) {
                     // stencil outside the tile: straight to the global grid
                     float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
                     gatomic_add(g + 0, c4.x);

@@ -33,7 +33,7 @@ void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes,
 void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st);
 void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
                        hipStream_t st);
-void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
+void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals, int slots,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st);
 void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st);

@@ -35,7 +35,7 @@ struct Profiler {
 // One captured call of n substeps (MPM_OPT_GRAPH) and the host-side
 // sequencing state that call leaves behind.
 struct GraphEntry {
-    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0;
+    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0, node_slots = 0;
     hipGraphExec_t exec = nullptr;
     int since_sort_after = 0;
 };
@@ -54,6 +54,7 @@ struct mpm_ctx {
     hipStream_t stream0 = nullptr;
     // options
     int scheme = MPM_SCHEME_TILED, sort_every = 16, block = 256, item = 512, use_graph = 0, persistent = 0;
+    int node_slots = 3;                // particles per half-wave step in the P2G node pass (1 or 3)
     int spin_limit = 1 << 22;
     // device buffers carved from the caller's workspace
     mpm::EnvDev *env = nullptr;

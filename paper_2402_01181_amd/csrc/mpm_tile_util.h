@@ -108,18 +108,19 @@ __device__ __forceinline__ void store_payload(Payload4 &P, const float fx[3], in
     P.q3 = make_float4(M[5], M[6], M[7], M[8]);
 }
 
-// Node-pass role of a lane: lane o < 27 of each half-wave takes stencil node
-// (o0, o1, o2); the quadratic B-spline of that offset is alpha (fx - c)^2 +
-// gamma per axis (fx in [0.5, 1.5)), three constants instead of a branch.
-struct NodeLane {
+// One particle per half-wave step (node_pass1).  Lane o < 27 of each
+// half-wave takes stencil node (o0, o1, o2); the quadratic B-spline of that
+// offset is alpha (fx - c)^2 + gamma per axis (fx in [0.5, 1.5)), three
+// constants instead of a branch.
+struct NodeLane1 {
     bool on;
     int o0, o1, o2, lo;   // lo: tile offset of the node from the stencil base
     float wc[3], wa[3], wg[3];
 };
 
-__device__ __forceinline__ NodeLane node_lane_of(int lane)
+__device__ __forceinline__ NodeLane1 node_lane1(int lane)
 {
-    NodeLane L;
+    NodeLane1 L;
     const int o = lane & 31;
     L.on = o < 27;
     L.o0 = o / 9; L.o1 = (o / 3) % 3; L.o2 = o % 3;
@@ -134,16 +135,18 @@ __device__ __forceinline__ NodeLane node_lane_of(int lane)
     return L;
 }
 
-// Node pass of one half-wave over payloads [r0, r1).  Consecutive particles
-// with the same stencil (the sort groups particles by cell) are summed in
-// registers and the sum is added to the half-wave's own LDS tile with a plain
-// read-modify-write when the stencil changes: the 27 lanes touch 27 distinct
-// nodes and no other half-wave writes the tile, so no atomic is needed.  A
-// stencil outside the tile goes to `outside(c4, i, j, k)` (node indices).
+// node_pass1: the node pass of one half-wave over payloads [r0, r1), one
+// particle per step.  Consecutive particles with the same stencil (the sort
+// groups particles by cell) are summed in registers and the sum is added to
+// the half-wave's own LDS tile with a plain read-modify-write when the
+// stencil changes: the 27 lanes touch 27 distinct nodes and no other
+// half-wave writes the tile, so no atomic is needed.  A stencil outside the
+// tile goes to `outside(c4, i, j, k)` (node indices).
 template <class Outside>
-__device__ __forceinline__ void node_pass(const Payload4 *pay, int r0, int r1, float4 *tile, const NodeLane &L,
-                                          float s, Outside &&outside)
+__device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, float4 *tile, int lane, float s,
+                                           Outside &&outside)
 {
+    const NodeLane1 L = node_lane1(lane);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int cur = -1;
     for (int r = r0; L.on && r < r1; ++r) {
@@ -179,6 +182,124 @@ __device__ __forceinline__ void node_pass(const Payload4 *pay, int r0, int r1, f
         float4 old = tile[cur];
         tile[cur] = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
     }
+}
+
+// Three particles per half-wave step (node_pass3).  Lane o < 27 of a
+// half-wave belongs to slot k = o / 9 (three particles are in flight per
+// half-wave) and takes the stencil column (o0, o1) = ((o % 9) / 3, o % 3),
+// i.e. the three nodes (o0, o1, 0..2).
+struct NodeLane3 {
+    bool on;
+    int slot, o0, o1, lo;   // lo: tile offset of node (o0, o1, 0) from the stencil base
+    float wc[2], wa[2], wg[2];
+};
+
+__device__ __forceinline__ NodeLane3 node_lane3(int lane)
+{
+    NodeLane3 L;
+    const int o = lane & 31;
+    L.on = o < 27;
+    L.slot = o / 9;
+    L.o0 = (o % 9) / 3;
+    L.o1 = o % 3;
+    L.lo = (L.o0 * TILE + L.o1) * TILE;
+    const int oo[2] = {L.o0, L.o1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        L.wc[k] = 1.5f - 0.5f * oo[k];
+        L.wa[k] = oo[k] == 1 ? -1.0f : 0.5f;
+        L.wg[k] = oo[k] == 1 ? 0.75f : 0.0f;
+    }
+    return L;
+}
+
+// node_pass3: the node pass of one half-wave over payloads [r0, r1): the
+// run is cut into three contiguous parts, one per slot, processed side by
+// side (one particle per slot per step).  Consecutive particles of a slot with the same stencil
+// (the sort groups particles by cell) are summed in registers, three nodes
+// per lane; when a slot's stencil changes its sums are added to the
+// half-wave's LDS tile with plain read-modify-writes, one slot after the
+// other (a slot's 9 lanes x 3 nodes are 27 distinct nodes, and no other
+// half-wave writes the tile), so no atomic is needed.  A stencil outside the
+// tile goes to `outside(c4, i, j, k)` (node indices), node by node.
+template <class Outside>
+__device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, float4 *tile, int lane, float s,
+                                           Outside &&outside)
+{
+    const NodeLane3 L = node_lane3(lane);
+    const int per = (r1 - r0 + 2) / 3;
+    const int my0 = r0 + L.slot * per, my1 = min(r1, my0 + per);
+    float4 acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int cur = -1;
+    // add a slot's sums to the tile, slot by slot (only lanes with `go` write).
+    // Per lane the three rounds are exclusive, so the compiler could merge them
+    // into one; the memory barriers between them keep three separate LDS
+    // read-modify-writes, executed in order by the wavefront, so slots that
+    // share nodes never write them in the same instruction.
+    auto flush = [&](bool go) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (go && L.slot == k) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float4 old = tile[cur + c];
+                    tile[cur + c] = make_float4(old.x + acc[c].x, old.y + acc[c].y, old.z + acc[c].z, old.w + acc[c].w);
+                }
+            }
+            asm volatile("" ::: "memory");
+        }
+    };
+    for (int i = 0; i < per; ++i) {
+        const int r = my0 + i;
+        const bool live = L.on && r < my1;
+        const Payload4 &P = pay[live ? r : r0];
+        const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
+        const int pk = live ? __float_as_int(fk.w) : 0;
+        const bool in_tile = (pk & (KEY_VALID | KEY_IN_TILE)) == (KEY_VALID | KEY_IN_TILE);
+        const int l = (pk >> 2) + L.lo;
+        const bool change = in_tile && l != cur;
+        if (__ballot(change && cur >= 0)) flush(change && cur >= 0);
+        if (change) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+            cur = l;
+        }
+        if (!(pk & KEY_VALID)) continue;
+        const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1];
+        const float w01 = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]);
+        const float f2 = fk.z;
+        const float w2[3] = {0.5f * (1.5f - f2) * (1.5f - f2), 0.75f - (f2 - 1.0f) * (f2 - 1.0f),
+                             0.5f * (f2 - 0.5f) * (f2 - 0.5f)};
+        const float d0 = L.o0 - fk.x, d1 = L.o1 - fk.y;
+        // g + M (d0, d1, .) for this column; the third axis is added per node
+        const float bx = fmaf(q1.w, d0, fmaf(q2.x, d1, q1.x));
+        const float by = fmaf(q2.z, d0, fmaf(q2.w, d1, q1.y));
+        const float bz = fmaf(q3.y, d0, fmaf(q3.z, d1, q1.z));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float d2 = c - f2, w = w01 * w2[c];
+            const float4 c4 = make_float4(w * s, w * fmaf(q2.y, d2, bx), w * fmaf(q3.x, d2, by), w * fmaf(q3.w, d2, bz));
+            if (in_tile) {
+                acc[c].x += c4.x; acc[c].y += c4.y; acc[c].z += c4.z; acc[c].w += c4.w;
+            } else {
+                outside(c4, ((pk >> 2) & 1023) + L.o0, ((pk >> 12) & 1023) + L.o1, ((pk >> 22) & 1023) + c);
+            }
+        }
+    }
+    flush(cur >= 0);
+}
+
+// Node pass with `slots` (1 or 3) particles in flight per half-wave: one
+// particle per step keeps runs long at few particles per cell; three per step
+// need a third of the arithmetic per node when cells hold many particles.
+template <class Outside>
+__device__ __forceinline__ void node_pass(int slots, const Payload4 *pay, int r0, int r1, float4 *tile, int lane,
+                                          float s, Outside &&outside)
+{
+    if (slots == 3) node_pass3(pay, r0, r1, tile, lane, s, outside);
+    else node_pass1(pay, r0, r1, tile, lane, s, outside);
 }
 
 // Half-wave hw of 2W takes the contiguous run [r0, r1) of a chunk of n payloads.

@@ -57,6 +57,7 @@ struct TiledArgs {
     int32_t *pidout;                      // copied when pidin != pidout
     const int4 *items;                    // (brick, first slot, count, environment)
     const int2 *totals;                   // .y = number of items
+    int slots;                            // node pass: particles per half-wave step (1 or 3)
     ActiveBuf act;
     int par;                              // dynamic list this kernel's P2G appends to
 };

@@ -41,18 +41,20 @@ def _pressing_scene(seed, N, n, S, contact=scenes.CONTACT_SLIP):
     return sc, env
 
 
-@pytest.mark.parametrize("scheme,contact", [("tiled", scenes.CONTACT_SLIP), ("direct", scenes.CONTACT_SLIP),
-                                            ("tiled", scenes.CONTACT_STICKY)])
-def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact):
+@pytest.mark.parametrize("scheme,contact,slots", [("tiled", scenes.CONTACT_SLIP, 3), ("direct", scenes.CONTACT_SLIP, 3),
+                                                  ("tiled", scenes.CONTACT_STICKY, 3), ("tiled", scenes.CONTACT_SLIP, 1)])
+def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots):
     Sim, L, torch = gpu
     S, N, n, k = 12, 2000, 32, 5
-    _say(f"adjoint vs oracle adjoint: {N} particles, {n}^3, {S} substeps, checkpoints every {k}, {scheme}, contact={contact}")
+    _say(f"adjoint vs oracle adjoint: {N} particles, {n}^3, {S} substeps, checkpoints every {k}, {scheme}, "
+         f"contact={contact}, node slots {slots}")
     sc, env = _pressing_scene(51 + contact, N, n, S, contact)
     rng = np.random.default_rng(3)
     W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
          rng.standard_normal((N, 3, 3))]
     sim = Sim(sc, max_tape=S, checkpoint_every=k,
-              options={L.OPT_SCHEME: L.SCHEME_TILED if scheme == "tiled" else L.SCHEME_DIRECT, L.OPT_SORT_EVERY: 3})
+              options={L.OPT_SCHEME: L.SCHEME_TILED if scheme == "tiled" else L.SCHEME_DIRECT, L.OPT_SORT_EVERY: 3,
+                       L.OPT_NODE_SLOTS: slots})
     sim.step(S, record_tape=True)
     soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
     g = sim.adjoint(S, soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))

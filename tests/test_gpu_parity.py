@@ -154,14 +154,16 @@ def test_status_flags_and_read_errors(gpu, orc, scheme):
     assert sim.lib.mpm_set_tool(sim.ctx, 0, 3, None, None, 0) == L.MPM_E_ARG
 
 
-def test_tiled_matches_direct_long_run(gpu, orc):
+@pytest.mark.parametrize("slots", [1, 3])
+def test_tiled_matches_direct_long_run(gpu, orc, slots):
     """Cross-check of the two schemes (different accumulation orders) on the
-    30K slab with the tool pushing: 200 substeps, several sorts, mid-call."""
+    30K slab with the tool pushing: 200 substeps, several sorts, mid-call,
+    with either node-pass form."""
     Sim, L = gpu
-    _say("tiled vs direct: slab 30K, 200 substeps")
+    _say(f"tiled (node slots {slots}) vs direct: slab 30K, 200 substeps")
     sc = scenes.slab_scene(seed=2, substeps=200)
     a = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_DIRECT})
-    b = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 16})
+    b = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 16, L.OPT_NODE_SLOTS: slots})
     a.step(120)
     a.step(80)
     b.step(120)
@@ -345,15 +347,17 @@ def _ragged_scene(seed=11):
     return scenes.Scene("ragged", envs, dt=1e-4, substeps=20)
 
 
-@pytest.mark.parametrize("block,item", [(64, 16), (256, 4096), (128, 48)])
-def test_ragged_tiny_environments(gpu, orc, block, item):
+@pytest.mark.parametrize("block,item,slots", [(64, 16, 3), (256, 4096, 1), (128, 48, 3), (256, 128, 1)])
+def test_ragged_tiny_environments(gpu, orc, block, item, slots):
     """Edge shapes: a one-particle environment, the smallest grid (8^3), item
     sizes from 16 to 4096 particles and workgroups of 64 to 256 threads; every
     environment free-runs 20 substeps against the oracle."""
     Sim, L = gpu
     sc = _ragged_scene()
-    _say(f"ragged tiny envs: N {[e.N for e in sc.envs]}, grids {[e.n for e in sc.envs]}, block {block}, item {item}")
-    sim = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: block, L.OPT_ITEM: item, L.OPT_SORT_EVERY: 7})
+    _say(f"ragged tiny envs: N {[e.N for e in sc.envs]}, grids {[e.n for e in sc.envs]}, block {block}, item {item}, "
+         f"slots {slots}")
+    sim = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: block, L.OPT_ITEM: item, L.OPT_SORT_EVERY: 7,
+                           L.OPT_NODE_SLOTS: slots})
     sim.step(13)
     sim.step(7)
     for e, env in enumerate(sc.envs):
@@ -375,7 +379,7 @@ def test_autotune_picks_and_caches(gpu, orc, tmp_path):
     sc = scenes.cube_scene(seed=1, substeps=10)
     cache = str(tmp_path / "tune.json")
     kw = dict(substeps=8, warmup=2, cache=cache, blocks=(64, 256), items=(64, 512), sort_every=(8, 16),
-              graph=(0, 1), persistent=(0,))
+              graph=(0, 1), persistent=(0,), slots=(3,))
     best = autotune(sc, **kw)
     _say(f"autotune cube: {best}")
     assert best[L.OPT_BLOCK] in (64, 256) and best[L.OPT_ITEM] in (64, 512) and best[L.OPT_SORT_EVERY] in (8, 16)
