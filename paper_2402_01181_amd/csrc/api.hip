@@ -72,6 +72,8 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.act.dlist = cv.take<int32_t>((size_t)2 * s.total_bricks);
     c.act.dcount = cv.take<int32_t>(2);
     c.act.nbricks = s.total_bricks;
+    c.brick_env = cv.take<int32_t>(s.total_bricks);
+    c.act.brick_env = c.brick_env;
     c.env_bofs = cv.take<int32_t>(s.n_envs + 1);
     c.act.env_bofs = c.env_bofs;
     c.barrier.count = cv.take<unsigned>(1);
@@ -120,7 +122,7 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
+                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
     for (const void *q : p)
         if (!q) return false;
     if (c.max_tape > 0) {
@@ -280,8 +282,9 @@ void sort_into_alt(mpm_ctx *c, hipStream_t st)
 
 int grid_blocks(const mpm_ctx *c)
 {
+    // one wavefront per brick up to 64K listed bricks; beyond that waves take several
     int64_t b = ((int64_t)c->total_bricks + 3) / 4;
-    return (int)std::max<int64_t>(8, std::min<int64_t>(b, 2048));
+    return (int)std::max<int64_t>(8, std::min<int64_t>(b, 16384));
 }
 
 // n substeps of the tiled scheme:
@@ -713,6 +716,7 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         launch_fill_f4(c->gV, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.scount), 1, 0u, st);
+        launch_brick_env(c->env_bofs, s.n_envs, s.total_bricks, c->brick_env, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.dcount), 2, 0u, st);
         launch_fill_u32(c->barrier.count, 1, 0u, st);
         launch_fill_u32(c->barrier.gen, 1, 0u, st);

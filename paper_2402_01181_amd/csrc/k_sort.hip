@@ -141,14 +141,14 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_chunks(SortBuf s, int nchunks)
 }
 
 // Write the items of each brick.
-__global__ __launch_bounds__(256) void k_make_items(SortBuf s, const int32_t *env_bofs, int n_envs, int nb, int P)
+__global__ __launch_bounds__(256) void k_make_items(SortBuf s, const int32_t *brick_env, int nb, int P)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nb) return;
     const int64_t c0 = (int64_t)k * 64;
     int2 o = add2(s.offset[c0], s.chunk_sum[c0 / SCAN_CHUNK]);
     int c = gload(s.brick_count + k);
-    const int env = c > 0 ? env_of_brick(env_bofs, n_envs, k) : 0;
+    const int env = c > 0 ? gload(brick_env + k) : 0;
     for (int j = 0, first = o.x; first < o.x + c; ++j, first += P) {
         int cnt = o.x + c - first;
         s.items[o.y + j] = make_int4(k, first, cnt < P ? cnt : P, env);
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_static_build(Dev d, SortBuf s, ActiveBu
 {
     const int b = blockIdx.x * 8 + (threadIdx.x >> 5), o = threadIdx.x & 31;
     if (b >= act.nbricks || o >= 27 || gload(s.brick_count + b) == 0) return;
-    const EnvDev e = load_env(d.env + env_of_brick(act.env_bofs, d.n_envs, b));
+    const EnvDev e = load_env(d.env + gload(act.brick_env + b));
     const int lb = b - e.bofs;
     const int bi = lb / (e.nb * e.nb) + o / 9 - 1, bj = (lb / e.nb) % e.nb + (o / 3) % 3 - 1,
               bk = lb % e.nb + o % 3 - 1;
@@ -222,7 +222,7 @@ void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total
     int nchunks = (ncells + SCAN_CHUNK - 1) / SCAN_CHUNK;
     launch_k(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, ncells, P);
     launch_k(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
-    launch_k(k_make_items, dim3(nblk), dim3(256), 0, st, s, act.env_bofs, d.n_envs, total_bricks, P);
+    launch_k(k_make_items, dim3(nblk), dim3(256), 0, st, s, act.brick_env, total_bricks, P);
     launch_k(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
 }
 

@@ -335,8 +335,9 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 }
 
 // Grid operation over the static brick list and dynamic list `par`: one
-// wavefront per 4^3 brick.  Writes V and clears P; clears the flags of the
-// dynamic bricks, and the other dynamic list's count for the next P2G.
+// wavefront per 4^3 brick.  Writes V and clears P of every brick that
+// received mass; clears the flags of the dynamic bricks, and the other
+// dynamic list's count for the next P2G.
 __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -354,7 +355,13 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         // node 64 b + l of the whole grid: P is loaded without waiting for the environment
         const int64_t g = (int64_t)b * BRICK_NODES + lane;
         float4 P = gload(d.gP + g);
-        int env = env_of_brick(a.env_bofs, d.n_envs, b);
+        if (!__any(P.x != 0.f)) {
+            // no mass reached the brick this substep: P is already clear and no
+            // particle's G2P reads its velocities, so there is nothing to write
+            if (dyn && lane == 0) gstore(a.flag + b, 0);
+            continue;
+        }
+        const int env = gload(a.brick_env + b);
         const EnvDev e = load_env(d.env + env);
         int lb = b - e.bofs;
         int gi, gj, gk;
@@ -498,6 +505,18 @@ int tiled_workgroups(int block)
     int g = per * cus;
     g -= g % NXCD;
     return g < NXCD ? NXCD : g;
+}
+
+__global__ __launch_bounds__(256) void k_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *out)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbricks; b += gridDim.x * blockDim.x)
+        out[b] = env_of_brick(env_bofs, n_envs, b);
+}
+
+void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *brick_env, hipStream_t st)
+{
+    const int nblk = (nbricks + 255) / 256;
+    launch_k(k_brick_env, dim3(nblk < 4096 ? nblk : 4096), dim3(256), 0, st, env_bofs, n_envs, nbricks, brick_env);
 }
 
 void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st)

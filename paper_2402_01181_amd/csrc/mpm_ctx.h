@@ -70,6 +70,7 @@ struct mpm_ctx {
     mpm::ParticleBuf alt{};          // sort destination
     mpm::SortBuf sort{};
     mpm::ActiveBuf act{};
+    int32_t *brick_env = nullptr;      // [total_bricks] environment of each brick
     int32_t *env_bofs = nullptr;
     int64_t max_items = 0;
     // sequencing state

@@ -42,6 +42,7 @@ struct ActiveBuf {
     int32_t *dlist;           // [2][nbricks] dynamic lists
     int32_t *dcount;          // [2]
     const int32_t *env_bofs;  // [n_envs + 1] first brick of each environment
+    const int32_t *brick_env; // [nbricks] environment of each brick
     int32_t nbricks;          // total bricks over all environments
 };
 
@@ -68,7 +69,7 @@ struct GridBarrier {
     unsigned *gen;
 };
 
-// act.flag == nullptr: the static brick list is left as it is (act.env_bofs is always used).
+// act.flag == nullptr: the static brick list is left as it is (act.brick_env is always used).
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
                  const ParticleBuf &dst, int full, hipStream_t st);
 size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
@@ -79,6 +80,8 @@ void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, 
 // fused G2P + P2G that also writes v and C (d.gV: this substep's grid, d.gP: the next one's)
 void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st);
+// brick_env[b] = environment of brick b (once, at create)
+void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *brick_env, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
 int tiled_workgroups(int block);
