@@ -59,8 +59,9 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.alt.pid = cv.take<int32_t>(s.ntot);
     c.sort.count = cv.take<int32_t>((size_t)s.total_bricks * 64);
     c.sort.brick_count = cv.take<int32_t>(s.total_bricks);
-    c.sort.offset = cv.take<int2>((size_t)s.total_bricks * 64);
-    c.sort.chunk_sum = cv.take<int2>(sort_chunk_count((int64_t)s.total_bricks * 64));
+    c.sort.offset = cv.take<int32_t>((size_t)s.total_bricks * 64);
+    c.sort.brick_offset = cv.take<int2>(s.total_bricks);
+    c.sort.chunk_sum = cv.take<int2>(sort_chunk_count(s.total_bricks));
     c.sort.totals = cv.take<int2>(1);
     c.sort.key = cv.take<int32_t>(s.ntot);
     c.sort.rank = cv.take<int32_t>(s.ntot);
@@ -120,7 +121,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
 bool all_carved(const mpm_ctx &c)
 {
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
-                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset,
+                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
                        c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
     for (const void *q : p)
@@ -715,6 +716,8 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
         launch_fill_f4(c->gP, s.total_nodes, st);
         launch_fill_f4(c->gV, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.count), (int64_t)s.total_bricks * 64, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.brick_count), s.total_bricks, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.scount), 1, 0u, st);
         launch_brick_env(c->env_bofs, s.n_envs, s.total_bricks, c->brick_env, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.dcount), 2, 0u, st);

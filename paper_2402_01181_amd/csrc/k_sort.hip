@@ -5,10 +5,13 @@
 //
 //   1. k_cell_count: cell of each particle; rank within the cell by an
 //      atomic counter (histogram), and particles per brick.
-//   2. scan of (particles, items) per cell, a brick's items = ceil(count / P)
-//      counted at its first cell.
-//   3. k_make_items: (brick, first slot, count) per item, brick-major order.
+//   2. scan of (particles, items) per brick, items = ceil(count / P).
+//   3. k_make_items: per occupied brick, the first slot of each of its 64
+//      cells (a wavefront scan) and its items (brick, first slot, count,
+//      environment); the counters are cleared for the next sort.
 //   4. k_sort_scatter: move particle state into its sorted slot.
+// Cell counts are only touched where particles are, so nothing proportional
+// to the grid is cleared or scanned.
 #include "mpm_tile_util.h"
 
 namespace mpm {
@@ -33,9 +36,10 @@ __device__ __forceinline__ int particle_cell(const EnvDev &e, float x0, float x1
 // every group adds the group's size to its cell's counter, all groups in one
 // atomic instruction, and each lane's rank is that base plus its position in
 // the group.
-__global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s)
+__global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf act)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+    if (act.flag && q == 0) gstore(act.scount, 0);   // the static list is rebuilt next
     const bool valid = q < d.ntot;
     const int N = d.ntot;
     int key = -1;
@@ -98,9 +102,9 @@ __device__ int2 block_exclusive_scan(int2 v, int2 *sh, int2 &total)
     return make_int2(incl.x - v.x, incl.y - v.y);
 }
 
-// Per cell: (particles, items), the brick's items ceil(count / P) counted at
-// its first cell; local exclusive scan per chunk of cells.
-__global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int ncells, int P)
+// Per brick: (particles, items = ceil(count / P)); local exclusive scan per
+// chunk of bricks.
+__global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int nb, int P)
 {
     __shared__ int2 sh[SCAN_T];
     int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_E;
@@ -108,9 +112,8 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int ncells, in
 #pragma unroll
     for (int i = 0; i < SCAN_E; ++i) {
         int k = base + i;
-        int c = k < ncells ? gload(s.count + k) : 0;
-        int bc = (k < ncells && (k & 63) == 0) ? gload(s.brick_count + (k >> 6)) : 0;
-        v[i] = make_int2(c, (bc + P - 1) / P);
+        int c = k < nb ? gload(s.brick_count + k) : 0;
+        v[i] = make_int2(c, (c + P - 1) / P);
         sum = add2(sum, v[i]);
     }
     int2 total;
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_local(SortBuf s, int ncells, in
 #pragma unroll
     for (int i = 0; i < SCAN_E; ++i) {
         int k = base + i;
-        if (k < ncells) s.offset[k] = ex;
+        if (k < nb) s.brick_offset[k] = ex;
         ex = add2(ex, v[i]);
     }
     if (threadIdx.x == 0) s.chunk_sum[blockIdx.x] = total;
@@ -140,19 +143,32 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_chunks(SortBuf s, int nchunks)
     if (threadIdx.x == 0) *s.totals = carry;
 }
 
-// Write the items of each brick.
+// One wavefront per brick: an occupied brick gets the first slot of each of
+// its 64 cells (exclusive scan of the cell counts across the lanes) and its
+// items; its counters are cleared for the next sort.
 __global__ __launch_bounds__(256) void k_make_items(SortBuf s, const int32_t *brick_env, int nb, int P)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (k >= nb) return;
-    const int64_t c0 = (int64_t)k * 64;
-    int2 o = add2(s.offset[c0], s.chunk_sum[c0 / SCAN_CHUNK]);
-    int c = gload(s.brick_count + k);
-    const int env = c > 0 ? gload(brick_env + k) : 0;
-    for (int j = 0, first = o.x; first < o.x + c; ++j, first += P) {
-        int cnt = o.x + c - first;
+    const int c = gload(s.brick_count + k);
+    if (c == 0) return;
+    const int2 o = add2(s.brick_offset[k], s.chunk_sum[k / SCAN_CHUNK]);
+    const int64_t cell = (int64_t)k * 64 + lane;
+    const int n = gload(s.count + cell);
+    int incl = n;                       // inclusive scan over the 64 lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    gstore(s.offset + cell, o.x + incl - n);
+    gstore(s.count + cell, 0);
+    const int env = gload(brick_env + k);
+    for (int j = lane, first = o.x + lane * P; first < o.x + c; j += 64, first += 64 * P) {
+        const int cnt = o.x + c - first;
         s.items[o.y + j] = make_int4(k, first, cnt < P ? cnt : P, env);
     }
+    if (lane == 0) gstore(s.brick_count + k, 0);
 }
 
 // Move each particle to its slot; full = 1 also moves v and C.
@@ -161,8 +177,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.ntot) return;
     const int N = d.ntot;
-    const int key = s.key[q];
-    int to = s.offset[key].x + s.chunk_sum[key / SCAN_CHUNK].x + s.rank[q];
+    const int to = s.offset[s.key[q]] + s.rank[q];
 #pragma unroll
     for (int c = 0; c < 3; ++c) dst.x[(size_t)c * N + to] = d.x[(size_t)c * N + q];
 #pragma unroll
@@ -199,33 +214,21 @@ __global__ __launch_bounds__(256) void k_static_build(Dev d, SortBuf s, ActiveBu
     if (gatomic_cas(act.flag + x, 0, 1)) gstore(act.slist + gatomic_add(act.scount, 1), x);
 }
 
-__global__ void k_zero_counts(SortBuf s, ActiveBuf act, int nb)
-{
-    if (act.flag && blockIdx.x == 0 && threadIdx.x == 0) gstore(act.scount, 0);
-    const int64_t ncells = (int64_t)nb * 64;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncells; k += (int64_t)gridDim.x * blockDim.x) {
-        s.count[k] = 0;
-        if (k < nb) s.brick_count[k] = 0;
-    }
-}
-
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
                  const ParticleBuf &dst, int full, hipStream_t st)
 {
+    // cell and brick counters are zero here: set at create, cleared by k_make_items
     const int nblk = (total_bricks + 255) / 256;
-    const int ncells = total_bricks * 64;
-    const int zblk = (ncells + 255) / 256;
     if (act.flag) launch_k(k_static_clear, dim3(nblk < 1024 ? nblk : 1024), dim3(256), 0, st, act);
-    launch_k(k_zero_counts, dim3(zblk < 8192 ? zblk : 8192), dim3(256), 0, st, s, act, total_bricks);
-    launch_k(k_cell_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s);
+    launch_k(k_cell_count, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, act);
     if (act.flag) launch_k(k_static_build, dim3((total_bricks + 7) / 8), dim3(256), 0, st, d, s, act);
-    int nchunks = (ncells + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    launch_k(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, ncells, P);
+    int nchunks = (total_bricks + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    launch_k(k_scan_local, dim3(nchunks), dim3(SCAN_T), 0, st, s, total_bricks, P);
     launch_k(k_scan_chunks, dim3(1), dim3(SCAN_T), 0, st, s, nchunks);
-    launch_k(k_make_items, dim3(nblk), dim3(256), 0, st, s, act.brick_env, total_bricks, P);
+    launch_k(k_make_items, dim3((total_bricks + 3) / 4), dim3(256), 0, st, s, act.brick_env, total_bricks, P);
     launch_k(k_sort_scatter, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, s, dst, full);
 }
 
-size_t sort_chunk_count(int64_t ncells) { return (size_t)((ncells + SCAN_CHUNK - 1) / SCAN_CHUNK); }
+size_t sort_chunk_count(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK); }
 
 }  // namespace mpm

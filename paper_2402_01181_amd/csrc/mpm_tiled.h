@@ -10,10 +10,11 @@ namespace mpm {
 // (brick * 64 + cell within the 4^3-cell brick): particles of one brick are
 // contiguous, and within it grouped by cell.
 struct SortBuf {
-    int32_t *count;        // [total_bricks * 64] particles per cell
-    int32_t *brick_count;  // [total_bricks] particles per brick
-    int2 *offset;          // [total_bricks * 64] (first slot, first item) before the chunk prefix
-    int2 *chunk_sum;       // [chunks] exclusive prefix of each scan chunk
+    int32_t *count;        // [total_bricks * 64] particles per cell (zero between sorts)
+    int32_t *brick_count;  // [total_bricks] particles per brick (zero between sorts)
+    int32_t *offset;       // [total_bricks * 64] first slot of each cell (occupied bricks only)
+    int2 *brick_offset;    // [total_bricks] (first slot, first item) before the chunk prefix
+    int2 *chunk_sum;       // [chunks] exclusive prefix of each scan chunk of bricks
     int2 *totals;          // [1] (particles, items)
     int32_t *key;          // [ntot] cell of each particle
     int32_t *rank;         // [ntot] rank within the cell
@@ -72,7 +73,7 @@ struct GridBarrier {
 // act.flag == nullptr: the static brick list is left as it is (act.brick_env is always used).
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
                  const ParticleBuf &dst, int full, hipStream_t st);
-size_t sort_chunk_count(int64_t ncells);   // scan chunks over ncells cells
+size_t sort_chunk_count(int64_t n);   // scan chunks over n bricks
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
