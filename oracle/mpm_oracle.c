@@ -24,10 +24,21 @@
  *  R7  Empty nodes (m_i == 0 exactly) get v_i = 0.
  *  R8  Grid-operation order: normalise, gravity, tool projection, boundary.
  *  R9  Contact iff the merged distance is < theta (per tool).
- *  R10 Tool distance: analytic capsule SDF in the tool frame (segment on the
- *      tool-frame x axis) and its analytic gradient as the normal, in place of
- *      a sampled SDF and central differences.
- *  R11 Normal n = R grad/|grad|; on the capsule axis n = R e_y.
+ *  R10 Tool distance, three shapes.  Capsule: analytic SDF (segment on the
+ *      tool-frame x axis) with its analytic gradient as the normal.  Box (the
+ *      gripper-jaw bounding box): analytic signed distance to a box of half
+ *      extents b, optionally rounded by r.  Sampled SDF: a lattice of
+ *      res^3 samples, sample (i,j,k) at lo + (i,j,k) h in the tool frame;
+ *      "nearest" reads the sample of the lattice cell the node falls in,
+ *      s = (x_ref - lo)/h, index floor(s) (the paper's SDF[x_ref/dx]), and
+ *      takes the central-difference gradient of that sample as the normal;
+ *      "trilinear" interpolates the samples and their central-difference
+ *      gradients over the cell.  A node whose lattice cell has no complete
+ *      central differences (index outside [1, res-2]) is outside the tool's
+ *      field: no contact with that tool.  The lattice coordinate s is formed
+ *      in FP64 (the kernels do the same), so both take the same cell.
+ *  R11 Normal n = R grad/|grad|; on the capsule axis, or where the gradient
+ *      vanishes (|grad| < 1e-12), n = R e_y.
  *  R12 Friction: Coulomb projection v_rel' = max(0, 1 + mu_f v_n/|v_t|) v_t,
  *      and 0 when |v_t| = 0 (the printed formula has no static clamp).
  *  R13 Slip contact projects only when v_n < 0; sticky contact sets the node
@@ -135,6 +146,120 @@ double orc_capsule_sdf(const double xref[3], double radius, double half_len, dou
     return sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) - radius;
 }
 
+/* Box of half extents b rounded by r (R10): outside the core box the offset
+ * q = x_ref - clamp(x_ref, -b, b) gives phi = |q| - r and l = q/|q|; inside,
+ * phi = max_a(|x_a| - b_a) - r with l = sign(x_k) e_k on the first axis k
+ * reaching the maximum.  Jl = dl/dx_ref: (I - l l^T) D / |q| outside, with
+ * D_aa = 1 on the axes the clamp is active on, and 0 inside. */
+double orc_box_sdf(const double xref[3], const double half[3], double radius, double l[3], double Jl[9])
+{
+    double q[3];
+    int outside = 0;
+    for (int a = 0; a < 3; ++a) {
+        double c = xref[a];
+        if (c < -half[a]) c = -half[a];
+        if (c > half[a]) c = half[a];
+        q[a] = xref[a] - c;
+        if (xref[a] < -half[a] || xref[a] > half[a]) outside = 1;
+    }
+    if (Jl) memset(Jl, 0, 9 * sizeof(double));
+    if (outside) {
+        double len = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        if (len < 1e-12) {
+            l[0] = 0.0; l[1] = 1.0; l[2] = 0.0;
+            return len - radius;
+        }
+        for (int a = 0; a < 3; ++a) l[a] = q[a] / len;
+        if (Jl)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    int act = xref[b] < -half[b] || xref[b] > half[b];
+                    Jl[3 * a + b] = act ? ((a == b ? 1.0 : 0.0) - l[a] * l[b]) / len : 0.0;
+                }
+        return len - radius;
+    }
+    int k = 0;
+    double best = fabs(xref[0]) - half[0];
+    for (int a = 1; a < 3; ++a)
+        if (fabs(xref[a]) - half[a] > best) { best = fabs(xref[a]) - half[a]; k = a; }
+    l[0] = l[1] = l[2] = 0.0;
+    l[k] = xref[k] >= 0.0 ? 1.0 : -1.0;
+    return best - radius;
+}
+
+static double sdf_at(const orc_tool *tl, int i, int j, int k)
+{
+    return (double)tl->sdf[((size_t)i * tl->sdf_res + j) * tl->sdf_res + k];
+}
+
+/* Central-difference gradient of the samples at lattice point (i,j,k)
+ * (Sec. III-C, normal equation). */
+static void sdf_grad(const orc_tool *tl, int i, int j, int k, double g[3])
+{
+    double h2 = 2.0 * tl->sdf_h;
+    g[0] = (sdf_at(tl, i + 1, j, k) - sdf_at(tl, i - 1, j, k)) / h2;
+    g[1] = (sdf_at(tl, i, j + 1, k) - sdf_at(tl, i, j - 1, k)) / h2;
+    g[2] = (sdf_at(tl, i, j, k + 1) - sdf_at(tl, i, j, k - 1)) / h2;
+}
+
+/* Sampled SDF (R10).  Returns phi (INFINITY outside the field) with the
+ * tool-frame unit normal l and Jl = dl/dx_ref. */
+double orc_sampled_sdf(const orc_tool *tl, const double xref[3], double l[3], double Jl[9])
+{
+    const int tri = tl->sdf_interp == ORC_SDF_TRILINEAR;
+    const double lim = tri ? tl->sdf_res - 2 : tl->sdf_res - 1;
+    double s[3];
+    int i0[3];
+    if (Jl) memset(Jl, 0, 9 * sizeof(double));
+    l[0] = 0.0; l[1] = 1.0; l[2] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        s[a] = (xref[a] - tl->sdf_lo[a]) / tl->sdf_h;
+        if (!(s[a] >= 1.0 && s[a] < lim)) return INFINITY;
+        i0[a] = (int)floor(s[a]);
+    }
+    double phi, g[3], dg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (!tri) {
+        phi = sdf_at(tl, i0[0], i0[1], i0[2]);
+        sdf_grad(tl, i0[0], i0[1], i0[2], g);
+    } else {
+        double f[3] = {s[0] - i0[0], s[1] - i0[1], s[2] - i0[2]};
+        phi = 0.0;
+        g[0] = g[1] = g[2] = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            int o[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+            double wa[3], w = 1.0, gw[3];
+            for (int a = 0; a < 3; ++a) {
+                wa[a] = o[a] ? f[a] : 1.0 - f[a];
+                w *= wa[a];
+            }
+            /* d w / d s_b */
+            for (int b = 0; b < 3; ++b) {
+                gw[b] = o[b] ? 1.0 : -1.0;
+                for (int a = 0; a < 3; ++a)
+                    if (a != b) gw[b] *= wa[a];
+            }
+            double Gc[3];
+            sdf_grad(tl, i0[0] + o[0], i0[1] + o[1], i0[2] + o[2], Gc);
+            phi += w * sdf_at(tl, i0[0] + o[0], i0[1] + o[1], i0[2] + o[2]);
+            for (int a = 0; a < 3; ++a) {
+                g[a] += w * Gc[a];
+                for (int b = 0; b < 3; ++b) dg[3 * a + b] += Gc[a] * gw[b] / tl->sdf_h;
+            }
+        }
+    }
+    double gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (gl < 1e-12) return phi;
+    for (int a = 0; a < 3; ++a) l[a] = g[a] / gl;
+    if (Jl && tri)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double v = 0.0;
+                for (int c = 0; c < 3; ++c) v += ((a == c ? 1.0 : 0.0) - l[a] * l[c]) * dg[3 * c + b];
+                Jl[3 * a + b] = v / gl;
+            }
+    return phi;
+}
+
 static int out_of_domain(const int base[3], int n)
 {
     for (int d = 0; d < 3; ++d)
@@ -219,25 +344,34 @@ void orc_grid_update(const orc_params *P, const orc_tool *tools, const double *T
                     memcpy(r.vhat, vv, sizeof vv);
                     /* z-buffer: nearest tool, ties to the lowest id (R15) */
                     double xi[3] = {i * dx, j * dx, k * dx};
-                    double best = INFINITY, bq[3] = {0, 0, 0};
+                    double best = INFINITY, bq[3] = {0, 0, 0}, bl[3] = {0, 1, 0}, bxr[3] = {0, 0, 0};
                     int bt = -1, bin = 0;
                     for (int t = 0; t < P->n_tools; ++t) {
                         const orc_tool *tl = &tools[t];
                         double d[3] = {xi[0] - T[3 * t + 0], xi[1] - T[3 * t + 1], xi[2] - T[3 * t + 2]};
-                        double xr[3], q[3];
-                        int in;
+                        double xr[3], q[3] = {0, 0, 0}, l[3] = {0, 1, 0}, phi;
+                        int in = 0;
                         for (int a = 0; a < 3; ++a) xr[a] = tl->R[0 + a] * d[0] + tl->R[3 + a] * d[1] + tl->R[6 + a] * d[2];
-                        double phi = orc_capsule_sdf(xr, tl->radius, tl->half_len, q, &in);
-                        if (phi < best) { best = phi; bt = t; memcpy(bq, q, sizeof q); bin = in; }
+                        if (tl->shape == ORC_TOOL_BOX) phi = orc_box_sdf(xr, tl->half, tl->radius, l, NULL);
+                        else if (tl->shape == ORC_TOOL_SDF) phi = orc_sampled_sdf(tl, xr, l, NULL);
+                        else phi = orc_capsule_sdf(xr, tl->radius, tl->half_len, q, &in);
+                        if (phi < best) {
+                            best = phi; bt = t; bin = in;
+                            memcpy(bq, q, sizeof q); memcpy(bl, l, sizeof l); memcpy(bxr, xr, sizeof xr);
+                        }
                     }
                     if (bt >= 0 && best < tools[bt].theta) {
                         const orc_tool *tl = &tools[bt];
                         const double *uc = u + 3 * bt;
                         double nrm[3];
-                        capsule_normal(tl, bq, nrm);
+                        if (tl->shape == ORC_TOOL_CAPSULE) capsule_normal(tl, bq, nrm);
+                        else
+                            for (int a = 0; a < 3; ++a)
+                                nrm[a] = tl->R[3 * a + 0] * bl[0] + tl->R[3 * a + 1] * bl[1] + tl->R[3 * a + 2] * bl[2];
                         r.tool = bt;
                         memcpy(r.n, nrm, sizeof nrm);
                         memcpy(r.q, bq, sizeof bq);
+                        memcpy(r.xr, bxr, sizeof bxr);
                         r.interior = bin;
                         if (tl->contact == ORC_CONTACT_STICKY) {
                             for (int a = 0; a < 3; ++a) vv[a] = uc[a];
@@ -399,6 +533,17 @@ static void grid_node_adjoint(const orc_tool *tools, const double *u, const orc_
     for (int k = 0; k < 3; ++k) {
         vhbar[k] = vrbar[k];
         ubar[3 * t + k] -= vrbar[k];
+    }
+    if (tl->shape != ORC_TOOL_CAPSULE) {
+        /* n = R l(x_ref), x_ref = R^T (x_i - T):  x_ref_bar = Jl^T R^T n_bar */
+        double l[3], Jl[9], nlbar[3], xrbar[3];
+        if (tl->shape == ORC_TOOL_BOX) orc_box_sdf(r->xr, tl->half, tl->radius, l, Jl);
+        else orc_sampled_sdf(tl, r->xr, l, Jl);
+        for (int b = 0; b < 3; ++b) nlbar[b] = tl->R[0 + b] * nbar[0] + tl->R[3 + b] * nbar[1] + tl->R[6 + b] * nbar[2];
+        for (int b = 0; b < 3; ++b) xrbar[b] = Jl[0 + b] * nlbar[0] + Jl[3 + b] * nlbar[1] + Jl[6 + b] * nlbar[2];
+        for (int a = 0; a < 3; ++a)
+            Tbar[3 * t + a] -= tl->R[3 * a + 0] * xrbar[0] + tl->R[3 * a + 1] * xrbar[1] + tl->R[3 * a + 2] * xrbar[2];
+        return;
     }
     /* n = R q/|q|, q = q(x_ref), x_ref = R^T (x_i - T) */
     double ql = sqrt(r->q[0] * r->q[0] + r->q[1] * r->q[1] + r->q[2] * r->q[2]);

@@ -34,6 +34,13 @@
 #define ORC_CONTACT_SLIP 0
 #define ORC_CONTACT_STICKY 1
 
+#define ORC_TOOL_CAPSULE 0   /* analytic capsule (segment on the tool-frame x axis) */
+#define ORC_TOOL_BOX 1       /* box of half extents `half`, corners rounded by `radius` */
+#define ORC_TOOL_SDF 2       /* signed distances sampled on a regular tool-frame lattice */
+
+#define ORC_SDF_NEAREST 0    /* the sample of the cell the point falls in (index truncation) */
+#define ORC_SDF_TRILINEAR 1  /* trilinear in the samples and in their central-difference gradients */
+
 typedef struct {
     int32_t n;          /* grid nodes per axis */
     int32_t bound;      /* boundary band width in nodes */
@@ -46,9 +53,15 @@ typedef struct {
 
 typedef struct {
     int32_t contact;    /* ORC_CONTACT_SLIP or ORC_CONTACT_STICKY */
-    int32_t pad;
+    int32_t shape;      /* ORC_TOOL_* */
     double radius, half_len, friction, theta;
     double R[9];        /* world-from-tool rotation, row-major */
+    double half[3];     /* box half extents (tool frame) */
+    double sdf_h;       /* sampled SDF: lattice spacing */
+    double sdf_lo[3];   /* sampled SDF: tool-frame position of sample (0,0,0) */
+    int32_t sdf_res;    /* sampled SDF: samples per axis */
+    int32_t sdf_interp; /* ORC_SDF_NEAREST or ORC_SDF_TRILINEAR */
+    const float *sdf;   /* sampled SDF: [res][res][res], sample (i,j,k) at lo + (i,j,k) h */
 } orc_tool;
 
 /* Per-node record of the grid operation, kept so the adjoint can replay the
@@ -61,6 +74,7 @@ typedef struct {
     int32_t branch;     /* 0 none/separating, 1 friction, 2 set to tool velocity */
     int32_t wall;
     int32_t interior;   /* tool-frame axial coordinate strictly inside the segment */
+    double xr[3];       /* node position in the colliding tool's frame */
 } orc_node_rec;
 
 void orc_lame(double E, double nu, double *mu, double *lam);
@@ -68,6 +82,8 @@ void orc_weights(const double x[3], double inv_dx, int base[3], double fx[3], do
                  double dw[3][3]);
 uint32_t orc_kirchhoff(const double F[9], double mu, double lam, double tau[9]);
 double orc_capsule_sdf(const double xref[3], double radius, double half_len, double q[3], int *interior);
+double orc_box_sdf(const double xref[3], const double half[3], double radius, double l[3], double Jl[9]);
+double orc_sampled_sdf(const orc_tool *tl, const double xref[3], double l[3], double Jl[9]);
 
 uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
                  const double *F, double *gm, double *gmv);

@@ -43,14 +43,17 @@ class Params(ct.Structure):
 
 
 class ToolC(ct.Structure):
-    _fields_ = [("contact", ct.c_int32), ("pad", ct.c_int32),
+    _fields_ = [("contact", ct.c_int32), ("shape", ct.c_int32),
                 ("radius", ct.c_double), ("half_len", ct.c_double), ("friction", ct.c_double),
-                ("theta", ct.c_double), ("R", ct.c_double * 9)]
+                ("theta", ct.c_double), ("R", ct.c_double * 9), ("half", ct.c_double * 3),
+                ("sdf_h", ct.c_double), ("sdf_lo", ct.c_double * 3), ("sdf_res", ct.c_int32),
+                ("sdf_interp", ct.c_int32), ("sdf", ct.c_void_p)]
 
 
 class NodeRec(ct.Structure):
     _fields_ = [("vhat", ct.c_double * 3), ("n", ct.c_double * 3), ("q", ct.c_double * 3),
-                ("tool", ct.c_int32), ("branch", ct.c_int32), ("wall", ct.c_int32), ("interior", ct.c_int32)]
+                ("tool", ct.c_int32), ("branch", ct.c_int32), ("wall", ct.c_int32), ("interior", ct.c_int32),
+                ("xr", ct.c_double * 3)]
 
 
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -70,6 +73,10 @@ def lib():
         L.orc_kirchhoff.restype = ct.c_uint32
         L.orc_capsule_sdf.argtypes = [_D, ct.c_double, ct.c_double, _D, ct.POINTER(ct.c_int)]
         L.orc_capsule_sdf.restype = ct.c_double
+        L.orc_box_sdf.argtypes = [_D, _D, ct.c_double, _D, _D]
+        L.orc_box_sdf.restype = ct.c_double
+        L.orc_sampled_sdf.argtypes = [T, _D, _D, _D]
+        L.orc_sampled_sdf.restype = ct.c_double
         L.orc_p2g.argtypes = [P, ct.c_int32, _D, _D, _D, _D, _D, _D]
         L.orc_p2g.restype = ct.c_uint32
         L.orc_grid_update.argtypes = [P, T, ct.c_void_p, ct.c_void_p, _D, _D, _D, ct.c_void_p]
@@ -119,10 +126,9 @@ class Sim:
                         rho=float(env.rho), V0=float(env.V0))
         nt = max(1, len(env.tools))
         self.tools = (ToolC * nt)()
+        self._sdf = []      # keeps the sample arrays the tool records point to alive
         for i, t in enumerate(env.tools):
-            self.tools[i] = ToolC(contact=t.contact, pad=0, radius=float(t.radius), half_len=float(t.half_len),
-                                  friction=float(t.friction), theta=float(t.theta),
-                                  R=(ct.c_double * 9)(*np.asarray(t.R, np.float64).reshape(-1)))
+            self.tools[i] = tool_record(t, self._sdf)
         self.n_traj = max([t.traj.shape[0] for t in env.tools], default=1)
         self.traj = np.zeros((nt, self.n_traj, 3))
         for i, t in enumerate(env.tools):
@@ -200,6 +206,39 @@ class Sim:
 
 
 # --- small helpers used by tests --------------------------------------------
+
+def tool_record(t, keep):
+    """The oracle's record of a scenes.Tool; sample arrays are appended to keep."""
+    rec = ToolC(contact=int(t.contact), shape=int(t.shape), radius=float(t.radius), half_len=float(t.half_len),
+                friction=float(t.friction), theta=float(t.theta),
+                R=(ct.c_double * 9)(*np.asarray(t.R, np.float64).reshape(-1)),
+                half=(ct.c_double * 3)(*np.asarray(t.half, np.float64)))
+    if t.sdf is not None:
+        a = np.ascontiguousarray(t.sdf, dtype=np.float32)
+        keep.append(a)
+        rec.sdf = a.ctypes.data
+        rec.sdf_res = a.shape[0]
+        rec.sdf_h = float(t.sdf_h)
+        rec.sdf_lo = (ct.c_double * 3)(*np.asarray(t.sdf_lo, np.float64))
+        rec.sdf_interp = int(t.sdf_interp)
+    return rec
+
+
+def box_sdf(xref, half, radius=0.0):
+    """(phi, l, Jl) of a box tool at tool-frame point xref."""
+    l, J = np.zeros(3), np.zeros(9)
+    phi = lib().orc_box_sdf(np.ascontiguousarray(np.asarray(xref, np.float64)),
+                            np.ascontiguousarray(np.asarray(half, np.float64)), float(radius), l, J)
+    return phi, l, J.reshape(3, 3)
+
+
+def sampled_sdf(tool, xref):
+    """(phi, l, Jl) of a sampled-SDF tool (scenes.Tool) at tool-frame point xref."""
+    keep = []
+    rec = tool_record(tool, keep)
+    l, J = np.zeros(3), np.zeros(9)
+    phi = lib().orc_sampled_sdf(ct.byref(rec), np.ascontiguousarray(np.asarray(xref, np.float64)), l, J)
+    return phi, l, J.reshape(3, 3)
 
 def lame(E, nu):
     mu, lam = ct.c_double(), ct.c_double()

@@ -23,13 +23,21 @@ import numpy as np
 
 CONTACT_SLIP = 0
 CONTACT_STICKY = 1
+TOOL_CAPSULE = 0
+TOOL_BOX = 1
+TOOL_SDF = 2
+SDF_NEAREST = 0
+SDF_TRILINEAR = 1
 
 
 @dataclass
 class Tool:
-    """A capsule tool: segment of half length ``half_len`` along the tool-frame x
-    axis, radius ``radius``; pose ``R`` (world-from-tool rotation) and ``T0``
-    (world position of the tool origin at the first substep)."""
+    """A rigid tool; pose ``R`` (world-from-tool rotation) and ``T0`` (world
+    position of the tool origin at the first substep).  Shapes: capsule
+    (segment of half length ``half_len`` along the tool-frame x axis, radius
+    ``radius``), box (half extents ``half``, corners rounded by ``radius``),
+    sampled SDF (``sdf[res][res][res]`` float32 signed distances, sample
+    (i,j,k) at ``sdf_lo + (i,j,k) * sdf_h`` in the tool frame)."""
     radius: float
     half_len: float
     R: np.ndarray                 # (3, 3) float32, row-major
@@ -38,6 +46,12 @@ class Tool:
     theta: float
     contact: int = CONTACT_SLIP
     traj: Optional[np.ndarray] = None   # (n_traj, 3) float32 per-substep velocity; last entry held
+    shape: int = TOOL_CAPSULE
+    half: tuple = (0.0, 0.0, 0.0)
+    sdf: Optional[np.ndarray] = None
+    sdf_h: float = 0.0
+    sdf_lo: tuple = (0.0, 0.0, 0.0)
+    sdf_interp: int = SDF_TRILINEAR
 
 
 @dataclass
@@ -121,6 +135,64 @@ def capsule_tool(T0, u=None, traj=None, radius=0.02, half_len=0.1, friction=0.3,
                 R=_f32(np.eye(3) if R is None else R), T0=_f32(T0),
                 friction=float(np.float32(friction)), theta=float(np.float32(theta)),
                 contact=int(contact), traj=_f32(traj))
+
+
+def box_tool(T0, half, u=None, traj=None, radius=0.0, friction=0.3, theta=1e-3,
+             contact=CONTACT_SLIP, R=None) -> Tool:
+    """A box of half extents ``half`` (a gripper jaw's bounding box)."""
+    t = capsule_tool(T0, u=u, traj=traj, radius=0.0, half_len=0.0, friction=friction, theta=theta,
+                     contact=contact, R=R)
+    t.radius = float(np.float32(radius))
+    t.shape = TOOL_BOX
+    t.half = tuple(float(h) for h in _f32(half))
+    return t
+
+
+def gripper_tools(center, u, close_speed=0.1, gap=0.03, jaw_half=(0.04, 0.03, 0.008), **kw):
+    """Two box jaws either side of ``center`` along z, moving with ``u`` and
+    closing towards each other at ``close_speed`` each."""
+    c = np.asarray(center, np.float64)
+    dz = np.array([0.0, 0.0, 0.5 * gap + jaw_half[2]])
+    u = np.asarray(u, np.float64)
+    cz = np.array([0.0, 0.0, close_speed])
+    return [box_tool(c - dz, jaw_half, u=u + cz, **kw), box_tool(c + dz, jaw_half, u=u - cz, **kw)]
+
+
+def probe_sdf_samples(res: int, extent: float, tip_radius=0.025, shaft_radius=0.008, shaft_len=0.1):
+    """Signed-distance samples of a ball-tipped probe, the stand-in for a
+    precomputed tool-mesh SDF: a ball of ``tip_radius`` at the tool origin
+    and a shaft (a rod of ``shaft_radius`` from the origin up the tool-frame
+    y axis, length ``shaft_len``), sampled on a ``res``^3 lattice spanning
+    [-extent/2, extent/2]^3; distance of the union = min of the two.
+    Returns (samples float32 [res][res][res], spacing, lattice origin)."""
+    h = extent / (res - 1)
+    lo = -0.5 * extent
+    ax = lo + h * np.arange(res)
+    X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+    ball = np.sqrt(X * X + Y * Y + Z * Z) - tip_radius
+    yc = np.clip(Y, 0.0, shaft_len)
+    rod = np.sqrt(X * X + (Y - yc) ** 2 + Z * Z) - shaft_radius
+    return _f32(np.minimum(ball, rod)), float(np.float32(h)), tuple(float(v) for v in _f32((lo, lo, lo)))
+
+
+def sdf_tool(T0, samples, h, lo, u=None, traj=None, interp=SDF_TRILINEAR, friction=0.3, theta=1e-3,
+             contact=CONTACT_SLIP, R=None) -> Tool:
+    t = capsule_tool(T0, u=u, traj=traj, radius=0.0, half_len=0.0, friction=friction, theta=theta,
+                     contact=contact, R=R)
+    t.shape = TOOL_SDF
+    t.sdf = np.ascontiguousarray(samples, dtype=np.float32)
+    t.sdf_h = float(np.float32(h))
+    t.sdf_lo = tuple(float(v) for v in _f32(lo))
+    t.sdf_interp = int(interp)
+    return t
+
+
+def rotation(rng, max_angle: float):
+    """Rotation by a uniform angle in [0, max_angle] about a random axis (FP32)."""
+    a = _unit(rng.standard_normal(3))
+    th = rng.uniform(0.0, max_angle)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return _f32(np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K)
 
 
 # ---------------------------------------------------------------------------
@@ -236,6 +308,35 @@ def small_slab_scene(seed: int, n_particles: int, n: int = 32, substeps: int = 1
     env = Env(n=n, x=x, v=v, C=C, F=F, E=E, nu=nu, rho=1e3, V0=0.5 * 0.1 * 0.5 / n_particles,
               tools=[tool])
     return Scene(f"small-slab-{n_particles}-{n}", [env], dt=dt, substeps=substeps)
+
+
+def tool_slab_scene(seed: int, n_particles: int, kind: str, n: int = 32, substeps: int = 10,
+                    dt: float = 5e-5, sdf_res: int = 48, interp: int = SDF_TRILINEAR,
+                    contact: int = CONTACT_SLIP, friction: float = 0.3) -> Scene:
+    """The reduced slab of ``small_slab_scene`` pressed by other tools:
+    ``kind`` "gripper" (two closing box jaws, slightly rotated), "sdf" (a
+    sampled ball-tipped probe, tilted, lattice ``sdf_res``^3 over 0.24 m) or
+    "mixed" (the probe and one jaw overlapping, for the z-buffer)."""
+    sc = small_slab_scene(seed, n_particles, n=n, substeps=substeps, dt=dt)
+    rng = np.random.default_rng(seed + 77)
+    env = sc.envs[0]
+    y0 = 3.0 / n
+    top = y0 + 0.1
+    # tool origins off the lattice of nodes
+    jitter = rng.uniform(-0.3, 0.3, 3) / n
+    kw = dict(friction=friction, contact=contact)
+    tools = []
+    if kind in ("gripper", "mixed"):
+        R = rotation(rng, 0.3)
+        jaws = gripper_tools((0.5 + jitter[0], top + 0.01, 0.5 + jitter[2]), (0.0, -0.2, 0.0), R=R, **kw)
+        tools += jaws if kind == "gripper" else jaws[:1]
+    if kind in ("sdf", "mixed"):
+        S, h, lo = probe_sdf_samples(sdf_res, 0.24)
+        tools.append(sdf_tool((0.5 - jitter[0], top + 0.005, 0.5 - jitter[2]), S, h, lo, u=(0.02, -0.25, 0.0),
+                              interp=interp, R=rotation(rng, 0.4), **kw))
+    env.tools = tools
+    sc.name = f"{kind}-slab-{n_particles}-{n}"
+    return sc
 
 
 def perturbed_state(rng, env: Env, v_scale=0.1, C_scale=2.0, F_scale=0.02):
