@@ -73,7 +73,15 @@ enum {
     MPM_F_STEP = 9      /* int32 [1]: substeps taken by the environment */
 };
 
-enum { MPM_TOOL_CAPSULE = 0 };
+/* Tool shapes (Sec. III-C: simple objects such as the gripper jaws by
+ * bounding boxes, objects with complex geometry by a precomputed SDF in the
+ * tool's frame; the analytic capsule is the SDF of a rod-like tool). */
+enum { MPM_TOOL_CAPSULE = 0, MPM_TOOL_BOX = 1, MPM_TOOL_SDF = 2 };
+/* Sampled-SDF lookup.  NEAREST: the sample of the lattice cell a node falls
+ * in (the index of x_ref/h truncated, as in the paper's SDF[x_ref/dx]) with
+ * the central-difference gradient there as the normal.  TRILINEAR: samples
+ * and central-difference gradients interpolated trilinearly over the cell. */
+enum { MPM_SDF_NEAREST = 0, MPM_SDF_TRILINEAR = 1 };
 enum { MPM_CONTACT_SLIP = 0, MPM_CONTACT_STICKY = 1 };
 enum { MPM_STAGE_P2G = 0, MPM_STAGE_GRID = 1, MPM_STAGE_G2P = 2 };
 
@@ -114,14 +122,27 @@ typedef struct {
 } mpm_desc;
 
 typedef struct {
-    int32_t shape;      /* MPM_TOOL_CAPSULE: segment [-half_len, half_len] on the tool-frame x axis */
+    int32_t shape;      /* MPM_TOOL_CAPSULE: segment [-half_len, half_len] on the tool-frame x axis, radius `radius`;
+                           MPM_TOOL_BOX: the box [-half, half] of the tool frame, edges rounded by `radius`;
+                           MPM_TOOL_SDF: signed distances sampled on a tool-frame lattice (sdf_* fields) */
     int32_t contact;    /* MPM_CONTACT_SLIP (Coulomb friction) or MPM_CONTACT_STICKY */
-    float radius;       /* capsule radius (m), > 0 */
-    float half_len;     /* half segment length (m), >= 0 */
+    float radius;       /* capsule radius (m), > 0; box rounding radius, >= 0; unused for MPM_TOOL_SDF */
+    float half_len;     /* capsule half segment length (m), >= 0 */
     float friction;     /* Coulomb coefficient, >= 0 (slip only) */
     float theta;        /* contact threshold: contact iff distance < theta (Sec. III-C) */
     float R[9];         /* world-from-tool rotation, row-major */
     float T0[3];        /* world position of the tool origin now */
+    float half[3];      /* MPM_TOOL_BOX: half extents (m), each >= 0 */
+    int32_t sdf_res;    /* MPM_TOOL_SDF: samples per axis, 4..2048 */
+    int32_t sdf_interp; /* MPM_TOOL_SDF: MPM_SDF_NEAREST or MPM_SDF_TRILINEAR */
+    float sdf_h;        /* MPM_TOOL_SDF: lattice spacing (m), > 0 */
+    float sdf_lo[3];    /* MPM_TOOL_SDF: tool-frame position of sample (0,0,0) */
+    const float *sdf;   /* MPM_TOOL_SDF: device array [res][res][res] of float32 signed distances (m), sample
+                           (i,j,k) at sdf_lo + (i,j,k) sdf_h (i along the tool-frame x axis), index
+                           (i*res + j)*res + k.  Caller-owned, read at every substep, must stay valid while
+                           the slot holds this tool.  A node whose lattice coordinate s = (x_ref - sdf_lo)/sdf_h
+                           (formed in FP64) has floor(s) outside [1, res-2] on any axis (trilinear: floor(s)+1
+                           too) has no complete central differences and is out of this tool's reach. */
 } mpm_tool;
 
 /* Adjoint inputs and outputs.  All pointers are device memory; particle
@@ -154,7 +175,10 @@ void mpm_destroy(mpm_ctx *ctx);
  * velocities; substep k after this call uses u[min(k, n_traj-1)] as the tool
  * velocity v_co and then advances the position, T <- T + dt u (FP64).  u is
  * read at every substep, so the caller may rewrite it between calls.
- * n_traj >= 1.  Passing tool == NULL clears the slot. */
+ * n_traj >= 1.  Passing tool == NULL clears the slot.  The nearest tool of
+ * any shape with distance < theta takes a node (the z-buffer / collision
+ * objects table of Sec. III-C; equal distances go to the lower slot).
+ * Returns MPM_E_ARG for a shape parameter out of range (see mpm_tool). */
 mpm_status mpm_set_tool(mpm_ctx *ctx, int32_t env, int32_t tool, const mpm_tool *desc,
                         const float *u, int32_t n_traj);
 

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(PKG, "libmpm355.so")
 MPM_OK, MPM_E_ARG, MPM_E_HIP, MPM_E_STATE, MPM_E_UNSUPPORTED, MPM_E_WORKSPACE = 0, -1, -2, -3, -4, -5
 FLAG_OUT_OF_DOMAIN, FLAG_INVERTED, FLAG_NONFINITE, FLAG_BARRIER_TIMEOUT = 1, 2, 4, 8
 F_X, F_V, F_C, F_F, F_GRID_M, F_GRID_MV, F_GRID_V, F_STATUS, F_TOOL_T, F_STEP = range(10)
-TOOL_CAPSULE = 0
+TOOL_CAPSULE, TOOL_BOX, TOOL_SDF = 0, 1, 2
+SDF_NEAREST, SDF_TRILINEAR = 0, 1
 CONTACT_SLIP, CONTACT_STICKY = 0, 1
 STAGE_P2G, STAGE_GRID, STAGE_G2P = 0, 1, 2
 OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM, OPT_NODE_SLOTS = range(8)
@@ -43,7 +44,9 @@ class MpmDesc(ct.Structure):
 class MpmTool(ct.Structure):
     _fields_ = [("shape", ct.c_int32), ("contact", ct.c_int32), ("radius", ct.c_float),
                 ("half_len", ct.c_float), ("friction", ct.c_float), ("theta", ct.c_float),
-                ("R", ct.c_float * 9), ("T0", ct.c_float * 3)]
+                ("R", ct.c_float * 9), ("T0", ct.c_float * 3), ("half", ct.c_float * 3),
+                ("sdf_res", ct.c_int32), ("sdf_interp", ct.c_int32), ("sdf_h", ct.c_float),
+                ("sdf_lo", ct.c_float * 3), ("sdf", ct.c_void_p)]
 
 
 class MpmAdjointIO(ct.Structure):

@@ -332,7 +332,7 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         }
     }
     for (int i = 0; i < n; ++i) {
-        timed(c, st, PK_GRID_ACTIVE, [&] { launch_grid_active(d, c->act, i & 1, grid_blocks(c), st); });
+        timed(c, st, PK_GRID_ACTIVE, [&] { launch_grid_active(d, c->act, i & 1, grid_blocks(c), c->has_sdf, st); });
         if (i == n - 1) {
             timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, tiled_args(c, in, A, 0), c->block, nb, st); });
         } else {
@@ -366,7 +366,8 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
     GraphEntry *ge = nullptr;
     for (auto &g : c->graphs)
         if (g.n == n && g.scheme == c->scheme && g.block == c->block && g.item == c->item &&
-            g.sort_every == c->sort_every && g.persistent == c->persistent && g.node_slots == c->node_slots)
+            g.sort_every == c->sort_every && g.persistent == c->persistent && g.node_slots == c->node_slots &&
+            g.sdf == c->has_sdf)
             ge = &g;
     if (!ge) {
         if (c->scheme == MPM_SCHEME_TILED && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -381,6 +382,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
         g.n = n; g.scheme = c->scheme; g.block = c->block; g.item = c->item; g.sort_every = c->sort_every;
         g.persistent = c->persistent;
         g.node_slots = c->node_slots;
+        g.sdf = c->has_sdf;
         if (c->persistent && c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -745,11 +747,27 @@ mpm_status mpm_set_tool(mpm_ctx *c, int32_t env, int32_t tool, const mpm_tool *t
         if (tool < 0 || tool >= c->max_tools) return fail(c, MPM_E_ARG, "tool slot out of range");
         ToolDev td{};
         if (t) {
-            if (t->shape != MPM_TOOL_CAPSULE) return fail(c, MPM_E_UNSUPPORTED, "only MPM_TOOL_CAPSULE is implemented");
             if (t->contact != MPM_CONTACT_SLIP && t->contact != MPM_CONTACT_STICKY) return fail(c, MPM_E_ARG, "bad contact mode");
-            if (!(t->radius > 0.f) || !(t->half_len >= 0.f) || !(t->friction >= 0.f) || !std::isfinite(t->theta) ||
-                !std::isfinite(t->radius) || !std::isfinite(t->half_len) || !std::isfinite(t->friction))
-                return fail(c, MPM_E_ARG, "tool needs radius > 0, half_len >= 0, friction >= 0, finite theta");
+            if (!(t->friction >= 0.f) || !std::isfinite(t->friction) || !std::isfinite(t->theta))
+                return fail(c, MPM_E_ARG, "tool needs friction >= 0 and a finite theta");
+            if (t->shape == MPM_TOOL_CAPSULE) {
+                if (!(t->radius > 0.f) || !(t->half_len >= 0.f) || !std::isfinite(t->radius) || !std::isfinite(t->half_len))
+                    return fail(c, MPM_E_ARG, "capsule needs radius > 0 and half_len >= 0");
+            } else if (t->shape == MPM_TOOL_BOX) {
+                if (!(t->radius >= 0.f) || !std::isfinite(t->radius)) return fail(c, MPM_E_ARG, "box needs radius >= 0");
+                for (int i = 0; i < 3; ++i)
+                    if (!(t->half[i] >= 0.f) || !std::isfinite(t->half[i])) return fail(c, MPM_E_ARG, "box needs half extents >= 0");
+            } else if (t->shape == MPM_TOOL_SDF) {
+                if (!t->sdf) return fail(c, MPM_E_ARG, "sampled SDF tool needs a device sample array");
+                if (t->sdf_res < 4 || t->sdf_res > 2048) return fail(c, MPM_E_ARG, "sdf_res must be in [4, 2048]");
+                if (t->sdf_interp != MPM_SDF_NEAREST && t->sdf_interp != MPM_SDF_TRILINEAR)
+                    return fail(c, MPM_E_ARG, "sdf_interp must be MPM_SDF_NEAREST or MPM_SDF_TRILINEAR");
+                if (!(t->sdf_h > 0.f) || !std::isfinite(t->sdf_h)) return fail(c, MPM_E_ARG, "sdf_h must be > 0");
+                for (int i = 0; i < 3; ++i)
+                    if (!std::isfinite(t->sdf_lo[i])) return fail(c, MPM_E_ARG, "sdf_lo must be finite");
+            } else {
+                return fail(c, MPM_E_ARG, "unknown tool shape");
+            }
             for (int i = 0; i < 9; ++i) if (!std::isfinite(t->R[i])) return fail(c, MPM_E_ARG, "R must be finite");
             for (int i = 0; i < 3; ++i) if (!std::isfinite(t->T0[i])) return fail(c, MPM_E_ARG, "T0 must be finite");
             if (!u || n_traj < 1) return fail(c, MPM_E_ARG, "u must be a device array with n_traj >= 1");
@@ -762,12 +780,20 @@ mpm_status mpm_set_tool(mpm_ctx *c, int32_t env, int32_t tool, const mpm_tool *t
             td.friction = t->friction;
             td.theta = t->theta;
             memcpy(td.R, t->R, sizeof td.R);
+            for (int i = 0; i < 3; ++i) td.half[i] = t->half[i];
+            td.sdf_res = t->sdf_res;
+            td.sdf_interp = t->sdf_interp;
+            td.sdf_h = t->sdf_h;
+            for (int i = 0; i < 3; ++i) td.sdf_lo[i] = t->sdf_lo[i];
+            td.sdf = t->shape == MPM_TOOL_SDF ? t->sdf : nullptr;
             td.k = 0;
             td.u = u;
             for (int i = 0; i < 3; ++i) td.T[i] = (double)t->T0[i];
         }
         size_t slot = (size_t)env * c->max_tools + tool;
         c->tools_h[slot] = td;
+        c->has_sdf = false;
+        for (const ToolDev &h : c->tools_h) c->has_sdf |= h.active && h.shape == MPM_TOOL_SDF;
         HIP_TRY(c, hipMemcpyAsync(c->tools + slot, &c->tools_h[slot], sizeof(ToolDev), hipMemcpyHostToDevice, c->stream0));
         HIP_TRY(c, hipStreamSynchronize(c->stream0));
         return MPM_OK;

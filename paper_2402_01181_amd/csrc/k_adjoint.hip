@@ -171,9 +171,8 @@ __device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, in
     ub = vb;                                   // v = v_rel' + u
     if (branch == 2) return make_float3(0.f, 0.f, 0.f);
     // friction branch: v = s v_t + u with s = 1 + mu vn/|vt|
-    CapsuleHit h = capsule_hit(T, i * e.dx, j * e.dx, k * e.dx);
     float3 u = tool_velocity(T);
-    float3 n = h.n;
+    float3 n = tool_hit(T, e, i, j, k).n;
     float r0 = vh.x - u.x, r1 = vh.y - u.y, r2 = vh.z - u.z;
     float vn = r0 * n.x + r1 * n.y + r2 * n.z;
     float t0 = r0 - vn * n.x, t1 = r1 - vn * n.y, t2 = r2 - vn * n.z;
@@ -188,18 +187,7 @@ __device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, in
     float rb0 = tb0 + vnb * n.x, rb1 = tb1 + vnb * n.y, rb2 = tb2 + vnb * n.z;
     float nb0 = -vn * tb0 + vnb * r0, nb1 = -vn * tb1 + vnb * r1, nb2 = -vn * tb2 + vnb * r2;
     ub.x -= rb0; ub.y -= rb1; ub.z -= rb2;
-    if (h.len >= 1e-12f) {
-        // n = R l, l = q/|q|, q = x_ref - clamp(x_ref.x) e_x, x_ref = R^T (x - T)
-        float lb0 = T.R[0] * nb0 + T.R[3] * nb1 + T.R[6] * nb2;
-        float lb1 = T.R[1] * nb0 + T.R[4] * nb1 + T.R[7] * nb2;
-        float lb2 = T.R[2] * nb0 + T.R[5] * nb1 + T.R[8] * nb2;
-        float dl = lb0 * h.l[0] + lb1 * h.l[1] + lb2 * h.l[2];
-        float qb0 = (lb0 - dl * h.l[0]) / h.len, qb1 = (lb1 - dl * h.l[1]) / h.len, qb2 = (lb2 - dl * h.l[2]) / h.len;
-        float xr0 = h.interior ? 0.0f : qb0;
-        Tb.x = -(T.R[0] * xr0 + T.R[1] * qb1 + T.R[2] * qb2);
-        Tb.y = -(T.R[3] * xr0 + T.R[4] * qb1 + T.R[5] * qb2);
-        Tb.z = -(T.R[6] * xr0 + T.R[7] * qb1 + T.R[8] * qb2);
-    }
+    Tb = tool_pose_bar(T, e, i, j, k, make_float3(nb0, nb1, nb2));
     return make_float3(rb0, rb1, rb2);
 }
 

@@ -82,11 +82,7 @@ __device__ __forceinline__ void advance_tools(const Dev &d, int t)
     if (t < d.n_envs * d.max_tools) {
         ToolDev &T = d.tools[t];
         if (T.active) {
-            float3 u = tool_velocity(T);
-            T.T[0] += (double)d.dt * u.x;
-            T.T[1] += (double)d.dt * u.y;
-            T.T[2] += (double)d.dt * u.z;
-            T.k += 1;
+            advance_tool(T, d.dt);
         }
     }
 }

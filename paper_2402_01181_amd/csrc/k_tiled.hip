@@ -25,11 +25,7 @@ __device__ __forceinline__ void advance_end_of_substep(const Dev &d)
     for (int t = threadIdx.x; t < d.n_envs * d.max_tools; t += blockDim.x) {
         ToolDev &T = d.tools[t];
         if (T.active) {
-            float3 u = tool_velocity(T);
-            T.T[0] += (double)d.dt * u.x;
-            T.T[1] += (double)d.dt * u.y;
-            T.T[2] += (double)d.dt * u.z;
-            T.k += 1;
+            advance_tool(T, d.dt);
         }
     }
 }
@@ -338,6 +334,7 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 // wavefront per 4^3 brick.  Writes V and clears P of every brick that
 // received mass; clears the flags of the dynamic bricks, and the other
 // dynamic list's count for the next P2G.
+template <bool SDF>
 __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -366,7 +363,7 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         int lb = b - e.bofs;
         int gi, gj, gk;
         brick_local_to_ijk(e, lb, lane, gi, gj, gk);
-        float3 v = grid_node_velocity(d, e, env, P, gi, gj, gk, nullptr);
+        float3 v = grid_node_velocity<SDF>(d, e, env, P, gi, gj, gk, nullptr);
         gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
         gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));
         if (dyn && lane == 0) gstore(a.flag + b, 0);
@@ -374,9 +371,10 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
     if (blockIdx.x == 0 && threadIdx.x == 0) gstore(a.dcount + (par ^ 1), 0);
 }
 
+template <bool SDF>
 __global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par)
 {
-    grid_active_body(d, a, par);
+    grid_active_body<SDF>(d, a, par);
 }
 
 // Grid-wide barrier for the persistent kernel: arrival counter plus a
@@ -422,7 +420,7 @@ __global__ __launch_bounds__(64 * W) void k_persistent(Dev d, TiledArgs first, T
     __syncthreads();
     for (int i = 0; i < m; ++i) {
         const int par = (par0 + i) & 1;
-        grid_active_body(d, first.act, par);
+        grid_active_body<true>(d, first.act, par);
         if (!grid_sync(bar, spin_limit, ok)) break;
         TiledArgs a = i == 0 ? first : rest;
         a.par = par ^ 1;
@@ -519,9 +517,10 @@ void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t 
     launch_k(k_brick_env, dim3(nblk < 4096 ? nblk : 4096), dim3(256), 0, st, env_bofs, n_envs, nbricks, brick_env);
 }
 
-void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st)
+void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, bool sdf, hipStream_t st)
 {
-    launch_k(k_grid_active, dim3(nblocks), dim3(256), 0, st, d, a, par);
+    if (sdf) launch_k(k_grid_active<true>, dim3(nblocks), dim3(256), 0, st, d, a, par);
+    else launch_k(k_grid_active<false>, dim3(nblocks), dim3(256), 0, st, d, a, par);
 }
 
 }  // namespace mpm

@@ -36,6 +36,7 @@ struct Profiler {
 // sequencing state that call leaves behind.
 struct GraphEntry {
     int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0, node_slots = 0;
+    bool sdf = false;
     hipGraphExec_t exec = nullptr;
     int since_sort_after = 0;
 };
@@ -75,6 +76,7 @@ struct mpm_ctx {
     int64_t max_items = 0;
     // sequencing state
     bool grid_clean = true;          // momentum buffer all zero, no active bricks
+    bool has_sdf = false;            // some active tool is a sampled SDF (grid kernel instantiation)
     bool items_valid = false;        // sort items match the current slot order and item size
     int items_P = 0;
     int since_sort = 0;

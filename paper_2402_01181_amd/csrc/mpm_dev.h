@@ -110,7 +110,14 @@ struct ToolDev {
     int32_t k;              // substeps taken since the slot was set
     const float *u;         // caller-owned [n_traj][3]
     double T[3];            // FP64 position of the tool origin
+    float half[3];          // box half extents
+    int32_t sdf_res, sdf_interp;
+    float sdf_h, sdf_lo[3];
+    int32_t pad;
+    const float *sdf;       // caller-owned [res][res][res] samples
 };
+
+static_assert(sizeof(ToolDev) == 152, "ToolDev layout");
 
 // Everything a kernel needs, passed by value.
 struct Dev {
@@ -293,60 +300,276 @@ __device__ __forceinline__ void update_h(float H[9], const float C[9], float dt)
 }
 
 // Grid operation of one node (Sec. III-B item 2, Sec. III-C): normalise +
-// gravity, z-buffer over the environment's tools (nearest capsule, ties to
-// the lowest slot), contact projection, then the boundary band has the last
-// word.  The forward and the adjoint take the same FP32 decisions through
-// the helpers below.
+// gravity, z-buffer over the environment's tools (nearest tool of any shape,
+// ties to the lowest slot), contact projection, then the boundary band has
+// the last word.  The forward and the adjoint take the same decisions
+// through the helpers below.
 __device__ __forceinline__ float3 tool_velocity(const ToolDev &t)
 {
     int k = t.k < t.n_traj ? t.k : t.n_traj - 1;
     return make_float3(t.u[3 * k], t.u[3 * k + 1], t.u[3 * k + 2]);
 }
 
-// Capsule distance in the tool frame: q = x_ref - clamp(x_ref.x) e_x,
-// phi = |q| - r; the contact normal is R q/|q| (R e_y on the axis).
-struct CapsuleHit {
-    float phi;
-    float3 n;          // world unit normal
-    float l[3];        // tool-frame unit normal
-    float len;         // |q|
-    bool interior;     // closest segment point strictly inside the segment
+// T_{s+1} = T_s + dt u_s in FP64, multiply then add (not fused, so the pose
+// has the bits of a plain FP64 evaluation of the recurrence).
+__device__ __forceinline__ void advance_tool(ToolDev &T, float dt)
+{
+#pragma clang fp contract(off)
+    float3 u = tool_velocity(T);
+    T.T[0] = T.T[0] + (double)dt * (double)u.x;
+    T.T[1] = T.T[1] + (double)dt * (double)u.y;
+    T.T[2] = T.T[2] + (double)dt * (double)u.z;
+    T.k += 1;
+}
+
+// x_ref = R^T (x - T) in FP32 (the analytic shapes).
+__device__ __forceinline__ void tool_frame(const ToolDev &t, const EnvDev &e, int i, int j, int k, float r[3])
+{
+    float dx0 = (float)(i * e.dx - t.T[0]), dx1 = (float)(j * e.dx - t.T[1]), dx2 = (float)(k * e.dx - t.T[2]);
+    r[0] = t.R[0] * dx0 + t.R[3] * dx1 + t.R[6] * dx2;
+    r[1] = t.R[1] * dx0 + t.R[4] * dx1 + t.R[7] * dx2;
+    r[2] = t.R[2] * dx0 + t.R[5] * dx1 + t.R[8] * dx2;
+}
+
+// Capsule: q = x_ref - clamp(x_ref.x, -h, h) e_x, phi = |q| - r, l = q/|q|
+// (e_y on the axis).  `interior`: the clamp is inactive.
+__device__ __forceinline__ float capsule_dist(const ToolDev &t, const float r[3], float l[3], float &len,
+                                              bool &interior)
+{
+    float c = fminf(fmaxf(r[0], -t.half_len), t.half_len);
+    interior = r[0] >= -t.half_len && r[0] <= t.half_len;
+    float q0 = r[0] - c;
+    len = sqrtf(q0 * q0 + r[1] * r[1] + r[2] * r[2]);
+    if (len < 1e-12f) { l[0] = 0.f; l[1] = 1.f; l[2] = 0.f; }
+    else { float il = 1.0f / len; l[0] = q0 * il; l[1] = r[1] * il; l[2] = r[2] * il; }
+    return len - t.radius;
+}
+
+// Box of half extents b rounded by r (a gripper jaw's bounding box): outside
+// the core, q = x_ref - clamp(x_ref, -b, b), phi = |q| - r, l = q/|q|;
+// inside, phi = max_a(|x_a| - b_a) - r and l = sign(x_k) e_k on the first
+// axis k reaching the maximum.
+__device__ __forceinline__ float box_dist(const ToolDev &t, const float r[3], float l[3], float &len, bool &outside)
+{
+    float q[3];
+    outside = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q[a] = r[a] - fminf(fmaxf(r[a], -t.half[a]), t.half[a]);
+        outside |= r[a] < -t.half[a] || r[a] > t.half[a];
+    }
+    len = 0.0f;
+    if (outside) {
+        len = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        if (len < 1e-12f) { l[0] = 0.f; l[1] = 1.f; l[2] = 0.f; }
+        else { float il = 1.0f / len; l[0] = q[0] * il; l[1] = q[1] * il; l[2] = q[2] * il; }
+        return len - t.radius;
+    }
+    int kk = 0;
+    float best = fabsf(r[0]) - t.half[0];
+#pragma unroll
+    for (int a = 1; a < 3; ++a)
+        if (fabsf(r[a]) - t.half[a] > best) { best = fabsf(r[a]) - t.half[a]; kk = a; }
+    l[0] = l[1] = l[2] = 0.0f;
+    l[kk] = r[kk] >= 0.0f ? 1.0f : -1.0f;
+    return best - t.radius;
+}
+
+// Sampled SDF: lattice coordinate s = (x_ref - lo) / h of a node, formed in
+// FP64 (plain multiply-then-add, as a scalar FP64 evaluation would) so the
+// cell it falls in is decided exactly; a cell without complete central
+// differences is outside the field.
+struct SdfCell {
+    bool valid;
+    int i0[3];
+    float f[3];
 };
 
-__device__ __forceinline__ CapsuleHit capsule_hit(const ToolDev &t, float px, float py, float pz)
+__device__ __forceinline__ SdfCell sdf_cell(const ToolDev &t, const EnvDev &e, int i, int j, int k)
 {
-    CapsuleHit h;
-    float dx0 = (float)(px - t.T[0]), dx1 = (float)(py - t.T[1]), dx2 = (float)(pz - t.T[2]);
-    // x_ref = R^T (x - T)
-    float r0 = t.R[0] * dx0 + t.R[3] * dx1 + t.R[6] * dx2;
-    float r1 = t.R[1] * dx0 + t.R[4] * dx1 + t.R[7] * dx2;
-    float r2 = t.R[2] * dx0 + t.R[5] * dx1 + t.R[8] * dx2;
-    float c = fminf(fmaxf(r0, -t.half_len), t.half_len);
-    h.interior = r0 >= -t.half_len && r0 <= t.half_len;
-    float q0 = r0 - c;
-    h.len = sqrtf(q0 * q0 + r1 * r1 + r2 * r2);
-    if (h.len < 1e-12f) { h.l[0] = 0.f; h.l[1] = 1.f; h.l[2] = 0.f; }
-    else { float il = 1.0f / h.len; h.l[0] = q0 * il; h.l[1] = r1 * il; h.l[2] = r2 * il; }
-    h.n.x = t.R[0] * h.l[0] + t.R[1] * h.l[1] + t.R[2] * h.l[2];
-    h.n.y = t.R[3] * h.l[0] + t.R[4] * h.l[1] + t.R[5] * h.l[2];
-    h.n.z = t.R[6] * h.l[0] + t.R[7] * h.l[1] + t.R[8] * h.l[2];
-    h.phi = h.len - t.radius;
+#pragma clang fp contract(off)
+    SdfCell c;
+    const double inv_n = 1.0 / (double)e.n;
+    const double d0 = (double)i * inv_n - t.T[0], d1 = (double)j * inv_n - t.T[1], d2 = (double)k * inv_n - t.T[2];
+    const double lim = t.sdf_interp == MPM_SDF_TRILINEAR ? t.sdf_res - 2 : t.sdf_res - 1;
+    double s[3];
+    c.valid = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double ra = (double)t.R[a] * d0 + (double)t.R[3 + a] * d1 + (double)t.R[6 + a] * d2;
+        s[a] = (ra - (double)t.sdf_lo[a]) / (double)t.sdf_h;
+        c.valid &= s[a] >= 1.0 && s[a] < lim;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double fl = c.valid ? floor(s[a]) : 1.0;
+        c.i0[a] = (int)fl;
+        c.f[a] = c.valid ? (float)(s[a] - fl) : 0.0f;
+    }
+    return c;
+}
+
+__device__ __forceinline__ float sdf_sample(const ToolDev &t, int i, int j, int k)
+{
+    return gload(t.sdf + ((size_t)i * t.sdf_res + j) * t.sdf_res + k);
+}
+
+// Central-difference gradient of the samples at a lattice point (Sec. III-C,
+// normal equation).
+__device__ __forceinline__ void sdf_grad(const ToolDev &t, int i, int j, int k, float g[3])
+{
+    const float s = 0.5f / t.sdf_h;
+    g[0] = (sdf_sample(t, i + 1, j, k) - sdf_sample(t, i - 1, j, k)) * s;
+    g[1] = (sdf_sample(t, i, j + 1, k) - sdf_sample(t, i, j - 1, k)) * s;
+    g[2] = (sdf_sample(t, i, j, k + 1) - sdf_sample(t, i, j, k - 1)) * s;
+}
+
+// Trilinear weight of corner (o0,o1,o2) and its derivatives in the cell
+// coordinates.
+__device__ __forceinline__ float corner_weight(const float f[3], int c, float dw[3])
+{
+    float wa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wa[a] = ((c >> (2 - a)) & 1) ? f[a] : 1.0f - f[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        float v = ((c >> (2 - b)) & 1) ? 1.0f : -1.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (a != b) v *= wa[a];
+        dw[b] = v;
+    }
+    return wa[0] * wa[1] * wa[2];
+}
+
+// Distance (INFINITY outside the field), unscaled gradient g and its norm.
+__device__ __forceinline__ float sampled_dist(const ToolDev &t, const SdfCell &c, float g[3], float &gl)
+{
+    g[0] = 0.f; g[1] = 1.f; g[2] = 0.f;
+    gl = 1.0f;
+    if (!c.valid) return INFINITY;
+    float phi;
+    if (t.sdf_interp == MPM_SDF_NEAREST) {
+        phi = sdf_sample(t, c.i0[0], c.i0[1], c.i0[2]);
+        sdf_grad(t, c.i0[0], c.i0[1], c.i0[2], g);
+    } else {
+        phi = 0.0f;
+        g[0] = g[1] = g[2] = 0.0f;
+#pragma unroll 1
+        for (int cc = 0; cc < 8; ++cc) {
+            const int i = c.i0[0] + ((cc >> 2) & 1), j = c.i0[1] + ((cc >> 1) & 1), k = c.i0[2] + (cc & 1);
+            float dw[3], G[3];
+            const float w = corner_weight(c.f, cc, dw);
+            sdf_grad(t, i, j, k, G);
+            phi += w * sdf_sample(t, i, j, k);
+            g[0] += w * G[0]; g[1] += w * G[1]; g[2] += w * G[2];
+        }
+    }
+    gl = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    return phi;
+}
+
+struct ToolHit {
+    float phi;
+    float3 n;          // world unit normal
+};
+
+// SDF = false leaves the sampled-SDF branch out (fewer registers); only for
+// launches where no active tool is a sampled SDF.
+template <bool SDF = true>
+__device__ __forceinline__ ToolHit tool_hit(const ToolDev &t, const EnvDev &e, int i, int j, int k)
+{
+    ToolHit h;
+    float l[3];
+    if (SDF && t.shape == MPM_TOOL_SDF) {
+        const SdfCell c = sdf_cell(t, e, i, j, k);
+        float g[3], gl;
+        h.phi = sampled_dist(t, c, g, gl);
+        if (gl < 1e-12f) { l[0] = 0.f; l[1] = 1.f; l[2] = 0.f; }
+        else { float il = 1.0f / gl; l[0] = g[0] * il; l[1] = g[1] * il; l[2] = g[2] * il; }
+    } else {
+        float r[3], len;
+        bool flag;
+        tool_frame(t, e, i, j, k, r);
+        h.phi = t.shape == MPM_TOOL_BOX ? box_dist(t, r, l, len, flag) : capsule_dist(t, r, l, len, flag);
+    }
+    h.n.x = t.R[0] * l[0] + t.R[1] * l[1] + t.R[2] * l[2];
+    h.n.y = t.R[3] * l[0] + t.R[4] * l[1] + t.R[5] * l[2];
+    h.n.z = t.R[6] * l[0] + t.R[7] * l[1] + t.R[8] * l[2];
     return h;
 }
 
-// Which tool (if any) a node touches: nearest active capsule with phi < theta.
-__device__ __forceinline__ int select_tool(const ToolDev *tl, int max_tools, float px, float py, float pz,
-                                           CapsuleHit &hit)
+// Collision objects table entry of a node: the nearest active tool with
+// phi < theta (the z-buffer over tools), or -1.
+template <bool SDF>
+__device__ __forceinline__ int select_tool(const ToolDev *tl, int max_tools, const EnvDev &e, int i, int j, int k,
+                                           ToolHit &hit)
 {
     float best = INFINITY;
     int bt = -1;
     for (int t = 0; t < max_tools; ++t) {
         if (!tl[t].active) continue;
-        CapsuleHit h = capsule_hit(tl[t], px, py, pz);
+        ToolHit h = tool_hit<SDF>(tl[t], e, i, j, k);
         if (h.phi < best) { best = h.phi; bt = t; hit = h; }
     }
     if (bt >= 0 && !(best < tl[bt].theta)) bt = -1;
     return bt;
+}
+
+// Adjoint of the tool position through the contact normal: given n_bar,
+// T_bar = -R x_ref_bar with x_ref_bar = (dl/dx_ref)^T R^T n_bar.
+__device__ __forceinline__ float3 tool_pose_bar(const ToolDev &t, const EnvDev &e, int i, int j, int k, float3 nb)
+{
+    const float lb0 = t.R[0] * nb.x + t.R[3] * nb.y + t.R[6] * nb.z;
+    const float lb1 = t.R[1] * nb.x + t.R[4] * nb.y + t.R[7] * nb.z;
+    const float lb2 = t.R[2] * nb.x + t.R[5] * nb.y + t.R[8] * nb.z;
+    float xb[3] = {0.f, 0.f, 0.f};
+    if (t.shape == MPM_TOOL_SDF) {
+        // trilinear: l = g/|g|, g = sum_c w_c G_c; nearest: l is constant in the cell
+        const SdfCell c = sdf_cell(t, e, i, j, k);
+        if (c.valid && t.sdf_interp == MPM_SDF_TRILINEAR) {
+            float g[3], gl;
+            sampled_dist(t, c, g, gl);
+            if (gl >= 1e-12f) {
+                const float il = 1.0f / gl;
+                const float l0 = g[0] * il, l1 = g[1] * il, l2 = g[2] * il;
+                const float dl = lb0 * l0 + lb1 * l1 + lb2 * l2;
+                const float gb0 = (lb0 - dl * l0) * il, gb1 = (lb1 - dl * l1) * il, gb2 = (lb2 - dl * l2) * il;
+                const float ih = 1.0f / t.sdf_h;
+#pragma unroll 1
+                for (int cc = 0; cc < 8; ++cc) {
+                    float dw[3], G[3];
+                    corner_weight(c.f, cc, dw);
+                    sdf_grad(t, c.i0[0] + ((cc >> 2) & 1), c.i0[1] + ((cc >> 1) & 1), c.i0[2] + (cc & 1), G);
+                    const float gg = (G[0] * gb0 + G[1] * gb1 + G[2] * gb2) * ih;
+                    xb[0] += gg * dw[0]; xb[1] += gg * dw[1]; xb[2] += gg * dw[2];
+                }
+            }
+        }
+    } else {
+        float r[3], l[3], len;
+        bool flag;
+        tool_frame(t, e, i, j, k, r);
+        bool live[3];
+        if (t.shape == MPM_TOOL_BOX) {
+            box_dist(t, r, l, len, flag);                 // flag: outside the core box
+#pragma unroll
+            for (int a = 0; a < 3; ++a) live[a] = flag && (r[a] < -t.half[a] || r[a] > t.half[a]);
+        } else {
+            capsule_dist(t, r, l, len, flag);             // flag: clamp inactive along the axis
+            live[0] = !flag; live[1] = live[2] = true;
+        }
+        if ((t.shape != MPM_TOOL_BOX || flag) && len >= 1e-12f) {
+            // l = q/|q|: q_bar = (l_bar - (l_bar . l) l)/|q|; x_ref_bar = D q_bar
+            const float dl = lb0 * l[0] + lb1 * l[1] + lb2 * l[2];
+            const float qb[3] = {(lb0 - dl * l[0]) / len, (lb1 - dl * l[1]) / len, (lb2 - dl * l[2]) / len};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xb[a] = live[a] ? qb[a] : 0.0f;
+        }
+    }
+    return make_float3(-(t.R[0] * xb[0] + t.R[1] * xb[1] + t.R[2] * xb[2]),
+                       -(t.R[3] * xb[0] + t.R[4] * xb[1] + t.R[5] * xb[2]),
+                       -(t.R[6] * xb[0] + t.R[7] * xb[1] + t.R[8] * xb[2]));
 }
 
 __device__ __forceinline__ bool boundary_node(const EnvDev &e, int i, int j, int k)
@@ -369,6 +592,7 @@ __device__ __forceinline__ float3 node_vhat(const Dev &d, float4 P)
     return make_float3(P.y / P.x + d.dt * d.gx, P.z / P.x + d.dt * d.gy, P.w / P.x + d.dt * d.gz);
 }
 
+template <bool SDF = true>
 __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev &e, int env, float4 P, int i,
                                                      int j, int k, ContactRec *rec)
 {
@@ -378,8 +602,8 @@ __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev 
     if (boundary_node(e, i, j, k)) return make_float3(0.f, 0.f, 0.f);
     if (d.max_tools > 0) {
         const ToolDev *tl = d.tools + (size_t)env * d.max_tools;
-        CapsuleHit h;
-        int bt = select_tool(tl, d.max_tools, i * e.dx, j * e.dx, k * e.dx, h);
+        ToolHit h;
+        int bt = select_tool<SDF>(tl, d.max_tools, e, i, j, k, h);
         if (bt >= 0) {
             const ToolDev &T = tl[bt];
             float3 u = tool_velocity(T);

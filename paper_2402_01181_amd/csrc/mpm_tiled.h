@@ -80,7 +80,7 @@ void launch_fused_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks
 void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 // fused G2P + P2G that also writes v and C (d.gV: this substep's grid, d.gP: the next one's)
 void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
-void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, hipStream_t st);
+void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, bool sdf, hipStream_t st);
 // brick_env[b] = environment of brick b (once, at create)
 void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *brick_env, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block

@@ -63,6 +63,7 @@ class Sim:
         self.max_tape = int(max_tape)
         self.options = dict(options or {})
         self.traj = {}
+        self._sdf = {}        # id(samples) -> (host array, device copy) of sampled-SDF tools
         self.ctx = ct.c_void_p()
         self._create(stream)
 
@@ -91,10 +92,23 @@ class Sim:
             u = torch.from_numpy(np.ascontiguousarray(np.asarray(tool.traj if traj is None else traj,
                                                                  np.float32))).to(self.device)
         self.traj[(env, slot)] = u
-        td = L.MpmTool(shape=L.TOOL_CAPSULE, contact=int(tool.contact), radius=tool.radius,
+        shape = int(getattr(tool, "shape", L.TOOL_CAPSULE))
+        td = L.MpmTool(shape=shape, contact=int(tool.contact), radius=tool.radius,
                        half_len=tool.half_len, friction=tool.friction, theta=tool.theta,
                        R=(ct.c_float * 9)(*np.asarray(tool.R, np.float32).reshape(-1).tolist()),
-                       T0=(ct.c_float * 3)(*np.asarray(tool.T0, np.float32).tolist()))
+                       T0=(ct.c_float * 3)(*np.asarray(tool.T0, np.float32).tolist()),
+                       half=(ct.c_float * 3)(*np.asarray(getattr(tool, "half", (0, 0, 0)), np.float32).tolist()))
+        if shape == L.TOOL_SDF:
+            # device copy of the samples, shared by every slot given the same array
+            key = id(tool.sdf)
+            if key not in self._sdf:
+                self._sdf[key] = (tool.sdf, torch.from_numpy(np.ascontiguousarray(tool.sdf, np.float32)).to(self.device))
+            S = self._sdf[key][1]
+            td.sdf = S.data_ptr()
+            td.sdf_res = int(S.shape[0])
+            td.sdf_interp = int(tool.sdf_interp)
+            td.sdf_h = float(tool.sdf_h)
+            td.sdf_lo = (ct.c_float * 3)(*np.asarray(tool.sdf_lo, np.float32).tolist())
         L.check(self.lib.mpm_set_tool(self.ctx, env, slot, ct.byref(td), ct.c_void_p(u.data_ptr()), u.shape[0]),
                 self.ctx)
 
