@@ -78,11 +78,12 @@ def _events_ms(torch, fn):
     return a.elapsed_time(b)
 
 
-def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200):
+def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200):
     """The other forms of the substep on the same GPU: the batched workload
     (256 environments, launch options tuned for it when `tune`) and the
     differentiable slab (forward with tape + hand adjoint, checkpoints every
-    20) against its plain forward with the slab's options."""
+    20) against its plain forward with the slab's options, and the slab with
+    box-gripper and sampled-SDF tools in place of the capsule."""
     from paper_2402_01181_amd import scenes
     out = {}
     bsc = scenes.batched_scene()
@@ -125,6 +126,29 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200):
                               "value": N * adj_steps / (ms_fa * 1e-3), "unit": "particle-substeps/s",
                               "ratio_to_forward": ms_fa / ms_f}
     ad.close()
+    # the other tool shapes on the headline slab: box gripper jaws and a
+    # 256^3 sampled SDF (nearest sample and trilinear), grid kernel timed
+    # with the library's event timer
+    tools = {}
+    for name, kind, interp in (("box_gripper", "gripper", scenes.SDF_TRILINEAR),
+                               ("sdf256_nearest", "sdf", scenes.SDF_NEAREST),
+                               ("sdf256_trilinear", "sdf", scenes.SDF_TRILINEAR)):
+        tsc = scenes.slab_tool_scene(kind, interp=interp)
+        ts = Sim(tsc, options=opts)
+        ts.step(20)
+        ms_t = _events_ms(torch, lambda: ts.step(tool_steps))
+        ts.profile(True)
+        ts.step(tool_steps)
+        torch.cuda.synchronize()
+        ts.profile(False)
+        rep = ts.profile_report()
+        grid = {k: 1e3 * t / n for k, (t, n) in rep.items() if k.startswith("grid")}
+        tools[name] = {"ms_per_substep": ms_t / tool_steps, "value": tsc.n_particles * tool_steps / (ms_t * 1e-3),
+                       "grid_kernel_avg_us": grid, "status": int(ts.read(L.F_STATUS))}
+        ts.close()
+    out["tool_shapes"] = {"workload": "slab 30,000 particles, 64^3, capsule replaced by the named tool",
+                          "substeps": tool_steps, "unit": "particle-substeps/s", "shapes": tools,
+                          "value": min(v["value"] for v in tools.values())}
     return out
 
 

@@ -168,11 +168,14 @@ def probe_sdf_samples(res: int, extent: float, tip_radius=0.025, shaft_radius=0.
     h = extent / (res - 1)
     lo = -0.5 * extent
     ax = lo + h * np.arange(res)
-    X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
-    ball = np.sqrt(X * X + Y * Y + Z * Z) - tip_radius
-    yc = np.clip(Y, 0.0, shaft_len)
-    rod = np.sqrt(X * X + (Y - yc) ** 2 + Z * Z) - shaft_radius
-    return _f32(np.minimum(ball, rod)), float(np.float32(h)), tuple(float(v) for v in _f32((lo, lo, lo)))
+    Y, Z = np.meshgrid(ax, ax, indexing="ij")
+    dy = Y - np.clip(Y, 0.0, shaft_len)
+    out = np.empty((res, res, res), np.float32)
+    for i, x in enumerate(ax):          # one x slice at a time keeps the temporaries small
+        ball = np.sqrt(x * x + Y * Y + Z * Z) - tip_radius
+        rod = np.sqrt(x * x + dy * dy + Z * Z) - shaft_radius
+        out[i] = np.minimum(ball, rod)
+    return out, float(np.float32(h)), tuple(float(v) for v in _f32((lo, lo, lo)))
 
 
 def sdf_tool(T0, samples, h, lo, u=None, traj=None, interp=SDF_TRILINEAR, friction=0.3, theta=1e-3,
@@ -336,6 +339,27 @@ def tool_slab_scene(seed: int, n_particles: int, kind: str, n: int = 32, substep
                               interp=interp, R=rotation(rng, 0.4), **kw))
     env.tools = tools
     sc.name = f"{kind}-slab-{n_particles}-{n}"
+    return sc
+
+
+def slab_tool_scene(kind: str, seed: int = 2, n_particles: int = 30000, substeps: int = 1000,
+                    sdf_res: int = 256, interp: int = SDF_TRILINEAR) -> Scene:
+    """The 30K slab with its capsule replaced by a box gripper ("gripper":
+    two jaws 1 cm into the top surface, pushing at 0.2 m/s and closing at
+    0.1 m/s each) or a sampled ball-tipped probe ("sdf": ``sdf_res``^3
+    samples at spacing 1/256 m around the tool origin, so 256 samples span
+    the unit domain, tip 2 cm into the top surface, pushing at 0.2 m/s)."""
+    sc = slab_scene(seed=seed, n_particles=n_particles, substeps=substeps)
+    top = 3.0 / 64 + 0.1
+    if kind == "gripper":
+        tools = gripper_tools((0.5, top + 0.02, 0.5), (0.0, -0.2, 0.0))
+    elif kind == "sdf":
+        S, h, lo = probe_sdf_samples(sdf_res, (sdf_res - 1) / 256.0)
+        tools = [sdf_tool((0.5, top + 0.005, 0.5), S, h, lo, u=(0.0, -0.2, 0.0), interp=interp)]
+    else:
+        raise ValueError(kind)
+    sc.envs[0].tools = tools
+    sc.name = f"slab-{kind}-{n_particles // 1000}k-64"
     return sc
 
 
