@@ -1,0 +1,71 @@
+"""Stiffness sweep (the paper's four-modulus experiment, Sec. IV Fig. seq2)
+and material identification through the hand adjoint, on the GPU.  The sweep
+is checked against the FP64 oracle environment by environment; the fit must
+recover the modulus and Poisson ratio a trajectory was made with."""
+import numpy as np
+import pytest
+
+from paper_2402_01181_amd import scenes
+from parity import TOL_DRIFT, oracle_sim_like
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU")
+    from paper_2402_01181_amd import _lib, sysid
+    from paper_2402_01181_amd.sim import Sim
+    return Sim, _lib, sysid, torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _press_scene(N=6000, n=32, S=150):
+    return scenes.small_slab_scene(81, N, n=n, substeps=S, u=(0.0, -0.5, 0.0), dt=1e-4, E=1e4, nu=0.3)
+
+
+def test_stiffness_sweep_monotone_and_matches_oracle(gpu, orc):
+    Sim, L, sysid, torch = gpu
+    S = 150
+    Es = [2e3, 5e3, 1e4, 2e4]
+    _say(f"stiffness sweep: 6000 particles, 32^3, {S} substeps, E = {Es}, one batched call")
+    sc = _press_scene(S=S)
+    d = sysid.stiffness_sweep(sc, Es, S, options={L.OPT_SCHEME: L.SCHEME_TILED})
+    _say(f"  largest displacement per E: {d['max']}, mean: {d['mean']}")
+    assert np.all(np.diff(d["max"]) < 0) and np.all(np.diff(d["mean"]) < 0)
+    for k, E in enumerate(Es):
+        o = oracle_sim_like(orc, sc)
+        o.P.E = float(np.float32(E))
+        o.run(S)
+        do = np.linalg.norm(o.state.x - sc.envs[0].x.astype(np.float64), axis=1)
+        _say(f"  E={E:g}: max gpu {d['max'][k]:.6e} oracle {do.max():.6e}, mean gpu {d['mean'][k]:.6e} "
+             f"oracle {do.mean():.6e}")
+        assert abs(d["max"][k] - do.max()) <= TOL_DRIFT
+        assert abs(d["mean"][k] - do.mean()) <= 1e-2 * do.mean()
+
+
+def test_identify_recovers_material(gpu, orc):
+    Sim, L, sysid, torch = gpu
+    S = 150
+    E_true, nu_true = 6e3, 0.32
+    _say(f"identification: 6000 particles, 32^3, {S} substeps, truth E={E_true:g} nu={nu_true}, "
+         f"start E=1.5e4 nu=0.42")
+    sc = _press_scene(S=S)
+    sc.envs[0].E, sc.envs[0].nu = float(np.float32(E_true)), float(np.float32(nu_true))
+    obs = Sim(sc)
+    obs.step(S)
+    x_obs = obs.positions().clone()
+    assert obs.read(L.F_STATUS) == 0
+    obs.close()
+    fit = sysid.identify(sc, x_obs, 1.5e4, 0.42, S, max_evals=40)
+    for h in fit["history"][:: max(1, len(fit["history"]) // 8)]:
+        _say(f"  E={h['E']:.2f} nu={h['nu']:.5f} loss={h['loss']:.3e}")
+    _say(f"  fit after {fit['evals']} evaluations: E={fit['E']:.2f} nu={fit['nu']:.5f} loss={fit['loss']:.3e}")
+    assert abs(fit["E"] - E_true) <= 1e-2 * E_true
+    assert abs(fit["nu"] - nu_true) <= 5e-3
+    assert fit["loss"] < 1e-4
