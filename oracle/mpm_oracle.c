@@ -776,3 +776,188 @@ uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *t
     free(gvbar); free(gmbar); free(gmvbar); free(rec); free(Tbar); free(T);
     return flags;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Surface extraction: marching cubes over the mass volume (Sec. III-A, the
+ * post-processing that turns the particles into a triangle mesh; Lorensen and
+ * Cline's method as cited there).
+ *
+ * Readings (R18): the mass volume is the P2G mass on the simulation grid,
+ * density rho_i = m_i / dx^3 at node i, and the surface is rho = iso.  A cell
+ * corner is inside when rho >= iso.  Per cell the surface is made of closed
+ * polygons found by walking the six faces: on a face, the edges whose two
+ * corners differ are crossed once; two crossings are joined by one segment;
+ * four crossings (diagonally opposite inside corners) by two segments, each
+ * cutting off one inside corner.  Each segment runs so that, seen from
+ * outside the cell, the inside corners it cuts off lie on its left; a
+ * crossing point is then the end of one segment and the start of the next,
+ * which chains the segments into polygons.  A polygon is split into a fan of
+ * triangles from its lowest-numbered edge, and polygons are taken in order of
+ * their lowest-numbered edge.  Crossing points are the linear interpolation
+ * of rho along the edge.  Triangles are wound so that their right-hand normal
+ * points out of the dense region.
+ *
+ * Numbering: corner c = 4 dx + 2 dy + dz at (i+dx, j+dy, k+dz) h; edge
+ * e = 4 a + p along axis a, p = the two other corner bits in axis order.
+ * Cells (i, j, k) in [0, n-1)^3, row-major. */
+
+static int mc_edge(int ca, int cb)
+{
+    int diff = ca ^ cb, a = diff == 4 ? 0 : diff == 2 ? 1 : 2;
+    int lo = ca & ~diff;
+    int bx = (lo >> 2) & 1, by = (lo >> 1) & 1, bz = lo & 1;
+    int p = a == 0 ? 2 * by + bz : a == 1 ? 2 * bx + bz : 2 * bx + by;
+    return 4 * a + p;
+}
+
+static void mc_edge_corners(int e, int *ca, int *cb)
+{
+    int a = e / 4, p = e % 4, hi = (p >> 1) & 1, lo = p & 1;
+    int bits[3];
+    if (a == 0) { bits[1] = hi; bits[2] = lo; }
+    else if (a == 1) { bits[0] = hi; bits[2] = lo; }
+    else { bits[0] = hi; bits[1] = lo; }
+    bits[a] = 0;
+    *ca = 4 * bits[0] + 2 * bits[1] + bits[2];
+    bits[a] = 1;
+    *cb = 4 * bits[0] + 2 * bits[1] + bits[2];
+}
+
+static void mc_corner_pos(int c, double p[3])
+{
+    p[0] = (c >> 2) & 1; p[1] = (c >> 1) & 1; p[2] = c & 1;
+}
+
+static void mc_edge_mid(int e, double m[3])
+{
+    int ca, cb;
+    double pa[3], pb[3];
+    mc_edge_corners(e, &ca, &cb);
+    mc_corner_pos(ca, pa);
+    mc_corner_pos(cb, pb);
+    for (int d = 0; d < 3; ++d) m[d] = 0.5 * (pa[d] + pb[d]);
+}
+
+/* Orientation test for a segment p -> q on the face with outward normal N
+ * cutting off inside corner K: K lies on the left, seen from outside. */
+static int mc_left(int p, int q, const double N[3], int K)
+{
+    double mp[3], mq[3], ck[3], d[3], l[3];
+    mc_edge_mid(p, mp);
+    mc_edge_mid(q, mq);
+    mc_corner_pos(K, ck);
+    for (int a = 0; a < 3; ++a) d[a] = mq[a] - mp[a];
+    l[0] = N[1] * d[2] - N[2] * d[1];
+    l[1] = N[2] * d[0] - N[0] * d[2];
+    l[2] = N[0] * d[1] - N[1] * d[0];
+    return l[0] * (ck[0] - mp[0]) + l[1] * (ck[1] - mp[1]) + l[2] * (ck[2] - mp[2]) > 0.0;
+}
+
+/* Triangles (as edge triples) of one cell case; returns their number, or -1
+ * if the face segments do not chain into closed polygons. */
+int orc_mc_case(int mask, int32_t tri[][3])
+{
+    int next[12];
+    for (int e = 0; e < 12; ++e) next[e] = -1;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s) {
+            int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+            int ring[4];
+            const int uv[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+            for (int r = 0; r < 4; ++r) {
+                int bits[3];
+                bits[a] = s;
+                bits[u] = uv[r][0];
+                bits[v] = uv[r][1];
+                ring[r] = 4 * bits[0] + 2 * bits[1] + bits[2];
+            }
+            double N[3] = {0.0, 0.0, 0.0};
+            N[a] = s ? 1.0 : -1.0;
+            int in[4], ncross = 0;
+            for (int r = 0; r < 4; ++r) in[r] = (mask >> ring[r]) & 1;
+            for (int r = 0; r < 4; ++r) ncross += in[r] != in[(r + 1) % 4];
+            if (ncross == 0) continue;
+            /* segments as (edge, edge, inside corner they cut off or bound) */
+            int segs[2][3], nseg = 0;
+            if (ncross == 2) {
+                int ends[2], ne = 0, K = -1;
+                for (int r = 0; r < 4; ++r) {
+                    if (in[r] != in[(r + 1) % 4]) ends[ne++] = mc_edge(ring[r], ring[(r + 1) % 4]);
+                    if (in[r] && K < 0) K = ring[r];
+                }
+                segs[0][0] = ends[0]; segs[0][1] = ends[1]; segs[0][2] = K;
+                nseg = 1;
+            } else {
+                for (int r = 0; r < 4; ++r)
+                    if (in[r]) {
+                        segs[nseg][0] = mc_edge(ring[(r + 3) % 4], ring[r]);
+                        segs[nseg][1] = mc_edge(ring[r], ring[(r + 1) % 4]);
+                        segs[nseg][2] = ring[r];
+                        ++nseg;
+                    }
+            }
+            for (int g = 0; g < nseg; ++g) {
+                int p = segs[g][0], q = segs[g][1];
+                if (!mc_left(p, q, N, segs[g][2])) { int t = p; p = q; q = t; }
+                if (next[p] >= 0) return -1;
+                next[p] = q;
+            }
+        }
+    int used[12] = {0}, nt = 0;
+    for (int e0 = 0; e0 < 12; ++e0) {
+        if (next[e0] < 0 || used[e0]) continue;
+        int loop[12], k = 0, e = e0;
+        do {
+            if (e < 0 || used[e] || k >= 12) return -1;
+            used[e] = 1;
+            loop[k++] = e;
+            e = next[e];
+        } while (e != e0);
+        for (int t = 1; t + 1 < k; ++t) {
+            tri[nt][0] = loop[0];
+            tri[nt][1] = loop[t + 1];
+            tri[nt][2] = loop[t];
+            ++nt;
+        }
+    }
+    for (int e = 0; e < 12; ++e)
+        if ((next[e] >= 0) != used[e]) return -1;
+    return nt;
+}
+
+int64_t orc_surface(int32_t n, double h, const double *rho, double iso, int32_t *cell_ntri, int32_t *tri_edges,
+                    double *tris, int64_t max_tris)
+{
+    const int nc = n - 1;
+    int64_t total = 0;
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j)
+            for (int k = 0; k < nc; ++k) {
+                double val[8];
+                int mask = 0;
+                for (int c = 0; c < 8; ++c) {
+                    val[c] = rho[IDX(n, i + ((c >> 2) & 1), j + ((c >> 1) & 1), k + (c & 1))];
+                    if (val[c] >= iso) mask |= 1 << c;
+                }
+                int32_t tri[12][3];
+                int nt = orc_mc_case(mask, tri);
+                if (nt < 0) return -1;
+                if (cell_ntri) cell_ntri[((size_t)i * nc + j) * nc + k] = nt;
+                for (int t = 0; t < nt; ++t, ++total) {
+                    if (total >= max_tris) continue;
+                    for (int v = 0; v < 3; ++v) {
+                        int ca, cb;
+                        double pa[3], pb[3];
+                        mc_edge_corners(tri[t][v], &ca, &cb);
+                        mc_corner_pos(ca, pa);
+                        mc_corner_pos(cb, pb);
+                        double f = (iso - val[ca]) / (val[cb] - val[ca]);
+                        const int cell[3] = {i, j, k};
+                        for (int d = 0; d < 3; ++d)
+                            tris[9 * total + 3 * v + d] = (cell[d] + pa[d] + f * (pb[d] - pa[d])) * h;
+                        if (tri_edges) tri_edges[3 * total + v] = tri[t][v];
+                    }
+                }
+            }
+    return total;
+}

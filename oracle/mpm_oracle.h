@@ -14,6 +14,8 @@
  *             friction, z-buffer over tools).
  *   G2P       Sec. III-B item 3 (velocity, affine matrix, advection).
  *   F update  Sec. III-B item 1, the F' = (I + dt C) F relation.
+ *   Surface   Sec. III-A post-processing: marching cubes over the mass
+ *             volume (orc_surface, orc_mc_case).
  * Readings where the paper is silent or garbled are listed beside each
  * function in mpm_oracle.c.
  *
@@ -97,6 +99,9 @@ uint32_t orc_substep(const orc_params *P, const orc_tool *tools, double *T, cons
 uint32_t orc_run(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
                  int32_t s0, int32_t S, double *T, int32_t N, double *x, double *v, double *C,
                  double *F);
+int orc_mc_case(int mask, int32_t tri[][3]);
+int64_t orc_surface(int32_t n, double h, const double *rho, double iso, int32_t *cell_ntri, int32_t *tri_edges,
+                    double *tris, int64_t max_tris);
 uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
                      int32_t S, const double *T0, int32_t N, const double *x0, const double *v0,
                      const double *C0, const double *F0, double *xbar, double *vbar, double *Cbar,

@@ -89,6 +89,11 @@ def lib():
                                   _D, _D, _D, _D, _D, _D, _D, _D,
                                   ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
         L.orc_adjoint.restype = ct.c_uint32
+        L.orc_mc_case.argtypes = [ct.c_int, ct.c_void_p]
+        L.orc_mc_case.restype = ct.c_int
+        L.orc_surface.argtypes = [ct.c_int32, ct.c_double, _D, ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                  ct.c_int64]
+        L.orc_surface.restype = ct.c_int64
         _lib = L
     return _lib
 
@@ -269,3 +274,28 @@ def capsule_sdf(xref, radius, half_len):
     phi = lib().orc_capsule_sdf(np.ascontiguousarray(np.asarray(xref, np.float64)), radius, half_len, q,
                                 ct.byref(inside))
     return phi, q, bool(inside.value)
+
+
+def mc_case(mask):
+    """Triangles of one marching-cubes cell case as edge triples, (T, 3)."""
+    tri = np.zeros((12, 3), np.int32)
+    nt = lib().orc_mc_case(int(mask), tri.ctypes.data_as(ct.c_void_p))
+    if nt < 0:
+        raise RuntimeError(f"case {mask}: face segments do not close")
+    return tri[:nt]
+
+
+def surface(rho, h, iso):
+    """Iso-surface rho = iso of a node field rho (n, n, n): triangles (T, 3, 3)
+    in cell order, triangles per cell ((n-1)^3,), edge ids (T, 3)."""
+    rho = np.ascontiguousarray(np.asarray(rho, np.float64))
+    n = rho.shape[0]
+    cells = np.zeros((n - 1) ** 3, np.int32)
+    total = lib().orc_surface(n, float(h), rho, float(iso), cells.ctypes.data_as(ct.c_void_p), None, None, 0)
+    if total < 0:
+        raise RuntimeError("face segments do not close")
+    tris = np.zeros((max(total, 1), 3, 3))
+    edges = np.zeros((max(total, 1), 3), np.int32)
+    lib().orc_surface(n, float(h), rho, float(iso), None, edges.ctypes.data_as(ct.c_void_p),
+                      tris.ctypes.data_as(ct.c_void_p), total)
+    return tris[:total], cells, edges[:total]
