@@ -78,12 +78,13 @@ def _events_ms(torch, fn):
     return a.elapsed_time(b)
 
 
-def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200):
+def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200, frames=40):
     """The other forms of the substep on the same GPU: the batched workload
     (256 environments, launch options tuned for it when `tune`) and the
     differentiable slab (forward with tape + hand adjoint, checkpoints every
-    20) against its plain forward with the slab's options, and the slab with
-    box-gripper and sampled-SDF tools in place of the capsule."""
+    20) against its plain forward with the slab's options, a rendered frame
+    (25 substeps + the surface mesh into pinned host memory), and the slab
+    with box-gripper and sampled-SDF tools in place of the capsule."""
     from paper_2402_01181_amd import scenes
     out = {}
     bsc = scenes.batched_scene()
@@ -146,6 +147,40 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
         tools[name] = {"ms_per_substep": ms_t / tool_steps, "value": tsc.n_particles * tool_steps / (ms_t * 1e-3),
                        "grid_kernel_avg_us": grid, "status": int(ts.read(L.F_STATUS))}
         ts.close()
+    # a rendered frame as in the paper: 25 substeps, then the surface mesh
+    # extracted on the device straight into pinned host memory, one sync
+    import ctypes as ct
+    fsc = scenes.slab_scene()
+    fs = Sim(fsc, options=opts)
+    fs.step(20)
+    cap = 1 << 16
+    host = torch.empty((cap, 3, 3), dtype=torch.float32, pin_memory=True)
+    cnt = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+    iso = 0.5 * float(fsc.envs[0].rho)
+
+    def extract():
+        L.check(fs.lib.mpm_extract_surface(fs.ctx, 0, iso, ct.c_void_p(host.data_ptr()), cap,
+                                           ct.c_void_p(cnt.data_ptr()), None), fs.ctx)
+
+    def frame():
+        fs.step(25)
+        extract()
+        torch.cuda.synchronize()
+        if int(cnt[0]) > cap:
+            raise RuntimeError("surface larger than the frame buffer")
+
+    for _ in range(3):
+        frame()
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        frame()
+    ms_frame = (time.perf_counter() - t0) * 1e3 / frames
+    ms_extract = _events_ms(torch, lambda: [extract() for _ in range(frames)]) / frames
+    out["frame"] = {"workload": "slab 30,000 particles, 64^3: 25 substeps + surface mesh into pinned host memory",
+                    "frames": frames, "ms_per_frame": ms_frame, "fps": 1e3 / ms_frame,
+                    "ms_surface_extraction": ms_extract, "triangles": int(cnt[0]),
+                    "value": 1e3 / ms_frame, "unit": "frames/s", "status": int(fs.read(L.F_STATUS))}
+    fs.close()
     out["tool_shapes"] = {"workload": "slab 30,000 particles, 64^3, capsule replaced by the named tool",
                           "substeps": tool_steps, "unit": "particle-substeps/s", "shapes": tools,
                           "value": min(v["value"] for v in tools.values())}
@@ -300,7 +335,7 @@ def main():
         sim.close()
         forms = measure_forms(torch, L, Sim, {k: v for k, v in opts.items() if k != L.OPT_GRAPH}, tune)
         for k, v in forms.items():
-            print(f"# form {k}: {v['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+            print(f"# form {k}: {v['value']:.4g} {v.get('unit', 'particle-substeps/s')}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

@@ -70,7 +70,9 @@ enum {
     MPM_F_GRID_V = 6,   /* float [3][n^3]: velocity after the last grid operation */
     MPM_F_STATUS = 7,   /* uint32 [1]: sticky MPM_FLAG_* bits of the environment */
     MPM_F_TOOL_T = 8,   /* double [max_tools][3]: current tool positions */
-    MPM_F_STEP = 9      /* int32 [1]: substeps taken by the environment */
+    MPM_F_STEP = 9,     /* int32 [1]: substeps taken by the environment */
+    MPM_F_DENSITY = 10  /* float [n^3]: density volume (kg/m^3) of the last mpm_extract_surface, which must
+                           have been for this environment (else MPM_E_STATE) */
 };
 
 /* Tool shapes (Sec. III-C: simple objects such as the gripper jaws by
@@ -181,6 +183,32 @@ void mpm_destroy(mpm_ctx *ctx);
  * Returns MPM_E_ARG for a shape parameter out of range (see mpm_tool). */
 mpm_status mpm_set_tool(mpm_ctx *ctx, int32_t env, int32_t tool, const mpm_tool *desc,
                         const float *u, int32_t n_traj);
+
+/* Triangle mesh of one environment's tissue surface, made on the device: the
+ * paper's post-processing (Sec. III-A) extracts the surface from the mass
+ * volume by marching cubes.  Density rho_i = sum_p w_ip m_p / dx^3 at every
+ * node of the environment's grid (the P2G mass, quadratic B-spline weights),
+ * then the surface rho = iso over the grid cells: a corner is inside when
+ * rho >= iso; on each cell face the edges whose corners differ are crossed
+ * (four crossings: two segments, each cutting off one inside corner); the
+ * crossings chain into polygons, each a fan of triangles from its lowest
+ * edge; crossing points interpolate rho linearly along the edge.  Triangles
+ * are wound with their normal pointing out of the tissue and come out in
+ * cell order (cell (i,j,k) of (n-1)^3, row-major); positions carry the
+ * rounding of the density's float atomic sums, which can differ per call.  The surface is open where the tissue touches the grid's
+ * outer faces.
+ *   tris   float [max_tris][3][3]: vertex positions (m); device memory, or
+ *          host memory from hipHostMalloc (the kernels then write it directly,
+ *          with no separate copy).  Only the first max_tris are written.
+ *   n_tris int64 [1], device or hipHostMalloc'd host memory: the number of
+ *          triangles of the whole surface (may exceed max_tris).
+ *   iso    density threshold (kg/m^3), > 0; half the material density puts
+ *          the surface near the tissue boundary.
+ * Stream-ordered, never synchronises; uses scratch sized for the largest
+ * environment, so calls on one context must not overlap.  Afterwards
+ * MPM_F_DENSITY reads the density volume. */
+mpm_status mpm_extract_surface(mpm_ctx *ctx, int32_t env, float iso, float *tris, int64_t max_tris, int64_t *n_tris,
+                               void *stream);
 
 /* Set a tunable (MPM_OPT_*).  Takes effect at the next substep call. */
 mpm_status mpm_set_option(mpm_ctx *ctx, int32_t option, int32_t value);

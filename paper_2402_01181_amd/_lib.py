@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libmpm355.so")
 
 MPM_OK, MPM_E_ARG, MPM_E_HIP, MPM_E_STATE, MPM_E_UNSUPPORTED, MPM_E_WORKSPACE = 0, -1, -2, -3, -4, -5
 FLAG_OUT_OF_DOMAIN, FLAG_INVERTED, FLAG_NONFINITE, FLAG_BARRIER_TIMEOUT = 1, 2, 4, 8
-F_X, F_V, F_C, F_F, F_GRID_M, F_GRID_MV, F_GRID_V, F_STATUS, F_TOOL_T, F_STEP = range(10)
+F_X, F_V, F_C, F_F, F_GRID_M, F_GRID_MV, F_GRID_V, F_STATUS, F_TOOL_T, F_STEP, F_DENSITY = range(11)
 TOOL_CAPSULE, TOOL_BOX, TOOL_SDF = 0, 1, 2
 SDF_NEAREST, SDF_TRILINEAR = 0, 1
 CONTACT_SLIP, CONTACT_STICKY = 0, 1
@@ -29,7 +29,7 @@ OPT_DEFAULTS = {OPT_SCHEME: SCHEME_TILED, OPT_SORT_EVERY: 16, OPT_BLOCK: 256, OP
 
 EXPORTS = ["mpm_workspace_size", "mpm_create", "mpm_destroy", "mpm_set_tool", "mpm_set_option",
            "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error",
-           "mpm_profile", "mpm_profile_read"]
+           "mpm_profile", "mpm_profile_read", "mpm_extract_surface"]
 
 
 class MpmDesc(ct.Structure):
@@ -92,6 +92,8 @@ def load(path: str = LIB_PATH):
     L.mpm_substep_adjoint.restype = i32
     L.mpm_read_state.argtypes = [vp, i32, i32, vp, ct.c_size_t, i32, vp]
     L.mpm_read_state.restype = i32
+    L.mpm_extract_surface.argtypes = [vp, i32, ct.c_float, vp, ct.c_int64, vp, vp]
+    L.mpm_extract_surface.restype = i32
     L.mpm_profile.argtypes = [vp, i32]
     L.mpm_profile.restype = i32
     L.mpm_profile_read.argtypes = [vp, i32, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_double),

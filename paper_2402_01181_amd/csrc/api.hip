@@ -30,7 +30,7 @@ struct Carver {
 
 struct Shape {
     int n_envs, max_tools, ntot;
-    int64_t total_nodes;
+    int64_t total_nodes, max_env_nodes, max_env_cells;
     int32_t total_bricks;
     int max_tape, ck;
 };
@@ -51,6 +51,11 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.pid = cv.take<int32_t>(s.ntot);
     c.gP = cv.take<float4>(s.total_nodes);
     c.gV = cv.take<float4>(s.total_nodes);
+    // surface extraction
+    c.surf.rho = cv.take<float>(s.max_env_nodes);
+    c.surf.ofs = cv.take<int32_t>(s.max_env_cells);
+    c.surf.chunk = cv.take<int32_t>(surf_chunk_count(s.max_env_cells));
+    c.surf.table = cv.take<McTable>(1);
     // tiled scheme
     c.alt.x = cv.take<float>((size_t)3 * s.ntot);
     c.alt.v = cv.take<float>((size_t)3 * s.ntot);
@@ -123,7 +128,8 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs};
+                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs,
+                       c.surf.rho, c.surf.ofs, c.surf.chunk, c.surf.table};
     for (const void *q : p)
         if (!q) return false;
     if (c.max_tape > 0) {
@@ -150,9 +156,11 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
     if (d->max_tape_substeps < 0) { why = "max_tape_substeps must be >= 0"; return false; }
     if (d->max_tape_substeps > 0 && d->checkpoint_every < 1) { why = "checkpoint_every must be >= 1"; return false; }
     if (!d->x0 || !d->v0 || !d->C0 || !d->F0 || !d->material) { why = "x0, v0, C0, F0 and material must be device pointers"; return false; }
-    int64_t ntot = 0, nodes = 0, bricks = 0;
+    int64_t ntot = 0, nodes = 0, bricks = 0, max_nodes = 0, max_cells = 0;
     for (int e = 0; e < d->n_envs; ++e) {
         int n = d->grid_n[e];
+        max_nodes = std::max(max_nodes, (int64_t)n * n * n);
+        max_cells = std::max(max_cells, (int64_t)(n - 1) * (n - 1) * (n - 1));
         if (n < 8 || n > 512 || n % 4) { why = "grid_n[" + std::to_string(e) + "] must be a multiple of 4 in [8, 512]"; return false; }
         if (2 * d->bound >= n) { why = "bound leaves no interior nodes"; return false; }
         if (d->n_particles[e] < 1) { why = "n_particles[" + std::to_string(e) + "] must be >= 1"; return false; }
@@ -168,6 +176,8 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
     s.ck = d->max_tape_substeps > 0 ? std::min(d->checkpoint_every, d->max_tape_substeps) : 1;
     s.ntot = (int)ntot;
     s.total_nodes = nodes;
+    s.max_env_nodes = max_nodes;
+    s.max_env_cells = max_cells;
     s.total_bricks = (int32_t)bricks;
     return true;
 }
@@ -704,6 +714,11 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
             return cleanup_fail(e2, "copy brick offsets");
         if ((e2 = hipMemcpyAsync(c->tools, c->tools_h.data(), sizeof(ToolDev) * c->tools_h.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
             return cleanup_fail(e2, "copy tools");
+        static McTable mc_table;
+        static const bool mc_ok = build_mc_table(mc_table);
+        if (!mc_ok) return cleanup_fail(hipErrorInvalidValue, "marching-cubes case table does not close");
+        if ((e2 = hipMemcpyAsync(const_cast<McTable *>(c->surf.table), &mc_table, sizeof(McTable), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return cleanup_fail(e2, "copy case table");
         size_t N = s.ntot;
         if ((e2 = hipMemcpyAsync(c->x, desc->x0, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e2 = hipMemcpyAsync(c->v, desc->v0, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
@@ -965,6 +980,10 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
     case MPM_F_STATUS: need = sizeof(uint32_t); break;
     case MPM_F_TOOL_T: need = sizeof(double) * 3 * std::max(1, c->max_tools); break;
     case MPM_F_STEP: need = sizeof(int32_t); break;
+    case MPM_F_DENSITY:
+        if (c->surf_env != env) return fail(c, MPM_E_STATE, "no surface extracted for this environment since the last one");
+        need = sizeof(float) * (size_t)nn;
+        break;
     default: return fail(c, MPM_E_ARG, "unknown field");
     }
     if (field <= MPM_F_F) need = sizeof(float) * comps * (size_t)np;
@@ -1021,6 +1040,11 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
                 }
         return MPM_OK;
     }
+    if (field == MPM_F_DENSITY) {
+        HIP_TRY(c, hipMemcpyAsync(dst, c->surf.rho, need, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        if (!dst_on_device) HIP_TRY(c, hipStreamSynchronize(st));
+        return MPM_OK;
+    }
     if (field == MPM_F_STATUS) {
         HIP_TRY(c, hipMemcpyAsync(dst, c->status + env, sizeof(uint32_t),
                                   dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
@@ -1049,6 +1073,41 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
         return MPM_OK;
     }
     return fail(c, MPM_E_ARG, "unknown field");
+}
+
+mpm_status mpm_extract_surface(mpm_ctx *c, int32_t env, float iso, float *tris, int64_t max_tris, int64_t *n_tris,
+                               void *stream)
+{
+    if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
+    if (env < 0 || env >= c->n_envs) return fail(c, MPM_E_ARG, "env out of range");
+    if (!(iso > 0.f) || !std::isfinite(iso)) return fail(c, MPM_E_ARG, "iso must be finite and > 0");
+    if (max_tris < 0 || (max_tris > 0 && !tris)) return fail(c, MPM_E_ARG, "tris must hold max_tris >= 0 triangles");
+    if (!n_tris) return fail(c, MPM_E_ARG, "n_tris is NULL");
+    hipStream_t st = as_stream(stream);
+    // device memory, or pinned host memory written through its device alias;
+    // anything else (pageable host memory) is refused rather than faulted on
+    auto device_alias = [&](void *p, void **out) -> bool {
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+        if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) { *out = p; return true; }
+        unsigned int hflags = 0;
+        if (at.type == hipMemoryTypeHost && at.devicePointer && hipHostGetFlags(&hflags, p) == hipSuccess) {
+            *out = static_cast<char *>(at.devicePointer) +
+                   (static_cast<char *>(p) - static_cast<char *>(at.hostPointer ? at.hostPointer : p));
+            return true;
+        }
+        return false;
+    };
+    void *tris_d = nullptr, *count_d = nullptr;
+    if (max_tris > 0 && !device_alias(tris, &tris_d))
+        return fail(c, MPM_E_ARG, "tris must be device memory or pinned (hipHostMalloc) host memory");
+    if (!device_alias(n_tris, &count_d))
+        return fail(c, MPM_E_ARG, "n_tris must be device memory or pinned (hipHostMalloc) host memory");
+    const int n = c->gn[env];
+    launch_surface(c->dev(), env, c->np[env], n, 1.0f / (float)n, iso, c->surf, static_cast<float *>(tris_d),
+                   max_tris, static_cast<int64_t *>(count_d), st);
+    c->surf_env = env;
+    return check_launch(c, "mpm_extract_surface");
 }
 
 mpm_status mpm_profile(mpm_ctx *c, int32_t enable)

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "mpm_adjoint.h"
+#include "mpm_surface.h"
 
 // Kernel kinds timed by the built-in profiler (mpm_profile_*).
 enum ProfKind {
@@ -77,6 +78,8 @@ struct mpm_ctx {
     // sequencing state
     bool grid_clean = true;          // momentum buffer all zero, no active bricks
     bool has_sdf = false;            // some active tool is a sampled SDF (grid kernel instantiation)
+    mpm::SurfBuf surf{};             // surface extraction scratch, sized for the largest environment
+    int surf_env = -1;               // environment whose density the scratch holds
     bool items_valid = false;        // sort items match the current slot order and item size
     int items_P = 0;
     int since_sort = 0;

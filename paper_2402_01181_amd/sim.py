@@ -174,9 +174,27 @@ class Sim:
             k += 1
         return out
 
+    # ------------------------------------------------------------------ surface
+    def extract_surface(self, env=0, iso=None, max_tris=None, stream=None):
+        """Tissue surface of one environment as a (T, 3, 3) float32 device
+        tensor of triangle vertices (mpm_extract_surface).  iso defaults to
+        half the material density.  Without max_tris the count is taken first
+        (one synchronisation), then the triangles."""
+        if iso is None:
+            iso = 0.5 * float(self.material[env, 2])
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        if max_tris is None:
+            L.check(self.lib.mpm_extract_surface(self.ctx, env, float(iso), None, 0, ct.c_void_p(count.data_ptr()),
+                                                 _stream_ptr(stream)), self.ctx)
+            max_tris = int(count.item())
+        tris = torch.empty((max(1, int(max_tris)), 3, 3), dtype=torch.float32, device=self.device)
+        L.check(self.lib.mpm_extract_surface(self.ctx, env, float(iso), ct.c_void_p(tris.data_ptr()), int(max_tris),
+                                             ct.c_void_p(count.data_ptr()), _stream_ptr(stream)), self.ctx)
+        return tris[:min(int(max_tris), int(count.item()))], int(count.item())
+
     # ------------------------------------------------------------------ reads
     _PCOMPS = {L.F_X: 3, L.F_V: 3, L.F_C: 9, L.F_F: 9}
-    _GCOMPS = {L.F_GRID_M: 1, L.F_GRID_MV: 3, L.F_GRID_V: 3}
+    _GCOMPS = {L.F_GRID_M: 1, L.F_GRID_MV: 3, L.F_GRID_V: 3, L.F_DENSITY: 1}
 
     def read(self, field, env=0, device=True):
         """A field of one environment as a torch tensor ([comps][N] particles,
