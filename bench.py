@@ -78,15 +78,31 @@ def _events_ms(torch, fn):
     return a.elapsed_time(b)
 
 
-def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200, frames=40):
+def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200, frames=40,
+                  only=None):
     """The other forms of the substep on the same GPU: the batched workload
     (256 environments, launch options tuned for it when `tune`) and the
     differentiable slab (forward with tape + hand adjoint, checkpoints every
     20) against its plain forward with the slab's options, a rendered frame
     (25 substeps + the surface mesh into pinned host memory), and the slab
-    with box-gripper and sampled-SDF tools in place of the capsule."""
+    with box-gripper and sampled-SDF tools in place of the capsule.  `only`
+    names one of them to run alone."""
     from paper_2402_01181_amd import scenes
     out = {}
+    want = lambda name: only is None or only == name
+    if want("batched"):
+        _form_batched(torch, L, Sim, opts, tune, batched_steps, out)
+    if want("forward_adjoint"):
+        _form_forward_adjoint(torch, L, Sim, opts, adj_steps, out)
+    if want("frame"):
+        _form_frame(torch, L, Sim, opts, frames, out)
+    if want("tool_shapes"):
+        _form_tool_shapes(torch, L, Sim, opts, tool_steps, out)
+    return out
+
+
+def _form_batched(torch, L, Sim, opts, tune, batched_steps, out):
+    from paper_2402_01181_amd import scenes
     bsc = scenes.batched_scene()
     bopts = dict(opts)
     if tune:
@@ -108,6 +124,10 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
                       "status": int(any(bs.read(L.F_STATUS, e) for e in range(bs.n_envs)))}
     bs.close()
     del bs
+
+
+def _form_forward_adjoint(torch, L, Sim, opts, adj_steps, out):
+    from paper_2402_01181_amd import scenes
     dsc = scenes.diff_scene(substeps=adj_steps)
     ck = dsc.extra["checkpoint_every"]
     fw = Sim(dsc, options=opts)
@@ -127,6 +147,10 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
                               "value": N * adj_steps / (ms_fa * 1e-3), "unit": "particle-substeps/s",
                               "ratio_to_forward": ms_fa / ms_f}
     ad.close()
+
+
+def _form_tool_shapes(torch, L, Sim, opts, tool_steps, out):
+    from paper_2402_01181_amd import scenes
     # the other tool shapes on the headline slab: box gripper jaws and a
     # 256^3 sampled SDF (nearest sample and trilinear), grid kernel timed
     # with the library's event timer
@@ -147,6 +171,13 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
         tools[name] = {"ms_per_substep": ms_t / tool_steps, "value": tsc.n_particles * tool_steps / (ms_t * 1e-3),
                        "grid_kernel_avg_us": grid, "status": int(ts.read(L.F_STATUS))}
         ts.close()
+    out["tool_shapes"] = {"workload": "slab 30,000 particles, 64^3, capsule replaced by the named tool",
+                          "substeps": tool_steps, "unit": "particle-substeps/s", "shapes": tools,
+                          "value": min(v["value"] for v in tools.values())}
+
+
+def _form_frame(torch, L, Sim, opts, frames, out):
+    from paper_2402_01181_amd import scenes
     # a rendered frame as in the paper: 25 substeps, then the surface mesh
     # extracted on the device straight into pinned host memory, one sync
     import ctypes as ct
@@ -181,10 +212,6 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
                     "ms_surface_extraction": ms_extract, "triangles": int(cnt[0]),
                     "value": 1e3 / ms_frame, "unit": "frames/s", "status": int(fs.read(L.F_STATUS))}
     fs.close()
-    out["tool_shapes"] = {"workload": "slab 30,000 particles, 64^3, capsule replaced by the named tool",
-                          "substeps": tool_steps, "unit": "particle-substeps/s", "shapes": tools,
-                          "value": min(v["value"] for v in tools.values())}
-    return out
 
 
 def stored_traffic(config: str, kernel: str, options) -> float | None:
@@ -245,6 +272,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (launch options: library defaults plus the flags given)")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
+    ap.add_argument("--only-form", default=None, choices=["batched", "forward_adjoint", "frame", "tool_shapes"],
+                    help="run just this form of the slab workload with default launch options and print it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -257,6 +286,11 @@ def main():
     import torch
     from paper_2402_01181_amd import _lib as L
     from paper_2402_01181_amd.sim import Sim
+
+    if args.only_form:
+        forms = measure_forms(torch, L, Sim, {L.OPT_SCHEME: L.SCHEME_TILED}, False, only=args.only_form)
+        print(json.dumps(forms), flush=True)
+        return
 
     scene, workload = make_scene(args.config)
     opts = {L.OPT_SCHEME: L.SCHEME_TILED if args.scheme == "tiled" else L.SCHEME_DIRECT}

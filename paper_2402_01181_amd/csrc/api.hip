@@ -1104,7 +1104,10 @@ mpm_status mpm_extract_surface(mpm_ctx *c, int32_t env, float iso, float *tris, 
     if (!device_alias(n_tris, &count_d))
         return fail(c, MPM_E_ARG, "n_tris must be device memory or pinned (hipHostMalloc) host memory");
     const int n = c->gn[env];
-    launch_surface(c->dev(), env, c->np[env], n, 1.0f / (float)n, iso, c->surf, static_cast<float *>(tris_d),
+    // the sorted work items are usable while the live state sits in their slots
+    SurfItems items{nullptr, nullptr, 0};
+    if (c->scheme == MPM_SCHEME_TILED && c->items_valid) items = SurfItems{c->sort.items, c->sort.totals, c->max_items};
+    launch_surface(c->dev(), env, c->np[env], n, 1.0f / (float)n, iso, c->surf, items, static_cast<float *>(tris_d),
                    max_tris, static_cast<int64_t *>(count_d), st);
     c->surf_env = env;
     return check_launch(c, "mpm_extract_surface");

@@ -4,7 +4,9 @@
 // without leaving the GPU:
 //
 //   k_surf_density  particle mass splatted with the quadratic B-spline onto a
-//                   dense n^3 node volume, density = m w / dx^3 (the P2G mass)
+//                   dense n^3 node volume, density = m w / dx^3 (the P2G mass);
+//                   k_surf_density_tiled does it per sorted work item through
+//                   an LDS tile when the last sort's items are valid
 //   k_surf_count    per cell: inside mask of the 8 corners (rho >= iso),
 //                   triangles from the case table, exclusive scan in chunks
 //   k_surf_top      scan of the chunk totals, total triangle count
@@ -22,8 +24,8 @@
 // (polygons in order of their lowest edge), wound with the normal pointing
 // out of the dense region.  Corner c = 4 dx + 2 dy + dz; edge e = 4 a + p
 // along axis a, p = the other two corner bits in axis order.
-#include "mpm_dev.h"
 #include "mpm_surface.h"
+#include "mpm_tile_util.h"
 
 #include <cstring>
 
@@ -187,6 +189,54 @@ __global__ __launch_bounds__(256) void k_surf_density(Dev d, int env, float *rho
             }
 }
 
+// The same with the work items of the last sort: each workgroup takes an item
+// (one brick's particles, in sorted slots) and sums its mass in a 6^3 LDS
+// tile, which it then adds to the volume node by node; particles that have
+// left the brick's tile since the sort add to the volume directly.  Cuts the
+// global atomics on the densely shared nodes by the particles per node.
+__global__ __launch_bounds__(256) void k_surf_density_tiled(Dev d, const int4 *items, const int2 *totals, int env,
+                                                            float *rho)
+{
+    __shared__ float tile[TILE * TILE * TILE];
+    const int nitems = gload(&totals->y);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 item = gload(items + it);
+        if (item.w != env) continue;
+        EnvDev e;
+        const Tile t = make_tile(d, item, e);
+        for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) tile[i] = 0.0f;
+        __syncthreads();
+        const float *mat = d.material + 4 * env;
+        const float md = gload(mat + 2) * gload(mat + 3) * e.inv_dx * e.inv_dx * e.inv_dx;
+        const int N = d.ntot, n = e.n;
+        for (int q = threadIdx.x; q < item.z; q += blockDim.x) {
+            const int g = item.y + q;
+            Stencil s;
+            make_stencil(gload(d.x + g), gload(d.x + N + g), gload(d.x + 2 * N + g), e.inv_dx, n, s);
+            if (s.outside) continue;
+            int l0, l1, l2;
+            const bool in = stencil_in_tile(t, s, l0, l1, l2);
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+                for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                    for (int o2 = 0; o2 < 3; ++o2) {
+                        const float w = md * s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                        if (in) atomicAdd(&tile[((l0 + o0) * TILE + (l1 + o1)) * TILE + (l2 + o2)], w);
+                        else gatomic_add(rho + ((size_t)(s.b[0] + o0) * n + (s.b[1] + o1)) * n + (s.b[2] + o2), w);
+                    }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) {
+            const float v = tile[i];
+            const int a = t.o[0] + i / (TILE * TILE), b = t.o[1] + (i / TILE) % TILE, c = t.o[2] + i % TILE;
+            if (v != 0.0f && a < n && b < n && c < n) gatomic_add(rho + ((size_t)a * n + b) * n + c, v);
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ int cell_mask(const float *rho, int n, int i, int j, int k, float iso, float val[8])
 {
     int m = 0;
@@ -303,14 +353,18 @@ __global__ __launch_bounds__(256) void k_surf_emit(const float *rho, int n, floa
     }
 }
 
-void launch_surface(const Dev &d, int env, int np, int n, float dx, float iso, const SurfBuf &b, float *tris,
-                    int64_t max_tris, int64_t *n_tris, hipStream_t st)
+void launch_surface(const Dev &d, int env, int np, int n, float dx, float iso, const SurfBuf &b,
+                    const SurfItems &items, float *tris, int64_t max_tris, int64_t *n_tris, hipStream_t st)
 {
     const int64_t nodes = (int64_t)n * n * n;
     const int64_t cells = (int64_t)(n - 1) * (n - 1) * (n - 1);
     const int nchunk = (int)((cells + SURF_CHUNK - 1) / SURF_CHUNK);
     launch_k(k_surf_clear, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 8192)), dim3(256), 0, st, b.rho, nodes);
-    if (np > 0) launch_k(k_surf_density, dim3((np + 255) / 256), dim3(256), 0, st, d, env, b.rho);
+    if (items.items)
+        launch_k(k_surf_density_tiled, dim3((unsigned)std::min<int64_t>(items.max_items, 4096)), dim3(256), 0, st, d,
+                 items.items, items.totals, env, b.rho);
+    else if (np > 0)
+        launch_k(k_surf_density, dim3((np + 255) / 256), dim3(256), 0, st, d, env, b.rho);
     launch_k(k_surf_count, dim3(nchunk), dim3(SURF_T), 0, st, b.rho, n, iso, b.table, b.ofs, b.chunk);
     launch_k(k_surf_top, dim3(1), dim3(SURF_T), 0, st, b.chunk, nchunk, n_tris);
     launch_k(k_surf_emit, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, b.rho, n, dx, iso, b.table,

@@ -22,10 +22,18 @@ struct SurfBuf {
     const McTable *table;   // device copy of the case table
 };
 
+// Work items of the last sort, when the particle buffers are in their sorted
+// slots (items == nullptr: no valid items, one atomic per weight instead).
+struct SurfItems {
+    const int4 *items;
+    const int2 *totals;
+    int64_t max_items;
+};
+
 // Builds the table from the face-walk rule; false if a case does not close.
 bool build_mc_table(McTable &t);
-void launch_surface(const Dev &d, int env, int np, int n, float dx, float iso, const SurfBuf &b, float *tris,
-                    int64_t max_tris, int64_t *n_tris, hipStream_t st);
+void launch_surface(const Dev &d, int env, int np, int n, float dx, float iso, const SurfBuf &b,
+                    const SurfItems &items, float *tris, int64_t max_tris, int64_t *n_tris, hipStream_t st);
 size_t surf_chunk_count(int64_t cells);
 
 }  // namespace mpm

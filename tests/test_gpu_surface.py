@@ -55,11 +55,14 @@ def _check(orc, sim, L, env=0, iso=None):
     return t, count
 
 
-def test_surface_small_slab(gpu, orc):
+@pytest.mark.parametrize("scheme", ["tiled", "direct"])
+def test_surface_small_slab(gpu, orc, scheme):
+    """tiled: density summed per sorted work item in LDS tiles; direct (no
+    work items): one global atomic per weight."""
     Sim, L, torch = gpu
-    _say("surface: small slab 4000 particles, 32^3, after 30 substeps")
+    _say(f"surface ({scheme}): small slab 4000 particles, 32^3, after 30 substeps")
     sc = scenes.small_slab_scene(91, 4000, n=32, substeps=30, u=(0.0, -0.5, 0.0))
-    sim = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED})
+    sim = Sim(sc, options={L.OPT_SCHEME: L.SCHEME_TILED if scheme == "tiled" else L.SCHEME_DIRECT})
     sim.step(30)
     t, _ = _check(orc, sim, L)
     assert _vol(t) > 0          # wound outward
