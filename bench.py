@@ -8,8 +8,9 @@ particle-substeps/s is quoted on.  Prints one JSON line.
   python bench.py [--steps K] [--warmup W] [--config slab|large|cube|batched]
 
 Launch options (workgroup size, particles per work item, sort interval,
-graph replay, persistent kernel) come from the autotuner unless
---no-autotune is given; explicit flags override them.
+graph replay, persistent kernel) come from the autotuner (which answers the
+benchmark workloads from the table measured on MI355X that ships with the
+package) unless --no-autotune is given; explicit flags override them.
 
 Timing: W untimed substeps, then K substeps bracketed by device syncs and
 hipEvents on the stream the library launches on.  A second pass of the same

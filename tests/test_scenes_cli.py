@@ -57,3 +57,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_shipped_tuning_table_is_well_formed():
+    """The launch-shape table shipped for the benchmark workloads holds
+    options the library accepts."""
+    import json
+    from paper_2402_01181_amd import _lib as L
+    from paper_2402_01181_amd.autotune import SHIPPED, shipped
+    table = json.load(open(SHIPPED))
+    assert table
+    for key, entry in table.items():
+        opts = shipped(key)
+        assert opts == {int(k): int(v) for k, v in entry["options"].items()}
+        assert opts[L.OPT_SCHEME] == L.SCHEME_TILED
+        assert opts[L.OPT_BLOCK] in (64, 128, 256)
+        assert 16 <= opts[L.OPT_ITEM] <= 4096 and opts[L.OPT_ITEM] % 16 == 0
+        assert opts[L.OPT_SORT_EVERY] >= 1 and opts[L.OPT_NODE_SLOTS] in (1, 3)
+    assert shipped("no such workload") is None
