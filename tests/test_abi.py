@@ -55,7 +55,10 @@ def test_workspace_size_and_validation(L):
     # more particles or a bigger grid need more workspace
     d2, k2 = _desc(L, np_=(1000,), gn=(64,))
     assert lib.mpm_workspace_size(ct.byref(d2)) > s1
-    bad = [dict(gn=(30,)), dict(gn=(4,)), dict(np_=(0,)), dict(dt=0.0), dict(dt=float("nan")),
+    # the largest grid is accepted, the next multiple of 4 is not
+    dmax, kmax = _desc(L, gn=(512,))
+    assert lib.mpm_workspace_size(ct.byref(dmax)) > lib.mpm_workspace_size(ct.byref(d2))
+    bad = [dict(gn=(30,)), dict(gn=(4,)), dict(gn=(516,)), dict(np_=(0,)), dict(dt=0.0), dict(dt=float("nan")),
            dict(bound=-1), dict(bound=16), dict(max_tools=9), dict(tape=-1), dict(tape=10, ck=0)]
     for kw in bad:
         db, kb = _desc(L, **kw)
@@ -78,3 +81,4 @@ def test_create_rejects_bad_arguments_without_touching_the_device(L):
     assert lib.mpm_substep(None, 1, 0, None) == L.MPM_E_ARG
     assert lib.mpm_read_state(None, 0, 0, None, 0, 0, None) == L.MPM_E_ARG
     assert lib.mpm_set_option(None, 0, 0) == L.MPM_E_ARG
+    assert lib.mpm_extract_surface(None, 0, 500.0, None, 0, None, None) == L.MPM_E_ARG

@@ -333,6 +333,31 @@ def test_far_drift_between_sorts(gpu, orc, persistent):
     assert tiled.read(L.F_STATUS) == 0 and tiled.read(L.F_STEP) == S
 
 
+@pytest.mark.parametrize("scheme", ["tiled", "direct"])
+def test_largest_grid_free_fall(gpu, orc, scheme):
+    """The largest grid (512^3, 134M nodes): a block at rest in free fall far
+    from the walls moves rigidly, x = x0 + dt^2 g S(S+1)/2, v = S dt g,
+    F = I (the substep's symplectic Euler with affine-exact transfers)."""
+    Sim, L = gpu
+    rng = np.random.default_rng(12)
+    x = scenes.box_uniform(rng, 20000, (0.40, 0.40, 0.40), (0.45, 0.45, 0.45))
+    v, C, F = scenes._rest_state(x)
+    env = scenes.Env(n=512, x=x, v=v, C=C, F=F, E=1e4, nu=0.3, rho=1e3, V0=0.05 ** 3 / x.shape[0])
+    S = 20
+    sc = scenes.Scene("free-fall-512", [env], dt=1e-4, substeps=S)
+    _say(f"largest grid ({scheme}): 20,000 particles on 512^3, {S} substeps of free fall")
+    sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme), L.OPT_SORT_EVERY: 8})
+    sim.step(S)
+    xt, vt, Ct, Ft = sim.particles()
+    dt, g = float(np.float32(sc.dt)), np.array(sc.gravity, np.float64)
+    x_exact = x.astype(np.float64) + dt * dt * g * S * (S + 1) / 2
+    ex, ev = np.abs(xt - x_exact).max(), np.abs(vt - S * dt * g).max()
+    eF, eC = np.abs(Ft - np.eye(3)).max(), np.abs(Ct).max()
+    _say(f"  |x - exact| {ex:.2e}, |v - exact| {ev:.2e}, |F - I| {eF:.2e}, |C| {eC:.2e}")
+    assert ex <= 1e-6 and ev <= 1e-5 and eF <= 1e-5 and eC <= 1e-3
+    assert sim.read(L.F_STATUS) == 0 and sim.read(L.F_STEP) == S
+
+
 def _ragged_scene(seed=11):
     """Three small environments of ragged sizes: one particle on an 8^3 grid,
     17 particles on a 12^3 grid, 300 in a cube on a 16^3 grid, all moving."""
