@@ -44,6 +44,11 @@ BYTES_PER_PARTICLE = 96
 BYTES_PER_NODE_SUBSTEP = 56
 BYTES_PER_NODE_FUSED = 28
 BYTES_PER_NODE_GRID = 28
+# Forward with tape + adjoint, per particle-substep: the recorded forward (96),
+# its recompute in reverse (96), the reverse substep (primal x, v, C, F read
+# 96 B + adjoint x, v, C, F read and written 192 B + node adjoints ~100 B =
+# ~390) and the checkpoints (96 B every 20 substeps); grid terms left out.
+BYTES_PER_PARTICLE_FWD_ADJ = 96 + 96 + 390 + 96 / 20
 
 
 def active_nodes(x: np.ndarray, n: int) -> int:
@@ -143,10 +148,12 @@ def _form_forward_adjoint(torch, L, Sim, opts, adj_steps, out):
         ad.adjoint(adj_steps, xbar=seed)
     fwd_adj()
     ms_fa = _events_ms(torch, fwd_adj)
+    gbps = N * BYTES_PER_PARTICLE_FWD_ADJ * adj_steps / (ms_fa * 1e-3) / 1e9
     out["forward_adjoint"] = {"workload": f"slab 30,000 particles, 64^3, {adj_steps} substeps, checkpoints every {ck}",
                               "substeps": adj_steps, "ms_forward": ms_f, "ms_forward_with_tape_plus_adjoint": ms_fa,
                               "value": N * adj_steps / (ms_fa * 1e-3), "unit": "particle-substeps/s",
-                              "ratio_to_forward": ms_fa / ms_f}
+                              "ratio_to_forward": ms_fa / ms_f, "algorithmic_GBps": gbps,
+                              "hbm_frac": gbps / HBM_PEAK_GBS}
     ad.close()
 
 
