@@ -2,11 +2,12 @@
  * mpm.h -- C ABI of the MI355X (gfx950) MLS-MPM tissue library.
  *
  * The library steps the MLS-MPM substep of arXiv 2402.01181 for Neo-Hookean
- * tissue touched by rigid capsule tools: P2G (Sec. III-B item 1, Eq. P2G and
- * Eq. fip), the grid operation with boundary nodes and tool contact
- * (Sec. III-B item 2, Sec. III-C), G2P with advection (Sec. III-B item 3)
- * and the deformation-gradient update, for one or many independent
- * environments at once, plus the reverse (adjoint) of those substeps.
+ * tissue touched by rigid tools (capsules, boxes, sampled SDFs): P2G
+ * (Sec. III-B item 1, Eq. P2G and Eq. fip), the grid operation with boundary
+ * nodes and tool contact (Sec. III-B item 2, Sec. III-C), G2P with advection
+ * (Sec. III-B item 3) and the deformation-gradient update, for one or many
+ * independent environments at once, plus the reverse (adjoint) of those
+ * substeps and the surface mesh of the tissue (Sec. III-A post-processing).
  *
  * Conventions shared by every entry point:
  *  - Device memory is owned by the CALLER: initial state, material table,
@@ -28,6 +29,10 @@
  *    (MPM_FLAG_*), read with mpm_read_state(..., MPM_F_STATUS, ...).
  *    mpm_substep and mpm_substep_adjoint never synchronise with the host and
  *    issue only kernel launches, so a caller may capture them in a hipGraph.
+ *    A captured call replays the launches it recorded (a counting sort
+ *    included if one fell in it); the context's host-side bookkeeping (the
+ *    substeps since the last sort) advances once, at capture, so a caller
+ *    mixing replays with direct calls should capture calls that sort.
  */
 #ifndef MPM355_MPM_H
 #define MPM355_MPM_H

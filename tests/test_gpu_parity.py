@@ -415,3 +415,41 @@ def test_autotune_picks_and_caches(gpu, orc, tmp_path):
     s = Sim(sc, options=best)   # the options are accepted by the library
     s.step(10)
     assert s.read(L.F_STATUS) == 0
+
+
+def test_caller_captured_graph(gpu, orc):
+    """mpm_substep issues only kernel launches and never synchronises, so a
+    caller can capture it in its own graph (here torch.cuda.graph): a
+    captured 16-substep call (with a sort inside) replayed five times, with
+    reads and eager work between the replays, against eager calls."""
+    Sim, L = gpu
+    import torch
+    _say("caller-captured graph: small slab 4000 particles, 32^3, 5 replays of 16 substeps")
+    sc = scenes.small_slab_scene(seed=31, n_particles=4000, n=32, substeps=96, u=(0.0, -0.5, 0.0))
+    opts = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 8}
+    eager = Sim(sc, options=opts)
+    capt = Sim(sc, options=opts)
+    eager.step(16)
+    capt.step(16)                      # warm: work items exist before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            capt.step(16)              # recorded, not run
+    torch.cuda.synchronize()
+    for r in range(5):
+        g.replay()
+        eager.step(16)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum().item()   # unrelated eager work between replays
+        xe, xc = eager.particles()[0], capt.particles()[0]
+        err = np.abs(xe - xc).max()
+        _say(f"  replay {r}: max |dx| = {err:.2e}")
+        assert err <= 1e-5 and np.isfinite(junk)
+        assert capt.read(L.F_STEP) == 16 * (r + 2)
+        np.testing.assert_array_equal(capt.read(L.F_TOOL_T), eager.read(L.F_TOOL_T))
+    o = oracle_sim_like(orc, sc).run(96)
+    assert np.abs(capt.particles()[0] - o.state.x).max() <= TOL_DRIFT
+    assert capt.read(L.F_STATUS) == 0
