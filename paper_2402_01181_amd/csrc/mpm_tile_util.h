@@ -118,6 +118,15 @@ struct NodeLane1 {
     float wc[3], wa[3], wg[3];
 };
 
+// An opaque copy of a value: the out-of-tile path of the node pass is rare, and
+// taking its key through this keeps the compiler from hoisting that path's
+// node-index arithmetic into the common (in-tile) path of every step.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 __device__ __forceinline__ NodeLane1 node_lane1(int lane)
 {
     NodeLane1 L;
@@ -157,11 +166,10 @@ __device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, 
         const float w = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]) *
                         fmaf(L.wa[2], t2 * t2, L.wg[2]);
         const float d0 = L.o0 - fk.x, d1 = L.o1 - fk.y, d2 = L.o2 - fk.z;
-        float4 c4;
-        c4.x = w * s;
-        c4.y = w * fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
-        c4.z = w * fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
-        c4.w = w * fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
+        // g + M d: the momentum term at this node before the weight
+        const float gx = fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
+        const float gy = fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
+        const float gz = fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
         if (!(pk & KEY_VALID)) continue;
         if (pk & KEY_IN_TILE) {
             const int l = (pk >> 2) + L.lo;
@@ -173,9 +181,11 @@ __device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, 
                 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                 cur = l;
             }
-            acc.x += c4.x; acc.y += c4.y; acc.z += c4.z; acc.w += c4.w;
+            acc.x = fmaf(w, s, acc.x); acc.y = fmaf(w, gx, acc.y); acc.z = fmaf(w, gy, acc.z); acc.w = fmaf(w, gz, acc.w);
         } else {
-            outside(c4, ((pk >> 2) & 1023) + L.o0, ((pk >> 12) & 1023) + L.o1, ((pk >> 22) & 1023) + L.o2);
+            const int k = opaque(pk);
+            outside(make_float4(w * s, w * gx, w * gy, w * gz), ((k >> 2) & 1023) + L.o0, ((k >> 12) & 1023) + L.o1,
+                    ((k >> 22) & 1023) + L.o2);
         }
     }
     if (cur >= 0) {
@@ -280,11 +290,14 @@ __device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float d2 = c - f2, w = w01 * w2[c];
-            const float4 c4 = make_float4(w * s, w * fmaf(q2.y, d2, bx), w * fmaf(q3.x, d2, by), w * fmaf(q3.w, d2, bz));
+            const float gx = fmaf(q2.y, d2, bx), gy = fmaf(q3.x, d2, by), gz = fmaf(q3.w, d2, bz);
             if (in_tile) {
-                acc[c].x += c4.x; acc[c].y += c4.y; acc[c].z += c4.z; acc[c].w += c4.w;
+                acc[c].x = fmaf(w, s, acc[c].x); acc[c].y = fmaf(w, gx, acc[c].y);
+                acc[c].z = fmaf(w, gy, acc[c].z); acc[c].w = fmaf(w, gz, acc[c].w);
             } else {
-                outside(c4, ((pk >> 2) & 1023) + L.o0, ((pk >> 12) & 1023) + L.o1, ((pk >> 22) & 1023) + c);
+                const int k = opaque(pk);
+                outside(make_float4(w * s, w * gx, w * gy, w * gz), ((k >> 2) & 1023) + L.o0,
+                        ((k >> 12) & 1023) + L.o1, ((k >> 22) & 1023) + c);
             }
         }
     }
