@@ -344,6 +344,12 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
     int bs = i < a.nbricks ? gload(a.slist + i) : 0;
     const int ns = gload(a.scount), nd = gload(a.dcount + par);
     const int32_t *dl = a.dlist + (size_t)par * a.nbricks;
+    // one environment: its entry is loaded once, before the loop; several: each
+    // brick's environment is looked up beside its P (not after the emptiness test),
+    // so a listed brick waits for two dependent loads after its id, not three
+    const bool one_env = d.n_envs == 1;
+    EnvDev e1{};
+    if (one_env) e1 = load_env(d.env);
     for (; i < ns + nd; i += stride) {
         const bool dyn = i >= ns;
         const int b = dyn ? gload(dl + (i - ns)) : bs;
@@ -352,14 +358,19 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         // node 64 b + l of the whole grid: P is loaded without waiting for the environment
         const int64_t g = (int64_t)b * BRICK_NODES + lane;
         float4 P = gload(d.gP + g);
+        int env = 0;
+        if (!one_env) {
+            env = gload(a.brick_env + b);
+            asm volatile("" :: "v"(env));   // keeps the load here, issued with P's
+        }
         if (!__any(P.x != 0.f)) {
             // no mass reached the brick this substep: P is already clear and no
             // particle's G2P reads its velocities, so there is nothing to write
             if (dyn && lane == 0) gstore(a.flag + b, 0);
             continue;
         }
-        const int env = gload(a.brick_env + b);
-        const EnvDev e = load_env(d.env + env);
+        EnvDev e = e1;
+        if (!one_env) e = load_env(d.env + env);
         int lb = b - e.bofs;
         int gi, gj, gk;
         brick_local_to_ijk(e, lb, lane, gi, gj, gk);
