@@ -477,11 +477,6 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
                 if (!s.outside) {
                     int l0, l1, l2;
                     const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
-                    // node velocity of stencil node (a0, a1, a2)
-                    auto Vat = [&](int a0, int a1, int a2) -> float4 {
-                        return in_tile ? tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]
-                                       : gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
-                    };
                     float dw[3][3];
                     weight_grads(s, dw);
                     // the particle's adjoint state first: Bbar and vbar_t do not depend on the
@@ -512,32 +507,73 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
                     // one pass: B = sum w V q^T (the recomputed C = (4/dx) B) and the x adjoint
                     float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     float fxb[3] = {0.f, 0.f, 0.f};
+                    // Separable form of the stencil sums.  Per node only wb = V . g(a)
+                    // (g(a) = vbar_t + Bbar (a - f), linear in the node offset a) and the
+                    // weighted node velocity are formed; the sums then run over the third
+                    // axis, the second and the first:
+                    //   B[i][j] = sum w V_i a_j - f_j S_i,  fxb[k] = sum (dw/dx_k) wb - (Bbar^T S)_k,
+                    //   S = sum w V.
                     auto stencil_pass = [&](auto Vat) {
+                        float gf[3];   // vbar_t - Bbar f
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            gf[i] = vbt[i] - (Bb[3 * i] * s.fx[0] + Bb[3 * i + 1] * s.fx[1] + Bb[3 * i + 2] * s.fx[2]);
+                        float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
+                        float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
                         for (int a0 = 0; a0 < 3; ++a0) {
-                            const float w0 = s.w[0][a0], d0w = dw[0][a0];
-                            const float q0 = a0 - s.fx[0];
+                            float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
+                            float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-                            for (int a1 = 0; a1 < 3; ++a1)
+                            for (int a1 = 0; a1 < 3; ++a1) {
+                                float X = 0.f, Y = 0.f, AV[3] = {0.f, 0.f, 0.f}, BV[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                                 for (int a2 = 0; a2 < 3; ++a2) {
-                                    const float q1 = a1 - s.fx[1], q2 = a2 - s.fx[2];
-                                    const float w12 = s.w[1][a1] * s.w[2][a2];
-                                    const float w = w0 * w12;
-                                    const float4 V = Vat(a0, a1, a2);
-                                    const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
-                                    B[0] += wx * q0; B[1] += wx * q1; B[2] += wx * q2;
-                                    B[3] += wy * q0; B[4] += wy * q1; B[5] += wy * q2;
-                                    B[6] += wz * q0; B[7] += wz * q1; B[8] += wz * q2;
-                                    const float g0 = vbt[0] + Bb[0] * q0 + Bb[1] * q1 + Bb[2] * q2;
-                                    const float g1 = vbt[1] + Bb[3] * q0 + Bb[4] * q1 + Bb[5] * q2;
-                                    const float g2 = vbt[2] + Bb[6] * q0 + Bb[7] * q1 + Bb[8] * q2;
-                                    const float wb = V.x * g0 + V.y * g1 + V.z * g2;
-                                    fxb[0] += -(Bb[0] * wx + Bb[3] * wy + Bb[6] * wz) + wb * d0w * w12;
-                                    fxb[1] += -(Bb[1] * wx + Bb[4] * wy + Bb[7] * wz) + wb * w0 * dw[1][a1] * s.w[2][a2];
-                                    fxb[2] += -(Bb[2] * wx + Bb[5] * wy + Bb[8] * wz) + wb * w0 * s.w[1][a1] * dw[2][a2];
+                                    const float4 V4 = Vat(a0, a1, a2);
+                                    const float V[3] = {V4.x, V4.y, V4.z};
+                                    const float w2 = s.w[2][a2];
+                                    float wb = 0.f;
+#pragma unroll
+                                    for (int i = 0; i < 3; ++i)
+                                        wb = fmaf(V[i], gf[i] + Bb[3 * i] * a0 + Bb[3 * i + 1] * a1 + Bb[3 * i + 2] * a2, wb);
+                                    X = fmaf(w2, wb, X);
+                                    Y = fmaf(dw[2][a2], wb, Y);
+#pragma unroll
+                                    for (int i = 0; i < 3; ++i) {
+                                        AV[i] = fmaf(w2, V[i], AV[i]);
+                                        BV[i] = fmaf(w2 * a2, V[i], BV[i]);
+                                    }
                                 }
+                                const float w1 = s.w[1][a1], d1 = dw[1][a1];
+                                X1 = fmaf(w1, X, X1);
+                                X1d = fmaf(d1, X, X1d);
+                                Y1 = fmaf(w1, Y, Y1);
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) {
+                                    E1[i] = fmaf(w1, AV[i], E1[i]);
+                                    E2[i] = fmaf(w1 * a1, AV[i], E2[i]);
+                                    E3[i] = fmaf(w1, BV[i], E3[i]);
+                                }
+                            }
+                            const float w0 = s.w[0][a0], d0 = dw[0][a0];
+                            g0 = fmaf(d0, X1, g0);
+                            g1 = fmaf(w0, X1d, g1);
+                            g2 = fmaf(w0, Y1, g2);
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                S[i] = fmaf(w0, E1[i], S[i]);
+                                Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
+                                Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
+                                Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
+                            }
                         }
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) B[3 * i + j] = Mo[i][j] - s.fx[j] * S[i];
+                        fxb[0] = g0 - (Bb[0] * S[0] + Bb[3] * S[1] + Bb[6] * S[2]);
+                        fxb[1] = g1 - (Bb[1] * S[0] + Bb[4] * S[1] + Bb[7] * S[2]);
+                        fxb[2] = g2 - (Bb[2] * S[0] + Bb[5] * S[1] + Bb[8] * S[2]);
                     };
                     if (in_tile)
                         stencil_pass([&](int a0, int a1, int a2) { return tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
@@ -659,32 +695,78 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
                     float vbp[3] = {0.f, 0.f, 0.f}, Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     float fxb[3] = {0.f, 0.f, 0.f};
                     const float dx = e.dx;
+                    // Separable form of the stencil sums.  Per node only the momentum
+                    // weight wb = m pm + q . c(a) (c(a) = m v + A (a - f) dx, the affine
+                    // momentum at node offset a) and the node's weighted values are formed;
+                    // the sums then run over the third axis, the second and the first:
+                    //   vbp = m S,  Ab[i][j] = dx (sum w q_i a_j - f_j S_i),
+                    //   fxb[k] = sum (dw/dx_k) wb - dx (A^T S)_k,  S = sum w q.
                     auto stencil_pass = [&](auto Pat) {
+                        float lam[3][3], cf[3];   // lam[j][i] = dx A[i][j]; cf = m v - dx A f
 #pragma unroll
-                        for (int a0 = 0; a0 < 3; ++a0)
+                        for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                            for (int a1 = 0; a1 < 3; ++a1)
+                            for (int j = 0; j < 3; ++j) lam[j][i] = dx * A[3 * i + j];
+                            cf[i] = m * v[i] - (lam[0][i] * s.fx[0] + lam[1][i] * s.fx[1] + lam[2][i] * s.fx[2]);
+                        }
+                        float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
+                        float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+                        for (int a0 = 0; a0 < 3; ++a0) {
+                            float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
+                            float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int a1 = 0; a1 < 3; ++a1) {
+                                float X = 0.f, Y = 0.f, AQ[3] = {0.f, 0.f, 0.f}, BQ[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                                 for (int a2 = 0; a2 < 3; ++a2) {
                                     const float4 Pb = Pat(a0, a1, a2);
-                                    float w = s.w[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                    float d0 = (a0 - s.fx[0]) * dx, d1 = (a1 - s.fx[1]) * dx, d2 = (a2 - s.fx[2]) * dx;
-                                    vbp[0] += m * w * Pb.y; vbp[1] += m * w * Pb.z; vbp[2] += m * w * Pb.w;
-                                    float wy = w * Pb.y, wz = w * Pb.z, ww = w * Pb.w;
-                                    Ab[0] += wy * d0; Ab[1] += wy * d1; Ab[2] += wy * d2;
-                                    Ab[3] += wz * d0; Ab[4] += wz * d1; Ab[5] += wz * d2;
-                                    Ab[6] += ww * d0; Ab[7] += ww * d1; Ab[8] += ww * d2;
-                                    float c0 = m * v[0] + A[0] * d0 + A[1] * d1 + A[2] * d2;
-                                    float c1 = m * v[1] + A[3] * d0 + A[4] * d1 + A[5] * d2;
-                                    float c2 = m * v[2] + A[6] * d0 + A[7] * d1 + A[8] * d2;
-                                    float wb = m * Pb.x + Pb.y * c0 + Pb.z * c1 + Pb.w * c2;
-                                    float db0 = w * (A[0] * Pb.y + A[3] * Pb.z + A[6] * Pb.w);
-                                    float db1 = w * (A[1] * Pb.y + A[4] * Pb.z + A[7] * Pb.w);
-                                    float db2 = w * (A[2] * Pb.y + A[5] * Pb.z + A[8] * Pb.w);
-                                    fxb[0] += -dx * db0 + wb * dw[0][a0] * s.w[1][a1] * s.w[2][a2];
-                                    fxb[1] += -dx * db1 + wb * s.w[0][a0] * dw[1][a1] * s.w[2][a2];
-                                    fxb[2] += -dx * db2 + wb * s.w[0][a0] * s.w[1][a1] * dw[2][a2];
+                                    const float q[3] = {Pb.y, Pb.z, Pb.w};
+                                    const float w2 = s.w[2][a2];
+                                    float wb = m * Pb.x;
+#pragma unroll
+                                    for (int i = 0; i < 3; ++i)
+                                        wb = fmaf(q[i], cf[i] + lam[0][i] * a0 + lam[1][i] * a1 + lam[2][i] * a2, wb);
+                                    X = fmaf(w2, wb, X);
+                                    Y = fmaf(dw[2][a2], wb, Y);
+#pragma unroll
+                                    for (int i = 0; i < 3; ++i) {
+                                        AQ[i] = fmaf(w2, q[i], AQ[i]);
+                                        BQ[i] = fmaf(w2 * a2, q[i], BQ[i]);
+                                    }
                                 }
+                                const float w1 = s.w[1][a1], d1 = dw[1][a1];
+                                X1 = fmaf(w1, X, X1);
+                                X1d = fmaf(d1, X, X1d);
+                                Y1 = fmaf(w1, Y, Y1);
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) {
+                                    E1[i] = fmaf(w1, AQ[i], E1[i]);
+                                    E2[i] = fmaf(w1 * a1, AQ[i], E2[i]);
+                                    E3[i] = fmaf(w1, BQ[i], E3[i]);
+                                }
+                            }
+                            const float w0 = s.w[0][a0], d0 = dw[0][a0];
+                            g0 = fmaf(d0, X1, g0);
+                            g1 = fmaf(w0, X1d, g1);
+                            g2 = fmaf(w0, Y1, g2);
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                S[i] = fmaf(w0, E1[i], S[i]);
+                                Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
+                                Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
+                                Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
+                            }
+                        }
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            vbp[i] = m * S[i];
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) Ab[3 * i + j] = dx * (Mo[i][j] - s.fx[j] * S[i]);
+                        }
+                        fxb[0] = g0 - dx * (A[0] * S[0] + A[3] * S[1] + A[6] * S[2]);
+                        fxb[1] = g1 - dx * (A[1] * S[0] + A[4] * S[1] + A[7] * S[2]);
+                        fxb[2] = g2 - dx * (A[2] * S[0] + A[5] * S[1] + A[8] * S[2]);
                     };
                     if (in_tile)
                         stencil_pass([&](int a0, int a1, int a2) { return tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
