@@ -76,6 +76,50 @@ def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots):
         assert e <= TOL_GRAD, (name, e)
 
 
+def test_adjoint_with_particles_leaving_their_tiles(gpu, orc):
+    """The slab and the tool translate at 80 m/s along x, so within one tape
+    segment (6 substeps, one sort at its start) every particle moves more than
+    a cell and those at brick edges leave their work item's tile: the reverse
+    G2P and P2G passes then read node values from the global grid instead of
+    the LDS tile.  Gradients against the oracle's adjoint."""
+    Sim, L, torch = gpu
+    S, N, n, k = 12, 2000, 32, 6
+    drift = np.array([80.0, 0.0, 0.0])
+    sc, env = _pressing_scene(71, N, n, S)
+    env.v = (env.v + drift).astype(np.float32)
+    env.tools[0].traj = (env.tools[0].traj + drift).astype(np.float32)
+    _say(f"adjoint with tile drift: {N} particles, {n}^3, {S} substeps, checkpoints every {k}, drift {drift[0]} m/s")
+    o_fwd = oracle_sim_like(orc, sc)
+    x0 = o_fwd.state.x.copy()
+    o_fwd.run(k)
+    moved = (o_fwd.state.x[:, 0] - x0[:, 0]) * n   # in cells
+    _say(f"  displacement over one segment: {moved.min():.2f}..{moved.max():.2f} cells")
+    assert moved.min() > 1.0
+    rng = np.random.default_rng(5)
+    W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
+         rng.standard_normal((N, 3, 3))]
+    sim = Sim(sc, max_tape=S, checkpoint_every=k, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: k})
+    sim.step(S, record_tape=True)
+    assert sim.read(L.F_STATUS) == 0
+    soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
+    g = sim.adjoint(S, soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))
+    o = oracle_sim_like(orc, sc).adjoint(S, *W)
+    assert np.abs(o["gu"]).max() > 0
+    checks = {
+        "xbar0": (g["xbar0"].cpu().numpy().T, o["xbar"].reshape(N, 3)),
+        "vbar0": (g["vbar0"].cpu().numpy().T, o["vbar"].reshape(N, 3)),
+        "Cbar0": (g["Cbar0"].cpu().numpy().T, o["Cbar"].reshape(N, 9)),
+        "Fbar0": (g["Fbar0"].cpu().numpy().T, o["Fbar"].reshape(N, 9)),
+        "gE": (g["gE"].cpu().numpy(), [o["gE"]]),
+        "gnu": (g["gnu"].cpu().numpy(), [o["gnu"]]),
+        "gu": (g["gu"].cpu().numpy()[0, 0], o["gu"][:, 0]),
+    }
+    for name, (a, b) in checks.items():
+        e = _rel(a, b)
+        _say(f"  {name}: rel err {e:.2e}")
+        assert e <= TOL_GRAD, (name, e)
+
+
 def test_adjoint_window_shorter_than_tape(gpu, orc):
     """Reverse only the last 7 of 12 recorded substeps."""
     Sim, L, torch = gpu
