@@ -932,6 +932,7 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
             else launch_fill_u32(reinterpret_cast<uint32_t *>(adj[f]), (int64_t)comps[f] * N, 0u, st);
         }
         launch_fill_f4(T.adj.gVb, c->total_nodes, st);
+        launch_fill_f4(T.adj.gPb, c->total_nodes, st);   // bricks without mass are never written
         const int64_t ng = (int64_t)c->tool_slots() * c->max_tape * 3;
         launch_fill_f64(T.adj.ubar, ng, st);
         launch_fill_f64(T.adj.Tbar, ng, st);

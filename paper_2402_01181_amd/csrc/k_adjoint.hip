@@ -196,9 +196,13 @@ __global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total_nodes) return;
+    float4 P = gload(d.gP + g);                                // (m, vhat)
+    // a wavefront is one brick (environments' grids start at multiples of 64 nodes);
+    // a brick without mass is in no particle's stencil: its velocity adjoint was
+    // never scattered to (still zero) and its (m, mv) adjoint is never gathered
+    if (!__any(P.x > 0.0f)) return;
     float4 vb4 = gload(a.gVb + g);
     gstore(a.gVb + g, make_float4(0.f, 0.f, 0.f, 0.f));      // ready for the next reverse substep
-    float4 P = gload(d.gP + g);                                // (m, vhat)
     if (!(P.x > 0.0f)) {
         gstore(a.gPb + g, make_float4(0.f, 0.f, 0.f, 0.f));
         return;
