@@ -41,22 +41,13 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev
     return t;
 }
 
-// Item walk.  With at most one item per workgroup (G >= nitems): workgroup
-// x + NXCD r runs on XCD x (workgroups are dealt to the XCDs round-robin) and
-// takes every (G / NXCD)-th item, from its r-th on, of the contiguous eighth
-// of the (spatially ordered) item list that belongs to XCD x, so neighbouring
-// tiles, which share halo nodes, meet in one L2.  With more items than
-// workgroups the walk is flat (workgroup g takes items g, g + G, ...), which
-// spreads neighbouring items over the XCDs and measured faster at those sizes.
+// Item walk: workgroup x + NXCD r runs on XCD x (workgroups are dealt to the
+// XCDs round-robin) and takes every (G / NXCD)-th item, from its r-th on, of
+// the contiguous eighth of the (spatially ordered) item list that belongs to
+// XCD x, so neighbouring tiles, which share halo nodes, meet in one L2.
 __device__ __forceinline__ void item_range(int nitems, int &first, int &stride, int &end)
 {
     const int G = gridDim.x;         // multiple of NXCD
-    if (nitems > G) {
-        first = blockIdx.x;
-        stride = G;
-        end = nitems;
-        return;
-    }
     const int x = blockIdx.x % NXCD, r = blockIdx.x / NXCD;
     const int per = (nitems + NXCD - 1) / NXCD;
     first = x * per + r;
