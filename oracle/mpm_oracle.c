@@ -267,21 +267,24 @@ static int out_of_domain(const int base[3], int n)
     return 0;
 }
 
-/* P2G (Sec. III-B item 1, Eq. P2G and Eq. fip):
+/* P2G (Sec. III-B item 1, Eq. P2G and Eq. fip) onto the node planes
+ * i0 <= i < i1 of the grid (all of it: 0, n):
  *   m_i    = sum_p w_ip m_p
  *   (mv)_i = sum_p w_ip [ m_p v_p + m_p C_p (x_i - x_p) + f_ip dt ]
- *   f_ip dt = -dt V0 (4/dx^2) tau_p (x_i - x_p)                          */
-uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
-                 const double *F, double *gm, double *gmv)
+ *   f_ip dt = -dt V0 (4/dx^2) tau_p (x_i - x_p)
+ * Every node receives its terms in particle order, whatever the planes.    */
+static uint32_t p2g_planes(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
+                           const double *F, double *gm, double *gmv, int i0, int i1)
 {
     const int n = P->n;
     const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
     const double m = P->rho * P->V0;
+    const size_t plane = (size_t)n * n;
     double mu, lam;
     uint32_t flags = 0;
     orc_lame(P->E, P->nu, &mu, &lam);
-    memset(gm, 0, sizeof(double) * (size_t)n * n * n);
-    memset(gmv, 0, sizeof(double) * 3 * (size_t)n * n * n);
+    memset(gm + (size_t)i0 * plane, 0, sizeof(double) * (size_t)(i1 - i0) * plane);
+    memset(gmv + 3 * (size_t)i0 * plane, 0, sizeof(double) * 3 * (size_t)(i1 - i0) * plane);
     for (int p = 0; p < N; ++p) {
         int base[3];
         double fx[3], w[3][3], tau[9], A[9];
@@ -290,9 +293,11 @@ uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *
             flags |= ORC_FLAG_OUT_OF_DOMAIN;
             continue;
         }
+        if (base[0] + 2 < i0 || base[0] >= i1) continue;   /* no node on these planes */
         flags |= orc_kirchhoff(F + 9 * p, mu, lam, tau);
         for (int k = 0; k < 9; ++k) A[k] = -P->dt * P->V0 * D * tau[k] + m * C[9 * p + k];
-        for (int o0 = 0; o0 < 3; ++o0)
+        for (int o0 = 0; o0 < 3; ++o0) {
+            if (base[0] + o0 < i0 || base[0] + o0 >= i1) continue;
             for (int o1 = 0; o1 < 3; ++o1)
                 for (int o2 = 0; o2 < 3; ++o2) {
                     double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
@@ -304,8 +309,15 @@ uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *
                         gmv[3 * i + a] += wt * (m * v[3 * p + a] + Ad);
                     }
                 }
+        }
     }
     return flags;
+}
+
+uint32_t orc_p2g(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
+                 const double *F, double *gm, double *gmv)
+{
+    return p2g_planes(P, N, x, v, C, F, gm, gmv, 0, P->n);
 }
 
 /* World-frame contact normal of tool t at tool-frame offset q (R11). */
@@ -321,14 +333,15 @@ static void capsule_normal(const orc_tool *tl, const double q[3], double nrm[3])
     for (int a = 0; a < 3; ++a) nrm[a] = tl->R[3 * a + 0] * nl[0] + tl->R[3 * a + 1] * nl[1] + tl->R[3 * a + 2] * nl[2];
 }
 
-/* Grid operation (Sec. III-B item 2, Sec. III-C) for every node, with the
- * tool poses T[t][3] and velocities u[t][3] of this substep. */
-void orc_grid_update(const orc_params *P, const orc_tool *tools, const double *T, const double *u,
-                     const double *gm, const double *gmv, double *gv, orc_node_rec *rec)
+/* Grid operation (Sec. III-B item 2, Sec. III-C) for every node of the
+ * planes i0 <= i < i1, with the tool poses T[t][3] and velocities u[t][3] of
+ * this substep. */
+static void grid_update_planes(const orc_params *P, const orc_tool *tools, const double *T, const double *u,
+                               const double *gm, const double *gmv, double *gv, orc_node_rec *rec, int i0, int i1)
 {
     const int n = P->n;
     const double dx = 1.0 / n;
-    for (int i = 0; i < n; ++i)
+    for (int i = i0; i < i1; ++i)
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 size_t id = IDX(n, i, j, k);
@@ -399,16 +412,23 @@ void orc_grid_update(const orc_params *P, const orc_tool *tools, const double *T
             }
 }
 
-/* G2P and advection (Sec. III-B item 3) followed by the F update (R2):
+void orc_grid_update(const orc_params *P, const orc_tool *tools, const double *T, const double *u,
+                     const double *gm, const double *gmv, double *gv, orc_node_rec *rec)
+{
+    grid_update_planes(P, tools, T, u, gm, gmv, gv, rec, 0, P->n);
+}
+
+/* G2P and advection (Sec. III-B item 3) followed by the F update (R2) for
+ * particles p0 <= p < p1:
  *   v_p = sum_i w_ip v_i,  C_p = (4/dx^2) sum_i w_ip v_i (x_i - x_p)^T,
  *   x_p += dt v_p,  F_p <- (I + dt C_p) F_p.                              */
-uint32_t orc_g2p(const orc_params *P, int32_t N, double *x, double *v, double *C, double *F,
-                 const double *gv)
+static uint32_t g2p_range(const orc_params *P, int32_t p0, int32_t p1, double *x, double *v, double *C, double *F,
+                          const double *gv)
 {
     const int n = P->n;
     const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
     uint32_t flags = 0;
-    for (int p = 0; p < N; ++p) {
+    for (int p = p0; p < p1; ++p) {
         int base[3];
         double fx[3], w[3][3];
         orc_weights(x + 3 * p, inv_dx, base, fx, w, NULL);
@@ -449,6 +469,12 @@ uint32_t orc_g2p(const orc_params *P, int32_t N, double *x, double *v, double *C
     return flags;
 }
 
+uint32_t orc_g2p(const orc_params *P, int32_t N, double *x, double *v, double *C, double *F,
+                 const double *gv)
+{
+    return g2p_range(P, 0, N, x, v, C, F, gv);
+}
+
 /* One substep with tool poses T (advanced in place, R14) and velocities u. */
 uint32_t orc_substep(const orc_params *P, const orc_tool *tools, double *T, const double *u,
                      int32_t N, double *x, double *v, double *C, double *F,
@@ -485,6 +511,65 @@ uint32_t orc_run(const orc_params *P, const orc_tool *tools, const double *traj,
         flags |= orc_substep(P, tools, T, u, N, x, v, C, F, gm, gmv, gv);
     }
     free(gm); free(gmv); free(gv);
+    return flags;
+}
+
+/* The substep of orc_run spread over threads (OpenMP), for timing the oracle
+ * on a many-core host.  P2G: each thread owns a slab of node planes,
+ * i in [cut[t], cut[t+1]), balanced by the particles whose stencils reach it,
+ * and runs the plain P2G loop over all particles for its own nodes only; every
+ * node still receives its terms in particle order, so the grid is the serial
+ * one bit for bit (no private copies, nothing to reduce).  The grid operation
+ * is split over planes and G2P over particles, both without shared writes.
+ * The result equals orc_run's exactly. */
+uint32_t orc_run_threads(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
+                         int32_t s0, int32_t S, double *T, int32_t N, double *x, double *v, double *C,
+                         double *F, int32_t nthreads)
+{
+    const int n = P->n;
+    const size_t nn = (size_t)n * n * n;
+    double *gm = malloc(sizeof(double) * nn), *gmv = malloc(sizeof(double) * 3 * nn),
+           *gv = malloc(sizeof(double) * 3 * nn);
+    int *hist = malloc(sizeof(int) * (size_t)(n + 1)), *cut = malloc(sizeof(int) * (size_t)(nthreads + 1));
+    double u[3 * 64];
+    uint32_t flags = 0;
+    if (nthreads < 1) nthreads = 1;
+    for (int s = s0; s < s0 + S; ++s) {
+        if (P->n_tools > 0) traj_at(P, traj, n_traj, s, u);
+        /* plane slabs with about equal numbers of (particle, plane) pairs */
+        memset(hist, 0, sizeof(int) * (size_t)(n + 1));
+        long long pairs = 0;
+        for (int p = 0; p < N; ++p) {
+            int b = (int)floor(x[3 * p] * n - 0.5);
+            if (b < 0 || b + 2 > n - 1) continue;
+            hist[b] += 1; hist[b + 1] += 1; hist[b + 2] += 1;
+            pairs += 3;
+        }
+        cut[0] = 0;
+        long long acc = 0;
+        int t = 1;
+        for (int i = 0; i < n && t < nthreads; ++i) {
+            acc += hist[i];
+            while (t < nthreads && acc * nthreads >= pairs * t) cut[t++] = i + 1;
+        }
+        while (t <= nthreads) cut[t++] = n;
+        uint32_t f = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1) reduction(| : f)
+        for (int k = 0; k < nthreads; ++k)
+            if (cut[k] < cut[k + 1]) f |= p2g_planes(P, N, x, v, C, F, gm, gmv, cut[k], cut[k + 1]);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+        for (int i = 0; i < n; ++i) grid_update_planes(P, tools, T, u, gm, gmv, gv, NULL, i, i + 1);
+        const int chunk = (N + nthreads - 1) / nthreads;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1) reduction(| : f)
+        for (int k = 0; k < nthreads; ++k) {
+            int p0 = k * chunk, p1 = p0 + chunk < N ? p0 + chunk : N;
+            if (p0 < p1) f |= g2p_range(P, p0, p1, x, v, C, F, gv);
+        }
+        for (int tl = 0; tl < P->n_tools; ++tl)
+            for (int a = 0; a < 3; ++a) T[3 * tl + a] += P->dt * u[3 * tl + a];
+        flags |= f;
+    }
+    free(gm); free(gmv); free(gv); free(hist); free(cut);
     return flags;
 }
 
@@ -559,6 +644,182 @@ static void grid_node_adjoint(const orc_tool *tools, const double *u, const orc_
         Tbar[3 * t + a] -= tl->R[3 * a + 0] * xrbar[0] + tl->R[3 * a + 1] * xrbar[1] + tl->R[3 * a + 2] * xrbar[2];
 }
 
+/* Reverse of G2P, advection and the F update (Sec. III-B item 3, the F'
+ * relation) for every particle, from the substep-start x, F and the node
+ * velocities gv.  On entry xbar, vbar, Cbar, Fbar hold the adjoints of the
+ * state after the stage; on exit xbar and Fbar hold those of x and F before
+ * it and vbar, Cbar are zero (the stage overwrites v and C); gvbar receives
+ * the adjoint of the node velocities. */
+void orc_g2p_adjoint(const orc_params *P, int32_t N, const double *x, const double *F, const double *gv,
+                     double *xbar, double *vbar, double *Cbar, double *Fbar, double *gvbar)
+{
+    const int n = P->n;
+    const size_t nn = (size_t)n * n * n;
+    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx, dt = P->dt;
+    memset(gvbar, 0, sizeof(double) * 3 * nn);
+    for (int p = 0; p < N; ++p) {
+        int base[3];
+        double fx[3], w[3][3], dw[3][3];
+        orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
+        if (out_of_domain(base, n)) continue;  /* state passes through unchanged */
+        /* forward values of this particle's G2P */
+        double vp[3] = {0, 0, 0}, B[9] = {0};
+        for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+            double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+            double wt = w[0][o0] * w[1][o1] * w[2][o2];
+            const double *vi = gv + 3 * IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+            for (int a = 0; a < 3; ++a) {
+                vp[a] += wt * vi[a];
+                for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * dpos[b];
+            }
+        }
+        double Cn[9];
+        for (int k = 0; k < 9; ++k) Cn[k] = D * B[k];
+        const double *Fp = F + 9 * p;
+        double *Fb = Fbar + 9 * p, *Cb = Cbar + 9 * p, *vb = vbar + 3 * p, *xb = xbar + 3 * p;
+        /* F' = (I + dt C') F */
+        double Fbn[9], Cbt[9];
+        for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                s1 += ((c == a ? 1.0 : 0.0) + dt * Cn[3 * c + a]) * Fb[3 * c + b];
+                s2 += Fb[3 * a + c] * Fp[3 * b + c];
+            }
+            Fbn[3 * a + b] = s1;
+            Cbt[3 * a + b] = Cb[3 * a + b] + dt * s2;
+        }
+        /* x' = x + dt v' */
+        double vbt[3] = {vb[0] + dt * xb[0], vb[1] + dt * xb[1], vb[2] + dt * xb[2]};
+        double fxbar[3] = {0, 0, 0};
+        for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+            int o[3] = {o0, o1, o2};
+            double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+            double wt = w[0][o0] * w[1][o1] * w[2][o2];
+            size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+            const double *vi = gv + 3 * id;
+            double g[3];
+            for (int a = 0; a < 3; ++a)
+                g[a] = vbt[a] + D * (Cbt[3 * a + 0] * dpos[0] + Cbt[3 * a + 1] * dpos[1] + Cbt[3 * a + 2] * dpos[2]);
+            for (int a = 0; a < 3; ++a) gvbar[3 * id + a] += wt * g[a];
+            double wbar = vi[0] * g[0] + vi[1] * g[1] + vi[2] * g[2];
+            for (int b = 0; b < 3; ++b) {
+                double dposbar = wt * D * (Cbt[0 + b] * vi[0] + Cbt[3 + b] * vi[1] + Cbt[6 + b] * vi[2]);
+                double dwd = dw[b][o[b]];
+                for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
+                fxbar[b] += -dx * dposbar + wbar * dwd;
+            }
+        }
+        for (int a = 0; a < 3; ++a) xb[a] += inv_dx * fxbar[a];
+        memcpy(Fb, Fbn, sizeof Fbn);
+        for (int k = 0; k < 9; ++k) Cb[k] = 0.0;
+        vb[0] = vb[1] = vb[2] = 0.0;
+    }
+
+}
+
+/* Reverse of the grid operation (Sec. III-B item 2, Sec. III-C) at every
+ * node with mass, using the forward's node records (tool, contact branch,
+ * normal): gvbar is the adjoint of the node velocities; gmbar, gmvbar receive
+ * those of the node mass and momentum, and the tool-velocity and tool-position
+ * adjoints of this substep are added to ubar[t][3], Tbar[t][3]. */
+void orc_grid_adjoint(const orc_params *P, const orc_tool *tools, const double *u, const double *gm,
+                      const double *gmv, const orc_node_rec *rec, const double *gvbar, double *gmbar, double *gmvbar,
+                      double *ubar, double *Tbar)
+{
+    const size_t nn = (size_t)P->n * P->n * P->n;
+    for (size_t id = 0; id < nn; ++id) {
+        gmbar[id] = 0.0;
+        gmvbar[3 * id] = gmvbar[3 * id + 1] = gmvbar[3 * id + 2] = 0.0;
+        if (!(gm[id] > 0.0)) continue;
+        double vhbar[3];
+        grid_node_adjoint(tools, u, &rec[id], gvbar + 3 * id, vhbar,
+                          ubar, Tbar);
+        double pv[3];
+        for (int a = 0; a < 3; ++a) {
+            gmvbar[3 * id + a] = vhbar[a] / gm[id];
+            pv[a] = gmv[3 * id + a] / gm[id];
+        }
+        gmbar[id] = -(vhbar[0] * pv[0] + vhbar[1] * pv[1] + vhbar[2] * pv[2]) / gm[id];
+    }
+
+}
+
+/* Reverse of P2G and of the Neo-Hookean stress (Sec. III-B item 1, Eq. P2G,
+ * Eq. fip) for every particle, from the substep-start state: adds to xbar,
+ * vbar, Cbar, Fbar the adjoints through the node mass and momentum (adjoints
+ * gmbar, gmvbar) and to mubar, lambar those of the Lame parameters. */
+void orc_p2g_adjoint(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
+                     const double *F, const double *gmbar, const double *gmvbar, double *xbar, double *vbar,
+                     double *Cbar, double *Fbar, double *mubar, double *lambar)
+{
+    const int n = P->n;
+    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx, dt = P->dt;
+    const double m = P->rho * P->V0;
+    double mu, lam;
+    orc_lame(P->E, P->nu, &mu, &lam);
+    for (int p = 0; p < N; ++p) {
+        int base[3];
+        double fx[3], w[3][3], dw[3][3], tau[9], A[9];
+        orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
+        if (out_of_domain(base, n)) continue;
+        const double *Fp = F + 9 * p;
+        orc_kirchhoff(Fp, mu, lam, tau);
+        for (int k = 0; k < 9; ++k) A[k] = -dt * P->V0 * D * tau[k] + m * C[9 * p + k];
+        double vbp[3] = {0, 0, 0}, Abar[9] = {0}, fxbar[3] = {0, 0, 0};
+        for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
+            int o[3] = {o0, o1, o2};
+            double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
+            double wt = w[0][o0] * w[1][o1] * w[2][o2];
+            size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
+            const double *Pb = gmvbar + 3 * id;
+            double contrib[3];
+            for (int a = 0; a < 3; ++a) {
+                vbp[a] += m * wt * Pb[a];
+                for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * Pb[a] * dpos[b];
+                contrib[a] = m * v[3 * p + a] + A[3 * a + 0] * dpos[0] + A[3 * a + 1] * dpos[1] + A[3 * a + 2] * dpos[2];
+            }
+            double wbar = m * gmbar[id] + Pb[0] * contrib[0] + Pb[1] * contrib[1] + Pb[2] * contrib[2];
+            for (int b = 0; b < 3; ++b) {
+                double dposbar = wt * (A[0 + b] * Pb[0] + A[3 + b] * Pb[1] + A[6 + b] * Pb[2]);
+                double dwd = dw[b][o[b]];
+                for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
+                fxbar[b] += -dx * dposbar + wbar * dwd;
+            }
+        }
+        double *xb = xbar + 3 * p;
+        for (int a = 0; a < 3; ++a) {
+            xb[a] += inv_dx * fxbar[a];
+            vbar[3 * p + a] += vbp[a];
+        }
+        for (int k = 0; k < 9; ++k) Cbar[9 * p + k] += m * Abar[k];
+        double taub[9];
+        for (int k = 0; k < 9; ++k) taub[k] = -dt * P->V0 * D * Abar[k];
+        double J = det3(Fp);
+        double trt = taub[0] + taub[4] + taub[8];
+        double FFt_I = 0.0;
+        for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+            double FFt = 0.0;
+            for (int c = 0; c < 3; ++c) FFt += Fp[3 * a + c] * Fp[3 * b + c];
+            FFt_I += taub[3 * a + b] * (FFt - (a == b ? 1.0 : 0.0));
+        }
+        *mubar += FFt_I;
+        double *Fb = Fbar + 9 * p;
+        if (J > ORC_J_MIN) {
+            double Fit[9];
+            inv_transpose3(Fp, Fit);
+            *lambar += trt * log(J);
+            for (int k = 0; k < 9; ++k) Fb[k] += lam * trt * Fit[k];
+        } else {
+            *lambar += trt * log(ORC_J_MIN);
+        }
+        for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
+            double s1 = 0.0;
+            for (int c = 0; c < 3; ++c) s1 += (taub[3 * a + c] + taub[3 * c + a]) * Fp[3 * c + b];
+            Fb[3 * a + b] += mu * s1;
+        }
+    }
+}
+
 uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
                      int32_t S, const double *T0, int32_t N, const double *x0, const double *v0,
                      const double *C0, const double *F0, double *xbar, double *vbar, double *Cbar,
@@ -566,10 +827,7 @@ uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *t
 {
     const int n = P->n, nt = P->n_tools;
     const size_t nn = (size_t)n * n * n;
-    const double dx = 1.0 / n, inv_dx = (double)n, D = 4.0 * inv_dx * inv_dx;
-    const double m = P->rho * P->V0, dt = P->dt;
-    double mu, lam;
-    orc_lame(P->E, P->nu, &mu, &lam);
+    const double dt = P->dt;
     uint32_t flags = 0;
 
     /* forward with a full tape of substep-start states and tool poses */
@@ -612,144 +870,11 @@ uint32_t orc_adjoint(const orc_params *P, const orc_tool *tools, const double *t
         orc_p2g(P, N, x, v, C, F, gm, gmv);
         orc_grid_update(P, tools, Ts, us, gm, gmv, gv, rec);
 
-        /* reverse of F update, advection and G2P */
-        memset(gvbar, 0, sizeof(double) * 3 * nn);
-        for (int p = 0; p < N; ++p) {
-            int base[3];
-            double fx[3], w[3][3], dw[3][3];
-            orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
-            if (out_of_domain(base, n)) continue;  /* state passes through unchanged */
-            /* forward values of this particle's G2P */
-            double vp[3] = {0, 0, 0}, B[9] = {0};
-            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
-                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
-                double wt = w[0][o0] * w[1][o1] * w[2][o2];
-                const double *vi = gv + 3 * IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
-                for (int a = 0; a < 3; ++a) {
-                    vp[a] += wt * vi[a];
-                    for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * dpos[b];
-                }
-            }
-            double Cn[9];
-            for (int k = 0; k < 9; ++k) Cn[k] = D * B[k];
-            const double *Fp = F + 9 * p;
-            double *Fb = Fbar + 9 * p, *Cb = Cbar + 9 * p, *vb = vbar + 3 * p, *xb = xbar + 3 * p;
-            /* F' = (I + dt C') F */
-            double Fbn[9], Cbt[9];
-            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
-                double s1 = 0.0, s2 = 0.0;
-                for (int c = 0; c < 3; ++c) {
-                    s1 += ((c == a ? 1.0 : 0.0) + dt * Cn[3 * c + a]) * Fb[3 * c + b];
-                    s2 += Fb[3 * a + c] * Fp[3 * b + c];
-                }
-                Fbn[3 * a + b] = s1;
-                Cbt[3 * a + b] = Cb[3 * a + b] + dt * s2;
-            }
-            /* x' = x + dt v' */
-            double vbt[3] = {vb[0] + dt * xb[0], vb[1] + dt * xb[1], vb[2] + dt * xb[2]};
-            double fxbar[3] = {0, 0, 0};
-            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
-                int o[3] = {o0, o1, o2};
-                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
-                double wt = w[0][o0] * w[1][o1] * w[2][o2];
-                size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
-                const double *vi = gv + 3 * id;
-                double g[3];
-                for (int a = 0; a < 3; ++a)
-                    g[a] = vbt[a] + D * (Cbt[3 * a + 0] * dpos[0] + Cbt[3 * a + 1] * dpos[1] + Cbt[3 * a + 2] * dpos[2]);
-                for (int a = 0; a < 3; ++a) gvbar[3 * id + a] += wt * g[a];
-                double wbar = vi[0] * g[0] + vi[1] * g[1] + vi[2] * g[2];
-                for (int b = 0; b < 3; ++b) {
-                    double dposbar = wt * D * (Cbt[0 + b] * vi[0] + Cbt[3 + b] * vi[1] + Cbt[6 + b] * vi[2]);
-                    double dwd = dw[b][o[b]];
-                    for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
-                    fxbar[b] += -dx * dposbar + wbar * dwd;
-                }
-            }
-            for (int a = 0; a < 3; ++a) xb[a] += inv_dx * fxbar[a];
-            memcpy(Fb, Fbn, sizeof Fbn);
-            for (int k = 0; k < 9; ++k) Cb[k] = 0.0;
-            vb[0] = vb[1] = vb[2] = 0.0;
-        }
-
-        /* reverse of the grid operation */
-        for (size_t id = 0; id < nn; ++id) {
-            gmbar[id] = 0.0;
-            gmvbar[3 * id] = gmvbar[3 * id + 1] = gmvbar[3 * id + 2] = 0.0;
-            if (!(gm[id] > 0.0)) continue;
-            double vhbar[3];
-            grid_node_adjoint(tools, us, &rec[id], gvbar + 3 * id, vhbar,
-                              gu + 3 * (size_t)nt * s, Tbar + 3 * (size_t)nt * s);
-            double pv[3];
-            for (int a = 0; a < 3; ++a) {
-                gmvbar[3 * id + a] = vhbar[a] / gm[id];
-                pv[a] = gmv[3 * id + a] / gm[id];
-            }
-            gmbar[id] = -(vhbar[0] * pv[0] + vhbar[1] * pv[1] + vhbar[2] * pv[2]) / gm[id];
-        }
-
-        /* reverse of P2G and of the stress */
-        for (int p = 0; p < N; ++p) {
-            int base[3];
-            double fx[3], w[3][3], dw[3][3], tau[9], A[9];
-            orc_weights(x + 3 * p, inv_dx, base, fx, w, dw);
-            if (out_of_domain(base, n)) continue;
-            const double *Fp = F + 9 * p;
-            orc_kirchhoff(Fp, mu, lam, tau);
-            for (int k = 0; k < 9; ++k) A[k] = -dt * P->V0 * D * tau[k] + m * C[9 * p + k];
-            double vbp[3] = {0, 0, 0}, Abar[9] = {0}, fxbar[3] = {0, 0, 0};
-            for (int o0 = 0; o0 < 3; ++o0) for (int o1 = 0; o1 < 3; ++o1) for (int o2 = 0; o2 < 3; ++o2) {
-                int o[3] = {o0, o1, o2};
-                double dpos[3] = {(o0 - fx[0]) * dx, (o1 - fx[1]) * dx, (o2 - fx[2]) * dx};
-                double wt = w[0][o0] * w[1][o1] * w[2][o2];
-                size_t id = IDX(n, base[0] + o0, base[1] + o1, base[2] + o2);
-                const double *Pb = gmvbar + 3 * id;
-                double contrib[3];
-                for (int a = 0; a < 3; ++a) {
-                    vbp[a] += m * wt * Pb[a];
-                    for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * Pb[a] * dpos[b];
-                    contrib[a] = m * v[3 * p + a] + A[3 * a + 0] * dpos[0] + A[3 * a + 1] * dpos[1] + A[3 * a + 2] * dpos[2];
-                }
-                double wbar = m * gmbar[id] + Pb[0] * contrib[0] + Pb[1] * contrib[1] + Pb[2] * contrib[2];
-                for (int b = 0; b < 3; ++b) {
-                    double dposbar = wt * (A[0 + b] * Pb[0] + A[3 + b] * Pb[1] + A[6 + b] * Pb[2]);
-                    double dwd = dw[b][o[b]];
-                    for (int e = 0; e < 3; ++e) if (e != b) dwd *= w[e][o[e]];
-                    fxbar[b] += -dx * dposbar + wbar * dwd;
-                }
-            }
-            double *xb = xbar + 3 * p;
-            for (int a = 0; a < 3; ++a) {
-                xb[a] += inv_dx * fxbar[a];
-                vbar[3 * p + a] += vbp[a];
-            }
-            for (int k = 0; k < 9; ++k) Cbar[9 * p + k] += m * Abar[k];
-            double taub[9];
-            for (int k = 0; k < 9; ++k) taub[k] = -dt * P->V0 * D * Abar[k];
-            double J = det3(Fp);
-            double trt = taub[0] + taub[4] + taub[8];
-            double FFt_I = 0.0;
-            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
-                double FFt = 0.0;
-                for (int c = 0; c < 3; ++c) FFt += Fp[3 * a + c] * Fp[3 * b + c];
-                FFt_I += taub[3 * a + b] * (FFt - (a == b ? 1.0 : 0.0));
-            }
-            mubar += FFt_I;
-            double *Fb = Fbar + 9 * p;
-            if (J > ORC_J_MIN) {
-                double Fit[9];
-                inv_transpose3(Fp, Fit);
-                lambar += trt * log(J);
-                for (int k = 0; k < 9; ++k) Fb[k] += lam * trt * Fit[k];
-            } else {
-                lambar += trt * log(ORC_J_MIN);
-            }
-            for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) {
-                double s1 = 0.0;
-                for (int c = 0; c < 3; ++c) s1 += (taub[3 * a + c] + taub[3 * c + a]) * Fp[3 * c + b];
-                Fb[3 * a + b] += mu * s1;
-            }
-        }
+        /* reverse of F update, advection and G2P, of the grid operation, of P2G and the stress */
+        orc_g2p_adjoint(P, N, x, F, gv, xbar, vbar, Cbar, Fbar, gvbar);
+        orc_grid_adjoint(P, tools, us, gm, gmv, rec, gvbar, gmbar, gmvbar, nt > 0 ? gu + 3 * (size_t)nt * s : NULL,
+                         Tbar + 3 * (size_t)nt * s);
+        orc_p2g_adjoint(P, N, x, v, C, F, gmbar, gmvbar, xbar, vbar, Cbar, Fbar, &mubar, &lambar);
     }
 
     /* tool pose T_s = T_0 + dt sum_{s'<s} u_{s'} */

@@ -99,6 +99,17 @@ uint32_t orc_substep(const orc_params *P, const orc_tool *tools, double *T, cons
 uint32_t orc_run(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
                  int32_t s0, int32_t S, double *T, int32_t N, double *x, double *v, double *C,
                  double *F);
+void orc_g2p_adjoint(const orc_params *P, int32_t N, const double *x, const double *F, const double *gv,
+                     double *xbar, double *vbar, double *Cbar, double *Fbar, double *gvbar);
+void orc_grid_adjoint(const orc_params *P, const orc_tool *tools, const double *u, const double *gm,
+                      const double *gmv, const orc_node_rec *rec, const double *gvbar, double *gmbar, double *gmvbar,
+                      double *ubar, double *Tbar);
+void orc_p2g_adjoint(const orc_params *P, int32_t N, const double *x, const double *v, const double *C,
+                     const double *F, const double *gmbar, const double *gmvbar, double *xbar, double *vbar,
+                     double *Cbar, double *Fbar, double *mubar, double *lambar);
+uint32_t orc_run_threads(const orc_params *P, const orc_tool *tools, const double *traj, int32_t n_traj,
+                         int32_t s0, int32_t S, double *T, int32_t N, double *x, double *v, double *C,
+                         double *F, int32_t nthreads);
 int orc_mc_case(int mask, int32_t tri[][3]);
 int64_t orc_surface(int32_t n, double h, const double *rho, double iso, int32_t *cell_ntri, int32_t *tri_edges,
                     double *tris, int64_t max_tris);

@@ -26,14 +26,27 @@ FLAG_NONFINITE = 4
 J_MIN = 1e-6
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no host-specific ISA)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-Wno-unused-parameter", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+CFLAGS = ["-O3", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+def build(force: bool = True, out: str = LIB, native: bool = False, extra=()) -> str:
+    """Compile the oracle with gcc: -O3 and OpenMP (for orc_run_threads), ISO C
+    (so no floating-point contraction and no fast-math).  native=True adds
+    -march=native, for a library built and timed on the same host."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        flags = CFLAGS + (["-march=native"] if native else []) + list(extra)
+        subprocess.check_call(["gcc", *flags, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (e.g. a
+    -march=native build made on the timing host); call before any other use."""
+    global _lib, LIB
+    _lib = None
+    LIB = path
 
 
 class Params(ct.Structure):
@@ -85,10 +98,17 @@ def lib():
         L.orc_run.argtypes = [P, T, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
                               ct.c_int32, _D, _D, _D, _D]
         L.orc_run.restype = ct.c_uint32
+        L.orc_run_threads.argtypes = [P, T, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                      ct.c_int32, _D, _D, _D, _D, ct.c_int32]
+        L.orc_run_threads.restype = ct.c_uint32
         L.orc_adjoint.argtypes = [P, T, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_int32,
                                   _D, _D, _D, _D, _D, _D, _D, _D,
                                   ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
         L.orc_adjoint.restype = ct.c_uint32
+        L.orc_g2p_adjoint.argtypes = [P, ct.c_int32, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_grid_adjoint.argtypes = [P, T, _D, _D, _D, ct.c_void_p, _D, _D, _D, ct.c_void_p, ct.c_void_p]
+        L.orc_p2g_adjoint.argtypes = [P, ct.c_int32, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                      ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
         L.orc_mc_case.argtypes = [ct.c_int, ct.c_void_p]
         L.orc_mc_case.restype = ct.c_int
         L.orc_surface.argtypes = [ct.c_int32, ct.c_double, _D, ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p,
@@ -155,10 +175,17 @@ class Sim:
         k = min(s, self.n_traj - 1)
         return np.ascontiguousarray(self.traj[:, k, :])
 
-    def run(self, S):
+    def run(self, S, threads=None):
+        """S substeps.  threads > 1: orc_run_threads on that many threads (the
+        same result bit for bit, in less wall time)."""
         st = self.state
-        self.flags |= lib().orc_run(ct.byref(self.P), self.tools, _ptr(self.traj), self.n_traj, self.s, S,
-                                    _ptr(self.T), st.x.shape[0], st.x, st.v, st.C, st.F)
+        if threads and threads > 1:
+            f = lib().orc_run_threads(ct.byref(self.P), self.tools, _ptr(self.traj), self.n_traj, self.s, S,
+                                      _ptr(self.T), st.x.shape[0], st.x, st.v, st.C, st.F, int(threads))
+        else:
+            f = lib().orc_run(ct.byref(self.P), self.tools, _ptr(self.traj), self.n_traj, self.s, S,
+                              _ptr(self.T), st.x.shape[0], st.x, st.v, st.C, st.F)
+        self.flags |= f
         self.s += S
         return self
 
@@ -189,6 +216,46 @@ class Sim:
         u = self.u_at(self.s)
         self.T[:self.n_tools] += self.P.dt * u[:self.n_tools]
         self.s += 1
+
+    # --- stage-level adjoints (the reverse of one stage, from the forward's inputs)
+    def g2p_adjoint(self, gv, xbar, vbar, Cbar, Fbar):
+        """Reverse of G2P + advection + F update from the current state (the
+        stage's input) and node velocities gv; seeds are the adjoints of the
+        stage's output.  Returns (xbar, vbar, Cbar, Fbar) of the input and the
+        node-velocity adjoint gvbar (n, n, n, 3)."""
+        st, n = self.state, self.n
+        c = lambda a, shp: np.ascontiguousarray(np.asarray(a, np.float64).reshape(shp)).copy()
+        N = st.x.shape[0]
+        xb, vb, Cb, Fb = c(xbar, (N, 3)), c(vbar, (N, 3)), c(Cbar, (N, 3, 3)), c(Fbar, (N, 3, 3))
+        gvb = np.zeros((n, n, n, 3))
+        lib().orc_g2p_adjoint(ct.byref(self.P), N, st.x, st.F, np.ascontiguousarray(gv, np.float64),
+                              xb, vb, Cb, Fb, gvb)
+        return xb, vb, Cb, Fb, gvb
+
+    def grid_adjoint(self, gm, gmv, rec, gvbar, u=None):
+        """Reverse of the grid operation with the node records `rec` of the
+        forward (grid_update(..., record=True)); returns (gmbar, gmvbar,
+        ubar [n_tools][3], Tbar [n_tools][3])."""
+        n, nt = self.n, max(1, self.n_tools)
+        u = self.u_at(self.s) if u is None else np.ascontiguousarray(np.asarray(u, np.float64).reshape(-1, 3))
+        gmb, gmvb = np.zeros((n, n, n)), np.zeros((n, n, n, 3))
+        ub, Tb = np.zeros((nt, 3)), np.zeros((nt, 3))
+        lib().orc_grid_adjoint(ct.byref(self.P), self.tools, np.ascontiguousarray(u), np.ascontiguousarray(gm),
+                               np.ascontiguousarray(gmv), ct.cast(rec, ct.c_void_p),
+                               np.ascontiguousarray(gvbar, np.float64), gmb, gmvb, _ptr(ub), _ptr(Tb))
+        return gmb, gmvb, ub[:self.n_tools], Tb[:self.n_tools]
+
+    def p2g_adjoint(self, gmbar, gmvbar):
+        """Reverse of P2G and the stress from the current state; returns the
+        state adjoints (xbar, vbar, Cbar, Fbar) and (mubar, lambar)."""
+        st = self.state
+        N = st.x.shape[0]
+        xb, vb, Cb, Fb = np.zeros((N, 3)), np.zeros((N, 3)), np.zeros((N, 3, 3)), np.zeros((N, 3, 3))
+        mub, lamb = ct.c_double(0.0), ct.c_double(0.0)
+        lib().orc_p2g_adjoint(ct.byref(self.P), N, st.x, st.v, st.C, st.F, np.ascontiguousarray(gmbar, np.float64),
+                              np.ascontiguousarray(gmvbar, np.float64), xb, vb, Cb, Fb, ct.byref(mub),
+                              ct.byref(lamb))
+        return xb, vb, Cb, Fb, mub.value, lamb.value
 
     def adjoint(self, S, xbar=None, vbar=None, Cbar=None, Fbar=None):
         """Reverse-mode gradients of S substeps from the current state.  Seeds
