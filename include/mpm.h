@@ -70,9 +70,14 @@ enum {
     MPM_F_V = 1,        /* float [3][N_env] */
     MPM_F_C = 2,        /* float [9][N_env] */
     MPM_F_F = 3,        /* float [9][N_env] */
-    MPM_F_GRID_M = 4,   /* float [n^3], node (i,j,k) at (i*n+j)*n+k: mass of the last P2G */
-    MPM_F_GRID_MV = 5,  /* float [3][n^3]: momentum of the last P2G */
-    MPM_F_GRID_V = 6,   /* float [3][n^3]: velocity after the last grid operation */
+    MPM_F_GRID_M = 4,   /* float [n^3], node (i,j,k) at (i*n+j)*n+k: mass (Eq. P2G, Sec. III-B item 1) held
+                           in the momentum buffer: the last P2G after MPM_STAGE_P2G, MPM_STAGE_TILED_P2G or a
+                           fused tiled stage.  The tiled grid operation consumes and clears it, so after
+                           mpm_substep in MPM_SCHEME_TILED (or MPM_STAGE_TILED_GRID) it reads zeros */
+    MPM_F_GRID_MV = 5,  /* float [3][n^3]: momentum held in the momentum buffer, as MPM_F_GRID_M */
+    MPM_F_GRID_V = 6,   /* float [3][n^3]: velocity after the last grid operation (Sec. III-B item 2); the
+                           tiled grid operation writes only nodes that received mass, the others keep
+                           older values (no particle's stencil reads them) */
     MPM_F_STATUS = 7,   /* uint32 [1]: sticky MPM_FLAG_* bits of the environment */
     MPM_F_TOOL_T = 8,   /* double [max_tools][3]: current tool positions */
     MPM_F_STEP = 9,     /* int32 [1]: substeps taken by the environment */
@@ -90,13 +95,33 @@ enum { MPM_TOOL_CAPSULE = 0, MPM_TOOL_BOX = 1, MPM_TOOL_SDF = 2 };
  * and central-difference gradients interpolated trilinearly over the cell. */
 enum { MPM_SDF_NEAREST = 0, MPM_SDF_TRILINEAR = 1 };
 enum { MPM_CONTACT_SLIP = 0, MPM_CONTACT_STICKY = 1 };
-enum { MPM_STAGE_P2G = 0, MPM_STAGE_GRID = 1, MPM_STAGE_G2P = 2 };
+/* Stages for mpm_run_stage.  The first three are the direct scheme's kernels;
+ * the TILED ones are mpm_substep's tiled-scheme kernels, launched one at a
+ * time in the order a call of mpm_substep launches them. */
+enum {
+    MPM_STAGE_P2G = 0,             /* direct: P2G of the current state into a cleared grid */
+    MPM_STAGE_GRID = 1,            /* direct: grid operation over every node */
+    MPM_STAGE_G2P = 2,             /* direct: G2P, advection and F update */
+    MPM_STAGE_TILED_P2G = 3,       /* opens a tiled sequence: the counting sort if one is due, then the
+                                      tiled P2G of the current state (MPM_F_GRID_M/MV read it) */
+    MPM_STAGE_TILED_GRID = 4,      /* grid operation over the listed bricks: writes MPM_F_GRID_V where mass
+                                      arrived and clears the momentum buffer; follows a P2G stage */
+    MPM_STAGE_TILED_FUSED = 5,     /* fused particle pass: G2P, F update, advection of this substep and the
+                                      P2G of the next one; writes x and F (v and C stay in registers, so
+                                      MPM_F_V / MPM_F_C are not current until a later TILED_FUSED_FULL or
+                                      TILED_G2P), MPM_F_GRID_M/MV read the new P2G; follows TILED_GRID */
+    MPM_STAGE_TILED_FUSED_FULL = 6,/* as TILED_FUSED, also writing v and C (the adjoint's recompute kernel) */
+    MPM_STAGE_TILED_G2P = 7        /* G2P, F update and advection only; closes the sequence; follows
+                                      TILED_GRID */
+};
 
 /* Tunables (mpm_set_option).  Every setting gives the same results up to
  * the order of floating-point accumulation. */
 enum {
     MPM_OPT_SCHEME = 0,       /* MPM_SCHEME_* */
-    MPM_OPT_SORT_EVERY = 1,   /* counting-sort particles by grid brick every k substeps (>= 1) */
+    MPM_OPT_SORT_EVERY = 1,   /* counting-sort particles by grid brick every k substeps (>= 1); setting it
+                                 (to any value, the current one included) restarts the schedule: the
+                                 next substep call opens with a sort */
     MPM_OPT_BLOCK = 2,        /* threads per workgroup of the tiled particle kernels: 64, 128, 256 */
     MPM_OPT_GRAPH = 3,        /* 1: mpm_substep replays an internally captured hipGraph */
     MPM_OPT_PERSISTENT = 4,   /* tiled scheme, 1: each run of up to sort_every substeps is one persistent
@@ -224,9 +249,17 @@ mpm_status mpm_set_option(mpm_ctx *ctx, int32_t option, int32_t value);
  * synchronises. */
 mpm_status mpm_substep(mpm_ctx *ctx, int32_t n_substeps, int32_t record_tape, void *stream);
 
-/* Run one stage of a substep in isolation, with the same kernels as
- * mpm_substep's direct scheme: P2G, then GRID, then G2P make one substep.
- * For inspection and per-stage checking; not for throughput. */
+/* Run one stage of a substep in isolation (Sec. III-B items 1-3), for
+ * inspection and per-stage checking; not for throughput.  Direct stages:
+ * P2G, then GRID, then G2P make one substep.  Tiled stages: TILED_P2G,
+ * then TILED_GRID, then either TILED_G2P (one substep) or a fused stage
+ * followed by TILED_GRID again (one more substep per fused stage), ending
+ * with TILED_G2P.  A stage out of that order returns MPM_E_STATE and
+ * launches nothing; so do mpm_substep, mpm_substep_adjoint,
+ * mpm_extract_surface and the direct stages while a tiled sequence is open
+ * (mpm_read_state may be called at any point).  A tiled sequence sorts only
+ * at its start and advances the step counters and tool poses like the
+ * mpm_substep calls it mirrors. */
 mpm_status mpm_run_stage(mpm_ctx *ctx, int32_t stage, void *stream);
 
 /* Reverse the last n_substeps recorded substeps (1 <= n <= tape length):

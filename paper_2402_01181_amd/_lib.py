@@ -21,6 +21,7 @@ TOOL_CAPSULE, TOOL_BOX, TOOL_SDF = 0, 1, 2
 SDF_NEAREST, SDF_TRILINEAR = 0, 1
 CONTACT_SLIP, CONTACT_STICKY = 0, 1
 STAGE_P2G, STAGE_GRID, STAGE_G2P = 0, 1, 2
+STAGE_TILED_P2G, STAGE_TILED_GRID, STAGE_TILED_FUSED, STAGE_TILED_FUSED_FULL, STAGE_TILED_G2P = 3, 4, 5, 6, 7
 OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM, OPT_NODE_SLOTS = range(8)
 SCHEME_DIRECT, SCHEME_TILED = 0, 1
 # option values a new context starts with

@@ -602,6 +602,46 @@ void reverse_substep(mpm_ctx *c, int slot, int jw, hipStream_t st)
     timed(c, st, PK_ADJ_P2G, [&] { launch_adj_p2g(d, a, st); });
 }
 
+// Checks shared by the surface entry points; device addresses of the outputs.
+mpm_status surface_args(mpm_ctx *c, int32_t env, float iso, float *tris, int64_t max_tris, int64_t *n_tris,
+                               void **tris_d, void **count_d)
+{
+    if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
+    if (env < 0 || env >= c->n_envs) return fail(c, MPM_E_ARG, "env out of range");
+    if (!(iso > 0.f) || !std::isfinite(iso)) return fail(c, MPM_E_ARG, "iso must be finite and > 0");
+    if (max_tris < 0 || (max_tris > 0 && !tris)) return fail(c, MPM_E_ARG, "tris must hold max_tris >= 0 triangles");
+    if (!n_tris) return fail(c, MPM_E_ARG, "n_tris is NULL");
+    if (c->tstage) return fail(c, MPM_E_STATE, "a tiled stage sequence is open: end it with MPM_STAGE_TILED_G2P");
+    // device memory, or pinned host memory written through its device alias;
+    // anything else (pageable host memory) is refused rather than faulted on
+    auto device_alias = [&](void *p, void **out) -> bool {
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+        if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) { *out = p; return true; }
+        unsigned int hflags = 0;
+        if (at.type == hipMemoryTypeHost && at.devicePointer && hipHostGetFlags(&hflags, p) == hipSuccess) {
+            *out = static_cast<char *>(at.devicePointer) +
+                   (static_cast<char *>(p) - static_cast<char *>(at.hostPointer ? at.hostPointer : p));
+            return true;
+        }
+        return false;
+    };
+    *tris_d = nullptr;
+    *count_d = nullptr;
+    if (max_tris > 0 && !device_alias(tris, tris_d))
+        return fail(c, MPM_E_ARG, "tris must be device memory or pinned (hipHostMalloc) host memory");
+    if (!device_alias(n_tris, count_d))
+        return fail(c, MPM_E_ARG, "n_tris must be device memory or pinned (hipHostMalloc) host memory");
+    return MPM_OK;
+}
+
+// The sorted work items are usable while the live state sits in their slots.
+SurfItems surface_items(const mpm_ctx *c)
+{
+    if (c->scheme == MPM_SCHEME_TILED && c->items_valid) return SurfItems{c->sort.items, c->sort.totals, c->max_items};
+    return SurfItems{nullptr, nullptr, 0};
+}
+
 }  // namespace
 
 extern "C" {
@@ -828,6 +868,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
     case MPM_OPT_SORT_EVERY:
         if (value < 1) return fail(c, MPM_E_ARG, "sort_every must be >= 1");
         c->sort_every = value;
+        c->since_sort = value;   // the schedule restarts: the next substep call opens with a sort
         return MPM_OK;
     case MPM_OPT_BLOCK:
         if (value != 64 && value != 128 && value != 256) return fail(c, MPM_E_ARG, "block must be 64, 128 or 256");
@@ -862,6 +903,7 @@ mpm_status mpm_substep(mpm_ctx *c, int32_t n_substeps, int32_t record_tape, void
 {
     if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
     if (n_substeps < 1) return fail(c, MPM_E_ARG, "n_substeps must be >= 1");
+    if (c->tstage) return fail(c, MPM_E_STATE, "a tiled stage sequence is open: end it with MPM_STAGE_TILED_G2P");
     hipStream_t st = as_stream(stream);
     if (!record_tape) {
         c->tape.len = 0;   // the tape no longer ends at the current state
@@ -893,6 +935,10 @@ mpm_status mpm_run_stage(mpm_ctx *c, int32_t stage, void *stream)
     if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
     hipStream_t st = as_stream(stream);
     Dev d = c->dev();
+    const bool tiled_stage = stage >= MPM_STAGE_TILED_P2G && stage <= MPM_STAGE_TILED_G2P;
+    if (c->tstage && !tiled_stage)
+        return fail(c, MPM_E_STATE, "a tiled stage sequence is open: end it with MPM_STAGE_TILED_G2P");
+    if (tiled_stage && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
     switch (stage) {
     case MPM_STAGE_P2G:
         launch_fill_f4(c->gP, c->total_nodes, st);
@@ -905,6 +951,46 @@ mpm_status mpm_run_stage(mpm_ctx *c, int32_t stage, void *stream)
     case MPM_STAGE_G2P:
         launch_g2p_direct(d, st);
         break;
+    case MPM_STAGE_TILED_P2G: {
+        // the head of mpm_substep's tiled scheme: sort when due, then P2G of the current state
+        if (c->tstage) return fail(c, MPM_E_STATE, "a tiled stage sequence is open: end it with MPM_STAGE_TILED_G2P");
+        if (!c->grid_clean) {
+            launch_fill_f4(c->gP, c->total_nodes, st);
+            c->grid_clean = true;
+        }
+        ParticleBuf in = live(c);
+        if (!c->items_valid || c->items_P != c->item || c->since_sort >= c->sort_every) {
+            sort_into_alt(c, st);
+            in = c->alt;
+        }
+        launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, c->tiled_blocks, st);
+        c->tstage = 1;
+        c->tstage_i = 0;
+        c->tstage_in = in;
+        break;
+    }
+    case MPM_STAGE_TILED_GRID:
+        if (c->tstage != 1) return fail(c, MPM_E_STATE, "MPM_STAGE_TILED_GRID needs a tiled P2G before it");
+        launch_grid_active(d, c->act, c->tstage_i & 1, grid_blocks(c), c->has_sdf, st);
+        c->tstage = 2;
+        c->since_sort += 1;
+        break;
+    case MPM_STAGE_TILED_FUSED:
+    case MPM_STAGE_TILED_FUSED_FULL: {
+        if (c->tstage != 2) return fail(c, MPM_E_STATE, "a fused tiled stage needs MPM_STAGE_TILED_GRID before it");
+        const TiledArgs a = tiled_args(c, c->tstage_in, live(c), (c->tstage_i + 1) & 1);
+        if (stage == MPM_STAGE_TILED_FUSED) launch_fused_tiled(d, a, c->block, c->tiled_blocks, st);
+        else launch_fused_full_tiled(d, a, c->block, c->tiled_blocks, st);
+        c->tstage = 1;
+        c->tstage_i += 1;
+        c->tstage_in = live(c);
+        break;
+    }
+    case MPM_STAGE_TILED_G2P:
+        if (c->tstage != 2) return fail(c, MPM_E_STATE, "MPM_STAGE_TILED_G2P needs MPM_STAGE_TILED_GRID before it");
+        launch_g2p_tiled(d, tiled_args(c, c->tstage_in, live(c), 0), c->block, c->tiled_blocks, st);
+        c->tstage = 0;
+        break;
     default:
         return fail(c, MPM_E_ARG, "unknown stage");
     }
@@ -916,6 +1002,7 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
     if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
     if (!io) return fail(c, MPM_E_ARG, "io is NULL");
     if (n_substeps < 1) return fail(c, MPM_E_ARG, "n_substeps must be >= 1");
+    if (c->tstage) return fail(c, MPM_E_STATE, "a tiled stage sequence is open: end it with MPM_STAGE_TILED_G2P");
     if (c->max_tape == 0 || c->tape.len < n_substeps)
         return fail(c, MPM_E_STATE, "no recorded tape of at least n_substeps substeps ending at the current state");
     hipStream_t st = as_stream(stream);
@@ -1079,37 +1166,12 @@ mpm_status mpm_read_state(mpm_ctx *c, int32_t env, int32_t field, void *dst, siz
 mpm_status mpm_extract_surface(mpm_ctx *c, int32_t env, float iso, float *tris, int64_t max_tris, int64_t *n_tris,
                                void *stream)
 {
-    if (!c) return fail(nullptr, MPM_E_ARG, "ctx is NULL");
-    if (env < 0 || env >= c->n_envs) return fail(c, MPM_E_ARG, "env out of range");
-    if (!(iso > 0.f) || !std::isfinite(iso)) return fail(c, MPM_E_ARG, "iso must be finite and > 0");
-    if (max_tris < 0 || (max_tris > 0 && !tris)) return fail(c, MPM_E_ARG, "tris must hold max_tris >= 0 triangles");
-    if (!n_tris) return fail(c, MPM_E_ARG, "n_tris is NULL");
-    hipStream_t st = as_stream(stream);
-    // device memory, or pinned host memory written through its device alias;
-    // anything else (pageable host memory) is refused rather than faulted on
-    auto device_alias = [&](void *p, void **out) -> bool {
-        hipPointerAttribute_t at{};
-        if (hipPointerGetAttributes(&at, p) != hipSuccess) { (void)hipGetLastError(); return false; }
-        if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) { *out = p; return true; }
-        unsigned int hflags = 0;
-        if (at.type == hipMemoryTypeHost && at.devicePointer && hipHostGetFlags(&hflags, p) == hipSuccess) {
-            *out = static_cast<char *>(at.devicePointer) +
-                   (static_cast<char *>(p) - static_cast<char *>(at.hostPointer ? at.hostPointer : p));
-            return true;
-        }
-        return false;
-    };
     void *tris_d = nullptr, *count_d = nullptr;
-    if (max_tris > 0 && !device_alias(tris, &tris_d))
-        return fail(c, MPM_E_ARG, "tris must be device memory or pinned (hipHostMalloc) host memory");
-    if (!device_alias(n_tris, &count_d))
-        return fail(c, MPM_E_ARG, "n_tris must be device memory or pinned (hipHostMalloc) host memory");
+    mpm_status r = surface_args(c, env, iso, tris, max_tris, n_tris, &tris_d, &count_d);
+    if (r != MPM_OK) return r;
     const int n = c->gn[env];
-    // the sorted work items are usable while the live state sits in their slots
-    SurfItems items{nullptr, nullptr, 0};
-    if (c->scheme == MPM_SCHEME_TILED && c->items_valid) items = SurfItems{c->sort.items, c->sort.totals, c->max_items};
-    launch_surface(c->dev(), env, c->np[env], n, 1.0f / (float)n, iso, c->surf, items, static_cast<float *>(tris_d),
-                   max_tris, static_cast<int64_t *>(count_d), st);
+    launch_surface(c->dev(), env, c->np[env], n, 1.0f / (float)n, iso, c->surf, surface_items(c),
+                   static_cast<float *>(tris_d), max_tris, static_cast<int64_t *>(count_d), as_stream(stream));
     c->surf_env = env;
     return check_launch(c, "mpm_extract_surface");
 }

@@ -200,7 +200,11 @@ __global__ void k_static_clear(ActiveBuf act)
 }
 
 // New static brick list: the 27-brick neighbourhood (within its environment's
-// grid) of every occupied particle brick; one lane per (brick, neighbour).
+// grid) of every occupied particle brick; one lane per (brick, neighbour).  A
+// brick a P2G listed as far (flag 2) before this sort, whose dynamic entry
+// the next grid operation has not consumed yet, moves to the static list
+// too (2 -> 1): later P2Gs add to it without listing it, so the static list
+// must hold it; the grid operation then skips its dynamic entry.
 __global__ __launch_bounds__(256) void k_static_build(Dev d, SortBuf s, ActiveBuf act)
 {
     const int b = blockIdx.x * 8 + (threadIdx.x >> 5), o = threadIdx.x & 31;
@@ -211,7 +215,8 @@ __global__ __launch_bounds__(256) void k_static_build(Dev d, SortBuf s, ActiveBu
               bk = lb % e.nb + o % 3 - 1;
     if (bi < 0 || bj < 0 || bk < 0 || bi >= e.nb || bj >= e.nb || bk >= e.nb) return;
     const int x = e.bofs + (bi * e.nb + bj) * e.nb + bk;
-    if (gatomic_cas(act.flag + x, 0, 1)) gstore(act.slist + gatomic_add(act.scount, 1), x);
+    if (gatomic_cas(act.flag + x, 0, 1) || gatomic_cas(act.flag + x, 2, 1))
+        gstore(act.slist + gatomic_add(act.scount, 1), x);
 }
 
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,

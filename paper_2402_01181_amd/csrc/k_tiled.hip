@@ -354,6 +354,8 @@ __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &
         const bool dyn = i >= ns;
         const int b = dyn ? gload(dl + (i - ns)) : bs;
         if (i + stride < a.nbricks) bs = gload(a.slist + i + stride);
+        // a sort between the listing P2G and this pass moved the brick to the static list
+        if (dyn && gload(a.flag + b) == 1) continue;
         // environments' grids are consecutive brick-major slices, so node l of brick b is
         // node 64 b + l of the whole grid: P is loaded without waiting for the environment
         const int64_t g = (int64_t)b * BRICK_NODES + lane;

@@ -85,6 +85,11 @@ struct mpm_ctx {
     int since_sort = 0;
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
     int persistent_blocks = -1;      // co-resident workgroups of the persistent kernel (0: unavailable)
+    // tiled stage sequence of mpm_run_stage: 0 none open, 1 a P2G awaits its grid
+    // operation, 2 a grid operation awaits its particle pass
+    int tstage = 0;
+    int tstage_i = 0;                // substeps the open sequence has taken (dynamic-list parity)
+    mpm::ParticleBuf tstage_in{};    // particle input of the sequence's next particle pass
     mpm::GridBarrier barrier{};
     // host mirror of the tool slots
     std::vector<mpm::ToolDev> tools_h;

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2402_01181_amd import scenes
-from parity import TOL_DRIFT, oracle_sim_like
+from parity import oracle_sim_like
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,9 @@ def test_stiffness_sweep_monotone_and_matches_oracle(gpu, orc):
         do = np.linalg.norm(o.state.x - sc.envs[0].x.astype(np.float64), axis=1)
         _say(f"  E={E:g}: max gpu {d['max'][k]:.6e} oracle {do.max():.6e}, mean gpu {d['mean'][k]:.6e} "
              f"oracle {do.mean():.6e}")
-        assert abs(d["max"][k] - do.max()) <= TOL_DRIFT
-        assert abs(d["mean"][k] - do.mean()) <= 1e-2 * do.mean()
+        # held to 0.1% of the displacement (about 2.5 um here); the runs agree to ~1e-7 m
+        assert abs(d["max"][k] - do.max()) <= 1e-3 * do.max()
+        assert abs(d["mean"][k] - do.mean()) <= 1e-3 * do.mean()
 
 
 def test_identify_recovers_material(gpu, orc):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2402_01181_amd import scenes
-from parity import FLOORS, TOL_DRIFT, TOL_SUBSTEP, oracle_sim_like, oracle_state_from_gpu, rel_err
+from parity import FLOORS, TOL_DRIFT, TOL_SUBSTEP, assert_free_running, oracle_sim_like, oracle_state_from_gpu, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -100,10 +100,7 @@ def test_free_running_tools(gpu, orc, kind, interp):
     sim.step(S // 2)
     o = oracle_sim_like(orc, sc).run(S)
     x = sim.particles()[0]
-    err = np.abs(x - o.state.x).max()
-    moved = np.abs(o.state.x - sc.envs[0].x).max()
-    _say(f"  max |dx| = {err:.2e} (largest displacement {moved:.2e})")
-    assert err <= TOL_DRIFT
+    assert_free_running(x, o.state.x, sc.envs[0].x, f"{kind} {S} substeps")
     assert sim.read(L.F_STATUS) == 0
 
 
