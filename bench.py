@@ -1,6 +1,10 @@
 """Throughput benchmark of the MLS-MPM substep on one MI355X.
 
-A step is one substep of every particle (P2G, grid operation, G2P, F update).
+A step is one substep of every particle (P2G, grid operation, G2P, F update),
+with its share of the counting sort by cell: the timed window opens with a
+sort and sorts every `sort_every` substeps after that, so K substeps carry
+ceil(K / sort_every) sorts (when K is below the tuned interval, the interval
+is set to K, which keeps exactly one sort per interval in the window).
 Default workload: the 30K-particle tissue slab on a 64^3 grid pushed by a
 capsule tool (dt 5e-5, E 1e4, nu 0.35), the configuration the headline
 particle-substeps/s is quoted on.  Prints one JSON line.
@@ -15,8 +19,14 @@ package) unless --no-autotune is given; explicit flags override them.
 Timing: W untimed substeps, then K substeps bracketed by device syncs and
 hipEvents on the stream the library launches on.  A second pass of the same
 length with the library's event timer on gives each kernel's average launch
-duration; the dominant kernel's roofline uses that duration.  The CPU baseline
-is the FP64 oracle (serial C) on a bounded sample of the same workload.
+duration; the dominant kernel's roofline uses that duration.  With the slab
+workload the default run also measures the other forms: the 1M-particle slab
+(`large`, with its own roofline), the 256-environment batch (eager, graph
+and persistent launches), forward + adjoint, a rendered frame and other tool
+shapes.  The CPU baseline is the FP64 oracle, built -O3 -march=native on
+this host, threaded (per-thread node slabs, the serial result bit for bit)
+on the host cores this process may use, and serial, on bounded samples of
+the same workload.
 """
 from __future__ import annotations
 
@@ -84,10 +94,11 @@ def _events_ms(torch, fn):
     return a.elapsed_time(b)
 
 
-def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, tool_steps=200, frames=40,
+def measure_forms(torch, L, Sim, opts, tune, batched_steps=64, adj_steps=200, tool_steps=200, frames=40,
                   only=None):
-    """The other forms of the substep on the same GPU: the batched workload
-    (256 environments, launch options tuned for it when `tune`) and the
+    """The other forms of the substep on the same GPU: the 1M-particle slab,
+    the batched workload (256 environments, launch options tuned for it when
+    `tune`) and the
     differentiable slab (forward with tape + hand adjoint, checkpoints every
     20) against its plain forward with the slab's options, a rendered frame
     (25 substeps + the surface mesh into pinned host memory), and the slab
@@ -96,6 +107,8 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
     from paper_2402_01181_amd import scenes
     out = {}
     want = lambda name: only is None or only == name
+    if want("large"):
+        _form_large(torch, L, Sim, tune, out)
     if want("batched"):
         _form_batched(torch, L, Sim, opts, tune, batched_steps, out)
     if want("forward_adjoint"):
@@ -108,24 +121,43 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=40, adj_steps=200, to
 
 
 def _form_batched(torch, L, Sim, opts, tune, batched_steps, out):
+    """The 256-environment batch with the launch forms of the batched row:
+    per-phase launches (eager), the same captured in a hipGraph, and the
+    persistent kernel (a run of sort_every substeps per launch) replayed from
+    a graph.  Each window opens with a sort; the form's value is the fastest."""
     from paper_2402_01181_amd import scenes
     bsc = scenes.batched_scene()
     bopts = dict(opts)
     if tune:
         from paper_2402_01181_amd.autotune import autotune
         bopts.update(autotune(bsc))
-    bs = Sim(bsc, options=bopts)
-    bs.step(5)
-    ms = _events_ms(torch, lambda: bs.step(batched_steps))
+    se = window_sort_every(bopts.get(L.OPT_SORT_EVERY, L.OPT_DEFAULTS[L.OPT_SORT_EVERY]), batched_steps)
+    bs = Sim(bsc, options={**bopts, L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0})
     nb = bsc.n_particles
+    variants = {}
+    for name, graph, pers in (("eager", 0, 0), ("graph", 1, 0), ("persistent_graph", 1, 1)):
+        bs.set_option(L.OPT_GRAPH, graph)
+        bs.set_option(L.OPT_PERSISTENT, pers)
+        bs.set_option(L.OPT_SORT_EVERY, se)
+        bs.step(batched_steps)        # warm-up (captures the graph)
+        ms = timed_substeps(torch, L, bs, batched_steps, 0, se)
+        variants[name] = {"graph": graph, "persistent": pers, "ms_per_substep": ms / batched_steps,
+                          "value": nb * batched_steps / (ms * 1e-3)}
+    bs.set_option(L.OPT_GRAPH, 0)
+    bs.set_option(L.OPT_PERSISTENT, 0)
     x = [bs.read(L.F_X, e, device=False).T for e in range(bs.n_envs)]
     nodes = sum(active_nodes(xx, int(bs.gn[e])) for e, xx in enumerate(x))
     bytes_step = nb * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
+    best = max(variants, key=lambda k: variants[k]["value"])
+    ms_sub = variants[best]["ms_per_substep"]
     out["batched"] = {"workload": "256 environments, 5K-50K particles each (seeded), 32^3/64^3 grids, own capsules",
-                      "particles": nb, "substeps": batched_steps, "ms_per_substep": ms / batched_steps,
-                      "value": nb * batched_steps / (ms * 1e-3), "unit": "particle-substeps/s",
-                      "algorithmic_GBps": bytes_step / (ms / batched_steps * 1e-3) / 1e9,
-                      "hbm_frac": bytes_step / (ms / batched_steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "particles": nb, "substeps": batched_steps, "sort_every": se,
+                      "sorts_in_window": 1 + (batched_steps - 1) // se, "used": best,
+                      "graph": variants[best]["graph"], "persistent": variants[best]["persistent"],
+                      "ms_per_substep": ms_sub, "value": variants[best]["value"], "unit": "particle-substeps/s",
+                      "algorithmic_GBps": bytes_step / (ms_sub * 1e-3) / 1e9,
+                      "hbm_frac": bytes_step / (ms_sub * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "variants": variants,
                       "options": {str(k): v for k, v in bopts.items()},
                       "status": int(any(bs.read(L.F_STATUS, e) for e in range(bs.n_envs)))}
     bs.close()
@@ -245,26 +277,143 @@ def stored_traffic(config: str, kernel: str, options) -> float | None:
     return None if k is None else float(k["bytes_per_dispatch"])
 
 
-def cpu_baseline(scene, substeps: int):
-    """The FP64 oracle as it stands, serial, on the first `substeps` substeps of
-    environment 0 of the same scene."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _usable_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(scene, substeps: int, serial_substeps: int):
+    """The FP64 oracle as it stands (built -O3 -march=native here) on the
+    first substeps of environment 0 of the same scene: threaded over the
+    host cores this process may use (at most 16, the host share of one GPU),
+    and serial on a shorter sample."""
+    import tempfile
     from oracle import oracle
-    oracle.lib()
+    lib = os.path.join(tempfile.mkdtemp(prefix="mpm_oracle_native_"), "libmpm_oracle_native.so")
+    oracle.use_library(oracle.build(force=True, out=lib, native=True))
     env = scene.envs[0]
+    threads = max(1, min(16, _usable_cores()))
     sim = oracle.Sim(env, scene.dt, gravity=scene.gravity, bound=scene.bound)
     t0 = time.perf_counter()
-    sim.run(substeps)
-    dt = time.perf_counter() - t0
-    return {"value": env.N * substeps / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"environment 0 ({env.N} particles, {env.n}^3 grid), first {substeps} substeps, "
-                      f"FP64 serial C, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+    sim.run(substeps, threads=threads)
+    dt_t = time.perf_counter() - t0
+    ser = oracle.Sim(env, scene.dt, gravity=scene.gravity, bound=scene.bound)
+    t0 = time.perf_counter()
+    ser.run(serial_substeps)
+    dt_s = time.perf_counter() - t0
+    model = _cpu_model()
+    return {"value": env.N * substeps / dt_t, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"environment 0 ({env.N} particles, {env.n}^3 grid), first {substeps} substeps, FP64 C "
+                      f"(gcc -O3 -march=native) on {threads} OpenMP threads, {dt_t:.1f} s",
+            "cpu_model": model, "nproc": os.cpu_count(), "usable_cores": _usable_cores(),
+            "serial": {"value": env.N * serial_substeps / dt_s, "substeps": serial_substeps, "seconds": dt_s,
+                       "cores": 1}}
+
+
+def _roofline(rep, N, nodes, K, traffic):
+    """Roofline of the dominant kernel (by total time) from the library's
+    event timer: algorithmic bytes per launch over its average duration."""
+    dom = max(rep, key=lambda k: rep[k][0])
+    t_ms, n_launch = rep[dom]
+    avg_s = t_ms / n_launch * 1e-3
+    if dom.startswith("persistent"):
+        # one launch runs a whole run of substeps between sorts
+        per_launch = (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) * K / n_launch
+    elif dom.startswith("fused"):
+        per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_FUSED
+    elif dom.startswith("grid"):
+        per_launch = nodes * BYTES_PER_NODE_GRID
+    else:
+        per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
+    achieved = per_launch / avg_s / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic(dom),
+            "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
+
+
+def timed_substeps(torch, L, sim, K, W, sort_every):
+    """W untimed substeps, then K timed substeps that open with a sort (the
+    sort schedule restarts) and sort every `sort_every` after it.  Returns
+    the window's milliseconds."""
+    if W:
+        sim.step(W)
+    sim.set_option(L.OPT_SORT_EVERY, sort_every)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def event_pass(torch, L, sim, K, sort_every):
+    """The same K substeps again (opening with a sort) with the library's
+    event timer on: {kernel: (total ms, launches)}."""
+    sim.set_option(L.OPT_GRAPH, 0)   # the event timer brackets eager launches
+    sim.set_option(L.OPT_SORT_EVERY, sort_every)
+    sim.profile(True)
+    sim.step(K)
+    torch.cuda.synchronize()
+    sim.profile(False)
+    return sim.profile_report()
+
+
+def window_sort_every(tuned: int, K: int) -> int:
+    """The sort interval used in a window of K substeps: the tuned one, or K
+    when the window is shorter (one sort per interval, as in a long run)."""
+    return min(int(tuned), int(K))
+
+
+def _form_large(torch, L, Sim, tune, out, steps=64, warmup=10):
+    """The 1,048,576-particle slab on 128^3 (the metric's second size):
+    throughput over a window that opens with a sort, and the dominant
+    kernel's roofline from the event pass."""
+    from paper_2402_01181_amd import scenes
+    sc = scenes.large_slab_scene()
+    lopts = {L.OPT_SCHEME: L.SCHEME_TILED}
+    if tune:
+        from paper_2402_01181_amd.autotune import autotune
+        lopts.update(autotune(sc))
+    se = window_sort_every(lopts.get(L.OPT_SORT_EVERY, L.OPT_DEFAULTS[L.OPT_SORT_EVERY]), steps)
+    ls = Sim(sc, options=lopts)
+    ms = timed_substeps(torch, L, ls, steps, warmup, se)
+    N = sc.n_particles
+    nodes = active_nodes(ls.read(L.F_X, 0, device=False).T, int(ls.gn[0]))
+    rep = event_pass(torch, L, ls, steps, se)
+    kernels = {k: {"avg_us": 1e3 * t / n, "launches": n, "total_ms": t} for k, (t, n) in rep.items()}
+    roof = _roofline(rep, N, nodes, steps, lambda k: stored_traffic("large", k, ls.options))
+    out["large"] = {"workload": "large slab 1,048,576 particles, 128^3 grid, sticky capsule pull along a "
+                                "4-leg path at 0.2 m/s, dt 2e-5",
+                    "particles": N, "substeps": steps, "sort_every": se, "sorts_in_window": 1 + (steps - 1) // se,
+                    "ms_per_substep": ms / steps, "value": N * steps / (ms * 1e-3), "unit": "particle-substeps/s",
+                    "active_nodes": nodes,
+                    "algorithmic_GBps": (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) / (ms / steps * 1e-3) / 1e9,
+                    "roofline": roof, "kernels": kernels,
+                    "options": {str(k): v for k, v in ls.options.items()}, "status": int(ls.read(L.F_STATUS))}
+    ls.close()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=1024)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="slab")
     ap.add_argument("--scheme", default="tiled", choices=["tiled", "direct"])
     ap.add_argument("--sort-every", type=int, default=None)
@@ -280,7 +429,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (launch options: library defaults plus the flags given)")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
-    ap.add_argument("--only-form", default=None, choices=["batched", "forward_adjoint", "frame", "tool_shapes"],
+    ap.add_argument("--only-form", default=None,
+                    choices=["large", "batched", "forward_adjoint", "frame", "tool_shapes"],
                     help="run just this form of the slab workload with default launch options and print it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
@@ -323,21 +473,15 @@ def main():
     sim = Sim(scene, options=opts)
     N = scene.n_particles
     K, W = args.steps, args.warmup
+    se = window_sort_every(sim.options.get(L.OPT_SORT_EVERY, L.OPT_DEFAULTS[L.OPT_SORT_EVERY]), K) \
+        if args.scheme == "tiled" else sim.options.get(L.OPT_SORT_EVERY, L.OPT_DEFAULTS[L.OPT_SORT_EVERY])
+    sorts = 1 + (K - 1) // se if args.scheme == "tiled" else 0
 
-    print(f"# bench: {workload}; N={N}; warmup {W}, timed {K} substeps", file=sys.stderr, flush=True)
-    if W:
-        sim.step(W)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(K)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    print(f"# bench: {workload}; N={N}; warmup {W}, timed {K} substeps opening with a sort, sort every {se} "
+          f"({sorts} sorts in the window)", file=sys.stderr, flush=True)
+    ms = timed_substeps(torch, L, sim, K, W, se)
     value = N * K / (ms * 1e-3)
-    print(f"# timed: {ms:.2f} ms, {value:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+    print(f"# timed: {ms:.3f} ms, {value:.4g} particle-substeps/s", file=sys.stderr, flush=True)
 
     status = [sim.read(L.F_STATUS, e) for e in range(sim.n_envs)]
     x_final = [sim.read(L.F_X, e, device=False).T for e in range(sim.n_envs)]
@@ -345,30 +489,9 @@ def main():
 
     roofline, kernels = None, {}
     if not args.no_profile_pass:
-        sim.set_option(L.OPT_GRAPH, 0)   # the event timer brackets eager launches
-        sim.profile(True)
-        sim.step(K)
-        torch.cuda.synchronize()
-        sim.profile(False)
-        rep = sim.profile_report()
+        rep = event_pass(torch, L, sim, K, se)
         kernels = {k: {"avg_us": 1e3 * t / n, "launches": n, "total_ms": t} for k, (t, n) in rep.items()}
-        dom = max(rep, key=lambda k: rep[k][0])
-        t_ms, n_launch = rep[dom]
-        avg_s = t_ms / n_launch * 1e-3
-        if dom.startswith("persistent"):
-            # one launch runs a whole run of substeps between sorts
-            per_launch = (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) * (
-                rep.get("persistent_tiled", (0, 1))[1] and K / rep["persistent_tiled"][1])
-        elif dom.startswith("fused"):
-            per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_FUSED
-        elif dom.startswith("grid"):
-            per_launch = nodes * BYTES_PER_NODE_GRID
-        else:
-            per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
-        achieved = per_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(args.config, dom, sim.options),
-                    "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
+        roofline = _roofline(rep, N, nodes, K, lambda k: stored_traffic(args.config, k, sim.options))
         print(f"# kernels: " + ", ".join(f"{k} {v['avg_us']:.2f}us x{v['launches']}" for k, v in kernels.items()),
               file=sys.stderr, flush=True)
 
@@ -381,9 +504,13 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        default_cpu = {"slab": 1500, "large": 40, "cube": 200, "batched": 600}
-        cpu = cpu_baseline(scene, args.cpu_substeps or default_cpu.get(args.config, 50))
-        print(f"# cpu baseline: {cpu['value']:.4g} particle-substeps/s", file=sys.stderr, flush=True)
+        default_cpu = {"slab": (1000, 300), "large": (20, 10), "cube": (200, 200), "batched": (400, 200)}
+        sub, ser = default_cpu.get(args.config, (50, 50))
+        if args.cpu_substeps:
+            sub = ser = args.cpu_substeps
+        cpu = cpu_baseline(scene, sub, ser)
+        print(f"# cpu baseline: {cpu['value']:.4g} particle-substeps/s on {cpu['cores']} threads "
+              f"({cpu['cpu_model']}), serial {cpu['serial']['value']:.4g}", file=sys.stderr, flush=True)
 
     out = {
         "metric": "particle-substeps/sec",
@@ -400,6 +527,7 @@ def main():
         "data": "synthetic (seeded particles in a box, analytic capsule tool)",
         "config": {"workload": workload, "config": args.config, "particles": N,
                    "grid": [int(g) for g in sim.gn[:4]], "envs": sim.n_envs, "substeps_timed": K,
+                   "sort_every": se, "sorts_in_window": sorts,
                    "scheme": args.scheme, "options": {str(k): v for k, v in sim.options.items()},
                    "active_nodes": nodes,
                    "algorithmic_bytes_per_substep": N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP},
