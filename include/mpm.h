@@ -12,8 +12,9 @@
  * Conventions shared by every entry point:
  *  - Device memory is owned by the CALLER: initial state, material table,
  *    tool trajectories, gradient outputs and the single workspace the
- *    library carves all its device buffers from.  The library owns only the
- *    host-side context object.  It never calls hipMalloc/hipFree.
+ *    library carves all its device buffers from (mpm_create_static takes the
+ *    workspace from a device array inside the library instead).  The library
+ *    owns only the host-side context object.  It never calls hipMalloc/hipFree.
  *  - Streams are hipStream_t passed as void*; NULL means the null stream.
  *    A context is used from one stream at a time and is not thread-safe.
  *  - Particle arrays are FP32, structure-of-arrays, component-major and
@@ -199,7 +200,32 @@ size_t mpm_workspace_size(const mpm_desc *desc);
 mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_bytes, void *stream,
                       mpm_ctx **out);
 
-/* Release the host object.  NULL is a no-op.  Does not touch the workspace. */
+/* Size of the workspace mpm_create_static uses (64 MiB per device). */
+#define MPM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops and harnesses that forbid hipMalloc): mpm_create
+ * with the workspace taken from a device array inside the library instead of
+ * a caller allocation.  The array holds MPM_STATIC_WORKSPACE_BYTES; each GPU
+ * the library runs on keeps its own copy until the process ends.  The context
+ * lives on the current device; desc, stream and out as for mpm_create, and
+ * the context is used and released exactly like one from mpm_create.
+ *  - A description needing more than MPM_STATIC_WORKSPACE_BYTES
+ *    (mpm_workspace_size) returns MPM_E_WORKSPACE and creates nothing.
+ *  - A device's array serves one context at a time: while a context made by
+ *    this call is alive on the device, another call on it returns
+ *    MPM_E_STATE.  Work of two contexts sharing one array would race, and
+ *    this keeps them apart.  mpm_destroy frees the array for the next call.
+ *  - The array keeps what the previous context left there; creation clears
+ *    everything that must start at zero, as mpm_create does for a fresh
+ *    caller workspace.
+ *  - Calls no hipMalloc/hipFree or other allocating routine.  The first call
+ *    on a device looks up the array's device address (hipGetSymbolAddress). */
+mpm_status mpm_create_static(const mpm_desc *desc, void *stream, mpm_ctx **out);
+
+/* Release the host object.  NULL is a no-op.  Does not touch the workspace
+ * (of a mpm_create_static context: frees the device's static workspace for
+ * the next mpm_create_static). */
 void mpm_destroy(mpm_ctx *ctx);
 
 /* Set tool slot `tool` of environment `env` (Sec. III-C): shape, contact

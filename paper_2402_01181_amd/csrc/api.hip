@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "mpm_ctx.h"
@@ -11,6 +12,14 @@
 using namespace mpm;
 
 static thread_local std::string g_last_error = "no error";
+
+// Workspace of mpm_create_static: a device array of MPM_STATIC_WORKSPACE_BYTES
+// in the library's code object, so each GPU the library runs on holds its own
+// copy until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.  One context at a time may use a device's copy.
+static __device__ __align__(256) unsigned char scratch[MPM_STATIC_WORKSPACE_BYTES];
 
 namespace {
 
@@ -662,7 +671,11 @@ size_t mpm_workspace_size(const mpm_desc *desc)
     }
 }
 
-mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_bytes, void *stream, mpm_ctx **out)
+}  // extern "C"
+
+namespace {
+
+mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_bytes, void *stream, mpm_ctx **out)
 {
     try {
         if (!out) return fail(nullptr, MPM_E_ARG, "out is NULL");
@@ -789,8 +802,68 @@ mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_by
     }
 }
 
+constexpr int MAX_STATIC_DEVICES = 64;
+struct StaticWorkspace {
+    void *ptr = nullptr;   // device address of this device's `scratch`
+    bool in_use = false;   // a live context was created in it
+};
+std::mutex g_static_mu;
+StaticWorkspace g_static[MAX_STATIC_DEVICES];
+
+}  // namespace
+
+extern "C" {
+
+mpm_status mpm_create(const mpm_desc *desc, void *workspace, size_t workspace_bytes, void *stream, mpm_ctx **out)
+{
+    return create_in(desc, workspace, workspace_bytes, stream, out);
+}
+
+mpm_status mpm_create_static(const mpm_desc *desc, void *stream, mpm_ctx **out)
+{
+    try {
+        if (!out) return fail(nullptr, MPM_E_ARG, "out is NULL");
+        *out = nullptr;
+        const size_t need = mpm_workspace_size(desc);
+        if (need == 0) return fail(nullptr, MPM_E_ARG, g_last_error);
+        if (need > MPM_STATIC_WORKSPACE_BYTES)
+            return fail(nullptr, MPM_E_WORKSPACE,
+                        "this description needs " + std::to_string(need) + " bytes of workspace; the static "
+                        "workspace holds " + std::to_string((size_t)MPM_STATIC_WORKSPACE_BYTES) +
+                        " (use mpm_create with a caller-allocated workspace)");
+        int dev = 0;
+        HIP_TRY(nullptr, hipGetDevice(&dev));
+        if (dev < 0 || dev >= MAX_STATIC_DEVICES)
+            return fail(nullptr, MPM_E_UNSUPPORTED, "static workspace: device index beyond " +
+                                                        std::to_string(MAX_STATIC_DEVICES - 1));
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        StaticWorkspace &w = g_static[dev];
+        if (!w.ptr) {
+            void *p = nullptr;
+            HIP_TRY(nullptr, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (!p || (reinterpret_cast<uintptr_t>(p) & 255))
+                return fail(nullptr, MPM_E_HIP, "static workspace: no 256-byte aligned device address");
+            w.ptr = p;
+        }
+        if (w.in_use)
+            return fail(nullptr, MPM_E_STATE, "the static workspace of device " + std::to_string(dev) +
+                                                  " is held by a live context; destroy it first");
+        mpm_status r = create_in(desc, w.ptr, MPM_STATIC_WORKSPACE_BYTES, stream, out);
+        if (r != MPM_OK) return r;
+        w.in_use = true;
+        (*out)->static_dev = dev;
+        return MPM_OK;
+    } catch (...) {
+        return fail(nullptr, MPM_E_ARG, "internal error in mpm_create_static");
+    }
+}
+
 void mpm_destroy(mpm_ctx *ctx)
 {
+    if (ctx && ctx->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static[ctx->static_dev].in_use = false;
+    }
     delete ctx;
 }
 

@@ -44,6 +44,7 @@ struct GraphEntry {
 
 struct mpm_ctx {
     std::string err;
+    int static_dev = -1;             // device whose static workspace holds the buffers (mpm_create_static)
     // configuration
     int n_envs = 0, max_tools = 0, ntot = 0, bound = 0;
     float dt = 0.f, g[3] = {0.f, 0.f, 0.f};

@@ -28,7 +28,10 @@ class Sim:
     """All environments of a scene in one context on one GPU."""
 
     def __init__(self, scene, device="cuda", max_tape: int = 0, checkpoint_every: int = 20,
-                 options: Optional[Dict[int, int]] = None, stream=None):
+                 options: Optional[Dict[int, int]] = None, stream=None, static_workspace: bool = False):
+        """static_workspace: create the context with mpm_create_static (the
+        library's own per-device workspace of STATIC_WORKSPACE_BYTES; one such
+        context per device at a time) instead of a torch-allocated workspace."""
         if not torch.cuda.is_available():
             raise RuntimeError("a ROCm GPU is required (there is no CPU path)")
         self.lib = L.load()
@@ -59,7 +62,8 @@ class Sim:
         if size == 0:
             raise L.MpmError(L.MPM_E_ARG, self.lib.mpm_last_error(None).decode())
         self.workspace_bytes = size
-        self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        self.static_workspace = bool(static_workspace)
+        self.workspace = None if self.static_workspace else torch.empty(size + 256, dtype=torch.uint8, device=dev)
         self.max_tape = int(max_tape)
         self.options = dict(options or {})
         self.traj = {}
@@ -68,10 +72,14 @@ class Sim:
         self._create(stream)
 
     def _create(self, stream=None):
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
-        L.check(self.lib.mpm_create(ct.byref(self.desc), ct.c_void_p(aligned), self.workspace_bytes,
-                                    _stream_ptr(stream), ct.byref(self.ctx)))
+        if self.static_workspace:
+            with torch.cuda.device(self.device):
+                L.check(self.lib.mpm_create_static(ct.byref(self.desc), _stream_ptr(stream), ct.byref(self.ctx)))
+        else:
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            L.check(self.lib.mpm_create(ct.byref(self.desc), ct.c_void_p(aligned), self.workspace_bytes,
+                                        _stream_ptr(stream), ct.byref(self.ctx)))
         for e, env in enumerate(self.scene.envs):
             for k, tool in enumerate(env.tools):
                 self.set_tool(e, k, tool, traj=self.traj.get((e, k)))
