@@ -123,8 +123,9 @@ def measure_forms(torch, L, Sim, opts, tune, batched_steps=64, adj_steps=200, to
 def _form_batched(torch, L, Sim, opts, tune, batched_steps, out):
     """The 256-environment batch with the launch forms of the batched row:
     per-phase launches (eager), the same captured in a hipGraph, and the
-    persistent kernel (a run of sort_every substeps per launch) replayed from
-    a graph.  Each window opens with a sort; the form's value is the fastest."""
+    persistent kernel (a run of sort_every substeps per launch, a barrier per
+    environment group), launched directly or replayed from a graph.  Each
+    window opens with a sort; the form's value is the fastest variant."""
     from paper_2402_01181_amd import scenes
     bsc = scenes.batched_scene()
     bopts = dict(opts)
@@ -135,7 +136,7 @@ def _form_batched(torch, L, Sim, opts, tune, batched_steps, out):
     bs = Sim(bsc, options={**bopts, L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0})
     nb = bsc.n_particles
     variants = {}
-    for name, graph, pers in (("eager", 0, 0), ("graph", 1, 0), ("persistent_graph", 1, 1)):
+    for name, graph, pers in (("eager", 0, 0), ("graph", 1, 0), ("persistent", 0, 1), ("persistent_graph", 1, 1)):
         bs.set_option(L.OPT_GRAPH, graph)
         bs.set_option(L.OPT_PERSISTENT, pers)
         bs.set_option(L.OPT_SORT_EVERY, se)
@@ -431,7 +432,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
     ap.add_argument("--only-form", default=None,
                     choices=["large", "batched", "forward_adjoint", "frame", "tool_shapes"],
-                    help="run just this form of the slab workload with default launch options and print it")
+                    help="run just this form (launch options as in the default run; library defaults with "
+                         "--no-autotune) and print it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -446,7 +448,12 @@ def main():
     from paper_2402_01181_amd.sim import Sim
 
     if args.only_form:
-        forms = measure_forms(torch, L, Sim, {L.OPT_SCHEME: L.SCHEME_TILED}, False, only=args.only_form)
+        fopts = {L.OPT_SCHEME: L.SCHEME_TILED}
+        if not args.no_autotune:
+            # the slab's launch options, as the default run passes them to the forms
+            from paper_2402_01181_amd.autotune import autotune
+            fopts.update(autotune(make_scene("slab")[0], verbose=False))
+        forms = measure_forms(torch, L, Sim, fopts, not args.no_autotune, only=args.only_form)
         print(json.dumps(forms), flush=True)
         return
 

@@ -62,7 +62,7 @@ enum {
     MPM_FLAG_OUT_OF_DOMAIN = 1u,    /* a particle's 3x3x3 stencil left the grid; it was frozen */
     MPM_FLAG_INVERTED = 2u,         /* det F <= 1e-6 (FP64); the stress used ln(1e-6) */
     MPM_FLAG_NONFINITE = 4u,        /* a particle position or velocity became non-finite */
-    MPM_FLAG_BARRIER_TIMEOUT = 8u   /* persistent kernel: a grid barrier exceeded its spin limit */
+    MPM_FLAG_BARRIER_TIMEOUT = 8u   /* persistent kernel: a group barrier exceeded its spin limit */
 };
 
 /* Fields for mpm_read_state. */
@@ -126,8 +126,13 @@ enum {
     MPM_OPT_BLOCK = 2,        /* threads per workgroup of the tiled particle kernels: 64, 128, 256 */
     MPM_OPT_GRAPH = 3,        /* 1: mpm_substep replays an internally captured hipGraph */
     MPM_OPT_PERSISTENT = 4,   /* tiled scheme, 1: each run of up to sort_every substeps is one persistent
-                                 kernel (grid operation and particle pass separated by grid barriers with
-                                 a bounded spin; a timeout sets MPM_FLAG_BARRIER_TIMEOUT) */
+                                 kernel.  Every environment gets its own group of workgroups (in
+                                 proportion to its particles; small environments share one) and steps
+                                 through the run alone: grid operation, then particle pass, separated by
+                                 barriers of that group only (a counter per environment, bounded spin; a
+                                 timeout sets MPM_FLAG_BARRIER_TIMEOUT).  Setting it (or the block or
+                                 item size while it is on) builds the group table with a synchronous
+                                 copy, so set it outside stream capture */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
     MPM_OPT_ITEM = 6,         /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
     MPM_OPT_NODE_SLOTS = 7    /* tiled scheme: particles per half-wavefront step of the P2G node pass, 1 or 3

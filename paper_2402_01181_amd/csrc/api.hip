@@ -91,8 +91,10 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.act.brick_env = c.brick_env;
     c.env_bofs = cv.take<int32_t>(s.n_envs + 1);
     c.act.env_bofs = c.env_bofs;
-    c.barrier.count = cv.take<unsigned>(1);
-    c.barrier.gen = cv.take<unsigned>(1);
+    c.wg_tab = cv.take<int4>(MAX_PERSISTENT_WG);
+    c.arrive = cv.take<unsigned>((size_t)2 * s.n_envs);
+    c.ecount = c.arrive ? reinterpret_cast<int32_t *>(c.arrive + s.n_envs) : nullptr;
+    c.elist = cv.take<int32_t>(s.total_bricks);
     // adjoint tape
     if (s.max_tape > 0) {
         const size_t st24 = (size_t)24 * s.ntot;
@@ -137,7 +139,7 @@ bool all_carved(const mpm_ctx &c)
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
                        c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
-                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.barrier.count, c.barrier.gen, c.act.env_bofs,
+                       c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.wg_tab, c.arrive, c.elist, c.act.env_bofs,
                        c.surf.rho, c.surf.ofs, c.surf.chunk, c.surf.table};
     for (const void *q : p)
         if (!q) return false;
@@ -307,6 +309,120 @@ int grid_blocks(const mpm_ctx *c)
     return (int)std::max<int64_t>(8, std::min<int64_t>(b, 16384));
 }
 
+// Work of each environment in one substep of the persistent kernel, in
+// particle-equivalents, from the current positions (counted on the host):
+// its particles, a fixed cost per work item (bricks it occupies, at most
+// `item` particles per item) and per brick of the static neighbourhood the
+// grid operation visits.  The kernel's own per-item split uses the same
+// fixed cost.
+mpm_status work_estimate(mpm_ctx *c, std::vector<int64_t> &work)
+{
+    std::vector<float> x((size_t)3 * c->ntot);
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(x.data(), c->x, x.size() * sizeof(float), hipMemcpyDeviceToHost));
+    const size_t N = c->ntot;
+    work.assign(c->n_envs, 0);
+    std::vector<int32_t> cnt;
+    std::vector<uint8_t> near;
+    for (int e = 0; e < c->n_envs; ++e) {
+        const int n = c->gn[e], nb = n / 4;
+        cnt.assign((size_t)nb * nb * nb, 0);
+        for (int p = c->pofs[e]; p < c->pofs[e + 1]; ++p) {
+            int t[3];
+            for (int a = 0; a < 3; ++a) {
+                const float v = x[a * N + p] * n - 0.5f;
+                t[a] = std::isfinite(v) ? (int)std::floor(std::min(std::max(v, 0.0f), (float)(n - 3))) : 0;
+            }
+            ++cnt[((size_t)(t[0] >> 2) * nb + (t[1] >> 2)) * nb + (t[2] >> 2)];
+        }
+        near.assign(cnt.size(), 0);
+        int64_t items = 0, bricks = 0;
+        for (int bi = 0; bi < nb; ++bi)
+            for (int bj = 0; bj < nb; ++bj)
+                for (int bk = 0; bk < nb; ++bk) {
+                    const int k = cnt[((size_t)bi * nb + bj) * nb + bk];
+                    if (!k) continue;
+                    items += (k + c->item - 1) / c->item;
+                    for (int a = std::max(bi - 1, 0); a <= std::min(bi + 1, nb - 1); ++a)
+                        for (int b = std::max(bj - 1, 0); b <= std::min(bj + 1, nb - 1); ++b)
+                            for (int q = std::max(bk - 1, 0); q <= std::min(bk + 1, nb - 1); ++q)
+                                near[((size_t)a * nb + b) * nb + q] = 1;
+                }
+        for (uint8_t f : near) bricks += f;
+        work[e] = c->np[e] + (int64_t)ITEM_FIXED_COST * items + 16 * bricks;
+    }
+    return MPM_OK;
+}
+
+// Environment groups of the persistent kernel for the current block and item
+// sizes.  Each environment gets workgroups in proportion to the work items of
+// its particles (at least one, at most one per item); when there are more
+// environments than workgroups, consecutive environments share one workgroup
+// (a group of one member, which never waits).  Host computation and
+// synchronous copies: called from mpm_set_option, never under stream capture.
+mpm_status build_groups(mpm_ctx *c)
+{
+    c->groups_n = 0;
+    c->groups_block = c->block;
+    c->groups_item = c->item;
+    const int G = std::min(persistent_workgroups(c->block), MAX_PERSISTENT_WG);
+    if (G <= 0) return MPM_OK;   // occupancy unknown: the persistent option falls back to per-phase launches
+    const int E = c->n_envs;
+    std::vector<int4> tab;
+    std::vector<int64_t> work;
+    if (mpm_status r = work_estimate(c, work)) return r;
+    int64_t total = 0;
+    for (int e = 0; e < E; ++e) total += work[e];
+    if (E > G) {
+        // consecutive environments per workgroup, each filled to about the
+        // particles left over the workgroups left; the last takes the rest
+        double left = (double)total;
+        int e = 0;
+        for (int b = 0; b < G && e < E; ++b) {
+            const double target = left / (G - b);
+            const int first = e;
+            double w = 0.0;
+            do {
+                w += work[e];
+                ++e;
+            } while (e < E && (b == G - 1 || w + 0.5 * work[e] <= target));
+            left -= w;
+            tab.push_back(make_int4(first, e - first, 0, 1));
+        }
+    } else {
+        std::vector<int> g(E);
+        int used = 0;
+        for (int e = 0; e < E; ++e) {
+            const int cap = std::max(1, (int)(work[e] / (c->item + ITEM_FIXED_COST)) + 1);
+            g[e] = std::min(cap, std::max(1, (int)((double)G * work[e] / total)));
+            used += g[e];
+        }
+        while (used > G) {   // at least one each: take back from the largest groups
+            int big = 0;
+            for (int e = 1; e < E; ++e) if (g[e] > g[big]) big = e;
+            --g[big]; --used;
+        }
+        for (bool grew = true; used < G && grew;) {   // spare workgroups to the most loaded groups
+            grew = false;
+            int best = -1;
+            double load = 0.0;
+            for (int e = 0; e < E; ++e) {
+                const int cap = std::max(1, (int)(work[e] / (c->item + ITEM_FIXED_COST)) + 1);
+                if (g[e] >= cap) continue;
+                const double l = (double)work[e] / g[e];
+                if (l > load) { load = l; best = e; }
+            }
+            if (best >= 0) { ++g[best]; ++used; grew = true; }
+        }
+        for (int e = 0; e < E; ++e)
+            for (int r = 0; r < g[e]; ++r) tab.push_back(make_int4(e, 1, r, g[e]));
+    }
+    const int n = (int)tab.size();
+    HIP_TRY(c, hipMemcpy(c->wg_tab, tab.data(), sizeof(int4) * n, hipMemcpyHostToDevice));
+    c->groups_n = n;
+    return MPM_OK;
+}
+
 // n substeps of the tiled scheme:
 //   [sort] head P2G, then n x (grid op, fused G2P+P2G) with the last fused
 //   step replaced by a G2P-only tail that materialises v and C.
@@ -324,32 +440,38 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         sort_into_alt(c, st);
         in = c->alt;
     }
+    const bool pers = c->persistent && c->groups_n > 0 && c->groups_block == c->block && c->groups_item == c->item;
+    if (pers) {
+        // runs of up to sort_every substeps, one persistent launch each, sorts in
+        // between; the kernel finds far-drift bricks by their flags (no dynamic lists)
+        auto args = [&](const ParticleBuf &i, const ParticleBuf &o) {
+            TiledArgs a = tiled_args(c, i, o, 0);
+            a.act.elist = c->elist;
+            a.act.ecount = c->ecount;
+            return a;
+        };
+        timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, args(in, in), c->block, nb, st); });
+        const EnvGroups g{c->wg_tab, c->arrive, c->sort, c->total_bricks};
+        for (int done = 0; done < n;) {
+            if (done > 0) {
+                sort_into_alt(c, st);
+                in = c->alt;
+            }
+            const int m = std::min(n - done, c->sort_every);
+            const int tail = done + m == n;
+            timed(c, st, PK_FILL, [&] { launch_fill_u32(c->arrive, 2 * c->n_envs, 0u, st); });
+            timed(c, st, PK_PERSISTENT, [&] {
+                launch_persistent(d, args(in, A), args(A, A), g, m, tail, c->spin_limit, c->has_sdf, c->block,
+                                  c->groups_n, st);
+            });
+            in = A;
+            done += m;
+            c->since_sort = m;
+        }
+        return;
+    }
     // substep i: P2G lists far bricks in dynamic list i&1, its grid operation consumes it
     timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, nb, st); });
-    if (c->persistent) {
-        if (c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
-        const int pb = c->persistent_blocks;
-        if (pb > 0) {
-            // runs of up to sort_every substeps, one persistent launch each, sorts in between
-            for (int done = 0; done < n;) {
-                if (done > 0) {
-                    sort_into_alt(c, st);
-                    in = c->alt;
-                }
-                const int m = std::min(n - done, c->sort_every);
-                const int tail = done + m == n;
-                TiledArgs first = tiled_args(c, in, A, 0), rest = tiled_args(c, A, A, 0);
-                timed(c, st, PK_FILL, [&] { launch_fill_u32(c->barrier.count, 1, 0u, st); });
-                timed(c, st, PK_PERSISTENT, [&] {
-                    launch_persistent(d, first, rest, m, done & 1, tail, c->barrier, c->spin_limit, c->block, pb, st);
-                });
-                in = A;
-                done += m;
-                c->since_sort = m;
-            }
-            return;
-        }
-    }
     for (int i = 0; i < n; ++i) {
         timed(c, st, PK_GRID_ACTIVE, [&] { launch_grid_active(d, c->act, i & 1, grid_blocks(c), c->has_sdf, st); });
         if (i == n - 1) {
@@ -402,7 +524,6 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
         g.persistent = c->persistent;
         g.node_slots = c->node_slots;
         g.sdf = c->has_sdf;
-        if (c->persistent && c->persistent_blocks < 0) c->persistent_blocks = persistent_workgroups(c->block);
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -791,8 +912,7 @@ mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_byt
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.scount), 1, 0u, st);
         launch_brick_env(c->env_bofs, s.n_envs, s.total_bricks, c->brick_env, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.dcount), 2, 0u, st);
-        launch_fill_u32(c->barrier.count, 1, 0u, st);
-        launch_fill_u32(c->barrier.gen, 1, 0u, st);
+        launch_fill_u32(c->arrive, 2 * s.n_envs, 0u, st);
         if ((e2 = hipGetLastError()) != hipSuccess) return cleanup_fail(e2, "init kernels");
         if ((e2 = hipStreamSynchronize(st)) != hipSuccess) return cleanup_fail(e2, "create sync");
         *out = c;
@@ -947,12 +1067,11 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         if (value != 64 && value != 128 && value != 256) return fail(c, MPM_E_ARG, "block must be 64, 128 or 256");
         c->block = value;
         c->tiled_blocks = 0;
-        c->persistent_blocks = -1;
-        return MPM_OK;
+        return c->persistent ? build_groups(c) : MPM_OK;
     case MPM_OPT_ITEM:
         if (value < 16 || value > 4096 || value % 16) return fail(c, MPM_E_ARG, "item size must be a multiple of 16 in [16, 4096]");
         c->item = value;
-        return MPM_OK;
+        return c->persistent ? build_groups(c) : MPM_OK;
     case MPM_OPT_NODE_SLOTS:
         if (value != 1 && value != 3) return fail(c, MPM_E_ARG, "node slots must be 1 or 3");
         c->node_slots = value;
@@ -962,7 +1081,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         return MPM_OK;
     case MPM_OPT_PERSISTENT:
         c->persistent = value != 0;
-        return MPM_OK;
+        return c->persistent ? build_groups(c) : MPM_OK;
     case MPM_OPT_SPIN_LIMIT:
         if (value < 1) return fail(c, MPM_E_ARG, "spin limit must be > 0");
         c->spin_limit = value;

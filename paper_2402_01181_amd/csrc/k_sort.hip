@@ -82,6 +82,7 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf 
 
 // Block-wide exclusive scan of int2 over 256 threads x 4 elements.
 constexpr int SCAN_T = 256, SCAN_E = 4, SCAN_CHUNK = SCAN_T * SCAN_E;
+static_assert(SCAN_CHUNK == SORT_SCAN_CHUNK, "brick scan chunk");
 
 __device__ __forceinline__ int2 add2(int2 a, int2 b) { return make_int2(a.x + b.x, a.y + b.y); }
 

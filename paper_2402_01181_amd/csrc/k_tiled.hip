@@ -14,6 +14,8 @@
 // Workgroups are persistent over the item list; workgroup w runs on XCD
 // w % 8 and walks a contiguous eighth of the (spatially ordered) items, so
 // neighbouring tiles, which share halo nodes, stay in one XCD's L2.
+#include <algorithm>
+
 #include "mpm_tile_util.h"
 
 namespace mpm {
@@ -32,6 +34,7 @@ __device__ __forceinline__ void advance_end_of_substep(const Dev &d)
 
 // G2P of one particle whose stencil is outside the item's tile (drift since
 // the sort): velocity and C = (4/dx) sum w v (o - fx)^T from global memory.
+template <bool COH>
 __device__ __forceinline__ void g2p_global(const Dev &d, const EnvDev &e, const Stencil &s, float vp[3], float Cn[9])
 {
     float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -42,7 +45,8 @@ __device__ __forceinline__ void g2p_global(const Dev &d, const EnvDev &e, const 
         for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
             for (int o2 = 0; o2 < 3; ++o2) {
-                const float4 V = gload(d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2));
+                const float4 *q = d.gV + node_id(e, s.b[0] + o0, s.b[1] + o1, s.b[2] + o2);
+                const float4 V = COH ? cload(q) : gload(q);
                 const float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
                 const float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
                 const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
@@ -98,8 +102,13 @@ struct TiledShared {
     Payload4 pay[64 * W];
 };
 
-template <int MODE, int W>
-__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W> &sh)
+// Items first, first + stride, ... below end.  COH (persistent kernel): node
+// velocities are read with device-coherent loads (other workgroups of the
+// same launch wrote them), and the tool poses and step counters are left to
+// the caller.
+template <int MODE, int W, bool COH = false>
+__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W> &sh, int first,
+                                           int stride, int end)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1 || MODE == 3;
     constexpr int T = 64 * W;
@@ -108,15 +117,28 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
-    const int nitems = gload(a.totals).y;
-    int first, stride, end;
-    item_range(nitems, first, stride, end);
     int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
+    // a single environment (and its material) is loaded once, beside the first
+    // item, so a tile's node loads wait for the item alone
+    const bool one_env = d.n_envs == 1;
+    EnvDev e1{};
+    float mat1[4] = {0.f, 0.f, 0.f, 0.f};
+    if (one_env) {
+        e1 = load_env(d.env);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mat1[c] = gload(d.material + c);
+    }
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
         EnvDev e;
-        const Tile t = make_tile(d, item, e);
+        Tile t;
+        if (one_env) {
+            e = e1;
+            t = tile_of(e, item);
+        } else {
+            t = make_tile(d, item, e);
+        }
         const int item_end = item.y + item.z;
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass
@@ -133,9 +155,14 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         prefetch(item.y);
         float mu = 0.f, lam = 0.f, m = 0.f, V0 = 0.f;
         if (P2G) {
-            const float *mat = d.material + 4 * t.env;
-            const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2);
-            V0 = gload(mat + 3);
+            float E, nu, rho;
+            if (one_env) {
+                E = mat1[0]; nu = mat1[1]; rho = mat1[2]; V0 = mat1[3];
+            } else {
+                const float *mat = d.material + 4 * t.env;
+                E = gload(mat); nu = gload(mat + 1); rho = gload(mat + 2);
+                V0 = gload(mat + 3);
+            }
             lame(E, nu, mu, lam);
             m = rho * V0;
         }
@@ -146,7 +173,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             if (G2P) {
                 int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                 float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
+                if (i < e.n && j < e.n && k < e.n) V = COH ? cload(d.gV + node_id(e, i, j, k)) : gload(d.gV + node_id(e, i, j, k));
                 tv[n] = V;
             }
         }
@@ -219,7 +246,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
                         } else {
-                            g2p_global(d, e, s, v, C);
+                            g2p_global<COH>(d, e, s, v, C);
                         }
                         x[0] += d.dt * v[0];
                         x[1] += d.dt * v[1];
@@ -290,7 +317,8 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     gatomic_add(g + 3, c4.w);
                     const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
                     if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1)
-                        mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2));
+                        mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2), t.env,
+                                       e.bofs);
                 });
             }
             if (P2G) __syncthreads();   // payload slots are rewritten by the next chunk
@@ -318,6 +346,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
         __syncthreads();
     }
+    if (COH) return;
     if (G2P) advance_end_of_substep(d);
     // the tail ends a call: both dynamic lists start empty at the next head
     if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.dcount) gstore(a.act.dcount + tid, 0);
@@ -327,7 +356,9 @@ template <int MODE, int W>
 __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 {
     __shared__ TiledShared<W> sh;
-    tiled_body<MODE, W>(d, a, sh);
+    int first, stride, end;
+    item_range(gload(a.totals).y, first, stride, end);
+    tiled_body<MODE, W>(d, a, sh, first, stride, end);
 }
 
 // Grid operation over the static brick list and dynamic list `par`: one
@@ -390,59 +421,190 @@ __global__ __launch_bounds__(256) void k_grid_active(Dev d, ActiveBuf a, int par
     grid_active_body<SDF>(d, a, par);
 }
 
-// Grid-wide barrier for the persistent kernel: arrival counter plus a
-// generation word, agent-scope release/acquire around it, and a bounded spin.
-// Returns false (and the caller exits) if the spin limit is reached, which
-// happens only if not every workgroup is resident.
-__device__ __forceinline__ bool grid_sync(const GridBarrier &b, int spin_limit, int &ok_shared)
+// ---------------------------------------------------------------------------
+// Persistent form: one launch runs m substeps (a run between two sorts) of
+// every environment.  Each environment has its own group of workgroups and
+// its own completion counter; the group alternates the grid operation over
+// the environment's flagged bricks and the particle pass over its items,
+// with a group barrier after each, so environments never wait for each
+// other.  The grid data that crosses workgroups inside the launch (momentum
+// P, velocity V, brick flags) moves only through device-coherent accesses
+// (float atomics, cload / cstore), so a barrier needs no cache write-back or
+// invalidation: a workgroup waits until its own memory operations have
+// completed, then adds one to the counter; the others wait for the count.
+// A workgroup keeps the particles of the same items through the run, so
+// particle state never crosses workgroups.
+
+// Barrier k (1, 2, ...) of a group of gsize workgroups on counter ctr.
+// Returns false, after setting MPM_FLAG_BARRIER_TIMEOUT, if the spin limit
+// ran out (some workgroup of the group is not resident).
+__device__ __forceinline__ bool group_barrier(const Dev &d, int env, unsigned *ctr, unsigned target, int spin_limit,
+                                              int &ok_shared)
 {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads, stores and atomics have completed
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned g = __hip_atomic_load(gptr(b.gen), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned arrived = __hip_atomic_fetch_add(gptr(b.count), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-        int ok = 1;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(gptr(b.count), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gptr(b.gen), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int spins = 0;
-            while (__hip_atomic_load(gptr(b.gen), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (++spins > spin_limit) { ok = 0; break; }
-                __builtin_amdgcn_s_sleep(2);
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __hip_atomic_fetch_add(gptr(ctr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(gptr(ctr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > spin_limit) { ok = 0; break; }
+            __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (!ok) set_flag(d.status, env, MPM_FLAG_BARRIER_TIMEOUT);
         ok_shared = ok;
     }
     __syncthreads();
     return ok_shared != 0;
 }
 
-// Persistent form: for m substeps, the grid operation over the listed bricks
-// and then the fused particle pass (or, for the last substep of a call, the
-// G2P-only tail), separated by grid barriers.  `first` reads the particles
-// from the sort destination, `rest` from the live buffers.
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_persistent(Dev d, TiledArgs first, TiledArgs rest, int m, int par0,
-                                                       int tail_last, GridBarrier bar, int spin_limit)
+// List the environment's flagged bricks (static neighbourhood 1, far-drift
+// 2) for a run: the wavefronts of the group sweep the flags 64 at a time and
+// append to the environment's run list.  Bricks a particle reaches later in
+// the run are appended by mark_far_brick, so the list only grows.
+__device__ __forceinline__ void list_env_bricks(const EnvDev &e, int env, const ActiveBuf &a, int rank, int gsize)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nbe = e.nb * e.nb * e.nb;
+    for (int c0 = (rank * nw + wave) * 64; c0 < nbe; c0 += gsize * nw * 64) {
+        const int f = c0 + lane < nbe ? cload(a.flag + e.bofs + c0 + lane) : 0;
+        const unsigned long long listed = __ballot(f != 0);
+        if (!listed) continue;
+        int base = 0;
+        if (lane == 0) base = gatomic_add(a.ecount + env, (int)__popcll(listed));
+        base = __shfl(base, 0);
+        if (f != 0) cstore(a.elist + e.bofs + base + (int)__popcll(listed & ((1ull << lane) - 1ull)), e.bofs + c0 + lane);
+    }
+}
+
+// Grid operation of one environment by workgroup `rank` of a group of
+// `gsize`: the group's wavefronts take the run list's bricks in turn, one
+// node per lane.  last: the final grid operation of the call, which returns
+// far-drift flags to 0 (the G2P tail after it lists nothing).
+template <bool SDF>
+__device__ __forceinline__ void grid_env_phase(const Dev &d, const EnvDev &e, int env, const ToolDev *tl,
+                                               const ActiveBuf &a, int rank, int gsize, bool last)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int n = cload(a.ecount + env);
+    for (int j = rank * nw + wave; j < n; j += gsize * nw) {
+        const int b = cload(a.elist + e.bofs + j), lb = b - e.bofs;
+        float4 *gp = d.gP + (int64_t)b * BRICK_NODES + lane;
+        const float4 P = cload(gp);
+        if (__any(P.x != 0.f)) {
+            int gi, gj, gk;
+            brick_local_to_ijk(e, lb, lane, gi, gj, gk);
+            const float3 v = grid_node_velocity_tl<SDF>(d, e, tl, P, gi, gj, gk, nullptr);
+            cstore(d.gV + (int64_t)b * BRICK_NODES + lane, make_float4(v.x, v.y, v.z, 0.f));
+            cstore(gp, make_float4(0.f, 0.f, 0.f, 0.f));
+        }
+        if (last && lane == 0 && cload(a.flag + b) == 2) cstore(a.flag + b, 0);
+    }
+}
+
+// The contiguous items [i0, i1) of group member `rank` of `gsize` among an
+// environment's items [ie0, ie1): the items are cut where the running sum of
+// their weights crosses multiples of 1/gsize of the total (a block-wide
+// scan in chunks of the workgroup's size; `scratch` holds blockDim.x / 64 + 3
+// ints of LDS).  Every member computes the same cuts.
+__device__ __forceinline__ void member_items(const int4 *items, int ie0, int ie1, int rank, int gsize, int *scratch,
+                                             int &i0, int &i1)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    int *wsum = scratch, *lo = scratch + nw, *hi = scratch + nw + 1, *tot = scratch + nw + 2;
+    // total weight
+    int part = 0;
+    for (int i = ie0 + tid; i < ie1; i += blockDim.x) part += gload(items + i).z + ITEM_FIXED_COST;
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (tid == 0) { *lo = ie1; *hi = ie0; *tot = 0; }
+    __syncthreads();
+    if (lane == 0) atomicAdd(tot, part);
+    __syncthreads();
+    const long long W = *tot;
+    if (W == 0) {   // no items
+        i0 = i1 = ie0;
+        __syncthreads();
+        return;
+    }
+    int carry = 0;
+    for (int c0 = ie0; c0 < ie1; c0 += blockDim.x) {
+        const int i = c0 + tid;
+        const int w = i < ie1 ? gload(items + i).z + ITEM_FIXED_COST : 0;
+        int incl = w;   // inclusive scan within the wavefront
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int before = carry;
+        for (int q = 0; q < wave; ++q) before += wsum[q];
+        int chunk_total = 0;
+        for (int q = 0; q < nw; ++q) chunk_total += wsum[q];
+        // the member owning an item is the one whose share holds the item's start
+        const long long start = before + incl - w;
+        if (i < ie1 && (int)((start * gsize) / W) == rank) {
+            atomicMin(lo, i);
+            atomicMax(hi, i + 1);
+        }
+        carry += chunk_total;
+        __syncthreads();
+    }
+    i0 = *lo;
+    i1 = *hi;
+    if (i1 < i0) i1 = i0;
+    __syncthreads();
+}
+
+// First work item of the bricks from brick k on (the sort's per-brick item
+// prefix; the total past the last brick).
+__device__ __forceinline__ int item_prefix(const SortBuf &s, int k, int nbricks)
+{
+    if (k >= nbricks) return gload(s.totals).y;
+    return gload(s.brick_offset + k).y + gload(s.chunk_sum + k / SORT_SCAN_CHUNK).y;
+}
+
+template <int W, bool SDF>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_persistent(Dev d, TiledArgs first, TiledArgs rest, EnvGroups g, int m,
+                                                       int tail_last, int spin_limit)
 {
     __shared__ TiledShared<W> sh;
+    __shared__ ToolDev tl[MAX_TOOLS];
     __shared__ int ok;
-    if (threadIdx.x == 0) ok = 1;
-    __syncthreads();
-    for (int i = 0; i < m; ++i) {
-        const int par = (par0 + i) & 1;
-        grid_active_body<true>(d, first.act, par);
-        if (!grid_sync(bar, spin_limit, ok)) break;
-        TiledArgs a = i == 0 ? first : rest;
-        a.par = par ^ 1;
-        if (i == m - 1 && tail_last) tiled_body<2, W>(d, a, sh);
-        else tiled_body<1, W>(d, a, sh);
-        if (!grid_sync(bar, spin_limit, ok)) break;
+    const int4 me = gload(g.wg + blockIdx.x);   // (first env, env count, rank, group size)
+    const int mt = d.max_tools;
+    for (int ei = 0; ei < me.y; ++ei) {
+        const int env = me.x + ei;
+        const EnvDev e = load_env(d.env + env);
+        // the environment's tool slots, advanced here substep by substep (every
+        // workgroup of the group does the same FP64 arithmetic)
+        for (int w = threadIdx.x; w < mt * (int)(sizeof(ToolDev) / 4); w += blockDim.x)
+            reinterpret_cast<int *>(tl)[w] = gload(reinterpret_cast<const int *>(d.tools + (size_t)env * mt) + w);
+        const int ie0 = item_prefix(g.sort, e.bofs, g.nbricks), ie1 = item_prefix(g.sort, e.bofs + e.nb * e.nb * e.nb, g.nbricks);
+        int i0, i1;
+        member_items(first.items, ie0, ie1, me.z, me.w, reinterpret_cast<int *>(sh.pay), i0, i1);
+        unsigned *ctr = g.arrive + env;
+        unsigned k = 0;
+        if (threadIdx.x == 0) ok = 1;
+        __syncthreads();
+        list_env_bricks(e, env, first.act, me.z, me.w);
+        for (int i = 0; i < m && group_barrier(d, env, ctr, ++k * me.w, spin_limit, ok); ++i) {
+            grid_env_phase<SDF>(d, e, env, tl, first.act, me.z, me.w, i == m - 1 && tail_last);
+            if (!group_barrier(d, env, ctr, ++k * me.w, spin_limit, ok)) break;
+            const TiledArgs &a = i == 0 ? first : rest;
+            if (i == m - 1 && tail_last) tiled_body<2, W, true>(d, a, sh, i0, 1, i1);
+            else tiled_body<1, W, true>(d, a, sh, i0, 1, i1);
+            if (threadIdx.x < mt && tl[threadIdx.x].active) advance_tool(tl[threadIdx.x], d.dt);
+            __syncthreads();
+        }
+        if (me.z == 0) {
+            for (int w = threadIdx.x; w < mt * (int)(sizeof(ToolDev) / 4); w += blockDim.x)
+                gstore(reinterpret_cast<int *>(d.tools + (size_t)env * mt) + w, reinterpret_cast<const int *>(tl)[w]);
+            if (threadIdx.x == 0) gstore(d.step + env, gload(d.step + env) + m);
+        }
+        __syncthreads();
     }
-    if (!ok && threadIdx.x == 0)
-        for (int e = 0; e < d.n_envs; ++e) set_flag(d.status, e, MPM_FLAG_BARRIER_TIMEOUT);
 }
 
 template <int MODE>
@@ -473,15 +635,23 @@ void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nb
     launch_mode<3>(d, a, block, nblocks, st);
 }
 
-void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, int m, int par0, int tail_last,
-                       const GridBarrier &bar, int spin_limit, int block, int nblocks, hipStream_t st)
+template <bool SDF>
+static void launch_persistent_sdf(const Dev &d, const TiledArgs &first, const TiledArgs &rest, const EnvGroups &g,
+                                  int m, int tail_last, int spin_limit, int block, int nblocks, hipStream_t st)
 {
     if (block == 64)
-        launch_k((k_persistent<1>), dim3(nblocks), dim3(64), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<1, SDF>), dim3(nblocks), dim3(64), 0, st, d, first, rest, g, m, tail_last, spin_limit);
     else if (block == 128)
-        launch_k((k_persistent<2>), dim3(nblocks), dim3(128), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<2, SDF>), dim3(nblocks), dim3(128), 0, st, d, first, rest, g, m, tail_last, spin_limit);
     else
-        launch_k((k_persistent<4>), dim3(nblocks), dim3(256), 0, st, d, first, rest, m, par0, tail_last, bar, spin_limit);
+        launch_k((k_persistent<4, SDF>), dim3(nblocks), dim3(256), 0, st, d, first, rest, g, m, tail_last, spin_limit);
+}
+
+void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, const EnvGroups &g, int m,
+                       int tail_last, int spin_limit, bool sdf, int block, int nblocks, hipStream_t st)
+{
+    if (sdf) launch_persistent_sdf<true>(d, first, rest, g, m, tail_last, spin_limit, block, nblocks, st);
+    else launch_persistent_sdf<false>(d, first, rest, g, m, tail_last, spin_limit, block, nblocks, st);
 }
 
 int persistent_workgroups(int block)
@@ -491,12 +661,18 @@ int persistent_workgroups(int block)
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
     }
+    // the SDF instance uses the more registers; its occupancy holds for both
     hipError_t e;
-    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<1>, 64, 0);
-    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<2>, 128, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<4>, 256, 0);
-    if (e != hipSuccess || per < 1) return 0;
-    int g = per * cus;
+    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<1, true>, 64, 0);
+    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<2, true>, 128, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<4, true>, 256, 0);
+    int per2 = 0;
+    hipError_t e2;
+    if (block == 64) e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, k_persistent<1, false>, 64, 0);
+    else if (block == 128) e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, k_persistent<2, false>, 128, 0);
+    else e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, k_persistent<4, false>, 256, 0);
+    if (e != hipSuccess || e2 != hipSuccess || per < 1 || per2 < 1) return 0;
+    int g = std::min(per, per2) * cus;
     g -= g % NXCD;
     return g;
 }

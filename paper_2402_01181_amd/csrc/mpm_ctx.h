@@ -85,13 +85,18 @@ struct mpm_ctx {
     int items_P = 0;
     int since_sort = 0;
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
-    int persistent_blocks = -1;      // co-resident workgroups of the persistent kernel (0: unavailable)
+    // persistent kernel: environment groups (wg_tab) for groups_block threads and
+    // groups_item particles per item, groups_n workgroups (0: not available)
+    int groups_block = 0, groups_item = 0, groups_n = 0;
     // tiled stage sequence of mpm_run_stage: 0 none open, 1 a P2G awaits its grid
     // operation, 2 a grid operation awaits its particle pass
     int tstage = 0;
     int tstage_i = 0;                // substeps the open sequence has taken (dynamic-list parity)
     mpm::ParticleBuf tstage_in{};    // particle input of the sequence's next particle pass
-    mpm::GridBarrier barrier{};
+    int4 *wg_tab = nullptr;          // [MAX_PERSISTENT_WG] workgroup -> (first env, env count, rank, group size)
+    unsigned *arrive = nullptr;      // [2 n_envs] group barrier counters, then the run-list counts (ecount)
+    int32_t *ecount = nullptr;       // = arrive + n_envs
+    int32_t *elist = nullptr;        // [total_bricks] per-environment run lists of the persistent kernel
     // host mirror of the tool slots
     std::vector<mpm::ToolDev> tools_h;
     Profiler prof;

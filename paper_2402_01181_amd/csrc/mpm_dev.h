@@ -82,6 +82,38 @@ __device__ __forceinline__ int2 gload(const int2 *p)
     return make_int2(r.x, r.y);
 }
 
+// Device-coherent accesses: agent-scope relaxed atomic loads and stores (on
+// gfx950 they carry the device-scope cache bit, so they neither hit a stale
+// line of another XCD's L2 nor leave the value in one).  The persistent
+// kernel moves grid data between workgroups of one launch with them.
+__device__ __forceinline__ float4 cload(const float4 *p)
+{
+    typedef __attribute__((address_space(1))) uint64_t *gp64;
+    const uint64_t a = __hip_atomic_load((gp64)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load((gp64)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float4(__uint_as_float((uint32_t)a), __uint_as_float((uint32_t)(a >> 32)),
+                       __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
+}
+
+__device__ __forceinline__ void cstore(float4 *p, float4 v)
+{
+    typedef __attribute__((address_space(1))) uint64_t *gp64;
+    const uint64_t a = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+    const uint64_t b = (uint64_t)__float_as_uint(v.z) | ((uint64_t)__float_as_uint(v.w) << 32);
+    __hip_atomic_store((gp64)p, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((gp64)p + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int cload(const int *p)
+{
+    return __hip_atomic_load(gptr(const_cast<int *>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void cstore(int *p, int v)
+{
+    __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int BRICK = 4;            // grid bricks are 4x4x4 nodes = 64 nodes = one wavefront
 constexpr int BRICK_NODES = 64;
 constexpr int MAX_TOOLS = 8;
@@ -592,16 +624,17 @@ __device__ __forceinline__ float3 node_vhat(const Dev &d, float4 P)
     return make_float3(P.y / P.x + d.dt * d.gx, P.z / P.x + d.dt * d.gy, P.w / P.x + d.dt * d.gz);
 }
 
+// Velocity of node (i,j,k) after the grid operation, with the environment's
+// tool slots at tl (global memory, or a workgroup's LDS copy).
 template <bool SDF = true>
-__device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev &e, int env, float4 P, int i,
-                                                     int j, int k, ContactRec *rec)
+__device__ __forceinline__ float3 grid_node_velocity_tl(const Dev &d, const EnvDev &e, const ToolDev *tl, float4 P,
+                                                        int i, int j, int k, ContactRec *rec)
 {
     if (rec) { rec->tool = -1; rec->branch = 0; }
     if (!(P.x > 0.0f)) return make_float3(0.f, 0.f, 0.f);
     float3 v = node_vhat(d, P);
     if (boundary_node(e, i, j, k)) return make_float3(0.f, 0.f, 0.f);
     if (d.max_tools > 0) {
-        const ToolDev *tl = d.tools + (size_t)env * d.max_tools;
         ToolHit h;
         int bt = select_tool<SDF>(tl, d.max_tools, e, i, j, k, h);
         if (bt >= 0) {
@@ -628,6 +661,13 @@ __device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev 
         }
     }
     return v;
+}
+
+template <bool SDF = true>
+__device__ __forceinline__ float3 grid_node_velocity(const Dev &d, const EnvDev &e, int env, float4 P, int i,
+                                                     int j, int k, ContactRec *rec)
+{
+    return grid_node_velocity_tl<SDF>(d, e, d.tools + (size_t)env * d.max_tools, P, i, j, k, rec);
 }
 
 __device__ __forceinline__ void set_flag(uint32_t *status, int env, uint32_t f)

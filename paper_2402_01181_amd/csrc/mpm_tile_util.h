@@ -41,6 +41,22 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev
     return t;
 }
 
+// Tile of a work item of the environment e already loaded.
+__device__ __forceinline__ Tile tile_of(const EnvDev &e, const int4 &item)
+{
+    Tile t;
+    t.env = item.w;
+    const int lb = item.x - e.bofs;
+    t.bk = lb % e.nb;
+    const int r = lb / e.nb;
+    t.bj = r % e.nb;
+    t.bi = r / e.nb;
+    t.o[0] = 4 * t.bi;
+    t.o[1] = 4 * t.bj;
+    t.o[2] = 4 * t.bk;
+    return t;
+}
+
 // Item walk: workgroup x + NXCD r runs on XCD x (workgroups are dealt to the
 // XCDs round-robin) and takes every (G / NXCD)-th item, from its r-th on, of
 // the contiguous eighth of the (spatially ordered) item list that belongs to
@@ -55,13 +71,19 @@ __device__ __forceinline__ void item_range(int nitems, int &first, int &stride, 
     stride = G / NXCD;
 }
 
-// A stencil reached brick b outside the static neighbourhood of the
-// particle's sort-time brick: list b once for the next grid operation.
-__device__ __forceinline__ void mark_far_brick(const ActiveBuf &act, int par, int b)
+// A stencil reached brick b (of environment env, whose bricks start at
+// bofs) outside the static neighbourhood of the particle's sort-time brick:
+// list b once for the next grid operation (flag 2, and an entry in dynamic
+// list `par`, or in the environment's run list in the persistent kernel).
+__device__ __forceinline__ void mark_far_brick(const ActiveBuf &act, int par, int b, int env, int bofs)
 {
     if (!act.flag) return;   // no bookkeeping (tape recompute)
-    if (gatomic_cas(act.flag + b, 0, 2)) {
-        int slot = gatomic_add(act.dcount + par, 1);
+    if (!gatomic_cas(act.flag + b, 0, 2)) return;
+    if (act.elist) {
+        const int slot = gatomic_add(act.ecount + env, 1);
+        cstore(act.elist + bofs + slot, b);
+    } else {
+        const int slot = gatomic_add(act.dcount + par, 1);
         gstore(act.dlist + (size_t)par * act.nbricks + slot, b);
     }
 }

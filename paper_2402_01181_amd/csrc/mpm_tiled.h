@@ -45,6 +45,11 @@ struct ActiveBuf {
     const int32_t *env_bofs;  // [n_envs + 1] first brick of each environment
     const int32_t *brick_env; // [nbricks] environment of each brick
     int32_t nbricks;          // total bricks over all environments
+    // persistent kernel: per-environment brick lists of a run (environment e's
+    // entries at elist[env_bofs[e]..], ecount[e] of them); far bricks are
+    // appended there instead of to the dynamic lists.  Null otherwise.
+    int32_t *elist;
+    int32_t *ecount;
 };
 
 // Tile geometry: the nodes reached by the stencils of a brick of 4^3 cells
@@ -64,10 +69,24 @@ struct TiledArgs {
     int par;                              // dynamic list this kernel's P2G appends to
 };
 
-// Grid-wide barrier state of the persistent kernel (reset before each launch).
-struct GridBarrier {
-    unsigned *count;
-    unsigned *gen;
+// Bricks per chunk of the sort's brick scan (brick_offset is a prefix within
+// its chunk, chunk_sum the prefix of the chunks).
+constexpr int SORT_SCAN_CHUNK = 1024;
+
+// Most workgroups the persistent kernel launches (its group table's size).
+constexpr int MAX_PERSISTENT_WG = 8192;
+// Cost weight of a work item of z particles in the persistent kernel's work
+// split: z + ITEM_FIXED_COST (the tile's staging and flush, in particles).
+constexpr int ITEM_FIXED_COST = 96;
+
+// Environment groups of the persistent kernel: workgroup b serves
+// environments wg[b].x .. wg[b].x + wg[b].y - 1 as member wg[b].z of a group
+// of wg[b].w workgroups (a group with several environments has one member).
+struct EnvGroups {
+    const int4 *wg;        // [launched workgroups]
+    unsigned *arrive;      // [n_envs] barrier counters, zero at each launch
+    SortBuf sort;          // the last sort: items per brick
+    int nbricks;
 };
 
 // act.flag == nullptr: the static brick list is left as it is (act.brick_env is always used).
@@ -86,11 +105,12 @@ void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t 
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
 int tiled_workgroups(int block);
-// Persistent kernel: m substeps of (grid operation, fused particle pass), the
-// last one a G2P-only tail if tail_last; nblocks must not exceed
-// persistent_workgroups(block) (all workgroups co-resident), 0 if unknown.
-void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, int m, int par0, int tail_last,
-                       const GridBarrier &bar, int spin_limit, int block, int nblocks, hipStream_t st);
+// Persistent kernel: m substeps of (grid operation, fused particle pass) per
+// environment group, the last one a G2P-only tail if tail_last; groups
+// synchronise through their own counters.  nblocks must not exceed
+// persistent_workgroups(block) (all workgroups co-resident; 0 if unknown).
+void launch_persistent(const Dev &d, const TiledArgs &first, const TiledArgs &rest, const EnvGroups &g, int m,
+                       int tail_last, int spin_limit, bool sdf, int block, int nblocks, hipStream_t st);
 int persistent_workgroups(int block);
 
 }  // namespace mpm

@@ -270,8 +270,8 @@ def test_batched_teacher_forced_parity(gpu, orc):
 
 @pytest.mark.parametrize("use_graph", [0, 1])
 def test_persistent_matches_eager(gpu, orc, use_graph):
-    """MPM_OPT_PERSISTENT: runs of up to sort_every substeps in one kernel with
-    grid barriers; 3 calls of 40 substeps (runs of 16, 16, 8) against the
+    """MPM_OPT_PERSISTENT: runs of up to sort_every substeps in one kernel (one
+    environment, so one group of workgroups); 3 calls of 40 substeps (runs of 16, 16, 8) against the
     same calls launched per phase.  No barrier may time out."""
     Sim, L = gpu
     _say(f"persistent (graph={use_graph}) vs eager: slab 30K, 3 x 40 substeps")
@@ -315,10 +315,63 @@ def test_persistent_batched_and_single_substeps(gpu, orc):
         np.testing.assert_array_equal(pers.read(L.F_TOOL_T, e), eager.read(L.F_TOOL_T, e))
 
 
+def _many_small_envs(n_envs=700, seed=21):
+    """n_envs slabs of 100-300 particles on 16^3 grids, each pressed by its own
+    capsule: more environments than the persistent kernel has workgroups at
+    256 threads, so workgroups step several environments each."""
+    rng = np.random.default_rng(seed)
+    envs = []
+    for _ in range(n_envs):
+        N = int(rng.integers(100, 301))
+        y0 = 3.0 / 16
+        x = scenes.box_uniform(rng, N, (0.25, y0, 0.25), (0.75, y0 + 0.15, 0.75))
+        v, C, F = scenes._rest_state(x)
+        u = rng.uniform(0.05, 0.2) * scenes._unit((rng.uniform(-0.3, 0.3), -1.0, rng.uniform(-0.3, 0.3)))
+        tool = scenes.capsule_tool(T0=(0.5, y0 + 0.16, 0.5), u=u, radius=0.03, friction=0.3)
+        envs.append(scenes.Env(n=16, x=x, v=v, C=C, F=F, E=float(rng.uniform(3e3, 3e4)),
+                               nu=float(rng.uniform(0.25, 0.45)), rho=1e3, V0=0.5 * 0.15 * 0.5 / N, tools=[tool]))
+    return scenes.Scene(f"many-{n_envs}", envs, dt=1e-4, substeps=30)
+
+
+def test_persistent_more_envs_than_workgroups(gpu, orc):
+    """Persistent form with 700 environments at 256 threads per workgroup
+    (fewer co-resident workgroups than environments): calls of 1, 9 and 20
+    substeps against the per-phase launches, then one teacher-forced pair of
+    substeps of three environments against the oracle."""
+    Sim, L = gpu
+    sc = _many_small_envs()
+    opts = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 8, L.OPT_BLOCK: 256, L.OPT_ITEM: 128}
+    _say(f"persistent, {len(sc.envs)} environments of 100-300 particles on 16^3, calls 1, 9, 20")
+    eager = Sim(sc, options=dict(opts))
+    pers = Sim(sc, options={**opts, L.OPT_PERSISTENT: 1})
+    for n in (1, 9, 20):
+        eager.step(n)
+        pers.step(n)
+    worst = 0.0
+    for e in range(len(sc.envs)):
+        xe, xp = eager.particles(e)[0], pers.particles(e)[0]
+        worst = max(worst, float(np.abs(xe - xp).max()))
+        assert pers.read(L.F_STATUS, e) == 0 and pers.read(L.F_STEP, e) == 30
+        np.testing.assert_array_equal(pers.read(L.F_TOOL_T, e), eager.read(L.F_TOOL_T, e))
+    moved = max(float(np.abs(pers.particles(e)[0] - sc.envs[e].x).max()) for e in (0, 350, 699))
+    _say(f"  max |x_persistent - x_eager| over all environments {worst:.2e} m (moved up to {moved:.2e} m)")
+    assert worst <= 1e-5 and moved > 0
+    refs = {}
+    for e in (0, 350, 699):
+        o = oracle_sim_like(orc, sc, e)
+        o.state = oracle_state_from_gpu(orc, pers, e)
+        o.T[:1] = pers.read(L.F_TOOL_T, e)
+        o.s = pers.read(L.F_STEP, e)
+        refs[e] = o.run(2)
+    pers.step(2)
+    for e, o in refs.items():
+        _compare_particles(o.state, pers, env=e, tol=2 * TOL_SUBSTEP, what=f"env {e} two substeps")
+
+
 @pytest.mark.parametrize("persistent,use_graph", [(1, 0), (1, 1), (0, 1)])
 def test_batch_forms_against_oracle(gpu, orc, persistent, use_graph):
     """The batched forms checked against the oracle itself: the persistent
-    kernel (runs of sort_every substeps, grid barriers), with or without an
+    kernel (runs of sort_every substeps, a barrier per environment group), with or without an
     internally captured graph, and the captured graph of per-phase launches.
     Each environment is teacher-forced over calls of two substeps (the fused
     particle pass runs between the two grid operations; 2e-5 after two
