@@ -197,7 +197,12 @@ typedef struct {
  * for an invalid description (mpm_create then reports why). */
 size_t mpm_workspace_size(const mpm_desc *desc);
 
-/* Create a context: validates desc, carves the caller's workspace (device
+/* Create a context holding the material points of Sec. III-B (position x,
+ * velocity v, affine velocity C and deformation gradient F per particle,
+ * with mass and volume from rho and V0, and Lame parameters from E and nu
+ * by the relation of Sec. III-B) and the background grid of each
+ * environment.  Validates desc (MPM_E_ARG for a bad field, e.g. E <= 0, nu
+ * outside (-1, 0.5) or not finite), carves the caller's workspace (device
  * memory of at least mpm_workspace_size(desc) bytes, 256-byte aligned, owned
  * by the caller and kept alive until mpm_destroy), copies the initial state
  * and clears the grids on `stream`.  Tools start unset.  On success *out owns
@@ -274,7 +279,11 @@ mpm_status mpm_extract_surface(mpm_ctx *ctx, int32_t env, float iso, float *tris
 /* Set a tunable (MPM_OPT_*).  Takes effect at the next substep call. */
 mpm_status mpm_set_option(mpm_ctx *ctx, int32_t option, int32_t value);
 
-/* Advance every environment by n_substeps >= 1 substeps on `stream`.
+/* Advance every environment by n_substeps >= 1 substeps on `stream`.  One
+ * substep is the MLS-MPM step of Sec. III-B: P2G of mass and APIC momentum
+ * with the Neo-Hookean stress force (item 1, Eq. P2G and Eq. fip), the grid
+ * operation with gravity, boundary nodes and tool contact (item 2, Sec.
+ * III-C), and G2P with advection and the update of F (item 3).
  * record_tape != 0 starts a new adjoint tape at the current state and
  * records these substeps (n_substeps <= max_tape_substeps).  Never
  * synchronises. */
@@ -303,9 +312,13 @@ mpm_status mpm_substep_adjoint(mpm_ctx *ctx, int32_t n_substeps, const mpm_adjoi
                                void *stream);
 
 /* Copy one field of environment env into dst (dst_bytes must equal the
- * field's size).  dst_on_device != 0: dst is device memory and the copy is
- * asynchronous on `stream`; otherwise dst is host memory and the call waits
- * for `stream`.  Particle fields come back in the original particle order. */
+ * field's size, else MPM_E_ARG; env out of range: MPM_E_ARG): the particle
+ * state the simulator hands on each step (Sec. III-A: particle positions go
+ * to surface extraction and rendering), the grid fields of Sec. III-B, the
+ * status bits, tool positions and step counters.  dst_on_device != 0: dst is
+ * device memory and the copy is asynchronous on `stream`; otherwise dst is
+ * host memory and the call waits for `stream`.  Particle fields come back in
+ * the original particle order. */
 mpm_status mpm_read_state(mpm_ctx *ctx, int32_t env, int32_t field, void *dst, size_t dst_bytes,
                           int32_t dst_on_device, void *stream);
 

@@ -176,6 +176,44 @@ def test_status_flags_and_read_errors(gpu, orc, scheme):
     assert sim.lib.mpm_set_tool(sim.ctx, 0, 3, None, None, 0) == L.MPM_E_ARG
 
 
+@pytest.mark.parametrize("scheme", ["direct", "tiled"])
+def test_nonfinite_flag(gpu, orc, scheme):
+    """A particle given a NaN velocity makes its node momenta NaN; the G2P
+    that follows gives NaN velocities and positions, which set
+    MPM_FLAG_NONFINITE (a NaN position then counts as outside the grid: the
+    particle is frozen and no index is formed from it)."""
+    Sim, L = gpu
+    _say(f"non-finite flag ({scheme})")
+    sc = scenes.small_slab_scene(seed=4, n_particles=500, n=32, substeps=1)
+    sc.envs[0].v[7] = [np.nan, 0.0, 0.0]
+    sim = Sim(sc, options={L.OPT_SCHEME: _scheme(L, scheme), L.OPT_SORT_EVERY: 2})
+    sim.step(4)
+    st = sim.read(L.F_STATUS)
+    _say(f"  status {st:#x}")
+    assert st & L.FLAG_NONFINITE
+    x = sim.particles()[0]
+    assert not np.isfinite(x[7]).all()
+    # a clean scene raises nothing
+    clean = Sim(scenes.small_slab_scene(seed=4, n_particles=500, n=32, substeps=1),
+                options={L.OPT_SCHEME: _scheme(L, scheme)})
+    clean.step(4)
+    assert clean.read(L.F_STATUS) == 0
+
+
+@pytest.mark.parametrize("field,value", [("E", 0.0), ("E", float("nan")), ("E", float("inf")), ("nu", 0.5),
+                                         ("nu", -1.0), ("nu", float("nan")), ("rho", 0.0), ("V0", -1.0)])
+def test_material_validation(gpu, orc, field, value):
+    """mpm_create reads the material table and refuses E <= 0 or non-finite,
+    nu outside (-1, 0.5), rho <= 0 and V0 <= 0 with MPM_E_ARG."""
+    Sim, L = gpu
+    sc = scenes.small_slab_scene(seed=5, n_particles=200, n=16, substeps=1)
+    setattr(sc.envs[0], field, value)
+    with pytest.raises(L.MpmError) as e:
+        Sim(sc)
+    assert e.value.code == L.MPM_E_ARG
+    assert "material" in str(e.value)
+
+
 @pytest.mark.parametrize("slots", [1, 3])
 def test_tiled_matches_direct_long_run(gpu, orc, slots):
     """Cross-check of the two schemes (different accumulation orders) on the
