@@ -692,24 +692,40 @@ void reverse_segment_tiled(mpm_ctx *c, int s_begin, int lo, int s_end, int s0, h
     a.Cb = T.adj_slot + 6 * N;
     a.Fb = T.adj_slot + 15 * N;
     const ActiveBuf ta = tape_act(c);
-    for (int j = s_end - 1; j >= lo; --j) {
-        const int slot = j - s_begin;
+    // recorded state of tape slot `slot` (substep s_begin + slot)
+    auto slot_dev = [&](int slot) {
         ParticleBuf sv = seg_view(c, slot);
         Dev d = c->dev();
         d.x = sv.x; d.v = sv.v; d.C = sv.C; d.H = sv.H; d.pid = nullptr;
         d.gP = T.seg_P + (size_t)slot * c->total_nodes;
         d.gV = T.seg_V + (size_t)slot * c->total_nodes;
         d.tools = T.seg_tools + (size_t)slot * c->tool_slots();
+        return d;
+    };
+    // reverse G2P of the last substep; then per substep j the reverse grid
+    // operation, and the reverse P2G of j fused with the reverse G2P of j - 1
+    // (one pass over the particles), the last reverse P2G on its own
+    timed(c, st, PK_ADJ_G2P, [&] {
+        launch_adj_g2p_tiled(slot_dev(s_end - 1 - s_begin), a, c->sort.items, c->sort.totals, c->node_slots, ta,
+                             c->block, c->tiled_blocks, st);
+    });
+    for (int j = s_end - 1; j >= lo; --j) {
+        const int slot = j - s_begin;
+        const Dev d = slot_dev(slot);
         a.j = j - s0;
-        timed(c, st, PK_ADJ_G2P, [&] {
-            launch_adj_g2p_tiled(d, a, c->sort.items, c->sort.totals, c->node_slots, ta, c->block, c->tiled_blocks, st);
-        });
         timed(c, st, PK_ADJ_GRID, [&] {
             launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
         });
-        timed(c, st, PK_ADJ_P2G, [&] {
-            launch_adj_p2g_tiled(d, a, c->sort.items, c->sort.totals, ta, c->block, c->tiled_blocks, st);
-        });
+        if (j > lo) {
+            timed(c, st, PK_ADJ_P2G, [&] {
+                launch_adj_pair_tiled(d, slot_dev(slot - 1), a, c->sort.items, c->sort.totals, c->node_slots, ta,
+                                      c->block, c->tiled_blocks, st);
+            });
+        } else {
+            timed(c, st, PK_ADJ_P2G, [&] {
+                launch_adj_p2g_tiled(d, a, c->sort.items, c->sort.totals, ta, c->block, c->tiled_blocks, st);
+            });
+        }
     }
     timed(c, st, PK_ADJ_MISC, [&] { launch_permute(T.adj_slot, T.perm, c->ntot, 24, T.adj_state, 1, st); });
 }

@@ -438,18 +438,327 @@ struct AdjTiledArgs {
     ActiveBuf act;      // unused by the reverse kernels (no marking)
 };
 
-// Reverse of G2P + advection + F update.  Pass 1 (lane = particle) forms C'
-// from the tape's node velocities (LDS tile), the particle adjoints and the
-// weight-gradient terms; pass 2 (lane = stencil node) adds
-// w (vbar_t + Bbar q) to per-wavefront tiles, flushed to the node-velocity
-// adjoint with one float atomic per component.
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTiledArgs ta)
+// Reverse of G2P + advection + F update for one particle whose stencil s
+// lies in the grid (state H at the start of the substep, node velocities
+// through Vat(a0, a1, a2)).  In: the adjoints xb, vb, Cb, Fb of the state
+// after the substep; out: those of the state before it (vb and Cb become
+// zero: v and C enter the substep only through P2G), and the payload of the
+// node-velocity adjoint w (vbt + Bb q).
+//
+// Separable form of the stencil sums.  Per node only wb = V . g(a)
+// (g(a) = vbar_t + Bbar (a - f), linear in the node offset a) and the
+// weighted node velocity are formed; the sums then run over the third axis,
+// the second and the first:
+//   B[i][j] = sum w V_i a_j - f_j S_i,  fxb[k] = sum (dw/dx_k) wb - (Bbar^T S)_k,
+//   S = sum w V.
+template <class VTile, class VGlobal>
+__device__ __forceinline__ void adj_g2p_particle(const Dev &d, const EnvDev &e, const Stencil &s, const float H[9],
+                                                 float xb[3], float vb[3], float Cb[9], float Fb[9], bool in_tile,
+                                                 VTile vtile, VGlobal vglobal, float vbt[3], float Bb[9])
+{
+    float dw[3][3];
+    weight_grads(s, dw);
+    // the particle's adjoint state first: Bbar and vbar_t do not depend on the
+    // recomputed C, so one pass over the stencil serves C and the x adjoint
+    const float cs = 4.0f * e.inv_dx;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float cbt = Cb[3 * r + c] + d.dt * (Fb[3 * r + c] + Fb[3 * r] * H[3 * c] + Fb[3 * r + 1] * H[3 * c + 1] +
+                                                      Fb[3 * r + 2] * H[3 * c + 2]);
+            Bb[3 * r + c] = cs * cbt;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) vbt[i] = vb[i] + d.dt * xb[i];
+    float gf[3];   // vbar_t - Bbar f
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        gf[i] = vbt[i] - (Bb[3 * i] * s.fx[0] + Bb[3 * i + 1] * s.fx[1] + Bb[3 * i + 2] * s.fx[2]);
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
+    float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    auto sums = [&](auto Vat) {
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) {
+        float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
+        float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a1 = 0; a1 < 3; ++a1) {
+            float X = 0.f, Y = 0.f, AV[3] = {0.f, 0.f, 0.f}, BV[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a2 = 0; a2 < 3; ++a2) {
+                const float4 V4 = Vat(a0, a1, a2);
+                const float V[3] = {V4.x, V4.y, V4.z};
+                const float w2 = s.w[2][a2];
+                float wb = 0.f;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    wb = fmaf(V[i], gf[i] + Bb[3 * i] * a0 + Bb[3 * i + 1] * a1 + Bb[3 * i + 2] * a2, wb);
+                X = fmaf(w2, wb, X);
+                Y = fmaf(dw[2][a2], wb, Y);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    AV[i] = fmaf(w2, V[i], AV[i]);
+                    BV[i] = fmaf(w2 * a2, V[i], BV[i]);
+                }
+            }
+            const float w1 = s.w[1][a1], d1 = dw[1][a1];
+            X1 = fmaf(w1, X, X1);
+            X1d = fmaf(d1, X, X1d);
+            Y1 = fmaf(w1, Y, Y1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                E1[i] = fmaf(w1, AV[i], E1[i]);
+                E2[i] = fmaf(w1 * a1, AV[i], E2[i]);
+                E3[i] = fmaf(w1, BV[i], E3[i]);
+            }
+        }
+        const float w0 = s.w[0][a0], d0 = dw[0][a0];
+        g0 = fmaf(d0, X1, g0);
+        g1 = fmaf(w0, X1d, g1);
+        g2 = fmaf(w0, Y1, g2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            S[i] = fmaf(w0, E1[i], S[i]);
+            Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
+            Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
+            Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
+        }
+    }
+    };
+    if (in_tile) sums(vtile); else sums(vglobal);
+    float B[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) B[3 * i + j] = Mo[i][j] - s.fx[j] * S[i];
+    const float fxb[3] = {g0 - (Bb[0] * S[0] + Bb[3] * S[1] + Bb[6] * S[2]),
+                          g1 - (Bb[1] * S[0] + Bb[4] * S[1] + Bb[7] * S[2]),
+                          g2 - (Bb[2] * S[0] + Bb[5] * S[1] + Bb[8] * S[2])};
+    // F' = (I + dt C') F with C' = cs B:  Fbar <- (I + dt C')^T Fbar'
+    float Fbn[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * cs * (B[r] * Fb[c] + B[3 + r] * Fb[3 + c] + B[6 + r] * Fb[6 + c]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        Fb[c] = Fbn[c];
+        Cb[c] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xb[c] += e.inv_dx * fxb[c];
+        vb[c] = 0.0f;
+    }
+}
+
+// Reverse of P2G and of the stress for one particle whose stencil s lies in
+// the grid (state v, C, H; node adjoints (m, mv)bar through Pat(a0, a1, a2)).
+// Adds its terms to the adjoints xb, vb, Cb, Fb of the state before the
+// substep and returns the particle's dL/dmu, dL/dlambda terms.
+//
+// Separable form of the stencil sums.  Per node only the momentum weight
+// wb = m pm + q . c(a) (c(a) = m v + A (a - f) dx, the affine momentum at
+// node offset a) and the node's weighted values are formed; the sums then run
+// over the third axis, the second and the first:
+//   vbp = m S,  Ab[i][j] = dx (sum w q_i a_j - f_j S_i),
+//   fxb[k] = sum (dw/dx_k) wb - dx (A^T S)_k,  S = sum w q.
+template <class PTile, class PGlobal>
+__device__ __forceinline__ void adj_p2g_particle(const Dev &d, const EnvDev &e, const Stencil &s, const float H[9],
+                                                 const float C[9], const float v[3], float mu, float lamda, float m,
+                                                 float kf, bool in_tile, PTile ptile, PGlobal pglobal, float xb[3],
+                                                 float vb[3], float Cb[9], float Fb[9], double &mub, double &lamb)
+{
+    float F[9], tau[9], A[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) F[c] = H[c] + ((c & 3) == 0 ? 1.0f : 0.0f);
+    // the forward's FP32 stress (same formulas, same inversion decision)
+    const float jm1 = jm1_f(H);
+    const bool inverted = inverted_f(H, jm1);
+    kirchhoff_f(H, jm1, inverted, mu, lamda, tau);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
+    float dw[3][3];
+    weight_grads(s, dw);
+    const float dx = e.dx;
+    float lam[3][3], cf[3];   // lam[j][i] = dx A[i][j]; cf = m v - dx A f
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lam[j][i] = dx * A[3 * i + j];
+        cf[i] = m * v[i] - (lam[0][i] * s.fx[0] + lam[1][i] * s.fx[1] + lam[2][i] * s.fx[2]);
+    }
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
+    float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    auto sums = [&](auto Pat) {
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) {
+        float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
+        float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a1 = 0; a1 < 3; ++a1) {
+            float X = 0.f, Y = 0.f, AQ[3] = {0.f, 0.f, 0.f}, BQ[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a2 = 0; a2 < 3; ++a2) {
+                const float4 Pb = Pat(a0, a1, a2);
+                const float q[3] = {Pb.y, Pb.z, Pb.w};
+                const float w2 = s.w[2][a2];
+                float wb = m * Pb.x;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    wb = fmaf(q[i], cf[i] + lam[0][i] * a0 + lam[1][i] * a1 + lam[2][i] * a2, wb);
+                X = fmaf(w2, wb, X);
+                Y = fmaf(dw[2][a2], wb, Y);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    AQ[i] = fmaf(w2, q[i], AQ[i]);
+                    BQ[i] = fmaf(w2 * a2, q[i], BQ[i]);
+                }
+            }
+            const float w1 = s.w[1][a1], d1 = dw[1][a1];
+            X1 = fmaf(w1, X, X1);
+            X1d = fmaf(d1, X, X1d);
+            Y1 = fmaf(w1, Y, Y1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                E1[i] = fmaf(w1, AQ[i], E1[i]);
+                E2[i] = fmaf(w1 * a1, AQ[i], E2[i]);
+                E3[i] = fmaf(w1, BQ[i], E3[i]);
+            }
+        }
+        const float w0 = s.w[0][a0], d0 = dw[0][a0];
+        g0 = fmaf(d0, X1, g0);
+        g1 = fmaf(w0, X1d, g1);
+        g2 = fmaf(w0, Y1, g2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            S[i] = fmaf(w0, E1[i], S[i]);
+            Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
+            Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
+            Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
+        }
+    }
+    };
+    if (in_tile) sums(ptile); else sums(pglobal);
+    float Ab[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        vb[i] += m * S[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Ab[3 * i + j] = dx * (Mo[i][j] - s.fx[j] * S[i]);
+    }
+    const float fxb[3] = {g0 - dx * (A[0] * S[0] + A[3] * S[1] + A[6] * S[2]),
+                          g1 - dx * (A[1] * S[0] + A[4] * S[1] + A[7] * S[2]),
+                          g2 - dx * (A[2] * S[0] + A[5] * S[1] + A[8] * S[2])};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xb[c] += e.inv_dx * fxb[c];
+    float taub[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        Cb[c] += m * Ab[c];
+        taub[c] = kf * Ab[c];
+    }
+    // tau-bar -> F-bar: mu (tau-bar + tau-bar^T) F + lam tr(tau-bar) cof(F) / J
+    float Fs[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Fs[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
+                                  (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
+    const float trt = taub[0] + taub[4] + taub[8];
+    const float lnJ = inverted ? -13.815510557964274f : log1pf(jm1);
+    if (!inverted) {
+        const float ci[9] = {F[4] * F[8] - F[5] * F[7], -(F[3] * F[8] - F[5] * F[6]), F[3] * F[7] - F[4] * F[6],
+                             -(F[1] * F[8] - F[2] * F[7]), F[0] * F[8] - F[2] * F[6], -(F[0] * F[7] - F[1] * F[6]),
+                             F[1] * F[5] - F[2] * F[4], -(F[0] * F[5] - F[2] * F[3]), F[0] * F[4] - F[1] * F[3]};
+        const float sc = lamda * trt / (1.0f + jm1);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Fs[c] = fmaf(sc, ci[c], Fs[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Fb[c] += Fs[c];
+    // dL/dmu and dL/dlam of this particle (summed per environment in FP64)
+    float ff = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float G = H[3 * r + c] + H[3 * c + r] + H[3 * r] * H[3 * c] + H[3 * r + 1] * H[3 * c + 1] +
+                            H[3 * r + 2] * H[3 * c + 2];
+            ff = fmaf(taub[3 * r + c], G, ff);
+        }
+    mub = ff;
+    lamb = (double)trt * lnJ;
+}
+
+// Adjoint state of particle slot q: load and store of xb, vb, Cb, Fb.
+__device__ __forceinline__ void load_adj(const AdjBuf &a, int N, uint32_t q, float xb[3], float vb[3], float Cb[9],
+                                         float Fb[9])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xb[c] = gload(a.xb + (size_t)c * N + q);
+        vb[c] = gload(a.vb + (size_t)c * N + q);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        Cb[c] = gload(a.Cb + (size_t)c * N + q);
+        Fb[c] = gload(a.Fb + (size_t)c * N + q);
+    }
+}
+
+__device__ __forceinline__ void store_adj(const AdjBuf &a, int N, uint32_t q, const float xb[3], const float vb[3],
+                                          const float Cb[9], const float Fb[9])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        gstore(a.xb + (size_t)c * N + q, xb[c]);
+        gstore(a.vb + (size_t)c * N + q, vb[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        gstore(a.Cb + (size_t)c * N + q, Cb[c]);
+        gstore(a.Fb + (size_t)c * N + q, Fb[c]);
+    }
+}
+
+// Shared memory of the tiled reverse kernels: node velocities (G2P reverse),
+// node adjoints (m, mv)bar (P2G reverse), per-half-wave tiles of the
+// node-velocity adjoint and the node pass's payloads.
+template <int W, bool PB, bool GV>
+struct AdjShared {
+    float4 tb[PB ? TILE_NODES : 1];
+    float4 tv[GV ? TILE_NODES : 1];
+    float4 tp[GV ? 2 * W * TILE_NODES : 1];
+    Payload4 pay[GV ? 64 * W : 1];
+};
+
+// Material of the tile's environment: mu, lambda, particle mass, stress factor.
+__device__ __forceinline__ void adj_material(const Dev &d, const EnvDev &e, int env, float &mu, float &lam, float &m,
+                                             float &kf)
+{
+    const float *mat = d.material + 4 * env;
+    const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
+    lame(E, nu, mu, lam);
+    m = rho * V0;
+    kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
+}
+
+// The tiled reverse pass over one item's particles.  PB: reverse of P2G of
+// substep j (state dp = slot j, node adjoints a.gPb); GV: then reverse of G2P
+// of the substep before, j - 1 with PB (state dg = slot j - 1, node velocities
+// dg.gV), scattering its node-velocity adjoint into a.gVb.  PB alone is the
+// reverse P2G of one substep, GV alone its reverse G2P; both at once walk two
+// reverse stages with one load and store of the particle adjoints.
+template <int W, bool PB, bool GV>
+__device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, const AdjBuf &a, const AdjTiledArgs &ta,
+                                               AdjShared<W, PB, GV> &sh)
 {
     constexpr int T = 64 * W;
-    __shared__ float4 tv[TILE_NODES];
-    __shared__ float4 tp[2 * W * TILE_NODES];
-    __shared__ Payload4 pay[T];
+    const Dev &d = GV ? dg : dp;   // environment tables (shared by both)
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);
     const int nitems = gload(ta.totals).y;
@@ -463,179 +772,136 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
         EnvDev e;
         const Tile t = make_tile(d, item, e);
         for (int n = tid; n < TILE_NODES; n += T) {
-            int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
-            for (int w = 0; w < 2 * W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
-            float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i < e.n && j < e.n && k < e.n) V = gload(d.gV + node_id(e, i, j, k));
-            tv[n] = V;
+            const int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
+            const bool in = i < e.n && j < e.n && k < e.n;
+            if (PB) sh.tb[n] = in ? gload(a.gPb + node_id(e, i, j, k)) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (GV) {
+                for (int w = 0; w < 2 * W; ++w) sh.tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
+                sh.tv[n] = in ? gload(dg.gV + node_id(e, i, j, k)) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         __syncthreads();
+        float mu = 0.f, lam = 0.f, m = 0.f, kf = 0.f;
+        if (PB) adj_material(d, e, t.env, mu, lam, m, kf);
         for (int chunk = item.y; chunk < item_end; chunk += T) {
             const int q = chunk + tid;
+            const bool active = q < item_end;
+            const uint32_t uq = (uint32_t)q;
+            double mub = 0.0, lamb = 0.0;
             int key = 0;
-            if (q < item_end) {
-                const uint32_t uq = (uint32_t)q;
-                float x0 = gload(d.x + uq), x1 = gload(d.x + N + uq), x2 = gload(d.x + 2 * N + uq);
-                Stencil s;
-                make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
-                if (!s.outside) {
-                    int l0, l1, l2;
-                    const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
-                    float dw[3][3];
-                    weight_grads(s, dw);
-                    // the particle's adjoint state first: Bbar and vbar_t do not depend on the
-                    // recomputed C, so one pass over the stencil serves C and the x adjoint
-                    const float cs = 4.0f * e.inv_dx;
-                    float H[9], Fb[9], Cb[9], xb[3], vb[3];
+            if (active) {
+                // reverse P2G terms first, into zeroed sums; the particle's adjoint
+                // state is loaded after them, so it is not held across the stencil sums
+                float xb[3] = {0.f, 0.f, 0.f}, vb[3] = {0.f, 0.f, 0.f};
+                float Cb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float Fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (PB) {
+                    Stencil s;
+                    make_stencil(gload(dp.x + uq), gload(dp.x + N + uq), gload(dp.x + 2 * N + uq), e.inv_dx, e.n, s);
+                    if (!s.outside) {
+                        float H[9], C[9], v[3];
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        H[c] = gload(d.H + (size_t)c * N + uq);
-                        Fb[c] = gload(a.Fb + (size_t)c * N + uq);
-                        Cb[c] = gload(a.Cb + (size_t)c * N + uq);
-                    }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        xb[c] = gload(a.xb + (size_t)c * N + uq);
-                        vb[c] = gload(a.vb + (size_t)c * N + uq);
-                    }
-                    float Bb[9];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float cbt = Cb[3 * r + c] + d.dt * (Fb[3 * r + c] + Fb[3 * r] * H[3 * c] + Fb[3 * r + 1] * H[3 * c + 1] +
-                                                                Fb[3 * r + 2] * H[3 * c + 2]);
-                            Bb[3 * r + c] = cs * cbt;
-                        }
-                    const float vbt[3] = {vb[0] + d.dt * xb[0], vb[1] + d.dt * xb[1], vb[2] + d.dt * xb[2]};
-                    // one pass: B = sum w V q^T (the recomputed C = (4/dx) B) and the x adjoint
-                    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    float fxb[3] = {0.f, 0.f, 0.f};
-                    // Separable form of the stencil sums.  Per node only wb = V . g(a)
-                    // (g(a) = vbar_t + Bbar (a - f), linear in the node offset a) and the
-                    // weighted node velocity are formed; the sums then run over the third
-                    // axis, the second and the first:
-                    //   B[i][j] = sum w V_i a_j - f_j S_i,  fxb[k] = sum (dw/dx_k) wb - (Bbar^T S)_k,
-                    //   S = sum w V.
-                    auto stencil_pass = [&](auto Vat) {
-                        float gf[3];   // vbar_t - Bbar f
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-                            gf[i] = vbt[i] - (Bb[3 * i] * s.fx[0] + Bb[3 * i + 1] * s.fx[1] + Bb[3 * i + 2] * s.fx[2]);
-                        float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
-                        float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-#pragma unroll
-                        for (int a0 = 0; a0 < 3; ++a0) {
-                            float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
-                            float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                            for (int a1 = 0; a1 < 3; ++a1) {
-                                float X = 0.f, Y = 0.f, AV[3] = {0.f, 0.f, 0.f}, BV[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                                for (int a2 = 0; a2 < 3; ++a2) {
-                                    const float4 V4 = Vat(a0, a1, a2);
-                                    const float V[3] = {V4.x, V4.y, V4.z};
-                                    const float w2 = s.w[2][a2];
-                                    float wb = 0.f;
-#pragma unroll
-                                    for (int i = 0; i < 3; ++i)
-                                        wb = fmaf(V[i], gf[i] + Bb[3 * i] * a0 + Bb[3 * i + 1] * a1 + Bb[3 * i + 2] * a2, wb);
-                                    X = fmaf(w2, wb, X);
-                                    Y = fmaf(dw[2][a2], wb, Y);
-#pragma unroll
-                                    for (int i = 0; i < 3; ++i) {
-                                        AV[i] = fmaf(w2, V[i], AV[i]);
-                                        BV[i] = fmaf(w2 * a2, V[i], BV[i]);
-                                    }
-                                }
-                                const float w1 = s.w[1][a1], d1 = dw[1][a1];
-                                X1 = fmaf(w1, X, X1);
-                                X1d = fmaf(d1, X, X1d);
-                                Y1 = fmaf(w1, Y, Y1);
-#pragma unroll
-                                for (int i = 0; i < 3; ++i) {
-                                    E1[i] = fmaf(w1, AV[i], E1[i]);
-                                    E2[i] = fmaf(w1 * a1, AV[i], E2[i]);
-                                    E3[i] = fmaf(w1, BV[i], E3[i]);
-                                }
-                            }
-                            const float w0 = s.w[0][a0], d0 = dw[0][a0];
-                            g0 = fmaf(d0, X1, g0);
-                            g1 = fmaf(w0, X1d, g1);
-                            g2 = fmaf(w0, Y1, g2);
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                S[i] = fmaf(w0, E1[i], S[i]);
-                                Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
-                                Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
-                                Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
-                            }
+                        for (int c = 0; c < 9; ++c) {
+                            H[c] = gload(dp.H + (size_t)c * N + uq);
+                            C[c] = gload(dp.C + (size_t)c * N + uq);
                         }
 #pragma unroll
-                        for (int i = 0; i < 3; ++i)
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) B[3 * i + j] = Mo[i][j] - s.fx[j] * S[i];
-                        fxb[0] = g0 - (Bb[0] * S[0] + Bb[3] * S[1] + Bb[6] * S[2]);
-                        fxb[1] = g1 - (Bb[1] * S[0] + Bb[4] * S[1] + Bb[7] * S[2]);
-                        fxb[2] = g2 - (Bb[2] * S[0] + Bb[5] * S[1] + Bb[8] * S[2]);
-                    };
-                    if (in_tile)
-                        stencil_pass([&](int a0, int a1, int a2) { return tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
-                    else
-                        stencil_pass([&](int a0, int a1, int a2) {
-                            return gload(d.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
-                        });
-                    float Fbn[9];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            Fbn[3 * r + c] = Fb[3 * r + c] + d.dt * cs * (B[r] * Fb[c] + B[3 + r] * Fb[3 + c] + B[6 + r] * Fb[6 + c]);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        gstore(a.xb + (size_t)c * N + uq, xb[c] + e.inv_dx * fxb[c]);
-                        gstore(a.vb + (size_t)c * N + uq, 0.0f);
+                        for (int c = 0; c < 3; ++c) v[c] = gload(dp.v + (size_t)c * N + uq);
+                        int l0, l1, l2;
+                        const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
+                        adj_p2g_particle(
+                            dp, e, s, H, C, v, mu, lam, m, kf, in_tile,
+                            [&](int a0, int a1, int a2) { return sh.tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; },
+                            [&](int a0, int a1, int a2) {
+                                return gload(a.gPb + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                            },
+                            xb, vb, Cb, Fb, mub, lamb);
                     }
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        gstore(a.Fb + (size_t)c * N + uq, Fbn[c]);
-                        gstore(a.Cb + (size_t)c * N + uq, 0.0f);
-                    }
-                    // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q)
-                    key = in_tile ? key_in_tile(l0, l1, l2) : key_global(s.b);
-                    store_payload(pay[tid], s.fx, key, vbt, Bb);
                 }
-            }
-            if (!key) pay[tid].fk.w = __int_as_float(0);
-            __syncthreads();
-            int r0, r1;
-            half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
-            // .x sums the weights (the flush skips nodes no particle reached)
-            node_pass(ta.slots, pay, r0, r1, tp + hw * TILE_NODES, lane, 1.0f, [&](const float4 &c4, int i, int j, int k) {
-                float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
-                gatomic_add(g + 0, c4.y);
-                gatomic_add(g + 1, c4.z);
-                gatomic_add(g + 2, c4.w);
-            });
-            __syncthreads();
-        }
-        for (int n = tid; n < TILE_NODES; n += T) {
-            float4 sum = tp[n];
+                {
+                    float axb[3], avb[3], aCb[9], aFb[9];
+                    load_adj(a, N, uq, axb, avb, aCb, aFb);
 #pragma unroll
-            for (int w = 1; w < 2 * W; ++w) {
-                float4 q4 = tp[w * TILE_NODES + n];
-                sum.x += q4.x; sum.y += q4.y; sum.z += q4.z; sum.w += q4.w;
+                    for (int c = 0; c < 3; ++c) { xb[c] += axb[c]; vb[c] += avb[c]; }
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) { Cb[c] += aCb[c]; Fb[c] += aFb[c]; }
+                }
+                if (GV) {
+                    Stencil s;
+                    make_stencil(gload(dg.x + uq), gload(dg.x + N + uq), gload(dg.x + 2 * N + uq), e.inv_dx, e.n, s);
+                    if (!s.outside) {   // a frozen particle's adjoints pass through
+                        float H[9];
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) H[c] = gload(dg.H + (size_t)c * N + uq);
+                        int l0, l1, l2;
+                        const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
+                        float vbt[3], Bb[9];
+                        adj_g2p_particle(
+                            dg, e, s, H, xb, vb, Cb, Fb, in_tile,
+                            [&](int a0, int a1, int a2) { return sh.tv[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; },
+                            [&](int a0, int a1, int a2) {
+                                return gload(dg.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
+                            },
+                            vbt, Bb);
+                        // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q)
+                        key = in_tile ? key_in_tile(l0, l1, l2) : key_global(s.b);
+                        store_payload(sh.pay[tid], s.fx, key, vbt, Bb);
+                    }
+                }
+                store_adj(a, N, uq, xb, vb, Cb, Fb);
             }
-            if (sum.x != 0.f) {
-                int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
-                float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
-                gatomic_add(g + 0, sum.y);
-                gatomic_add(g + 1, sum.z);
-                gatomic_add(g + 2, sum.w);
+            if (PB) {
+                // every particle of an item belongs to the tile's environment
+                wave_env_add(a.mubar, t.env, mub, active);
+                wave_env_add(a.lambar, t.env, lamb, active);
+            }
+            if (GV) {
+                if (!key) sh.pay[tid].fk.w = __int_as_float(0);
+                __syncthreads();
+                int r0, r1;
+                half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
+                // .x sums the weights (the flush skips nodes no particle reached)
+                node_pass(ta.slots, sh.pay, r0, r1, sh.tp + hw * TILE_NODES, lane, 1.0f,
+                          [&](const float4 &c4, int i, int j, int k) {
+                              float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
+                              gatomic_add(g + 0, c4.y);
+                              gatomic_add(g + 1, c4.z);
+                              gatomic_add(g + 2, c4.w);
+                          });
+                __syncthreads();
+            }
+        }
+        if (GV) {
+            for (int n = tid; n < TILE_NODES; n += T) {
+                float4 sum = sh.tp[n];
+#pragma unroll
+                for (int w = 1; w < 2 * W; ++w) {
+                    const float4 q4 = sh.tp[w * TILE_NODES + n];
+                    sum.x += q4.x; sum.y += q4.y; sum.z += q4.z; sum.w += q4.w;
+                }
+                if (sum.x != 0.f) {
+                    const int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
+                    float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
+                    gatomic_add(g + 0, sum.y);
+                    gatomic_add(g + 1, sum.z);
+                    gatomic_add(g + 2, sum.w);
+                }
             }
         }
         __syncthreads();
     }
+}
+
+// Reverse of G2P + advection + F update (pass 1, lane = particle: C' from
+// the tape's node velocities in an LDS tile, the particle adjoints and the
+// weight-gradient terms; pass 2, lane = stencil node: w (vbar_t + Bbar q)
+// into per-half-wave tiles, flushed to the node-velocity adjoint with one
+// float atomic per component).
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTiledArgs ta)
+{
+    __shared__ AdjShared<W, false, true> sh;
+    adj_tiled_body<W, false, true>(d, d, a, ta, sh);
 }
 
 // Reverse of P2G and of the stress, gathering the node adjoints (m, mv)bar
@@ -643,198 +909,17 @@ __global__ __launch_bounds__(64 * W) void k_adj_g2p_tiled(Dev d, AdjBuf a, AdjTi
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTiledArgs ta)
 {
-    constexpr int T = 64 * W;
-    __shared__ float4 tb[TILE_NODES];
-    const int N = d.ntot, tid = threadIdx.x;
-    const int nitems = gload(ta.totals).y;
-    int first, stride, end;
-    item_range(nitems, first, stride, end);
-    int4 next = first < end ? gload(ta.items + first) : make_int4(0, 0, 0, 0);
-    for (int it = first; it < end; it += stride) {
-        const int4 item = next;   // loaded one iteration ahead
-        if (it + stride < end) next = gload(ta.items + it + stride);
-        EnvDev e;
-        const Tile t = make_tile(d, item, e);
-        for (int n = tid; n < TILE_NODES; n += T) {
-            int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
-            float4 Pb = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i < e.n && j < e.n && k < e.n) Pb = gload(a.gPb + node_id(e, i, j, k));
-            tb[n] = Pb;
-        }
-        __syncthreads();
-        const float *mat = d.material + 4 * t.env;
-        const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
-        float mu, lam;
-        lame(E, nu, mu, lam);
-        const float m = rho * V0;
-        const float kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
-        for (int chunk = item.y; chunk < item.y + item.z; chunk += T) {
-            const int q = chunk + tid;
-            bool active = q < item.y + item.z;
-            double mub = 0.0, lamb = 0.0;
-            if (active) {
-                float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
-                Stencil s;
-                make_stencil(x0, x1, x2, e.inv_dx, e.n, s);
-                if (!s.outside) {
-                    int l0, l1, l2;
-                    const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
-                    float H[9], F[9], C[9], v[3], tau[9], A[9];
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        H[c] = gload(d.H + (size_t)c * N + q);
-                        F[c] = H[c] + ((c & 3) == 0 ? 1.0f : 0.0f);
-                        C[c] = gload(d.C + (size_t)c * N + q);
-                    }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) v[c] = gload(d.v + (size_t)c * N + q);
-                    // the forward's FP32 stress (same formulas, same inversion decision)
-                    const float jm1 = jm1_f(H);
-                    const bool inverted = inverted_f(H, jm1);
-                    kirchhoff_f(H, jm1, inverted, mu, lam, tau);
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) A[c] = kf * tau[c] + m * C[c];
-                    float dw[3][3];
-                    weight_grads(s, dw);
-                    float vbp[3] = {0.f, 0.f, 0.f}, Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    float fxb[3] = {0.f, 0.f, 0.f};
-                    const float dx = e.dx;
-                    // Separable form of the stencil sums.  Per node only the momentum
-                    // weight wb = m pm + q . c(a) (c(a) = m v + A (a - f) dx, the affine
-                    // momentum at node offset a) and the node's weighted values are formed;
-                    // the sums then run over the third axis, the second and the first:
-                    //   vbp = m S,  Ab[i][j] = dx (sum w q_i a_j - f_j S_i),
-                    //   fxb[k] = sum (dw/dx_k) wb - dx (A^T S)_k,  S = sum w q.
-                    auto stencil_pass = [&](auto Pat) {
-                        float lam[3][3], cf[3];   // lam[j][i] = dx A[i][j]; cf = m v - dx A f
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) lam[j][i] = dx * A[3 * i + j];
-                            cf[i] = m * v[i] - (lam[0][i] * s.fx[0] + lam[1][i] * s.fx[1] + lam[2][i] * s.fx[2]);
-                        }
-                        float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // sum of (dw/dx_k) wb
-                        float S[3] = {0.f, 0.f, 0.f}, Mo[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-#pragma unroll
-                        for (int a0 = 0; a0 < 3; ++a0) {
-                            float X1 = 0.f, X1d = 0.f, Y1 = 0.f;
-                            float E1[3] = {0.f, 0.f, 0.f}, E2[3] = {0.f, 0.f, 0.f}, E3[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                            for (int a1 = 0; a1 < 3; ++a1) {
-                                float X = 0.f, Y = 0.f, AQ[3] = {0.f, 0.f, 0.f}, BQ[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                                for (int a2 = 0; a2 < 3; ++a2) {
-                                    const float4 Pb = Pat(a0, a1, a2);
-                                    const float q[3] = {Pb.y, Pb.z, Pb.w};
-                                    const float w2 = s.w[2][a2];
-                                    float wb = m * Pb.x;
-#pragma unroll
-                                    for (int i = 0; i < 3; ++i)
-                                        wb = fmaf(q[i], cf[i] + lam[0][i] * a0 + lam[1][i] * a1 + lam[2][i] * a2, wb);
-                                    X = fmaf(w2, wb, X);
-                                    Y = fmaf(dw[2][a2], wb, Y);
-#pragma unroll
-                                    for (int i = 0; i < 3; ++i) {
-                                        AQ[i] = fmaf(w2, q[i], AQ[i]);
-                                        BQ[i] = fmaf(w2 * a2, q[i], BQ[i]);
-                                    }
-                                }
-                                const float w1 = s.w[1][a1], d1 = dw[1][a1];
-                                X1 = fmaf(w1, X, X1);
-                                X1d = fmaf(d1, X, X1d);
-                                Y1 = fmaf(w1, Y, Y1);
-#pragma unroll
-                                for (int i = 0; i < 3; ++i) {
-                                    E1[i] = fmaf(w1, AQ[i], E1[i]);
-                                    E2[i] = fmaf(w1 * a1, AQ[i], E2[i]);
-                                    E3[i] = fmaf(w1, BQ[i], E3[i]);
-                                }
-                            }
-                            const float w0 = s.w[0][a0], d0 = dw[0][a0];
-                            g0 = fmaf(d0, X1, g0);
-                            g1 = fmaf(w0, X1d, g1);
-                            g2 = fmaf(w0, Y1, g2);
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                S[i] = fmaf(w0, E1[i], S[i]);
-                                Mo[i][0] = fmaf(w0 * a0, E1[i], Mo[i][0]);
-                                Mo[i][1] = fmaf(w0, E2[i], Mo[i][1]);
-                                Mo[i][2] = fmaf(w0, E3[i], Mo[i][2]);
-                            }
-                        }
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            vbp[i] = m * S[i];
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) Ab[3 * i + j] = dx * (Mo[i][j] - s.fx[j] * S[i]);
-                        }
-                        fxb[0] = g0 - dx * (A[0] * S[0] + A[3] * S[1] + A[6] * S[2]);
-                        fxb[1] = g1 - dx * (A[1] * S[0] + A[4] * S[1] + A[7] * S[2]);
-                        fxb[2] = g2 - dx * (A[2] * S[0] + A[5] * S[1] + A[8] * S[2]);
-                    };
-                    if (in_tile)
-                        stencil_pass([&](int a0, int a1, int a2) { return tb[((l0 + a0) * TILE + l1 + a1) * TILE + l2 + a2]; });
-                    else
-                        stencil_pass([&](int a0, int a1, int a2) {
-                            return gload(a.gPb + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
-                        });
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float *px = a.xb + (size_t)c * N + q;
-                        gstore(px, gload(px) + e.inv_dx * fxb[c]);
-                        float *pv = a.vb + (size_t)c * N + q;
-                        gstore(pv, gload(pv) + vbp[c]);
-                    }
-                    float taub[9];
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        float *pc = a.Cb + (size_t)c * N + q;
-                        gstore(pc, gload(pc) + m * Ab[c]);
-                        taub[c] = kf * Ab[c];
-                    }
-                    float Fb[9];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            Fb[3 * r + c] = mu * ((taub[3 * r] + taub[r]) * F[c] + (taub[3 * r + 1] + taub[3 + r]) * F[3 + c] +
-                                                  (taub[3 * r + 2] + taub[6 + r]) * F[6 + c]);
-                    // tau-bar -> F-bar: mu (tau-bar + tau-bar^T) F + lam tr(tau-bar) cof(F) / J
-                    const float trt = taub[0] + taub[4] + taub[8];
-                    const float lnJ = inverted ? -13.815510557964274f : log1pf(jm1);
-                    if (!inverted) {
-                        const float ci[9] = {F[4] * F[8] - F[5] * F[7], -(F[3] * F[8] - F[5] * F[6]), F[3] * F[7] - F[4] * F[6],
-                                             -(F[1] * F[8] - F[2] * F[7]), F[0] * F[8] - F[2] * F[6], -(F[0] * F[7] - F[1] * F[6]),
-                                             F[1] * F[5] - F[2] * F[4], -(F[0] * F[5] - F[2] * F[3]), F[0] * F[4] - F[1] * F[3]};
-                        const float sc = lam * trt / (1.0f + jm1);
-#pragma unroll
-                        for (int c = 0; c < 9; ++c) Fb[c] = fmaf(sc, ci[c], Fb[c]);
-                    }
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) {
-                        float *pf = a.Fb + (size_t)c * N + q;
-                        gstore(pf, gload(pf) + Fb[c]);
-                    }
-                    // dL/dmu and dL/dlam of this particle (summed per environment in FP64)
-                    float ff = 0.0f;
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const float G = H[3 * r + c] + H[3 * c + r] + H[3 * r] * H[3 * c] + H[3 * r + 1] * H[3 * c + 1] +
-                                            H[3 * r + 2] * H[3 * c + 2];
-                            ff = fmaf(taub[3 * r + c], G, ff);
-                        }
-                    mub = ff;
-                    lamb = (double)trt * lnJ;
-                }
-            }
-            // every particle of an item belongs to the tile's environment
-            wave_env_add(a.mubar, t.env, mub, active);
-            wave_env_add(a.lambar, t.env, lamb, active);
-        }
-        __syncthreads();
-    }
+    __shared__ AdjShared<W, true, false> sh;
+    adj_tiled_body<W, true, false>(d, d, a, ta, sh);
+}
+
+// Reverse P2G of substep j (dp: slot j) and reverse G2P of substep j - 1
+// (dg: slot j - 1) in one pass over the particles.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBuf a, AdjTiledArgs ta)
+{
+    __shared__ AdjShared<W, true, true> sh;
+    adj_tiled_body<W, true, true>(dp, dg, a, ta, sh);
 }
 
 // dst[c][q] = src[c][perm[q]] (gather into slot order) or the reverse scatter.
@@ -902,6 +987,15 @@ void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, cons
     if (block == 64) launch_k((k_adj_p2g_tiled<1>), dim3(nblocks), dim3(64), 0, st, d, a, ta);
     else if (block == 128) launch_k((k_adj_p2g_tiled<2>), dim3(nblocks), dim3(128), 0, st, d, a, ta);
     else launch_k((k_adj_p2g_tiled<4>), dim3(nblocks), dim3(256), 0, st, d, a, ta);
+}
+
+void launch_adj_pair_tiled(const Dev &dp, const Dev &dg, const AdjBuf &a, const int4 *items, const int2 *totals,
+                           int slots, const ActiveBuf &act, int block, int nblocks, hipStream_t st)
+{
+    AdjTiledArgs ta{items, totals, slots, act};
+    if (block == 64) launch_k((k_adj_pair_tiled<1>), dim3(nblocks), dim3(64), 0, st, dp, dg, a, ta);
+    else if (block == 128) launch_k((k_adj_pair_tiled<2>), dim3(nblocks), dim3(128), 0, st, dp, dg, a, ta);
+    else launch_k((k_adj_pair_tiled<4>), dim3(nblocks), dim3(256), 0, st, dp, dg, a, ta);
 }
 
 void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter,

@@ -37,6 +37,10 @@ void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, cons
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st);
 void launch_adj_p2g_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals,
                           const ActiveBuf &act, int block, int nblocks, hipStream_t st);
+// reverse P2G of substep j (dp: its recorded state) and reverse G2P of substep
+// j - 1 (dg: its recorded state, node velocities dg.gV) in one kernel
+void launch_adj_pair_tiled(const Dev &dp, const Dev &dg, const AdjBuf &a, const int4 *items, const int2 *totals,
+                           int slots, const ActiveBuf &act, int block, int nblocks, hipStream_t st);
 // scatter == 0: dst[c][q] = src[c][perm[q]]; scatter != 0: dst[c][perm[q]] = src[c][q]
 void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter,
                     hipStream_t st);
