@@ -118,27 +118,11 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
     int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
-    // a single environment (and its material) is loaded once, beside the first
-    // item, so a tile's node loads wait for the item alone
-    const bool one_env = d.n_envs == 1;
-    EnvDev e1{};
-    float mat1[4] = {0.f, 0.f, 0.f, 0.f};
-    if (one_env) {
-        e1 = load_env(d.env);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) mat1[c] = gload(d.material + c);
-    }
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
         EnvDev e;
-        Tile t;
-        if (one_env) {
-            e = e1;
-            t = tile_of(e, item);
-        } else {
-            t = make_tile(d, item, e);
-        }
+        const Tile t = make_tile(d, item, e);
         const int item_end = item.y + item.z;
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass
@@ -155,14 +139,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         prefetch(item.y);
         float mu = 0.f, lam = 0.f, m = 0.f, V0 = 0.f;
         if (P2G) {
-            float E, nu, rho;
-            if (one_env) {
-                E = mat1[0]; nu = mat1[1]; rho = mat1[2]; V0 = mat1[3];
-            } else {
-                const float *mat = d.material + 4 * t.env;
-                E = gload(mat); nu = gload(mat + 1); rho = gload(mat + 2);
-                V0 = gload(mat + 3);
-            }
+            const float *mat = d.material + 4 * t.env;
+            const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2);
+            V0 = gload(mat + 3);
             lame(E, nu, mu, lam);
             m = rho * V0;
         }

@@ -41,22 +41,6 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev
     return t;
 }
 
-// Tile of a work item of the environment e already loaded.
-__device__ __forceinline__ Tile tile_of(const EnvDev &e, const int4 &item)
-{
-    Tile t;
-    t.env = item.w;
-    const int lb = item.x - e.bofs;
-    t.bk = lb % e.nb;
-    const int r = lb / e.nb;
-    t.bj = r % e.nb;
-    t.bi = r / e.nb;
-    t.o[0] = 4 * t.bi;
-    t.o[1] = 4 * t.bj;
-    t.o[2] = 4 * t.bk;
-    return t;
-}
-
 // Item walk: workgroup x + NXCD r runs on XCD x (workgroups are dealt to the
 // XCDs round-robin) and takes every (G / NXCD)-th item, from its r-th on, of
 // the contiguous eighth of the (spatially ordered) item list that belongs to
