@@ -50,10 +50,14 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 #   per active grid node: P2G writes (m, mv) 16 B, the grid operation reads
 #   them (16 B) and writes v (12 B), G2P reads v (12 B) = 56 B
 # The fused G2P+P2G kernel alone moves 96 B per particle + 28 B per active node.
+# With the grid operation at tile staging (one launch per substep) v never
+# reaches memory: P2G writes (m, mv) 16 B and the next launch reads them 16 B,
+# 32 B per active node for the substep and for its one kernel.
 BYTES_PER_PARTICLE = 96
 BYTES_PER_NODE_SUBSTEP = 56
 BYTES_PER_NODE_FUSED = 28
 BYTES_PER_NODE_GRID = 28
+BYTES_PER_NODE_GAS = 32
 # Forward with tape + adjoint, per particle-substep: the recorded forward (96),
 # its recompute in reverse (96), the reverse substep (primal x, v, C, F read
 # 96 B + adjoint x, v, C, F read and written 192 B + node adjoints ~100 B =
@@ -324,7 +328,11 @@ def cpu_baseline(scene, substeps: int, serial_substeps: int):
                        "cores": 1}}
 
 
-def _roofline(rep, N, nodes, K, traffic):
+def uses_gas(L, options) -> bool:
+    return bool(options.get(L.OPT_GRID_AT_STAGING, 0)) and not options.get(L.OPT_PERSISTENT, 0)
+
+
+def _roofline(rep, N, nodes, K, traffic, gas=False):
     """Roofline of the dominant kernel (by total time) from the library's
     event timer: algorithmic bytes per launch over its average duration."""
     dom = max(rep, key=lambda k: rep[k][0])
@@ -334,7 +342,7 @@ def _roofline(rep, N, nodes, K, traffic):
         # one launch runs a whole run of substeps between sorts
         per_launch = (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) * K / n_launch
     elif dom.startswith("fused"):
-        per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_FUSED
+        per_launch = N * BYTES_PER_PARTICLE + nodes * (BYTES_PER_NODE_GAS if gas else BYTES_PER_NODE_FUSED)
     elif dom.startswith("grid"):
         per_launch = nodes * BYTES_PER_NODE_GRID
     else:
@@ -398,7 +406,7 @@ def _form_large(torch, L, Sim, tune, out, steps=64, warmup=10):
     nodes = active_nodes(ls.read(L.F_X, 0, device=False).T, int(ls.gn[0]))
     rep = event_pass(torch, L, ls, steps, se)
     kernels = {k: {"avg_us": 1e3 * t / n, "launches": n, "total_ms": t} for k, (t, n) in rep.items()}
-    roof = _roofline(rep, N, nodes, steps, lambda k: stored_traffic("large", k, ls.options))
+    roof = _roofline(rep, N, nodes, steps, lambda k: stored_traffic("large", k, ls.options), uses_gas(L, ls.options))
     out["large"] = {"workload": "large slab 1,048,576 particles, 128^3 grid, sticky capsule pull along a "
                                 "4-leg path at 0.2 m/s, dt 2e-5",
                     "particles": N, "substeps": steps, "sort_every": se, "sorts_in_window": 1 + (steps - 1) // se,
@@ -423,6 +431,7 @@ def main():
     ap.add_argument("--graph", type=int, default=None)
     ap.add_argument("--persistent", type=int, default=None)
     ap.add_argument("--slots", type=int, default=None, help="node-pass particles per half-wave step (1 or 3)")
+    ap.add_argument("--gas", type=int, default=None, help="grid operation at tile staging (1) or a grid kernel (0)")
     ap.add_argument("--cpu-substeps", type=int, default=None,
                     help="oracle substeps for the CPU baseline (default: about 10-20 s of CPU work)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -470,6 +479,7 @@ def main():
     if args.graph is not None: opts[L.OPT_GRAPH] = args.graph
     if args.persistent is not None: opts[L.OPT_PERSISTENT] = args.persistent
     if args.slots is not None: opts[L.OPT_NODE_SLOTS] = args.slots
+    if args.gas is not None: opts[L.OPT_GRID_AT_STAGING] = args.gas
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -498,7 +508,8 @@ def main():
     if not args.no_profile_pass:
         rep = event_pass(torch, L, sim, K, se)
         kernels = {k: {"avg_us": 1e3 * t / n, "launches": n, "total_ms": t} for k, (t, n) in rep.items()}
-        roofline = _roofline(rep, N, nodes, K, lambda k: stored_traffic(args.config, k, sim.options))
+        roofline = _roofline(rep, N, nodes, K, lambda k: stored_traffic(args.config, k, sim.options),
+                             uses_gas(L, sim.options))
         print(f"# kernels: " + ", ".join(f"{k} {v['avg_us']:.2f}us x{v['launches']}" for k, v in kernels.items()),
               file=sys.stderr, flush=True)
 
@@ -537,7 +548,8 @@ def main():
                    "sort_every": se, "sorts_in_window": sorts,
                    "scheme": args.scheme, "options": {str(k): v for k, v in sim.options.items()},
                    "active_nodes": nodes,
-                   "algorithmic_bytes_per_substep": N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP},
+                   "algorithmic_bytes_per_substep": N * BYTES_PER_PARTICLE + nodes * (
+                       BYTES_PER_NODE_GAS if uses_gas(L, sim.options) else BYTES_PER_NODE_SUBSTEP)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

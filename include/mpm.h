@@ -78,7 +78,8 @@ enum {
     MPM_F_GRID_MV = 5,  /* float [3][n^3]: momentum held in the momentum buffer, as MPM_F_GRID_M */
     MPM_F_GRID_V = 6,   /* float [3][n^3]: velocity after the last grid operation (Sec. III-B item 2); the
                            tiled grid operation writes only nodes that received mass, the others keep
-                           older values (no particle's stencil reads them) */
+                           older values (no particle's stencil reads them); with MPM_OPT_GRID_AT_STAGING
+                           the last substep of a call writes the nodes of bricks that hold particles */
     MPM_F_STATUS = 7,   /* uint32 [1]: sticky MPM_FLAG_* bits of the environment */
     MPM_F_TOOL_T = 8,   /* double [max_tools][3]: current tool positions */
     MPM_F_STEP = 9,     /* int32 [1]: substeps taken by the environment */
@@ -135,8 +136,15 @@ enum {
                                  copy, so set it outside stream capture */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
     MPM_OPT_ITEM = 6,         /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
-    MPM_OPT_NODE_SLOTS = 7    /* tiled scheme: particles per half-wavefront step of the P2G node pass, 1 or 3
+    MPM_OPT_NODE_SLOTS = 7,   /* tiled scheme: particles per half-wavefront step of the P2G node pass, 1 or 3
                                  (3: a third of the arithmetic per node, better at many particles per cell) */
+    MPM_OPT_GRID_AT_STAGING = 8 /* tiled scheme, 1: one launch per substep.  The particle pass applies
+                                 the grid operation (Sec. III-B item 2) to each node of its 8^3 velocity
+                                 tile as it stages it, from the momentum of the substep, so no grid
+                                 kernel runs in between; momentum grids rotate over three buffers.
+                                 Pays where work items are few and full (one slab); used without
+                                 sampled-SDF tools and without MPM_OPT_PERSISTENT.  0 (default): a grid
+                                 kernel over the listed bricks between particle passes */
 };
 enum {
     MPM_SCHEME_DIRECT = 0,    /* one thread per particle, global float atomics, dense grid pass */

@@ -22,12 +22,13 @@ SDF_NEAREST, SDF_TRILINEAR = 0, 1
 CONTACT_SLIP, CONTACT_STICKY = 0, 1
 STAGE_P2G, STAGE_GRID, STAGE_G2P = 0, 1, 2
 STAGE_TILED_P2G, STAGE_TILED_GRID, STAGE_TILED_FUSED, STAGE_TILED_FUSED_FULL, STAGE_TILED_G2P = 3, 4, 5, 6, 7
-OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM, OPT_NODE_SLOTS = range(8)
+(OPT_SCHEME, OPT_SORT_EVERY, OPT_BLOCK, OPT_GRAPH, OPT_PERSISTENT, OPT_SPIN_LIMIT, OPT_ITEM, OPT_NODE_SLOTS,
+ OPT_GRID_AT_STAGING) = range(9)
 SCHEME_DIRECT, SCHEME_TILED = 0, 1
 STATIC_WORKSPACE_BYTES = 64 << 20   # MPM_STATIC_WORKSPACE_BYTES: the workspace of mpm_create_static
 # option values a new context starts with
 OPT_DEFAULTS = {OPT_SCHEME: SCHEME_TILED, OPT_SORT_EVERY: 16, OPT_BLOCK: 256, OPT_GRAPH: 0, OPT_PERSISTENT: 0,
-                OPT_ITEM: 512, OPT_NODE_SLOTS: 3}
+                OPT_ITEM: 512, OPT_NODE_SLOTS: 3, OPT_GRID_AT_STAGING: 0}
 
 EXPORTS = ["mpm_workspace_size", "mpm_create", "mpm_create_static", "mpm_destroy", "mpm_set_tool", "mpm_set_option",
            "mpm_substep", "mpm_run_stage", "mpm_substep_adjoint", "mpm_read_state", "mpm_last_error",

@@ -2,7 +2,8 @@
 
 Searches, in stages, the workgroup size (MPM_OPT_BLOCK) with the particles per
 work item (MPM_OPT_ITEM) and the node-pass form (MPM_OPT_NODE_SLOTS), the sort
-interval (MPM_OPT_SORT_EVERY), and the
+interval (MPM_OPT_SORT_EVERY), the grid operation at tile staging
+(MPM_OPT_GRID_AT_STAGING), and the
 persistent kernel (MPM_OPT_PERSISTENT) with or without graph replay
 (MPM_OPT_GRAPH) for a scene, timing short runs with HIP events on the
 stream the library launches on.  Every setting gives the same results up to
@@ -65,7 +66,7 @@ def _time(sim: Sim, substeps: int, warmup: int, repeats: int = 2) -> float:
 
 def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = CACHE,
              blocks=(64, 128, 256), items=(32, 64, 128, 256, 512, 1024), sort_every=(8, 16, 32, 64),
-             graph=(0, 1), persistent=(0, 1), slots=(1, 3), verbose: bool = False,
+             graph=(0, 1), persistent=(0, 1), slots=(1, 3), grid_at_staging=(0, 1), verbose: bool = False,
              use_shipped: bool = True) -> Dict[int, int]:
     """Best options {MPM_OPT_*: value} for this scene (tiled scheme)."""
     key = workload_key(scene)
@@ -84,7 +85,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
 
     sim = Sim(scene, options={L.OPT_SCHEME: L.SCHEME_TILED})
     best = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: 256, L.OPT_ITEM: 512, L.OPT_SORT_EVERY: 16,
-            L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0, L.OPT_NODE_SLOTS: 3}
+            L.OPT_GRAPH: 0, L.OPT_PERSISTENT: 0, L.OPT_NODE_SLOTS: 3, L.OPT_GRID_AT_STAGING: 0}
     log: List[dict] = []
 
     def trial(opts):
@@ -111,6 +112,7 @@ def autotune(scene, substeps: int = 40, warmup: int = 5, cache: Optional[str] = 
 
     stage([{L.OPT_BLOCK: b, L.OPT_ITEM: i, L.OPT_NODE_SLOTS: n} for b in blocks for i in items for n in slots])
     stage([{L.OPT_SORT_EVERY: k} for k in sort_every])
+    stage([{L.OPT_GRID_AT_STAGING: g} for g in grid_at_staging])
     stage([{L.OPT_PERSISTENT: p, L.OPT_GRAPH: g} for p in persistent for g in graph])
     sim.close()
     if cache:

@@ -60,6 +60,10 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.pid = cv.take<int32_t>(s.ntot);
     c.gP = cv.take<float4>(s.total_nodes);
     c.gV = cv.take<float4>(s.total_nodes);
+    c.gP1 = cv.take<float4>(s.total_nodes);
+    c.gP2 = cv.take<float4>(s.total_nodes);
+    c.poses = cv.take<ToolPose>((size_t)2 * s.n_envs * std::max(1, s.max_tools));
+    c.far_stamp = cv.take<int32_t>(4);
     // surface extraction
     c.surf.rho = cv.take<float>(s.max_env_nodes);
     c.surf.ofs = cv.take<int32_t>(s.max_env_cells);
@@ -137,7 +141,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
 bool all_carved(const mpm_ctx &c)
 {
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
-                       c.gP, c.gV, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
+                       c.gP, c.gV, c.gP1, c.gP2, c.poses, c.far_stamp, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
                        c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.wg_tab, c.arrive, c.elist, c.act.env_bofs,
                        c.surf.rho, c.surf.ofs, c.surf.chunk, c.surf.table};
@@ -423,6 +427,76 @@ mpm_status build_groups(mpm_ctx *c)
     return MPM_OK;
 }
 
+// n substeps with the grid operation at tile staging, one launch per substep.
+// Momentum grids rotate over three buffers: substep i (0-based) reads
+// buf[i % 3], its P2G writes buf[(i + 1) % 3], and it clears buf[(i + 2) % 3],
+// which held the momentum of substep i - 1 (read by the launch before).  A
+// clear covers the static brick list, or the whole grid when that momentum was
+// written before the last sort (a different static list) or reached a brick
+// outside its neighbourhood (a stamp).  The call ends with the clear of the
+// buffer the tail read, so every call starts and ends with all three zero.
+// Tool poses alternate between two pose arrays.  Particles enter from `in`
+// (the sort destination right after a sort).
+void substeps_gas(mpm_ctx *c, int n, ParticleBuf in, hipStream_t st)
+{
+    float4 *buf[3] = {c->gP, c->gP1, c->gP2};
+    const size_t slots = c->tool_slots();
+    ToolPose *pose[2] = {c->poses, c->poses + slots};
+    if (c->gas_blocks == 0) c->gas_blocks = tiled_workgroups(c->block, true);
+    const int nb = c->gas_blocks;
+    const ParticleBuf A = live(c);
+    const int m0 = c->gas_count;   // stamp of substep i's momentum: m0 + i
+    int sorted_at = -10;   // substep before which a sort ran mid-call (a sort before the head needs nothing)
+    auto args = [&](const ParticleBuf &i_, const ParticleBuf &o_) {
+        TiledArgs a = tiled_args(c, i_, o_, 0);
+        a.total_nodes = c->total_nodes;
+        a.far_stamp = c->far_stamp;
+        return a;
+    };
+    {
+        Dev d = c->dev();
+        d.gP = buf[0];
+        TiledArgs a = args(in, in);
+        a.write_slot = m0 & 3;
+        a.write_stamp = m0;
+        a.pose_out = pose[0];
+        timed(c, st, PK_P2G_TILED, [&] { launch_gas_head(d, a, c->block, nb, st); });
+    }
+    for (int i = 0; i < n; ++i) {
+        if (i > 0 && i < n - 1 && c->since_sort >= c->sort_every && in.x == A.x) {
+            sort_into_alt(c, st);
+            in = c->alt;
+            sorted_at = i;
+        }
+        const bool tail = i == n - 1;
+        Dev d = c->dev();
+        d.gP = tail ? nullptr : buf[(i + 1) % 3];
+        TiledArgs a = args(in, A);
+        a.gP_read = buf[i % 3];
+        a.gP_clear = i >= 1 ? buf[(i + 2) % 3] : nullptr;
+        // the momentum of substep i - 1 was written under the old static list if a sort ran before i or i - 1
+        a.full_clear = (sorted_at == i || sorted_at == i - 1) ? 1 : 0;
+        a.clear_slot = (m0 + i - 1) & 3;
+        a.clear_stamp = m0 + i - 1;
+        a.write_slot = (m0 + i + 1) & 3;
+        a.write_stamp = m0 + i + 1;
+        a.pose_in = pose[i & 1];
+        a.pose_out = pose[(i + 1) & 1];
+        if (tail) timed(c, st, PK_G2P_TILED, [&] { launch_gas_tail(d, a, c->block, nb, st); });
+        else timed(c, st, PK_FUSED_TILED, [&] { launch_gas_fused(d, a, c->block, nb, st); });
+        in = A;
+        c->since_sort += 1;
+    }
+    // the tail read buf[(n - 1) % 3]: clear it for the next call
+    TiledArgs a = args(A, A);
+    a.gP_clear = buf[(n - 1) % 3];
+    a.full_clear = sorted_at == n - 1 ? 1 : 0;
+    a.clear_slot = (m0 + n - 1) & 3;
+    a.clear_stamp = m0 + n - 1;
+    timed(c, st, PK_FILL, [&] { launch_gas_clear(c->dev(), a, st); });
+    c->gas_count = m0 + n;
+}
+
 // n substeps of the tiled scheme:
 //   [sort] head P2G, then n x (grid op, fused G2P+P2G) with the last fused
 //   step replaced by a G2P-only tail that materialises v and C.
@@ -470,6 +544,10 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         }
         return;
     }
+    if (c->grid_at_staging && !c->has_sdf) {
+        substeps_gas(c, n, in, st);
+        return;
+    }
     // substep i: P2G lists far bricks in dynamic list i&1, its grid operation consumes it
     timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, tiled_args(c, in, in, 0), c->block, nb, st); });
     for (int i = 0; i < n; ++i) {
@@ -508,7 +586,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
     for (auto &g : c->graphs)
         if (g.n == n && g.scheme == c->scheme && g.block == c->block && g.item == c->item &&
             g.sort_every == c->sort_every && g.persistent == c->persistent && g.node_slots == c->node_slots &&
-            g.sdf == c->has_sdf)
+            g.sdf == c->has_sdf && g.gas == c->grid_at_staging)
             ge = &g;
     if (!ge) {
         if (c->scheme == MPM_SCHEME_TILED && c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -524,6 +602,7 @@ mpm_status run_substeps_graph(mpm_ctx *c, int n, hipStream_t st)
         g.persistent = c->persistent;
         g.node_slots = c->node_slots;
         g.sdf = c->has_sdf;
+        g.gas = c->grid_at_staging;
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(c, MPM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -922,6 +1001,9 @@ mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_byt
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->step), s.n_envs, 0u, st);
         launch_fill_f4(c->gP, s.total_nodes, st);
         launch_fill_f4(c->gV, s.total_nodes, st);
+        launch_fill_f4(c->gP1, s.total_nodes, st);
+        launch_fill_f4(c->gP2, s.total_nodes, st);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->far_stamp), 4, 0xffffffffu, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.count), (int64_t)s.total_bricks * 64, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.brick_count), s.total_bricks, 0u, st);
@@ -1083,6 +1165,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         if (value != 64 && value != 128 && value != 256) return fail(c, MPM_E_ARG, "block must be 64, 128 or 256");
         c->block = value;
         c->tiled_blocks = 0;
+        c->gas_blocks = 0;
         return c->persistent ? build_groups(c) : MPM_OK;
     case MPM_OPT_ITEM:
         if (value < 16 || value > 4096 || value % 16) return fail(c, MPM_E_ARG, "item size must be a multiple of 16 in [16, 4096]");
@@ -1098,6 +1181,9 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
     case MPM_OPT_PERSISTENT:
         c->persistent = value != 0;
         return c->persistent ? build_groups(c) : MPM_OK;
+    case MPM_OPT_GRID_AT_STAGING:
+        c->grid_at_staging = value != 0;
+        return MPM_OK;
     case MPM_OPT_SPIN_LIMIT:
         if (value < 1) return fail(c, MPM_E_ARG, "spin limit must be > 0");
         c->spin_limit = value;

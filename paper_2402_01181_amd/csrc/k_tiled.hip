@@ -95,35 +95,121 @@ __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, c
 // per clock per CU on this chip, far below plain LDS traffic.  The 2W tiles
 // are summed and flushed to the global grid with one float atomic per
 // component per non-empty node.
-template <int W>
+template <int W, bool GAS = false>
 struct TiledShared {
-    float4 tv[TILE_NODES];            // node velocities
-    float4 tp[2 * W * TILE_NODES];    // per-half-wave (m, mv) tiles
+    float4 tv[GAS ? GTILE_NODES : TILE_NODES];   // node velocities (GAS: the 8^3 tile)
+    float4 tp[2 * W * TILE_NODES];               // per-half-wave (m, mv) tiles
     Payload4 pay[64 * W];
+    ToolDev tl[GAS ? MAX_TOOLS : 1];             // GAS: the item environment's tools at this substep
 };
+
+// Grid operation at staging: zero the momentum buffer of two substeps ago over
+// the static brick list (one wavefront per brick), or over the whole grid.
+__device__ __forceinline__ void gas_clear(const TiledArgs &a)
+{
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a.full_clear || gload(a.far_stamp + a.clear_slot) == a.clear_stamp) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.total_nodes; g += stride)
+            gstore(a.gP_clear + g, zero);
+        return;
+    }
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ns = gload(a.act.scount);
+    for (int i = blockIdx.x * nw + wave; i < ns; i += gridDim.x * nw)
+        gstore(a.gP_clear + (int64_t)gload(a.act.slist + i) * BRICK_NODES + lane, zero);
+}
+
+// Grid operation at staging, workgroup 0 at the end of a substep: the next
+// substep's tool poses (T <- T + dt u, as advance_tool) and step counters; the
+// tail of a call also writes the poses back into the tool table.
+__device__ __forceinline__ void gas_end_of_substep(const Dev &d, const TiledArgs &a, bool tail)
+{
+    if (blockIdx.x != 0) return;
+    for (int t = threadIdx.x; t < d.n_envs; t += blockDim.x) d.step[t] += 1;
+    for (int t = threadIdx.x; t < d.n_envs * d.max_tools; t += blockDim.x) {
+        ToolDev T = d.tools[t];
+        const ToolPose q = a.pose_in[t];
+        T.T[0] = q.T[0]; T.T[1] = q.T[1]; T.T[2] = q.T[2];
+        T.k = q.k;
+        if (T.active) advance_tool(T, d.dt);
+        a.pose_out[t] = ToolPose{{T.T[0], T.T[1], T.T[2]}, T.k, 0};
+        if (tail) {
+            d.tools[t].T[0] = T.T[0]; d.tools[t].T[1] = T.T[1]; d.tools[t].T[2] = T.T[2];
+            d.tools[t].k = T.k;
+        }
+    }
+}
+
+// G2P of one particle whose stencil is outside the 8^3 tile (grid operation
+// at staging): each node's velocity is the grid operation of its momentum.
+__device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, const ToolDev *tl, const float4 *gP,
+                                               const Stencil &s, float vp[3], float Cn[9])
+{
+    float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    vp[0] = vp[1] = vp[2] = 0.f;
+    for (int o0 = 0; o0 < 3; ++o0)
+        for (int o1 = 0; o1 < 3; ++o1)
+            for (int o2 = 0; o2 < 3; ++o2) {
+                const int i = s.b[0] + o0, j = s.b[1] + o1, k = s.b[2] + o2;
+                const float3 V = grid_node_velocity_tl<false>(d, e, tl, gload(gP + node_id(e, i, j, k)), i, j, k, nullptr);
+                const float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
+                const float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
+                vp[0] += wx; vp[1] += wy; vp[2] += wz;
+                B[0] += wx * d0; B[1] += wx * d1; B[2] += wx * d2;
+                B[3] += wy * d0; B[4] += wy * d1; B[5] += wy * d2;
+                B[6] += wz * d0; B[7] += wz * d1; B[8] += wz * d2;
+            }
+    const float cs = 4.0f * e.inv_dx;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Cn[c] = cs * B[c];
+}
 
 // Items first, first + stride, ... below end.  COH (persistent kernel): node
 // velocities are read with device-coherent loads (other workgroups of the
 // same launch wrote them), and the tool poses and step counters are left to
-// the caller.
-template <int MODE, int W, bool COH = false>
-__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W> &sh, int first,
+// the caller.  GAS (grid operation at staging, MODE 0-2): no grid kernel
+// runs between particle passes; the G2P stages the 8^3 node velocities of
+// its tile by applying the grid operation to this substep's momentum
+// (a.gP_read) with the tool poses of a.pose_in, and P2G writes the next
+// substep's momentum to d.gP.
+template <int MODE, int W, bool COH = false, bool GAS = false>
+__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
                                            int stride, int end)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1 || MODE == 3;
     constexpr int T = 64 * W;
+    constexpr int TS = GAS ? GTILE : TILE;   // velocity tile edge
     float4 *tv = sh.tv, *tp = sh.tp;
     Payload4 *pay = sh.pay;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
     int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
+    if (GAS && a.gP_clear) gas_clear(a);
+    int tl_env = -1;   // environment whose tools sh.tl holds
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
         EnvDev e;
         const Tile t = make_tile(d, item, e);
         const int item_end = item.y + item.z;
+        if (GAS && G2P && t.env != tl_env) {
+            // the environment's tool slots with this substep's poses
+            const int mt = d.max_tools, words = mt * (int)(sizeof(ToolDev) / 4);
+            __syncthreads();
+            for (int w = tid; w < words; w += T)
+                reinterpret_cast<int *>(sh.tl)[w] = gload(reinterpret_cast<const int *>(d.tools + (size_t)t.env * mt) + w);
+            __syncthreads();
+            if (tid < mt) {
+                const ToolPose q = a.pose_in[(size_t)t.env * mt + tid];
+                sh.tl[tid].T[0] = q.T[0]; sh.tl[tid].T[1] = q.T[1]; sh.tl[tid].T[2] = q.T[2];
+                sh.tl[tid].k = q.k;
+            }
+            __syncthreads();
+            tl_env = t.env;
+        }
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass
         float px[3], pH[9];
@@ -149,10 +235,25 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
             if (P2G)
                 for (int w = 0; w < 2 * W; ++w) tp[w * TILE_NODES + n] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (G2P) {
+            if (G2P && !GAS) {
                 int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
                 float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (i < e.n && j < e.n && k < e.n) V = COH ? cload(d.gV + node_id(e, i, j, k)) : gload(d.gV + node_id(e, i, j, k));
+                tv[n] = V;
+            }
+        }
+        if (GAS && G2P) {
+            for (int n = tid; n < GTILE_NODES; n += T) {
+                const int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
+                const int i = t.o[0] - 1 + la, j = t.o[1] - 1 + lb, k = t.o[2] - 1 + lc;
+                float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n) {
+                    const int64_t g = node_id(e, i, j, k);
+                    const float3 v = grid_node_velocity_tl<false>(d, e, sh.tl, gload(a.gP_read + g), i, j, k, nullptr);
+                    V = make_float4(v.x, v.y, v.z, 0.f);
+                    // the tail leaves the velocities of the item's own brick readable
+                    if (MODE == 2 && la >= 1 && la <= 4 && lb >= 1 && lb <= 4 && lc >= 1 && lc <= 4) gstore(d.gV + g, V);
+                }
                 tv[n] = V;
             }
         }
@@ -190,7 +291,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     bool inv = false;
                     if (G2P) {
                         int l0, l1, l2;
-                        if (stencil_in_tile(t, s, l0, l1, l2)) {
+                        if (GAS ? stencil_in_gtile(t, s, l0, l1, l2) : stencil_in_tile(t, s, l0, l1, l2)) {
                             // v = sum w V, B = sum w V (o - fx)^T, summed over o2 first
                             float q[3][3], w2q[3];
 #pragma unroll
@@ -200,7 +301,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                             }
                             float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                             v[0] = v[1] = v[2] = 0.f;
-                            const float4 *tb = tv + (l0 * TILE + l1) * TILE + l2;
+                            const float4 *tb = tv + (l0 * TS + l1) * TS + l2;
 #pragma unroll
                             for (int a0 = 0; a0 < 3; ++a0)
 #pragma unroll
@@ -208,7 +309,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                                     float sx = 0.f, sy = 0.f, sz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
 #pragma unroll
                                     for (int a2 = 0; a2 < 3; ++a2) {
-                                        const float4 V = tb[(a0 * TILE + a1) * TILE + a2];
+                                        const float4 V = tb[(a0 * TS + a1) * TS + a2];
                                         const float w2 = s.w[2][a2];
                                         sx = fmaf(w2, V.x, sx); sy = fmaf(w2, V.y, sy); sz = fmaf(w2, V.z, sz);
                                         ux = fmaf(w2q[a2], V.x, ux); uy = fmaf(w2q[a2], V.y, uy);
@@ -224,6 +325,8 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                             const float cs = 4.0f * e.inv_dx;
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
+                        } else if (GAS) {
+                            g2p_global_gas(d, e, sh.tl, a.gP_read, s, v, C);
                         } else {
                             g2p_global<COH>(d, e, s, v, C);
                         }
@@ -295,9 +398,12 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     gatomic_add(g + 2, c4.z);
                     gatomic_add(g + 3, c4.w);
                     const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
-                    if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1)
-                        mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2), t.env,
-                                       e.bofs);
+                    if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
+                        if (GAS) gstore(a.far_stamp + a.write_slot, a.write_stamp);   // cleared whole later
+                        else
+                            mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2),
+                                           t.env, e.bofs);
+                    }
                 });
             }
             if (P2G) __syncthreads();   // payload slots are rewritten by the next chunk
@@ -326,6 +432,15 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         __syncthreads();
     }
     if (COH) return;
+    if (GAS) {
+        if (G2P) gas_end_of_substep(d, a, MODE == 2);
+        else if (blockIdx.x == 0)   // head: this call's first poses from the tool table
+            for (int q = tid; q < d.n_envs * d.max_tools; q += T) {
+                const ToolDev &Tq = d.tools[q];
+                a.pose_out[q] = ToolPose{{Tq.T[0], Tq.T[1], Tq.T[2]}, Tq.k, 0};
+            }
+        return;
+    }
     if (G2P) advance_end_of_substep(d);
     // the tail ends a call: both dynamic lists start empty at the next head
     if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.dcount) gstore(a.act.dcount + tid, 0);
@@ -338,6 +453,23 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
     int first, stride, end;
     item_range(gload(a.totals).y, first, stride, end);
     tiled_body<MODE, W>(d, a, sh, first, stride, end);
+}
+
+// The grid-at-staging forms; three wavefronts per SIMD (at most 168 VGPRs),
+// the occupancy of the per-phase kernel.
+template <int MODE, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_tiled_gas(Dev d, TiledArgs a)
+{
+    __shared__ TiledShared<W, true> sh;
+    int first, stride, end;
+    item_range(gload(a.totals).y, first, stride, end);
+    tiled_body<MODE, W, false, true>(d, a, sh, first, stride, end);
+}
+
+// Grid operation at staging: the clear of one momentum buffer on its own.
+__global__ __launch_bounds__(256) void k_gas_clear(TiledArgs a)
+{
+    gas_clear(a);
 }
 
 // Grid operation over the static brick list and dynamic list `par`: one
@@ -586,12 +718,36 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 }
 
-template <int MODE>
+template <int MODE, bool GAS = false>
 static void launch_mode(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    if (block == 64) launch_k((k_tiled<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
+    if (GAS) {
+        if (block == 64) launch_k((k_tiled_gas<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
+        else if (block == 128) launch_k((k_tiled_gas<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
+        else launch_k((k_tiled_gas<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);
+    } else if (block == 64) launch_k((k_tiled<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
     else if (block == 128) launch_k((k_tiled<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
     else launch_k((k_tiled<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);
+}
+
+void launch_gas_head(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
+{
+    launch_mode<0, true>(d, a, block, nblocks, st);
+}
+
+void launch_gas_fused(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
+{
+    launch_mode<1, true>(d, a, block, nblocks, st);
+}
+
+void launch_gas_tail(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
+{
+    launch_mode<2, true>(d, a, block, nblocks, st);
+}
+
+void launch_gas_clear(const Dev &, const TiledArgs &a, hipStream_t st)
+{
+    launch_k(k_gas_clear, dim3(256), dim3(256), 0, st, a);
 }
 
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
@@ -656,7 +812,7 @@ int persistent_workgroups(int block)
     return g;
 }
 
-int tiled_workgroups(int block)
+int tiled_workgroups(int block, bool gas)
 {
     int dev = 0, cus = 256, per = 1;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -664,7 +820,11 @@ int tiled_workgroups(int block)
         if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
     }
     hipError_t e;
-    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 1>, 64, 0);
+    if (gas) {
+        if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled_gas<1, 1>, 64, 0);
+        else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled_gas<1, 2>, 128, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled_gas<1, 4>, 256, 0);
+    } else if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 1>, 64, 0);
     else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 2>, 128, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tiled<1, 4>, 256, 0);
     if (e != hipSuccess || per < 1) per = 1;

@@ -36,7 +36,7 @@ struct Profiler {
 // One captured call of n substeps (MPM_OPT_GRAPH) and the host-side
 // sequencing state that call leaves behind.
 struct GraphEntry {
-    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0, node_slots = 0;
+    int n = 0, scheme = 0, block = 0, item = 0, sort_every = 0, persistent = 0, node_slots = 0, gas = 0;
     bool sdf = false;
     hipGraphExec_t exec = nullptr;
     int since_sort_after = 0;
@@ -58,6 +58,7 @@ struct mpm_ctx {
     // options
     int scheme = MPM_SCHEME_TILED, sort_every = 16, block = 256, item = 512, use_graph = 0, persistent = 0;
     int node_slots = 3;                // particles per half-wave step in the P2G node pass (1 or 3)
+    int grid_at_staging = 0;           // one launch per substep (MPM_OPT_GRID_AT_STAGING)
     int spin_limit = 1 << 22;
     // device buffers carved from the caller's workspace
     mpm::EnvDev *env = nullptr;
@@ -69,6 +70,13 @@ struct mpm_ctx {
     float *x = nullptr, *v = nullptr, *C = nullptr, *H = nullptr;   // H = F - I
     int32_t *pid = nullptr;
     float4 *gP = nullptr, *gV = nullptr;
+    // grid operation at staging: the other two momentum buffers of the rotation
+    // (gP is the first), tool poses of two substeps, far-reach stamps, and the
+    // number of momentum grids produced so far (stamp values)
+    float4 *gP1 = nullptr, *gP2 = nullptr;
+    mpm::ToolPose *poses = nullptr;   // [2][n_envs * max_tools]
+    int32_t *far_stamp = nullptr;     // [4]
+    int gas_count = 0;
     // tiled scheme
     mpm::ParticleBuf alt{};          // sort destination
     mpm::SortBuf sort{};
@@ -85,6 +93,7 @@ struct mpm_ctx {
     int items_P = 0;
     int since_sort = 0;
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
+    int gas_blocks = 0;              // the same for the grid-at-staging kernels
     // persistent kernel: environment groups (wg_tab) for groups_block threads and
     // groups_item particles per item, groups_n workgroups (0: not available)
     int groups_block = 0, groups_item = 0, groups_n = 0;

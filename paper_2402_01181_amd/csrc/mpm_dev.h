@@ -151,6 +151,15 @@ struct ToolDev {
 
 static_assert(sizeof(ToolDev) == 152, "ToolDev layout");
 
+// A tool slot's pose at one substep (position and substeps taken), kept
+// apart from the slot when a kernel computes the grid operation of a substep
+// while the pose of the next one is being written.
+struct ToolPose {
+    double T[3];
+    int32_t k;
+    int32_t pad;
+};
+
 // Everything a kernel needs, passed by value.
 struct Dev {
     int32_t n_envs, max_tools, ntot, pad0;

@@ -80,6 +80,16 @@ __device__ __forceinline__ bool stencil_in_tile(const Tile &t, const Stencil &s,
     return l0 >= 0 && l1 >= 0 && l2 >= 0 && l0 <= TILE - 3 && l1 <= TILE - 3 && l2 <= TILE - 3;
 }
 
+// The stencil's base relative to the 8^3 velocity tile of the grid-at-staging
+// kernels (origin one node below the brick's), and whether the stencil lies in it.
+__device__ __forceinline__ bool stencil_in_gtile(const Tile &t, const Stencil &s, int &l0, int &l1, int &l2)
+{
+    l0 = s.b[0] - t.o[0] + 1;
+    l1 = s.b[1] - t.o[1] + 1;
+    l2 = s.b[2] - t.o[2] + 1;
+    return l0 >= 0 && l1 >= 0 && l2 >= 0 && l0 <= GTILE - 3 && l1 <= GTILE - 3 && l2 <= GTILE - 3;
+}
+
 // Per-particle inputs handed from a particle pass (lane = particle) to the
 // node pass of the same workgroup (lane = stencil node), 64 bytes = four LDS
 // vector reads: fx and a packed key, a 3-vector g, and a 3x3 matrix M row by

@@ -67,7 +67,27 @@ struct TiledArgs {
     int slots;                            // node pass: particles per half-wave step (1 or 3)
     ActiveBuf act;
     int par;                              // dynamic list this kernel's P2G appends to
+    // Grid operation at tile staging (one launch per substep): the kernel reads
+    // this substep's momentum gP_read and computes node velocities where it stages
+    // them, writes the next substep's momentum to the Dev's gP, and clears gP_clear
+    // (two substeps old) over the static brick list, or over the whole grid when
+    // full_clear is set or its P2G reached a far brick (far_stamp[clear_slot] ==
+    // clear_stamp; a P2G that reaches one stores write_stamp at write_slot).
+    const float4 *gP_read;
+    float4 *gP_clear;
+    int64_t total_nodes;
+    int full_clear;
+    int *far_stamp;                       // [4]; null: far bricks go to the dynamic lists
+    int write_slot, write_stamp, clear_slot, clear_stamp;
+    const ToolPose *pose_in;              // [n_envs][max_tools] this substep's tool poses
+    ToolPose *pose_out;                   // the next substep's (written by workgroup 0)
 };
+
+// Velocity tile of the grid-at-staging kernels: 8^3 nodes from the brick
+// origin minus one, so a stencil base that has drifted one cell either way
+// since the sort still reads the tile.
+constexpr int GTILE = 8;
+constexpr int GTILE_NODES = GTILE * GTILE * GTILE;
 
 // Bricks per chunk of the sort's brick scan (brick_offset is a prefix within
 // its chunk, chunk_sum the prefix of the chunks).
@@ -100,11 +120,20 @@ void launch_g2p_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, 
 // fused G2P + P2G that also writes v and C (d.gV: this substep's grid, d.gP: the next one's)
 void launch_fused_full_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_grid_active(const Dev &d, const ActiveBuf &a, int par, int nblocks, bool sdf, hipStream_t st);
+// Grid operation at staging: head P2G (initialises a.pose_out from the tool
+// table), fused substep (grid operation of this substep in the staging, G2P,
+// F update, advection, P2G of the next), tail (grid operation in the staging,
+// G2P; writes v, C and the node velocities of the items' bricks, and the
+// final tool poses into the table), and the clear of one momentum buffer.
+void launch_gas_head(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_gas_fused(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_gas_tail(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
+void launch_gas_clear(const Dev &d, const TiledArgs &a, hipStream_t st);
 // brick_env[b] = environment of brick b (once, at create)
 void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *brick_env, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
-int tiled_workgroups(int block);
+int tiled_workgroups(int block, bool gas = false);
 // Persistent kernel: m substeps of (grid operation, fused particle pass) per
 // environment group, the last one a G2P-only tail if tail_last; groups
 // synchronise through their own counters.  nblocks must not exceed

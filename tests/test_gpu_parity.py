@@ -560,13 +560,13 @@ def test_autotune_picks_and_caches(gpu, orc, tmp_path):
     sc = scenes.cube_scene(seed=1, substeps=10)
     cache = str(tmp_path / "tune.json")
     kw = dict(substeps=8, warmup=2, cache=cache, blocks=(64, 256), items=(64, 512), sort_every=(8, 16),
-              graph=(0, 1), persistent=(0,), slots=(3,), use_shipped=False)
+              graph=(0, 1), persistent=(0,), slots=(3,), grid_at_staging=(0, 1), use_shipped=False)
     best = autotune(sc, **kw)
     _say(f"autotune cube: {best}")
     assert best[L.OPT_BLOCK] in (64, 256) and best[L.OPT_ITEM] in (64, 512) and best[L.OPT_SORT_EVERY] in (8, 16)
     table = json.load(open(cache))
     entry = table[workload_key(sc)]
-    assert len(entry["trials"]) == 4 + 2 + 2
+    assert len(entry["trials"]) == 4 + 2 + 2 + 2
     assert autotune(sc, **kw) == best
     s = Sim(sc, options=best)   # the options are accepted by the library
     s.step(10)
