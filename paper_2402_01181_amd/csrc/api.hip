@@ -122,6 +122,10 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
         T.adj_slot = cv.take<float>(st24);
         T.perm = cv.take<int32_t>(s.ntot);
         T.iota = cv.take<int32_t>(s.ntot);
+        T.tflag = cv.take<int32_t>(s.total_bricks);
+        T.tslist = cv.take<int32_t>(s.total_bricks);
+        T.tscount = cv.take<int32_t>(1);
+        T.tfar = cv.take<int32_t>(k + 1);
         T.adj.xb = T.adj_state;
         T.adj.vb = T.adj_state ? T.adj_state + (size_t)3 * s.ntot : nullptr;
         T.adj.Cb = T.adj_state ? T.adj_state + (size_t)6 * s.ntot : nullptr;
@@ -151,7 +155,8 @@ bool all_carved(const mpm_ctx &c)
         const auto &T = c.tape;
         const void *t[] = {T.ckpt_state, T.ckpt_tools, T.ckpt_step, T.seg_state, T.seg_tools, T.seg_P, T.seg_V,
                            T.seg_dec, T.work, T.work_tools, T.work_step, T.work_status, T.adj_state, T.adj.gVb,
-                           T.adj.gPb, T.adj.ubar, T.adj.Tbar, T.adj.mubar, T.adj.lambar, T.adj_slot, T.perm, T.iota};
+                           T.adj.gPb, T.adj.ubar, T.adj.Tbar, T.adj.mubar, T.adj.lambar, T.adj_slot, T.perm, T.iota,
+                           T.tflag, T.tslist, T.tscount, T.tfar};
         for (const void *q : t)
             if (!q) return false;
     }
@@ -650,6 +655,36 @@ void save_checkpoint(mpm_ctx *c, int k, hipStream_t st)
     });
 }
 
+// The recompute's brick bookkeeping: its own static list (built by the
+// segment's sort, so the forward's lists are left as they were); far reaches
+// are stamped, not listed.
+ActiveBuf tape_act(const mpm_ctx *c)
+{
+    ActiveBuf a = c->act;
+    a.flag = c->tape.tflag;
+    a.slist = c->tape.tslist;
+    a.scount = c->tape.tscount;
+    a.dlist = nullptr;
+    a.dcount = nullptr;
+    a.elist = nullptr;
+    a.ecount = nullptr;
+    return a;
+}
+
+// Nodes a tape grid pass of slot `slot` visits (the tape's static list, or all
+// of them if that slot's P2G reached beyond it).
+TapeList tape_list(const mpm_ctx *c, int slot)
+{
+    const auto &T = c->tape;
+    return TapeList{T.tslist, T.tscount, c->brick_env, T.tfar, slot, T.stamp, 0};
+}
+
+TapeList dense_list(const mpm_ctx *c)
+{
+    const auto &T = c->tape;
+    return TapeList{T.tslist, T.tscount, c->brick_env, T.tfar, 0, 0, 1};
+}
+
 // Recompute substeps [s_begin, s_end) from checkpoint `seg`, keeping each
 // substep's starting state, tool table, grid (m, vhat), node velocities and
 // contact decisions in the segment tape.  Uses the direct-scheme kernels on
@@ -679,20 +714,13 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
         timed(c, st, PK_P2G_DIRECT, [&] { launch_p2g_direct(d, st); });
         timed(c, st, PK_GRID_DENSE, [&] {
             launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, nullptr, 0,
-                             nullptr, st);
+                             dense_list(c), st);
         });
         timed(c, st, PK_G2P_DIRECT, [&] { launch_g2p_direct(d, st); });
     }
 }
 
 // Tape bookkeeping without active-brick flags (the tape's grid passes are dense).
-ActiveBuf tape_act(const mpm_ctx *c)
-{
-    ActiveBuf a = c->act;
-    a.flag = nullptr;
-    return a;
-}
-
 ParticleBuf seg_view(const mpm_ctx *c, int slot)
 {
     const size_t N = c->ntot;
@@ -729,26 +757,33 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
         d.gV = T.seg_V + (size_t)slot * c->total_nodes;
         return d;
     };
+    // tape grids are zero outside the listed bricks (the reverse grid pass clears what it
+    // visits), so no P needs clearing here; a P2G that reaches beyond the list stamps its slot
+    T.stamp += 1;
+    auto stamped = [&](TiledArgs a, int slot) {
+        a.act = ta;
+        a.far_stamp = T.tfar;
+        a.write_slot = slot;
+        a.write_stamp = T.stamp;
+        return a;
+    };
     {
         Dev d = slot_dev(0);
         ParticleBuf in = seg_view(c, 0);
-        TiledArgs head = tiled_args(c, in, in, 0);
-        head.act = ta;
-        timed(c, st, PK_FILL, [&] { launch_fill_f4(d.gP, c->total_nodes, st); });
+        const TiledArgs head = stamped(tiled_args(c, in, in, 0), 0);
         timed(c, st, PK_P2G_TILED, [&] { launch_p2g_tiled(d, head, c->block, c->tiled_blocks, st); });
     }
     for (int j = s_begin; j < s_end; ++j) {
         const int slot = j - s_begin;
         const bool last = j + 1 == s_end;
         Dev d = slot_dev(slot);
-        // the grid pass also snapshots the tool table and zeroes the next substep's P
+        // the grid pass also snapshots the tool table
         float4 *next_P = last ? nullptr : T.seg_P + (size_t)(slot + 1) * c->total_nodes;
         timed(c, st, PK_GRID_DENSE, [&] {
             launch_grid_tape(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes,
-                             T.seg_tools + (size_t)slot * slots, (int)slots, next_P, st);
+                             T.seg_tools + (size_t)slot * slots, (int)slots, tape_list(c, slot), st);
         });
-        TiledArgs step = tiled_args(c, seg_view(c, slot), seg_view(c, slot + 1), 0);
-        step.act = ta;
+        const TiledArgs step = stamped(tiled_args(c, seg_view(c, slot), seg_view(c, slot + 1), 0), slot + 1);
         if (last) {
             timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, step, c->block, c->tiled_blocks, st); });
         } else {
@@ -793,7 +828,8 @@ void reverse_segment_tiled(mpm_ctx *c, int s_begin, int lo, int s_end, int s0, h
         const Dev d = slot_dev(slot);
         a.j = j - s0;
         timed(c, st, PK_ADJ_GRID, [&] {
-            launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
+            launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a,
+                            tape_list(c, slot), st);
         });
         if (j > lo) {
             timed(c, st, PK_ADJ_P2G, [&] {
@@ -822,7 +858,8 @@ void reverse_substep(mpm_ctx *c, int slot, int jw, hipStream_t st)
     a.j = jw;
     timed(c, st, PK_ADJ_G2P, [&] { launch_adj_g2p(d, a, st); });
     timed(c, st, PK_ADJ_GRID, [&] {
-        launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, st);
+        launch_adj_grid(d, c->env_gofs, c->total_nodes, T.seg_dec + (size_t)slot * c->total_nodes, a, dense_list(c),
+                        st);
     });
     timed(c, st, PK_ADJ_P2G, [&] { launch_adj_p2g(d, a, st); });
 }
@@ -996,7 +1033,14 @@ mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_byt
             return cleanup_fail(e2, "copy initial state");
         launch_add_identity(c->H, s.ntot, s.ntot, -1.0f, st);    // stored as H = F - I
         launch_iota(c->pid, s.ntot, st);
-        if (c->max_tape > 0) launch_iota(c->tape.iota, s.ntot, st);
+        if (c->max_tape > 0) {
+            launch_iota(c->tape.iota, s.ntot, st);
+            // tape grids start zero and are left zero by every reverse pass
+            launch_fill_f4(c->tape.seg_P, (int64_t)s.total_nodes * s.ck, st);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tflag), s.total_bricks, 0u, st);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tscount), 1, 0u, st);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tfar), s.ck + 1, 0xffffffffu, st);
+        }
         launch_fill_u32(c->status, s.n_envs, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->step), s.n_envs, 0u, st);
         launch_fill_f4(c->gP, s.total_nodes, st);
@@ -1321,13 +1365,23 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
         launch_fill_f64(T.adj.lambar, c->n_envs, st);
     });
     for (int seg = (len - 1) / k; seg >= s0 / k; --seg) {
-        const int sb = seg * k, se = std::min(sb + k, len);
-        if (c->scheme == MPM_SCHEME_TILED) {
+        const int sb = seg * k, se = std::min(sb + k, len), lo = std::max(sb, s0);
+        const bool tiled = c->scheme == MPM_SCHEME_TILED;
+        if (tiled) {
             recompute_segment_tiled(c, seg, sb, se, st);
-            reverse_segment_tiled(c, sb, std::max(sb, s0), se, s0, st);
+            reverse_segment_tiled(c, sb, lo, se, s0, st);
         } else {
             recompute_segment(c, seg, sb, se, st);
-            for (int j = se - 1; j >= std::max(sb, s0); --j) reverse_substep(c, j - sb, j - s0, st);
+            for (int j = se - 1; j >= lo; --j) reverse_substep(c, j - sb, j - s0, st);
+        }
+        // the reverse grid pass leaves each tape grid it visits zero; those of recomputed
+        // substeps before the window are cleared here
+        for (int j = sb; j < lo; ++j) {
+            Dev d = c->dev();
+            d.gP = T.seg_P + (size_t)(j - sb) * c->total_nodes;
+            timed(c, st, PK_ADJ_MISC, [&] {
+                launch_tape_clear(d, c->env_gofs, c->total_nodes, tiled ? tape_list(c, j - sb) : dense_list(c), st);
+            });
         }
     }
     timed(c, st, PK_ADJ_MISC, [&] {

@@ -15,32 +15,70 @@
 
 namespace mpm {
 
-// Grid pass of a tape recompute: like the dense grid operation, but it
-// writes (m, vhat) back into P, the final velocity into V and the contact
-// decision of each node.
-__global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gofs, int64_t total_nodes,
-                                                   ContactCode *dec, ToolDev *snap, int slots, float4 *next_P)
+// Grid pass of a tape recompute at node g (local index `local` in
+// environment env's grid): like the grid operation, but it writes (m, vhat)
+// back into P, the final velocity into V and the contact decision of the node.
+__device__ __forceinline__ void grid_tape_node(const Dev &d, const EnvDev &e, int env, int64_t g, int64_t local,
+                                               ContactCode *dec)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (snap && g < slots) snap[g] = d.tools[g];   // slots <= 8 * n_envs < total_nodes
-    if (g >= total_nodes) return;
-    if (next_P) gstore(next_P + g, make_float4(0.f, 0.f, 0.f, 0.f));
+    int i, j, k;
+    brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
+    const float4 P = gload(d.gP + g);
+    ContactRec rec;
+    const float3 v = grid_node_velocity(d, e, env, P, i, j, k, &rec);
+    const float3 vh = node_vhat(d, P);
+    gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
+    gstore(d.gP + g, make_float4(P.x, vh.x, vh.y, vh.z));
+    gstore(dec + g, (ContactCode)(rec.tool < 0 || rec.branch == 0 ? -1 : rec.tool * 4 + rec.branch));
+}
+
+__device__ __forceinline__ int env_of_node(const Dev &d, const int64_t *env_gofs, int64_t g)
+{
     int lo = 0, hi = d.n_envs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (gload(env_gofs + mid) <= g) lo = mid; else hi = mid - 1;
     }
-    const EnvDev e = load_env(d.env + lo);
-    int64_t local = g - e.gofs;
-    int i, j, k;
-    brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
-    float4 P = gload(d.gP + g);
-    ContactRec rec;
-    float3 v = grid_node_velocity(d, e, lo, P, i, j, k, &rec);
-    float3 vh = node_vhat(d, P);
-    gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
-    gstore(d.gP + g, make_float4(P.x, vh.x, vh.y, vh.z));
-    gstore(dec + g, (ContactCode)(rec.tool < 0 || rec.branch == 0 ? -1 : rec.tool * 4 + rec.branch));
+    return lo;
+}
+
+__device__ __forceinline__ bool tape_dense(const TapeList &tl)
+{
+    return tl.dense || gload(tl.far + tl.far_slot) == tl.far_stamp;
+}
+
+// Calls body(env, node, local index) for every node the pass visits: the
+// listed bricks, a wavefront each, or every node.
+template <class Body>
+__device__ __forceinline__ void tape_nodes(const Dev &d, const int64_t *env_gofs, int64_t total_nodes,
+                                           const TapeList &tl, Body &&body)
+{
+    if (tape_dense(tl)) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total_nodes; g += stride) {
+            const int env = env_of_node(d, env_gofs, g);
+            body(env, g, g - gload(env_gofs + env));
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int n = gload(tl.scount);
+    for (int i = blockIdx.x * nw + (threadIdx.x >> 6); i < n; i += gridDim.x * nw) {
+        const int b = gload(tl.slist + i), env = gload(tl.brick_env + b);
+        const int64_t g = (int64_t)b * BRICK_NODES + lane;
+        body(env, g, g - gload(env_gofs + env));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gofs, int64_t total_nodes,
+                                                   ContactCode *dec, ToolDev *snap, int slots, TapeList tl)
+{
+    if (snap)
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots; t += (int64_t)gridDim.x * blockDim.x)
+            snap[t] = d.tools[t];
+    tape_nodes(d, env_gofs, total_nodes, tl, [&](int env, int64_t g, int64_t local) {
+        grid_tape_node(d, load_env(d.env + env), env, g, local, dec);
+    });
 }
 
 __device__ __forceinline__ void weight_grads(const Stencil &s, float dw[3][3])
@@ -191,37 +229,33 @@ __device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, in
     return make_float3(rb0, rb1, rb2);
 }
 
-__global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs, int64_t total_nodes,
-                                                  const ContactCode *dec, AdjBuf a)
+// Reverse grid operation at node g; clears the node-velocity adjoint and the
+// tape's (m, v-hat) there.
+__device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int env, int64_t g, int64_t local,
+                                              const ContactCode *dec, const AdjBuf &a)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total_nodes) return;
-    float4 P = gload(d.gP + g);                                // (m, vhat)
+    const float4 P = gload(d.gP + g);                                // (m, vhat)
     // a wavefront is one brick (environments' grids start at multiples of 64 nodes);
     // a brick without mass is in no particle's stencil: its velocity adjoint was
-    // never scattered to (still zero) and its (m, mv) adjoint is never gathered
+    // never scattered to (still zero), its (m, mv) adjoint is never gathered and
+    // its tape entry is already zero
     if (!__any(P.x > 0.0f)) return;
-    float4 vb4 = gload(a.gVb + g);
+    const float4 vb4 = gload(a.gVb + g);
     gstore(a.gVb + g, make_float4(0.f, 0.f, 0.f, 0.f));      // ready for the next reverse substep
+    gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));       // the tape grid is zero between recomputes
     if (!(P.x > 0.0f)) {
         gstore(a.gPb + g, make_float4(0.f, 0.f, 0.f, 0.f));
         return;
     }
-    int lo = 0, hi = d.n_envs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (gload(env_gofs + mid) <= g) lo = mid; else hi = mid - 1;
-    }
-    const EnvDev e = load_env(d.env + lo);
-    int64_t local = g - e.gofs;
     int i, j, k;
     brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
     int tool;
     float3 ub, Tb;
-    float3 vh = make_float3(P.y, P.z, P.w);
-    float3 vhb = node_adjoint(d, e, lo, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z), tool, ub, Tb);
+    const float3 vh = make_float3(P.y, P.z, P.w);
+    const float3 vhb = node_adjoint(d, e, env, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z), tool,
+                                    ub, Tb);
     if (tool >= 0) {
-        size_t o = (((size_t)lo * d.max_tools + tool) * a.max_tape + a.j) * 3;
+        size_t o = (((size_t)env * d.max_tools + tool) * a.max_tape + a.j) * 3;
         gatomic_add(a.ubar + o + 0, (double)ub.x);
         gatomic_add(a.ubar + o + 1, (double)ub.y);
         gatomic_add(a.ubar + o + 2, (double)ub.z);
@@ -230,9 +264,17 @@ __global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs
         gatomic_add(a.Tbar + o + 2, (double)Tb.z);
     }
     // vhat = P/m + dt g:  Pbar = vhbar/m,  mbar = -vhbar . (P/m) / m
-    float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
-    float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
+    const float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
+    const float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
     gstore(a.gPb + g, make_float4(mb, vhb.x / P.x, vhb.y / P.x, vhb.z / P.x));
+}
+
+__global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs, int64_t total_nodes,
+                                                  const ContactCode *dec, AdjBuf a, TapeList tl)
+{
+    tape_nodes(d, env_gofs, total_nodes, tl, [&](int env, int64_t g, int64_t local) {
+        adj_grid_node(d, load_env(d.env + env), env, g, local, dec, a);
+    });
 }
 
 // Sum per environment over a wavefront, then one double atomic per wave.
@@ -940,11 +982,18 @@ static unsigned blocks_for(int64_t n)
     return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
-void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, ToolDev *snap,
-                      int slots, float4 *next_P, hipStream_t st)
+// enough workgroups for a node per thread up to 2M nodes, grid-stride beyond
+static unsigned tape_blocks(int64_t total_nodes)
 {
-    launch_k(k_grid_tape, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
-                       total_nodes, dec, snap, slots, next_P);
+    const int64_t b = (total_nodes + 255) / 256;
+    return (unsigned)(b < 8 ? 8 : (b > 8192 ? 8192 : b));
+}
+
+void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, ToolDev *snap,
+                      int slots, const TapeList &tl, hipStream_t st)
+{
+    launch_k(k_grid_tape, dim3(tape_blocks(total_nodes)), dim3(256), 0, st, d, env_gofs, total_nodes, dec, snap, slots,
+             tl);
 }
 
 void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)
@@ -952,11 +1001,22 @@ void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)
     launch_k(k_adj_g2p, dim3((d.ntot + 255) / 256), dim3(256), 0, st, d, a);
 }
 
-void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
-                     const AdjBuf &a, hipStream_t st)
+__global__ __launch_bounds__(256) void k_tape_clear(Dev d, const int64_t *env_gofs, int64_t total_nodes, TapeList tl)
 {
-    launch_k(k_adj_grid, dim3((unsigned)((total_nodes + 255) / 256)), dim3(256), 0, st, d, env_gofs,
-                       total_nodes, dec, a);
+    tape_nodes(d, env_gofs, total_nodes, tl,
+               [&](int, int64_t g, int64_t) { gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f)); });
+}
+
+void launch_tape_clear(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const TapeList &tl,
+                       hipStream_t st)
+{
+    launch_k(k_tape_clear, dim3(tape_blocks(total_nodes)), dim3(256), 0, st, d, env_gofs, total_nodes, tl);
+}
+
+void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
+                     const AdjBuf &a, const TapeList &tl, hipStream_t st)
+{
+    launch_k(k_adj_grid, dim3(tape_blocks(total_nodes)), dim3(256), 0, st, d, env_gofs, total_nodes, dec, a, tl);
 }
 
 void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st)

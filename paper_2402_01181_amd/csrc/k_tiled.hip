@@ -148,13 +148,17 @@ __device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, co
 {
     float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     vp[0] = vp[1] = vp[2] = 0.f;
+    // the loop stays rolled (its body holds a whole grid operation), so the
+    // weights are selected by offset rather than indexed: an indexed stencil
+    // would live in scratch memory
+    auto wsel = [&](int a, int o) { return o == 0 ? s.w[a][0] : (o == 1 ? s.w[a][1] : s.w[a][2]); };
     for (int o0 = 0; o0 < 3; ++o0)
         for (int o1 = 0; o1 < 3; ++o1)
             for (int o2 = 0; o2 < 3; ++o2) {
                 const int i = s.b[0] + o0, j = s.b[1] + o1, k = s.b[2] + o2;
                 const float3 V = grid_node_velocity_tl<false>(d, e, tl, gload(gP + node_id(e, i, j, k)), i, j, k, nullptr);
                 const float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
-                const float w = s.w[0][o0] * s.w[1][o1] * s.w[2][o2];
+                const float w = wsel(0, o0) * wsel(1, o1) * wsel(2, o2);
                 const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
                 vp[0] += wx; vp[1] += wy; vp[2] += wz;
                 B[0] += wx * d0; B[1] += wx * d1; B[2] += wx * d2;
@@ -399,7 +403,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     gatomic_add(g + 3, c4.w);
                     const int di = (i >> 2) - t.bi, dj = (j >> 2) - t.bj, dk = (k >> 2) - t.bk;
                     if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
-                        if (GAS) gstore(a.far_stamp + a.write_slot, a.write_stamp);   // cleared whole later
+                        // grid at staging and tape recompute: a stamp (that grid is then cleared or
+                        // swept whole); otherwise the brick goes to a list
+                        if (a.far_stamp) gstore(a.far_stamp + a.write_slot, a.write_stamp);
                         else
                             mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2),
                                            t.env, e.bofs);
@@ -721,7 +727,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
 template <int MODE, bool GAS = false>
 static void launch_mode(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
-    if (GAS) {
+    if constexpr (GAS) {
         if (block == 64) launch_k((k_tiled_gas<MODE, 1>), dim3(nblocks), dim3(64), 0, st, d, a);
         else if (block == 128) launch_k((k_tiled_gas<MODE, 2>), dim3(nblocks), dim3(128), 0, st, d, a);
         else launch_k((k_tiled_gas<MODE, 4>), dim3(nblocks), dim3(256), 0, st, d, a);

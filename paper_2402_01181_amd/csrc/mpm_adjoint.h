@@ -22,15 +22,35 @@ struct AdjBuf {
 // -1 no contact / unchanged, else tool * 4 + branch (branch as in ContactRec).
 typedef int8_t ContactCode;
 
-// Dense grid pass of the tape: V, (m, v-hat) and the contact decision of every node.  With
-// snap != nullptr the tool table (slots entries) is copied there; with
-// next_P != nullptr that grid is zeroed (the next substep's P2G target).
+// The nodes a tape grid pass visits: the tape's static brick list (one
+// wavefront per brick), or every node when `dense` is set or the P2G that
+// wrote this grid reached a brick outside the list (far[far_slot] ==
+// far_stamp).
+struct TapeList {
+    const int32_t *slist;
+    const int32_t *scount;
+    const int32_t *brick_env;
+    const int32_t *far;
+    int far_slot, far_stamp;
+    int dense;
+};
+
+// Grid pass of the tape: V, (m, v-hat) and the contact decision of the
+// visited nodes.  With snap != nullptr the tool table (slots entries) is
+// copied there.
 void launch_grid_tape(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, ContactCode *dec, ToolDev *snap,
-                      int slots, float4 *next_P, hipStream_t st);
+                      int slots, const TapeList &tl, hipStream_t st);
 void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st);
+// Reverse grid operation over the visited nodes; clears the node-velocity
+// adjoint and the tape's (m, v-hat) of every node it visits, so tape grids and
+// adjoints are zero outside the visited nodes between uses.
 void launch_adj_grid(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const ContactCode *dec,
-                     const AdjBuf &a, hipStream_t st);
+                     const AdjBuf &a, const TapeList &tl, hipStream_t st);
 void launch_adj_p2g(const Dev &d, const AdjBuf &a, hipStream_t st);
+// Zero the tape grid d.gP over the nodes tl visits (a recomputed substep the
+// reverse pass did not reach).
+void launch_tape_clear(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const TapeList &tl,
+                       hipStream_t st);
 void launch_adj_finish(const Dev &d, const AdjBuf &a, int n, double *gE, double *gnu, double *gu, double *gT,
                        hipStream_t st);
 void launch_adj_g2p_tiled(const Dev &d, const AdjBuf &a, const int4 *items, const int2 *totals, int slots,

@@ -128,6 +128,11 @@ struct mpm_ctx {
         float *adj_slot = nullptr;          // [24][ntot] the same in a segment's sorted slot order
         int32_t *perm = nullptr;            // [ntot] sorted slot -> original index of the current segment
         int32_t *iota = nullptr;            // [ntot] identity
+        // the recompute's own static brick list (built by its sort) and far-reach
+        // stamps per tape slot; tape grids are zero outside listed bricks between uses
+        int32_t *tflag = nullptr, *tslist = nullptr, *tscount = nullptr;
+        int32_t *tfar = nullptr;            // [k + 1]
+        int stamp = 0;
         int len = 0;                        // recorded substeps
     } tape;
     size_t tool_slots() const { return (size_t)n_envs * (max_tools > 0 ? max_tools : 1); }
