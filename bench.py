@@ -441,8 +441,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and forward+adjoint forms")
     ap.add_argument("--only-form", default=None,
                     choices=["large", "batched", "forward_adjoint", "frame", "tool_shapes"],
-                    help="run just this form (launch options as in the default run; library defaults with "
-                         "--no-autotune) and print it")
+                    help="run just this form (with the slab's launch options, as in the default run: the "
+                         "autotuner's, or the library defaults with --no-autotune, then the flags given) and print it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -456,23 +456,15 @@ def main():
     from paper_2402_01181_amd import _lib as L
     from paper_2402_01181_amd.sim import Sim
 
-    if args.only_form:
-        fopts = {L.OPT_SCHEME: L.SCHEME_TILED}
-        if not args.no_autotune:
-            # the slab's launch options, as the default run passes them to the forms
-            from paper_2402_01181_amd.autotune import autotune
-            fopts.update(autotune(make_scene("slab")[0], verbose=False))
-        forms = measure_forms(torch, L, Sim, fopts, not args.no_autotune, only=args.only_form)
-        print(json.dumps(forms), flush=True)
-        return
-
-    scene, workload = make_scene(args.config)
+    # the workload's launch options (for --only-form the slab's, as the default run
+    # passes them to the forms): the autotuner's, then the flags given
+    scene, workload = make_scene("slab" if args.only_form else args.config)
     opts = {L.OPT_SCHEME: L.SCHEME_TILED if args.scheme == "tiled" else L.SCHEME_DIRECT}
     tune = not args.no_autotune and args.scheme == "tiled"
     if tune:
-        from paper_2402_01181_amd.autotune import autotune
+        from paper_2402_01181_amd.autotune import autotune, workload_key
         opts.update(autotune(scene, verbose=False))
-        print(f"# autotuned options: {opts}", file=sys.stderr, flush=True)
+        print(f"# autotuned options for {workload_key(scene)}: {opts}", file=sys.stderr, flush=True)
     if args.sort_every: opts[L.OPT_SORT_EVERY] = args.sort_every
     if args.block: opts[L.OPT_BLOCK] = args.block
     if args.item: opts[L.OPT_ITEM] = args.item
@@ -480,6 +472,10 @@ def main():
     if args.persistent is not None: opts[L.OPT_PERSISTENT] = args.persistent
     if args.slots is not None: opts[L.OPT_NODE_SLOTS] = args.slots
     if args.gas is not None: opts[L.OPT_GRID_AT_STAGING] = args.gas
+    if args.only_form:
+        forms = measure_forms(torch, L, Sim, opts, tune, only=args.only_form)
+        print(json.dumps(forms), flush=True)
+        return
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

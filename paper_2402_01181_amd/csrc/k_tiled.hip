@@ -191,29 +191,32 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
     int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
-    if (GAS && a.gP_clear) gas_clear(a);
     int tl_env = -1;   // environment whose tools sh.tl holds
+    // the environment's tool slots with this substep's poses, into LDS
+    auto load_tools = [&](int env) {
+        const int mt = d.max_tools, words = mt * (int)(sizeof(ToolDev) / 4);
+        __syncthreads();
+        for (int w = tid; w < words; w += T)
+            reinterpret_cast<int *>(sh.tl)[w] = gload(reinterpret_cast<const int *>(d.tools + (size_t)env * mt) + w);
+        __syncthreads();
+        if (tid < mt) {
+            const ToolPose q = a.pose_in[(size_t)env * mt + tid];
+            sh.tl[tid].T[0] = q.T[0]; sh.tl[tid].T[1] = q.T[1]; sh.tl[tid].T[2] = q.T[2];
+            sh.tl[tid].k = q.k;
+        }
+        __syncthreads();
+        tl_env = env;
+    };
+    // a single environment's tools are loaded at once, beside the first item
+    if (GAS && G2P && d.n_envs == 1 && first < end) load_tools(0);
+    if (GAS && a.gP_clear) gas_clear(a);
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
         EnvDev e;
         const Tile t = make_tile(d, item, e);
         const int item_end = item.y + item.z;
-        if (GAS && G2P && t.env != tl_env) {
-            // the environment's tool slots with this substep's poses
-            const int mt = d.max_tools, words = mt * (int)(sizeof(ToolDev) / 4);
-            __syncthreads();
-            for (int w = tid; w < words; w += T)
-                reinterpret_cast<int *>(sh.tl)[w] = gload(reinterpret_cast<const int *>(d.tools + (size_t)t.env * mt) + w);
-            __syncthreads();
-            if (tid < mt) {
-                const ToolPose q = a.pose_in[(size_t)t.env * mt + tid];
-                sh.tl[tid].T[0] = q.T[0]; sh.tl[tid].T[1] = q.T[1]; sh.tl[tid].T[2] = q.T[2];
-                sh.tl[tid].k = q.k;
-            }
-            __syncthreads();
-            tl_env = t.env;
-        }
+        if (GAS && G2P && t.env != tl_env) load_tools(t.env);
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass
         float px[3], pH[9];
