@@ -103,42 +103,88 @@ struct TiledShared {
     ToolDev tl[GAS ? MAX_TOOLS : 1];             // GAS: the item environment's tools at this substep
 };
 
-// Grid operation at staging: zero the momentum buffer of two substeps ago over
-// the static brick list (one wavefront per brick), or over the whole grid.
-__device__ __forceinline__ void gas_clear(const TiledArgs &a)
+// Grid operation at staging: the momentum buffer of two substeps ago is
+// zeroed over the static brick list (one wavefront per brick), or over the
+// whole grid after a sort or a P2G that reached a far brick.  The loads that
+// decide it are issued at kernel start (gas_clear_issue) and the stores made
+// once the first tile is staged (gas_clear_finish), so their latency overlaps
+// the item's own loads.
+struct GasClear {
+    int stamp;   // far_stamp[clear_slot]
+    int ns;      // static list length
+    int sl;      // this wavefront's first listed brick
+};
+
+template <int T>
+__device__ __forceinline__ GasClear gas_clear_issue(const TiledArgs &a)
+{
+    GasClear c;
+    c.stamp = gload(a.far_stamp + a.clear_slot);
+    c.ns = gload(a.act.scount);
+    const int i0 = blockIdx.x * (T >> 6) + (threadIdx.x >> 6);
+    c.sl = i0 < a.act.nbricks ? gload(a.act.slist + i0) : 0;
+    return c;
+}
+
+template <int T>
+__device__ __forceinline__ void gas_clear_finish(const TiledArgs &a, const GasClear &c)
 {
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (a.full_clear || gload(a.far_stamp + a.clear_slot) == a.clear_stamp) {
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.total_nodes; g += stride)
+    if (a.full_clear || c.stamp == a.clear_stamp) {
+        const int64_t stride = (int64_t)gridDim.x * T;
+        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < a.total_nodes; g += stride)
             gstore(a.gP_clear + g, zero);
         return;
     }
-    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ns = gload(a.act.scount);
-    for (int i = blockIdx.x * nw + wave; i < ns; i += gridDim.x * nw)
-        gstore(a.gP_clear + (int64_t)gload(a.act.slist + i) * BRICK_NODES + lane, zero);
+    const int nw = T >> 6, i0 = blockIdx.x * nw + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int i = i0; i < c.ns; i += gridDim.x * nw)
+        gstore(a.gP_clear + (int64_t)(i == i0 ? c.sl : gload(a.act.slist + i)) * BRICK_NODES + lane, zero);
 }
 
-// Grid operation at staging, workgroup 0 at the end of a substep: the next
-// substep's tool poses (T <- T + dt u, as advance_tool) and step counters; the
-// tail of a call also writes the poses back into the tool table.
-__device__ __forceinline__ void gas_end_of_substep(const Dev &d, const TiledArgs &a, bool tail)
+// Tool poses of the grid-at-staging kernels, written by one workgroup at its
+// start (nothing in the launch reads what it writes: the kernels take T and k
+// from a.pose_in).  Head (MODE 0): this call's first poses from the tool table.
+// Otherwise the next substep's poses (T <- T + dt u, as advance_tool) and the
+// step counters; the tail of a call also writes the poses back into the table.
+template <int MODE, int T>
+__device__ __forceinline__ void gas_poses(const Dev &d, const TiledArgs &a)
 {
-    if (blockIdx.x != 0) return;
-    for (int t = threadIdx.x; t < d.n_envs; t += blockDim.x) d.step[t] += 1;
-    for (int t = threadIdx.x; t < d.n_envs * d.max_tools; t += blockDim.x) {
-        ToolDev T = d.tools[t];
+    const int nt = d.n_envs * d.max_tools;
+    if (MODE == 0) {
+        for (int q = threadIdx.x; q < nt; q += T) {
+            const ToolDev &Tq = d.tools[q];
+            a.pose_out[q] = ToolPose{{Tq.T[0], Tq.T[1], Tq.T[2]}, Tq.k, 0};
+        }
+        return;
+    }
+    for (int t = threadIdx.x; t < d.n_envs; t += T) d.step[t] += 1;
+    for (int t = threadIdx.x; t < nt; t += T) {
+        ToolDev Tt = d.tools[t];
         const ToolPose q = a.pose_in[t];
-        T.T[0] = q.T[0]; T.T[1] = q.T[1]; T.T[2] = q.T[2];
-        T.k = q.k;
-        if (T.active) advance_tool(T, d.dt);
-        a.pose_out[t] = ToolPose{{T.T[0], T.T[1], T.T[2]}, T.k, 0};
-        if (tail) {
-            d.tools[t].T[0] = T.T[0]; d.tools[t].T[1] = T.T[1]; d.tools[t].T[2] = T.T[2];
-            d.tools[t].k = T.k;
+        Tt.T[0] = q.T[0]; Tt.T[1] = q.T[1]; Tt.T[2] = q.T[2];
+        Tt.k = q.k;
+        if (Tt.active) advance_tool(Tt, d.dt);
+        a.pose_out[t] = ToolPose{{Tt.T[0], Tt.T[1], Tt.T[2]}, Tt.k, 0};
+        if (MODE == 2) {
+            d.tools[t].T[0] = Tt.T[0]; d.tools[t].T[1] = Tt.T[1]; d.tools[t].T[2] = Tt.T[2];
+            d.tools[t].k = Tt.k;
         }
     }
+}
+
+// Word w of environment env's tool slots as the grid-at-staging kernels see
+// them: the pose fields (T, k) from the substep's pose table, the rest from the
+// tool table.
+__device__ __forceinline__ const int *tool_word(const Dev &d, const ToolPose *pose, int env, int w)
+{
+    constexpr int WPT = (int)(sizeof(ToolDev) / 4);
+    constexpr int KW = (int)(offsetof(ToolDev, k) / 4), TW = (int)(offsetof(ToolDev, T) / 4);
+    const int slot = w / WPT, off = w - slot * WPT;
+    const size_t s = (size_t)env * d.max_tools + slot;
+    const int *pw = reinterpret_cast<const int *>(pose + s);
+    if (off == KW) return pw + offsetof(ToolPose, k) / 4;
+    if (off >= TW && off < TW + 6) return pw + offsetof(ToolPose, T) / 4 + (off - TW);
+    return reinterpret_cast<const int *>(d.tools + s) + off;
 }
 
 // G2P of one particle whose stencil is outside the 8^3 tile (grid operation
@@ -177,7 +223,10 @@ __device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, co
 // runs between particle passes; the G2P stages the 8^3 node velocities of
 // its tile by applying the grid operation to this substep's momentum
 // (a.gP_read) with the tool poses of a.pose_in, and P2G writes the next
-// substep's momentum to d.gP.
+// substep's momentum to d.gP.  GAS kernels take their item range from
+// a.totals (first, stride and end are ignored), after issuing the loads
+// that do not depend on it: the momentum clear's, and a single
+// environment's entry and tool slots.
 template <int MODE, int W, bool COH = false, bool GAS = false>
 __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
                                            int stride, int end)
@@ -190,33 +239,57 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
-    int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
-    int tl_env = -1;   // environment whose tools sh.tl holds
-    // the environment's tool slots with this substep's poses, into LDS
-    auto load_tools = [&](int env) {
-        const int mt = d.max_tools, words = mt * (int)(sizeof(ToolDev) / 4);
-        __syncthreads();
-        for (int w = tid; w < words; w += T)
-            reinterpret_cast<int *>(sh.tl)[w] = gload(reinterpret_cast<const int *>(d.tools + (size_t)env * mt) + w);
-        __syncthreads();
-        if (tid < mt) {
-            const ToolPose q = a.pose_in[(size_t)env * mt + tid];
-            sh.tl[tid].T[0] = q.T[0]; sh.tl[tid].T[1] = q.T[1]; sh.tl[tid].T[2] = q.T[2];
-            sh.tl[tid].k = q.k;
-        }
-        __syncthreads();
-        tl_env = env;
+
+    // GAS: an environment's tool slots (with this substep's poses) pass through
+    // registers (tw, environment tw_env) into LDS (sh.tl, environment tl_env)
+    constexpr int WPT = (int)(sizeof(ToolDev) / 4);
+    constexpr int NTW = GAS ? (MAX_TOOLS * WPT + T - 1) / T : 1;
+    int tw[NTW];
+    int tw_env = -1, tl_env = -1;
+    auto tools_issue = [&](int env) {
+        const int words = d.max_tools * WPT;
+#pragma unroll
+        for (int q = 0; q < NTW; ++q)
+            if (tid + q * T < words) tw[q] = gload(tool_word(d, a.pose_in, env, tid + q * T));
+        tw_env = env;
     };
-    // a single environment's tools are loaded at once, beside the first item
-    if (GAS && G2P && d.n_envs == 1 && first < end) load_tools(0);
-    if (GAS && a.gP_clear) gas_clear(a);
+    auto tools_commit = [&]() {   // sh.tl must be unused (after a barrier)
+        const int words = d.max_tools * WPT;
+#pragma unroll
+        for (int q = 0; q < NTW; ++q)
+            if (tid + q * T < words) reinterpret_cast<int *>(sh.tl)[tid + q * T] = tw[q];
+        tl_env = tw_env;
+    };
+    const bool one_env = GAS && d.n_envs == 1;
+    EnvDev e0;
+    GasClear clr;
+    bool clr_pending = false;
+    if constexpr (GAS) {
+        if (G2P && one_env) tools_issue(0);
+        if (one_env) e0 = load_env(d.env);
+        if (a.gP_clear) {
+            clr = gas_clear_issue<T>(a);
+            clr_pending = true;
+        }
+        // the last workgroup in launch order has the fewest items
+        if (blockIdx.x == gridDim.x - 1) gas_poses<MODE, T>(d, a);
+        item_range(gload(a.totals).y, first, stride, end);
+    }
+
+    int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
+        if (GAS && G2P && item.w != tw_env) tools_issue(item.w);
         EnvDev e;
-        const Tile t = make_tile(d, item, e);
+        Tile t;
+        if (one_env) {
+            e = e0;
+            t = tile_of(item, e);
+        } else {
+            t = make_tile(d, item, e);
+        }
         const int item_end = item.y + item.z;
-        if (GAS && G2P && t.env != tl_env) load_tools(t.env);
         // position and deformation of this lane's particle in the next chunk, loaded
         // ahead so the loads overlap the tile set-up (first chunk) or the node pass
         float px[3], pH[9];
@@ -250,21 +323,47 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             }
         }
         if (GAS && G2P) {
-            for (int n = tid; n < GTILE_NODES; n += T) {
-                const int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
-                const int i = t.o[0] - 1 + la, j = t.o[1] - 1 + lb, k = t.o[2] - 1 + lc;
-                float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n) {
-                    const int64_t g = node_id(e, i, j, k);
-                    const float3 v = grid_node_velocity_tl<false>(d, e, sh.tl, gload(a.gP_read + g), i, j, k, nullptr);
-                    V = make_float4(v.x, v.y, v.z, 0.f);
-                    // the tail leaves the velocities of the item's own brick readable
-                    if (MODE == 2 && la >= 1 && la <= 4 && lb >= 1 && lb <= 4 && lc >= 1 && lc <= 4) gstore(d.gV + g, V);
+            // a thread's momentum loads (up to four) are all issued before its first grid operation
+            constexpr int NS = GTILE_NODES / T, NG = NS < 4 ? NS : 4;
+#pragma unroll
+            for (int g0 = 0; g0 < NS; g0 += NG) {
+                float4 P[NG];
+                int64_t gid[NG];
+                bool in[NG];
+#pragma unroll
+                for (int q = 0; q < NG; ++q) {
+                    const int n = tid + (g0 + q) * T;
+                    const int i = t.o[0] - 1 + (n >> 6), j = t.o[1] - 1 + ((n >> 3) & 7), k = t.o[2] - 1 + (n & 7);
+                    in[q] = i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n;
+                    gid[q] = in[q] ? node_id(e, i, j, k) : 0;
+                    P[q] = in[q] ? gload(a.gP_read + gid[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                tv[n] = V;
+                if (g0 == 0 && t.env != tl_env) {
+                    tools_commit();
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int q = 0; q < NG; ++q) {
+                    const int n = tid + (g0 + q) * T;
+                    const int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
+                    float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (in[q]) {
+                        const float3 v = grid_node_velocity_tl<false>(d, e, sh.tl, P[q], t.o[0] - 1 + la,
+                                                                      t.o[1] - 1 + lb, t.o[2] - 1 + lc, nullptr);
+                        V = make_float4(v.x, v.y, v.z, 0.f);
+                        // the tail leaves the velocities of the item's own brick readable
+                        if (MODE == 2 && la >= 1 && la <= 4 && lb >= 1 && lb <= 4 && lc >= 1 && lc <= 4)
+                            gstore(d.gV + gid[q], V);
+                    }
+                    tv[n] = V;
+                }
             }
         }
         __syncthreads();
+        if (GAS && clr_pending) {
+            gas_clear_finish<T>(a, clr);
+            clr_pending = false;
+        }
 
         for (int chunk = item.y; chunk < item_end; chunk += T) {
             // ---- pass 1: lane = particle
@@ -419,14 +518,19 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
 
         if (P2G) {
-            // sum the wave tiles and flush the non-empty nodes (their bricks are in the static list)
+            // sum the wave tiles and flush the non-empty nodes (their bricks are in the static list);
+            // a node's 2W tile entries are read together, whole
             for (int n = tid; n < TILE_NODES; n += T) {
-                float4 sum = tp[n];
+                float4 q[2 * W];
+#pragma unroll
+                for (int w = 0; w < 2 * W; ++w) q[w] = tp[w * TILE_NODES + n];
+                float4 sum = q[0];
 #pragma unroll
                 for (int w = 1; w < 2 * W; ++w) {
-                    float4 q = tp[w * TILE_NODES + n];
-                    sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
+                    sum.x += q[w].x; sum.y += q[w].y; sum.z += q[w].z; sum.w += q[w].w;
                 }
+                // keeps the momentum sums from being sunk under the mass test
+                asm volatile("" : "+v"(sum.x), "+v"(sum.y), "+v"(sum.z), "+v"(sum.w));
                 if (sum.x != 0.f) {
                     int la = n / 36, lb = (n / 6) % 6, lc = n % 6;
                     int i = t.o[0] + la, j = t.o[1] + lb, k = t.o[2] + lc;
@@ -440,16 +544,8 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
         __syncthreads();
     }
-    if (COH) return;
-    if (GAS) {
-        if (G2P) gas_end_of_substep(d, a, MODE == 2);
-        else if (blockIdx.x == 0)   // head: this call's first poses from the tool table
-            for (int q = tid; q < d.n_envs * d.max_tools; q += T) {
-                const ToolDev &Tq = d.tools[q];
-                a.pose_out[q] = ToolPose{{Tq.T[0], Tq.T[1], Tq.T[2]}, Tq.k, 0};
-            }
-        return;
-    }
+    if (GAS && clr_pending) gas_clear_finish<T>(a, clr);   // a workgroup without items
+    if (COH || GAS) return;
     if (G2P) advance_end_of_substep(d);
     // the tail ends a call: both dynamic lists start empty at the next head
     if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.dcount) gstore(a.act.dcount + tid, 0);
@@ -464,21 +560,19 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
     tiled_body<MODE, W>(d, a, sh, first, stride, end);
 }
 
-// The grid-at-staging forms; three wavefronts per SIMD (at most 168 VGPRs),
-// the occupancy of the per-phase kernel.
+// The grid-at-staging forms; two wavefronts per SIMD (up to 256 VGPRs): with
+// the loads issued ahead of the item range, three (168 VGPRs) spill to scratch.
 template <int MODE, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_tiled_gas(Dev d, TiledArgs a)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_tiled_gas(Dev d, TiledArgs a)
 {
     __shared__ TiledShared<W, true> sh;
-    int first, stride, end;
-    item_range(gload(a.totals).y, first, stride, end);
-    tiled_body<MODE, W, false, true>(d, a, sh, first, stride, end);
+    tiled_body<MODE, W, false, true>(d, a, sh, 0, 0, 0);   // item range from a.totals
 }
 
 // Grid operation at staging: the clear of one momentum buffer on its own.
 __global__ __launch_bounds__(256) void k_gas_clear(TiledArgs a)
 {
-    gas_clear(a);
+    gas_clear_finish<256>(a, gas_clear_issue<256>(a));
 }
 
 // Grid operation over the static brick list and dynamic list `par`: one

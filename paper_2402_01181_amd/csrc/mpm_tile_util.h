@@ -24,12 +24,12 @@ __device__ __forceinline__ int env_of_brick(const int32_t *env_bofs, int n_envs,
     return lo;
 }
 
-// Tile of work item (brick, first slot, count, environment).
-__device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev &e)
+// Tile of work item (brick, first slot, count, environment) whose
+// environment entry e is at hand.
+__device__ __forceinline__ Tile tile_of(const int4 &item, const EnvDev &e)
 {
     Tile t;
     t.env = item.w;
-    e = load_env(d.env + t.env);
     int lb = item.x - e.bofs;
     t.bk = lb % e.nb;
     int r = lb / e.nb;
@@ -39,6 +39,13 @@ __device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev
     t.o[1] = 4 * t.bj;
     t.o[2] = 4 * t.bk;
     return t;
+}
+
+// Tile of a work item, loading its environment's entry into e.
+__device__ __forceinline__ Tile make_tile(const Dev &d, const int4 &item, EnvDev &e)
+{
+    e = load_env(d.env + item.w);
+    return tile_of(item, e);
 }
 
 // Item walk: workgroup x + NXCD r runs on XCD x (workgroups are dealt to the
