@@ -328,8 +328,10 @@ def cpu_baseline(scene, substeps: int, serial_substeps: int):
                        "cores": 1}}
 
 
-def uses_gas(L, options) -> bool:
-    return bool(options.get(L.OPT_GRID_AT_STAGING, 0)) and not options.get(L.OPT_PERSISTENT, 0)
+def uses_gas(L, options, n_envs=1) -> bool:
+    """The grid operation runs at tile staging (per-substep launches, or
+    persistent runs for a single environment)."""
+    return bool(options.get(L.OPT_GRID_AT_STAGING, 0)) and (not options.get(L.OPT_PERSISTENT, 0) or n_envs == 1)
 
 
 def _roofline(rep, N, nodes, K, traffic, gas=False):
@@ -339,8 +341,10 @@ def _roofline(rep, N, nodes, K, traffic, gas=False):
     t_ms, n_launch = rep[dom]
     avg_s = t_ms / n_launch * 1e-3
     if dom.startswith("persistent"):
-        # one launch runs a whole run of substeps between sorts
-        per_launch = (N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP) * K / n_launch
+        # one launch runs a whole run of substeps between sorts (with the grid at
+        # staging, every substep of the call but its tail)
+        per_substep = N * BYTES_PER_PARTICLE + nodes * (BYTES_PER_NODE_GAS if gas else BYTES_PER_NODE_SUBSTEP)
+        per_launch = per_substep * ((K - 1) if gas else K) / n_launch
     elif dom.startswith("fused"):
         per_launch = N * BYTES_PER_PARTICLE + nodes * (BYTES_PER_NODE_GAS if gas else BYTES_PER_NODE_FUSED)
     elif dom.startswith("grid"):

@@ -64,6 +64,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
     c.gP2 = cv.take<float4>(s.total_nodes);
     c.poses = cv.take<ToolPose>((size_t)2 * s.n_envs * std::max(1, s.max_tools));
     c.far_stamp = cv.take<int32_t>(4);
+    c.run_bar = cv.take<unsigned>(RUN_BARRIER_WORDS);
     // surface extraction
     c.surf.rho = cv.take<float>(s.max_env_nodes);
     c.surf.ofs = cv.take<int32_t>(s.max_env_cells);
@@ -145,7 +146,7 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
 bool all_carved(const mpm_ctx &c)
 {
     const void *p[] = {c.env, c.env_pofs, c.env_gofs, c.tools, c.status, c.step, c.x, c.v, c.C, c.H, c.pid,
-                       c.gP, c.gV, c.gP1, c.gP2, c.poses, c.far_stamp, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
+                       c.gP, c.gV, c.gP1, c.gP2, c.poses, c.far_stamp, c.run_bar, c.alt.x, c.alt.v, c.alt.C, c.alt.H, c.alt.pid, c.sort.count, c.sort.brick_count, c.sort.offset, c.sort.brick_offset,
                        c.sort.chunk_sum, c.sort.totals, c.sort.key, c.sort.rank, c.sort.items, c.act.flag,
                        c.act.slist, c.act.scount, c.act.dlist, c.act.dcount, c.brick_env, c.env_bofs, c.wg_tab, c.arrive, c.elist, c.act.env_bofs,
                        c.surf.rho, c.surf.ofs, c.surf.chunk, c.surf.table};
@@ -467,7 +468,33 @@ void substeps_gas(mpm_ctx *c, int n, ParticleBuf in, hipStream_t st)
         a.pose_out = pose[0];
         timed(c, st, PK_P2G_TILED, [&] { launch_gas_head(d, a, c->block, nb, st); });
     }
-    for (int i = 0; i < n; ++i) {
+    // persistent runs (one environment): the fused substeps between sorts, one launch each
+    if (c->persistent && c->n_envs == 1 && c->run_blocks == 0) c->run_blocks = gas_run_workgroups(c->block);
+    const bool runs = c->persistent && c->n_envs == 1 && c->run_blocks > 0;
+    for (int i = 0; runs && i < n - 1;) {
+        if (i > 0 && c->since_sort >= c->sort_every && in.x == A.x) {
+            sort_into_alt(c, st);
+            in = c->alt;
+            sorted_at = i;
+        }
+        const int m = std::max(1, std::min(n - 1 - i, c->sort_every - c->since_sort));
+        GasRun r{};
+        r.buf[0] = buf[0]; r.buf[1] = buf[1]; r.buf[2] = buf[2];
+        r.pose_in = pose[i & 1];
+        r.pose_out = pose[(i + m) & 1];
+        r.bar = c->run_bar;
+        r.i0 = i;
+        r.m = m;
+        r.m0 = m0;
+        r.sorted_at = sorted_at;
+        r.spin_limit = c->spin_limit;
+        const TiledArgs a = args(in, A);
+        timed(c, st, PK_PERSISTENT, [&] { launch_gas_run(c->dev(), a, r, c->block, c->run_blocks, st); });
+        in = A;
+        i += m;
+        c->since_sort += m;
+    }
+    for (int i = runs ? n - 1 : 0; i < n; ++i) {
         if (i > 0 && i < n - 1 && c->since_sort >= c->sort_every && in.x == A.x) {
             sort_into_alt(c, st);
             in = c->alt;
@@ -519,6 +546,11 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         sort_into_alt(c, st);
         in = c->alt;
     }
+    // grid at staging: per-substep launches, or persistent runs for one environment
+    if (c->grid_at_staging && !c->has_sdf && (!c->persistent || c->n_envs == 1)) {
+        substeps_gas(c, n, in, st);
+        return;
+    }
     const bool pers = c->persistent && c->groups_n > 0 && c->groups_block == c->block && c->groups_item == c->item;
     if (pers) {
         // runs of up to sort_every substeps, one persistent launch each, sorts in
@@ -547,10 +579,6 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
             done += m;
             c->since_sort = m;
         }
-        return;
-    }
-    if (c->grid_at_staging && !c->has_sdf) {
-        substeps_gas(c, n, in, st);
         return;
     }
     // substep i: P2G lists far bricks in dynamic list i&1, its grid operation consumes it
@@ -1048,6 +1076,7 @@ mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_byt
         launch_fill_f4(c->gP1, s.total_nodes, st);
         launch_fill_f4(c->gP2, s.total_nodes, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->far_stamp), 4, 0xffffffffu, st);
+        launch_fill_u32(c->run_bar, RUN_BARRIER_WORDS, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->act.flag), s.total_bricks, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.count), (int64_t)s.total_bricks * 64, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->sort.brick_count), s.total_bricks, 0u, st);
@@ -1210,6 +1239,7 @@ mpm_status mpm_set_option(mpm_ctx *c, int32_t option, int32_t value)
         c->block = value;
         c->tiled_blocks = 0;
         c->gas_blocks = 0;
+        c->run_blocks = 0;
         return c->persistent ? build_groups(c) : MPM_OK;
     case MPM_OPT_ITEM:
         if (value < 16 || value > 4096 || value % 16) return fail(c, MPM_E_ARG, "item size must be a multiple of 16 in [16, 4096]");

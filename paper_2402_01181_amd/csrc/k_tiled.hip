@@ -126,19 +126,23 @@ __device__ __forceinline__ GasClear gas_clear_issue(const TiledArgs &a)
     return c;
 }
 
-template <int T>
+// COH: device-coherent stores (workgroups of the same launch add to the buffer later).
+template <int T, bool COH = false>
 __device__ __forceinline__ void gas_clear_finish(const TiledArgs &a, const GasClear &c)
 {
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto put = [&](float4 *q) {
+        if (COH) cstore(q, zero);
+        else gstore(q, zero);
+    };
     if (a.full_clear || c.stamp == a.clear_stamp) {
         const int64_t stride = (int64_t)gridDim.x * T;
-        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < a.total_nodes; g += stride)
-            gstore(a.gP_clear + g, zero);
+        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < a.total_nodes; g += stride) put(a.gP_clear + g);
         return;
     }
     const int nw = T >> 6, i0 = blockIdx.x * nw + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     for (int i = i0; i < c.ns; i += gridDim.x * nw)
-        gstore(a.gP_clear + (int64_t)(i == i0 ? c.sl : gload(a.act.slist + i)) * BRICK_NODES + lane, zero);
+        put(a.gP_clear + (int64_t)(i == i0 ? c.sl : gload(a.act.slist + i)) * BRICK_NODES + lane);
 }
 
 // Tool poses of the grid-at-staging kernels, written by one workgroup at its
@@ -189,6 +193,7 @@ __device__ __forceinline__ const int *tool_word(const Dev &d, const ToolPose *po
 
 // G2P of one particle whose stencil is outside the 8^3 tile (grid operation
 // at staging): each node's velocity is the grid operation of its momentum.
+template <bool COH>
 __device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, const ToolDev *tl, const float4 *gP,
                                                const Stencil &s, float vp[3], float Cn[9])
 {
@@ -202,7 +207,8 @@ __device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, co
         for (int o1 = 0; o1 < 3; ++o1)
             for (int o2 = 0; o2 < 3; ++o2) {
                 const int i = s.b[0] + o0, j = s.b[1] + o1, k = s.b[2] + o2;
-                const float3 V = grid_node_velocity_tl<false>(d, e, tl, gload(gP + node_id(e, i, j, k)), i, j, k, nullptr);
+                const float4 *q = gP + node_id(e, i, j, k);
+                const float3 V = grid_node_velocity_tl<false>(d, e, tl, COH ? cload(q) : gload(q), i, j, k, nullptr);
                 const float d0 = o0 - s.fx[0], d1 = o1 - s.fx[1], d2 = o2 - s.fx[2];
                 const float w = wsel(0, o0) * wsel(1, o1) * wsel(2, o2);
                 const float wx = w * V.x, wy = w * V.y, wz = w * V.z;
@@ -216,20 +222,54 @@ __device__ __forceinline__ void g2p_global_gas(const Dev &d, const EnvDev &e, co
     for (int c = 0; c < 9; ++c) Cn[c] = cs * B[c];
 }
 
-// Items first, first + stride, ... below end.  COH (persistent kernel): node
-// velocities are read with device-coherent loads (other workgroups of the
-// same launch wrote them), and the tool poses and step counters are left to
-// the caller.  GAS (grid operation at staging, MODE 0-2): no grid kernel
-// runs between particle passes; the G2P stages the 8^3 node velocities of
-// its tile by applying the grid operation to this substep's momentum
-// (a.gP_read) with the tool poses of a.pose_in, and P2G writes the next
-// substep's momentum to d.gP.  GAS kernels take their item range from
-// a.totals (first, stride and end are ignored), after issuing the loads
-// that do not depend on it: the momentum clear's, and a single
-// environment's entry and tool slots.
-template <int MODE, int W, bool COH = false, bool GAS = false>
-__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
-                                           int stride, int end)
+// State of the grid-at-staging kernels that outlives one pass over the
+// items: a single environment's entry, an environment's tool slots (with the
+// substep's poses) on their way through registers (tw, environment tw_env)
+// into LDS (environment tl_env), and the momentum clear's prefetched values.
+template <int T>
+struct GasState {
+    static constexpr int WPT = (int)(sizeof(ToolDev) / 4);
+    static constexpr int NTW = (MAX_TOOLS * WPT + T - 1) / T;
+    int tw[NTW];
+    int tw_env = -1, tl_env = -1;
+    bool one_env = false;
+    EnvDev e0;
+    GasClear clr;
+    bool clr_pending = false;
+};
+
+template <int T>
+__device__ __forceinline__ void gas_tools_issue(const Dev &d, const ToolPose *pose, GasState<T> &gs, int env)
+{
+    const int words = d.max_tools * GasState<T>::WPT;
+#pragma unroll
+    for (int q = 0; q < GasState<T>::NTW; ++q)
+        if (threadIdx.x + q * T < words) gs.tw[q] = gload(tool_word(d, pose, env, threadIdx.x + q * T));
+    gs.tw_env = env;
+}
+
+// The issued tool slots into LDS; tl must be unused (after a barrier).
+template <int T>
+__device__ __forceinline__ void gas_tools_commit(const Dev &d, ToolDev *tl, GasState<T> &gs)
+{
+    const int words = d.max_tools * GasState<T>::WPT;
+#pragma unroll
+    for (int q = 0; q < GasState<T>::NTW; ++q)
+        if (threadIdx.x + q * T < words) reinterpret_cast<int *>(tl)[threadIdx.x + q * T] = gs.tw[q];
+    gs.tl_env = gs.tw_env;
+}
+
+// Items first, first + stride, ... below end.  COH (persistent kernels): grid
+// data that other workgroups of the same launch wrote is read with
+// device-coherent loads (node velocities; with GAS, the momentum), and GAS
+// clears and stamps are stored device-coherently.  GAS (grid operation at
+// staging, MODE 0-2): no grid kernel runs between particle passes; the G2P
+// stages the 8^3 node velocities of its tile by applying the grid operation
+// to this substep's momentum (a.gP_read) with the tool slots gs carries into
+// LDS, and P2G writes the next substep's momentum to d.gP.
+template <int MODE, int W, bool COH, bool GAS>
+__device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
+                                            int stride, int end, GasState<64 * W> &gs)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1 || MODE == 3;
     constexpr int T = 64 * W;
@@ -240,51 +280,15 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
 
-    // GAS: an environment's tool slots (with this substep's poses) pass through
-    // registers (tw, environment tw_env) into LDS (sh.tl, environment tl_env)
-    constexpr int WPT = (int)(sizeof(ToolDev) / 4);
-    constexpr int NTW = GAS ? (MAX_TOOLS * WPT + T - 1) / T : 1;
-    int tw[NTW];
-    int tw_env = -1, tl_env = -1;
-    auto tools_issue = [&](int env) {
-        const int words = d.max_tools * WPT;
-#pragma unroll
-        for (int q = 0; q < NTW; ++q)
-            if (tid + q * T < words) tw[q] = gload(tool_word(d, a.pose_in, env, tid + q * T));
-        tw_env = env;
-    };
-    auto tools_commit = [&]() {   // sh.tl must be unused (after a barrier)
-        const int words = d.max_tools * WPT;
-#pragma unroll
-        for (int q = 0; q < NTW; ++q)
-            if (tid + q * T < words) reinterpret_cast<int *>(sh.tl)[tid + q * T] = tw[q];
-        tl_env = tw_env;
-    };
-    const bool one_env = GAS && d.n_envs == 1;
-    EnvDev e0;
-    GasClear clr;
-    bool clr_pending = false;
-    if constexpr (GAS) {
-        if (G2P && one_env) tools_issue(0);
-        if (one_env) e0 = load_env(d.env);
-        if (a.gP_clear) {
-            clr = gas_clear_issue<T>(a);
-            clr_pending = true;
-        }
-        // the last workgroup in launch order has the fewest items
-        if (blockIdx.x == gridDim.x - 1) gas_poses<MODE, T>(d, a);
-        item_range(gload(a.totals).y, first, stride, end);
-    }
-
     int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
         if (it + stride < end) next = gload(a.items + it + stride);
-        if (GAS && G2P && item.w != tw_env) tools_issue(item.w);
+        if (GAS && G2P && item.w != gs.tw_env) gas_tools_issue(d, a.pose_in, gs, item.w);
         EnvDev e;
         Tile t;
-        if (one_env) {
-            e = e0;
+        if (gs.one_env) {
+            e = gs.e0;
             t = tile_of(item, e);
         } else {
             t = make_tile(d, item, e);
@@ -336,10 +340,10 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     const int i = t.o[0] - 1 + (n >> 6), j = t.o[1] - 1 + ((n >> 3) & 7), k = t.o[2] - 1 + (n & 7);
                     in[q] = i >= 0 && j >= 0 && k >= 0 && i < e.n && j < e.n && k < e.n;
                     gid[q] = in[q] ? node_id(e, i, j, k) : 0;
-                    P[q] = in[q] ? gload(a.gP_read + gid[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    P[q] = in[q] ? (COH ? cload(a.gP_read + gid[q]) : gload(a.gP_read + gid[q])) : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                if (g0 == 0 && t.env != tl_env) {
-                    tools_commit();
+                if (g0 == 0 && t.env != gs.tl_env) {
+                    gas_tools_commit(d, sh.tl, gs);
                     __syncthreads();
                 }
 #pragma unroll
@@ -360,9 +364,9 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
             }
         }
         __syncthreads();
-        if (GAS && clr_pending) {
-            gas_clear_finish<T>(a, clr);
-            clr_pending = false;
+        if (GAS && gs.clr_pending) {
+            gas_clear_finish<T, COH>(a, gs.clr);
+            gs.clr_pending = false;
         }
 
         for (int chunk = item.y; chunk < item_end; chunk += T) {
@@ -432,7 +436,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
                         } else if (GAS) {
-                            g2p_global_gas(d, e, sh.tl, a.gP_read, s, v, C);
+                            g2p_global_gas<COH>(d, e, sh.tl, a.gP_read, s, v, C);
                         } else {
                             g2p_global<COH>(d, e, s, v, C);
                         }
@@ -507,10 +511,13 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
                     if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
                         // grid at staging and tape recompute: a stamp (that grid is then cleared or
                         // swept whole); otherwise the brick goes to a list
-                        if (a.far_stamp) gstore(a.far_stamp + a.write_slot, a.write_stamp);
-                        else
+                        if (a.far_stamp) {
+                            if (COH) cstore(a.far_stamp + a.write_slot, a.write_stamp);
+                            else gstore(a.far_stamp + a.write_slot, a.write_stamp);
+                        } else {
                             mark_far_brick(a.act, a.par, e.bofs + ((i >> 2) * e.nb + (j >> 2)) * e.nb + (k >> 2),
                                            t.env, e.bofs);
+                        }
                     }
                 });
             }
@@ -544,11 +551,38 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
         __syncthreads();
     }
-    if (GAS && clr_pending) gas_clear_finish<T>(a, clr);   // a workgroup without items
+}
+
+// One pass of a tiled kernel over its items.  COH (persistent kernel): the
+// tool poses and step counters are left to the caller.  GAS kernels take their
+// item range from a.totals (first, stride and end are ignored), after issuing
+// the loads that do not depend on it: the momentum clear's, and a single
+// environment's entry and tool slots.
+template <int MODE, int W, bool COH = false, bool GAS = false>
+__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
+                                           int stride, int end)
+{
+    constexpr bool G2P = MODE >= 1;
+    constexpr int T = 64 * W;
+    GasState<T> gs;
+    if constexpr (GAS) {
+        gs.one_env = d.n_envs == 1;
+        if (G2P && gs.one_env) gas_tools_issue(d, a.pose_in, gs, 0);
+        if (gs.one_env) gs.e0 = load_env(d.env);
+        if (a.gP_clear) {
+            gs.clr = gas_clear_issue<T>(a);
+            gs.clr_pending = true;
+        }
+        // the last workgroup in launch order has the fewest items
+        if (blockIdx.x == gridDim.x - 1) gas_poses<MODE, T>(d, a);
+        item_range(gload(a.totals).y, first, stride, end);
+    }
+    tiled_items<MODE, W, COH, GAS>(d, a, sh, first, stride, end, gs);
+    if (GAS && gs.clr_pending) gas_clear_finish<T, COH>(a, gs.clr);   // a workgroup without items
     if (COH || GAS) return;
     if (G2P) advance_end_of_substep(d);
     // the tail ends a call: both dynamic lists start empty at the next head
-    if (MODE == 2 && blockIdx.x == 0 && tid < 2 && a.act.dcount) gstore(a.act.dcount + tid, 0);
+    if (MODE == 2 && blockIdx.x == 0 && threadIdx.x < 2 && a.act.dcount) gstore(a.act.dcount + threadIdx.x, 0);
 }
 
 template <int MODE, int W>
@@ -567,6 +601,109 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
 {
     __shared__ TiledShared<W, true> sh;
     tiled_body<MODE, W, false, true>(d, a, sh, 0, 0, 0);   // item range from a.totals
+}
+
+// Grid barrier of a persistent run.  Every wavefront's loads, stores and
+// atomics have completed before its workgroup arrives; a workgroup counts
+// itself on its XCD's counter, the last of an XCD counts the XCD on the global
+// counter, and all wait for NXCD * gen there (bounded spin: a timeout sets
+// MPM_FLAG_BARRIER_TIMEOUT and returns false).
+__device__ __forceinline__ bool run_barrier(const Dev &d, unsigned *ctr, unsigned gen, int spin_limit, int &ok_shared)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        unsigned *g = ctr + NXCD * RUN_BARRIER_LINE;
+        const unsigned per = gridDim.x / NXCD, x = blockIdx.x % NXCD;
+        if (__hip_atomic_fetch_add(gptr(ctr + x * RUN_BARRIER_LINE), 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * per)
+            __hip_atomic_fetch_add(gptr(g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(gptr(g), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen * NXCD) {
+            if (++spins > spin_limit) { ok = 0; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (!ok) set_flag(d.status, 0, MPM_FLAG_BARRIER_TIMEOUT);
+        ok_shared = ok;
+    }
+    __syncthreads();
+    return ok_shared != 0;
+}
+
+// A persistent run of the grid-at-staging form (GasRun): the fused substeps
+// between two sorts of a single environment in one launch, with every
+// workgroup resident (the launch uses the occupancy-derived count).  Between
+// substeps the workgroups meet at run_barrier; grid data crosses workgroups
+// only through device-scope atomics and device-coherent loads and stores.
+// Every workgroup keeps the tool slots in LDS and advances them itself after
+// each substep (the same FP64 arithmetic as the per-substep form); the item
+// list and static brick list stay those of the last sort.
+template <int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_gas_run(Dev d, TiledArgs a, GasRun r)
+{
+    __shared__ TiledShared<W, true> sh;
+    __shared__ int ok;
+    constexpr int T = 64 * W;
+    GasState<T> gs;
+    gs.one_env = true;
+    gas_tools_issue(d, r.pose_in, gs, 0);
+    gs.e0 = load_env(d.env);
+    const GasClear c0 = gas_clear_issue<T>(a);   // static list length and first entry (fixed for the run)
+    int first, stride, end;
+    item_range(gload(a.totals).y, first, stride, end);
+    gas_tools_commit(d, sh.tl, gs);
+    __syncthreads();
+    const int mt = d.max_tools;
+    int done = 0;
+    for (int s = 0; s < r.m; ++s) {
+        const int i = r.i0 + s;
+        TiledArgs as = a;
+        if (s > 0) {   // the first substep reads the call's input (a sort's output); later ones update in place
+            as.xin = a.xout; as.vin = a.vout; as.Cin = a.Cout; as.Hin = a.Hout; as.pidin = a.pidout;
+        }
+        Dev ds = d;
+        ds.gP = r.buf[(i + 1) % 3];
+        as.gP_read = r.buf[i % 3];
+        as.gP_clear = i >= 1 ? r.buf[(i + 2) % 3] : nullptr;
+        as.full_clear = (r.sorted_at == i || r.sorted_at == i - 1) ? 1 : 0;
+        as.clear_slot = (r.m0 + i - 1) & 3;
+        as.clear_stamp = r.m0 + i - 1;
+        as.write_slot = (r.m0 + i + 1) & 3;
+        as.write_stamp = r.m0 + i + 1;
+        if (as.gP_clear) {
+            gs.clr = c0;
+            gs.clr.stamp = cload(a.far_stamp + as.clear_slot);
+            gs.clr_pending = true;
+        }
+        // this substep's tool velocities (read now, applied after the substep)
+        float3 u = make_float3(0.f, 0.f, 0.f);
+        if (threadIdx.x < mt && sh.tl[threadIdx.x].active) u = tool_velocity(sh.tl[threadIdx.x]);
+        tiled_items<1, W, true, true>(ds, as, sh, first, stride, end, gs);
+        if (gs.clr_pending) {   // a workgroup without items
+            gas_clear_finish<T, true>(as, gs.clr);
+            gs.clr_pending = false;
+        }
+        if (threadIdx.x < mt && sh.tl[threadIdx.x].active) advance_tool_u(sh.tl[threadIdx.x], d.dt, u);
+        done = s + 1;
+        if (s + 1 < r.m && !run_barrier(d, r.bar, s + 1, r.spin_limit, ok)) break;
+    }
+    __syncthreads();
+    if (blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x < mt) {
+            const ToolDev &Tt = sh.tl[threadIdx.x];
+            r.pose_out[threadIdx.x] = ToolPose{{Tt.T[0], Tt.T[1], Tt.T[2]}, Tt.k, 0};
+        }
+        if (threadIdx.x == 0) d.step[0] += done;
+    }
+    // the last workgroup out zeroes the counters for the next run
+    if (threadIdx.x == 0) {
+        unsigned *ex = r.bar + (NXCD + 1) * RUN_BARRIER_LINE;
+        if (__hip_atomic_fetch_add(gptr(ex), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gridDim.x)
+            for (int q = 0; q <= NXCD + 1; ++q)
+                __hip_atomic_store(gptr(r.bar + q * RUN_BARRIER_LINE), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Grid operation at staging: the clear of one momentum buffer on its own.
@@ -853,6 +990,13 @@ void launch_gas_clear(const Dev &, const TiledArgs &a, hipStream_t st)
     launch_k(k_gas_clear, dim3(256), dim3(256), 0, st, a);
 }
 
+void launch_gas_run(const Dev &d, const TiledArgs &a, const GasRun &r, int block, int nblocks, hipStream_t st)
+{
+    if (block == 64) launch_k(k_gas_run<1>, dim3(nblocks), dim3(64), 0, st, d, a, r);
+    else if (block == 128) launch_k(k_gas_run<2>, dim3(nblocks), dim3(128), 0, st, d, a, r);
+    else launch_k(k_gas_run<4>, dim3(nblocks), dim3(256), 0, st, d, a, r);
+}
+
 void launch_p2g_tiled(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st)
 {
     launch_mode<0>(d, a, block, nblocks, st);
@@ -934,6 +1078,24 @@ int tiled_workgroups(int block, bool gas)
     int g = per * cus;
     g -= g % NXCD;
     return g < NXCD ? NXCD : g;
+}
+
+// Workgroups of a persistent grid-at-staging run: as many as are resident at
+// once (the run's barrier needs every one of them running).
+int gas_run_workgroups(int block)
+{
+    int dev = 0, cus = 256, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
+    }
+    hipError_t e;
+    if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gas_run<1>, 64, 0);
+    else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gas_run<2>, 128, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gas_run<4>, 256, 0);
+    if (e != hipSuccess || per < 1) return 0;
+    const int g = per * cus;
+    return g - g % NXCD;
 }
 
 __global__ __launch_bounds__(256) void k_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *out)

@@ -77,6 +77,7 @@ struct mpm_ctx {
     mpm::ToolPose *poses = nullptr;   // [2][n_envs * max_tools]
     int32_t *far_stamp = nullptr;     // [4]
     int gas_count = 0;
+    unsigned *run_bar = nullptr;      // [RUN_BARRIER_WORDS] barrier of the persistent grid-at-staging runs
     // tiled scheme
     mpm::ParticleBuf alt{};          // sort destination
     mpm::SortBuf sort{};
@@ -94,6 +95,7 @@ struct mpm_ctx {
     int since_sort = 0;
     int tiled_blocks = 0;            // persistent workgroups of the particle kernels
     int gas_blocks = 0;              // the same for the grid-at-staging kernels
+    int run_blocks = 0;              // and for their persistent runs (all resident at once)
     // persistent kernel: environment groups (wg_tab) for groups_block threads and
     // groups_item particles per item, groups_n workgroups (0: not available)
     int groups_block = 0, groups_item = 0, groups_n = 0;

@@ -352,7 +352,17 @@ __device__ __forceinline__ float3 tool_velocity(const ToolDev &t)
 }
 
 // T_{s+1} = T_s + dt u_s in FP64, multiply then add (not fused, so the pose
-// has the bits of a plain FP64 evaluation of the recurrence).
+// has the bits of a plain FP64 evaluation of the recurrence); u = u_s as
+// tool_velocity reads it.
+__device__ __forceinline__ void advance_tool_u(ToolDev &T, float dt, float3 u)
+{
+#pragma clang fp contract(off)
+    T.T[0] = T.T[0] + (double)dt * (double)u.x;
+    T.T[1] = T.T[1] + (double)dt * (double)u.y;
+    T.T[2] = T.T[2] + (double)dt * (double)u.z;
+    T.k += 1;
+}
+
 __device__ __forceinline__ void advance_tool(ToolDev &T, float dt)
 {
 #pragma clang fp contract(off)

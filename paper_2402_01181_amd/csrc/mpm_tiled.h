@@ -109,6 +109,25 @@ struct EnvGroups {
     int nbricks;
 };
 
+// A persistent run of the grid-at-staging form (one environment): the call's
+// fused substeps i0 .. i0 + m - 1 in one launch.  Substep i reads momentum
+// buffer buf[i % 3], adds the next substep's into buf[(i + 1) % 3] and clears
+// buf[(i + 2) % 3] for the substep after; its momentum carries stamp m0 + i.
+struct GasRun {
+    float4 *buf[3];
+    const ToolPose *pose_in;   // tool poses at substep i0
+    ToolPose *pose_out;        // at substep i0 + m (written by the last workgroup)
+    unsigned *bar;             // RUN_BARRIER_WORDS counters, zero between launches
+    int i0, m;
+    int m0;
+    int sorted_at;             // the call's substep before which a sort ran (-10: none)
+    int spin_limit;
+};
+// The run's grid barrier: a counter per XCD, a global one and an exit count,
+// each on its own 128-byte line.
+constexpr int RUN_BARRIER_LINE = 32;
+constexpr int RUN_BARRIER_WORDS = 10 * RUN_BARRIER_LINE;
+
 // act.flag == nullptr: the static brick list is left as it is (act.brick_env is always used).
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
                  const ParticleBuf &dst, int full, hipStream_t st);
@@ -129,11 +148,13 @@ void launch_gas_head(const Dev &d, const TiledArgs &a, int block, int nblocks, h
 void launch_gas_fused(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_gas_tail(const Dev &d, const TiledArgs &a, int block, int nblocks, hipStream_t st);
 void launch_gas_clear(const Dev &d, const TiledArgs &a, hipStream_t st);
+void launch_gas_run(const Dev &d, const TiledArgs &a, const GasRun &r, int block, int nblocks, hipStream_t st);
 // brick_env[b] = environment of brick b (once, at create)
 void launch_brick_env(const int32_t *env_bofs, int n_envs, int nbricks, int32_t *brick_env, hipStream_t st);
 // Persistent workgroup count for the tiled particle kernels at this block
 // size: co-resident blocks per CU x CUs, a multiple of the 8 XCDs.
 int tiled_workgroups(int block, bool gas = false);
+int gas_run_workgroups(int block);   // 0: occupancy unknown
 // Persistent kernel: m substeps of (grid operation, fused particle pass) per
 // environment group, the last one a G2P-only tail if tail_last; groups
 // synchronise through their own counters.  nblocks must not exceed

@@ -6,7 +6,11 @@ of its substep as it stages the 8^3 node-velocity tile.  Held to the oracle
 launch shape and full size, on the 1M-particle slab, with box tools, with
 particles drifting several cells between sorts, with calls of one substep,
 under graph replay, and against the per-phase launches (which keep a grid
-kernel between particle passes)."""
+kernel between particle passes).  With MPM_OPT_PERSISTENT the fused
+substeps between sorts run as one persistent launch with a grid barrier
+between substeps; the same checks run in that form (teacher-forced calls of
+four substeps, so a run of two crosses a barrier), and a spin limit of one
+forces the barrier's timeout from the host."""
 import numpy as np
 import pytest
 
@@ -31,23 +35,25 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _opts(L, block=256, item=128, sort_every=32, gas=1, slots=3):
+def _opts(L, block=256, item=128, sort_every=32, gas=1, slots=3, pers=0):
     return {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: block, L.OPT_ITEM: item, L.OPT_SORT_EVERY: sort_every,
-            L.OPT_NODE_SLOTS: slots, L.OPT_GRID_AT_STAGING: gas}
+            L.OPT_NODE_SLOTS: slots, L.OPT_GRID_AT_STAGING: gas, L.OPT_PERSISTENT: pers}
 
 
-def _pairs(orc, sim, L, sc, env, calls, tol=2 * TOL_SUBSTEP):
-    """Teacher-forced calls of two substeps against the oracle's two substeps
-    from the same FP32 state; returns the largest error."""
+def _pairs(orc, sim, L, sc, env, calls, k=2):
+    """Teacher-forced calls of k substeps against the oracle's k substeps
+    from the same FP32 state, held to k per-substep tolerances; returns the
+    largest error."""
     nt = len(sc.envs[env].tools)
+    tol = k * TOL_SUBSTEP
     worst = 0.0
     for call in range(calls):
         o = oracle_sim_like(orc, sc, env)
         o.state = oracle_state_from_gpu(orc, sim, env)
         o.T[:nt] = sim.read(L.F_TOOL_T, env)
         o.s = sim.read(L.F_STEP, env)
-        o.run(2, threads=oracle_threads())
-        sim.step(2)
+        o.run(k, threads=oracle_threads())
+        sim.step(k)
         x, v, C, F = sim.particles(env)
         e = max(rel_err(x, o.state.x, FLOORS["x"]), rel_err(v, o.state.v, FLOORS["v"]),
                 rel_err(F, o.state.F, FLOORS["F"]))
@@ -59,32 +65,36 @@ def _pairs(orc, sim, L, sc, env, calls, tol=2 * TOL_SUBSTEP):
     return worst
 
 
-def test_gas_slab_full_size_teacher_forced_and_free(gpu, orc):
+@pytest.mark.parametrize("pers", [0, 1])
+def test_gas_slab_full_size_teacher_forced_and_free(gpu, orc, pers):
     """The 30K slab at its shipped launch shape with the grid at staging:
-    200 free substeps against the oracle, then teacher-forced pairs."""
+    200 free substeps against the oracle, then teacher-forced calls."""
     Sim, L = gpu
     S = 200
+    k = 4 if pers else 2
     sc = scenes.slab_scene(substeps=S)
-    _say(f"grid at staging: slab 30K, 256/128/32/3, {S} free substeps, then 3 teacher-forced pairs")
-    sim = Sim(sc, options=_opts(L))
+    _say(f"grid at staging (persistent {pers}): slab 30K, 256/128/32/3, {S} free substeps, "
+         f"then 3 teacher-forced calls of {k}")
+    sim = Sim(sc, options=_opts(L, pers=pers))
     sim.step(S)
     o = oracle_sim_like(orc, sc).run(S, threads=oracle_threads())
     assert_free_running(sim.particles()[0], o.state.x, sc.envs[0].x, "slab 200 substeps")
     np.testing.assert_allclose(sim.read(L.F_TOOL_T), o.T[:1], rtol=1e-12)
     assert sim.read(L.F_STEP) == S and sim.read(L.F_STATUS) == 0
-    _pairs(orc, sim, L, sc, 0, 3)
+    _pairs(orc, sim, L, sc, 0, 3, k)
 
 
-def test_gas_perturbed_cube_and_edge_shapes(gpu, orc):
+@pytest.mark.parametrize("pers", [0, 1])
+def test_gas_perturbed_cube_and_edge_shapes(gpu, orc, pers):
     """A perturbed state (velocities, affine C and strain) on the cube, with
     the smallest workgroup and item sizes and one-particle node steps."""
     Sim, L = gpu
     sc = scenes.cube_scene(seed=31)
     scenes.perturbed_state(np.random.default_rng(32), sc.envs[0], v_scale=0.05, C_scale=1.0, F_scale=0.01)
     for block, item, slots in ((64, 16, 1), (128, 48, 3), (256, 512, 3)):
-        _say(f"grid at staging: perturbed cube, block {block}, item {item}, slots {slots}")
-        sim = Sim(sc, options=_opts(L, block=block, item=item, sort_every=3, slots=slots))
-        _pairs(orc, sim, L, sc, 0, 2)
+        _say(f"grid at staging (persistent {pers}): perturbed cube, block {block}, item {item}, slots {slots}")
+        sim = Sim(sc, options=_opts(L, block=block, item=item, sort_every=3, slots=slots, pers=pers))
+        _pairs(orc, sim, L, sc, 0, 2, 4 if pers else 2)
 
 
 def test_gas_large_slab_pairs(gpu, orc):
@@ -119,11 +129,13 @@ def test_gas_matches_per_phase_and_graph(gpu, orc):
     ref = Sim(sc, options=_opts(L, sort_every=16, gas=0))
     gas = Sim(sc, options=_opts(L, sort_every=16))
     gph = Sim(sc, options={**_opts(L, sort_every=16), L.OPT_GRAPH: 1})
+    run = Sim(sc, options=_opts(L, sort_every=16, pers=1))
+    rgph = Sim(sc, options={**_opts(L, sort_every=16, pers=1), L.OPT_GRAPH: 1})
     for n in (1, 2, 3, 40, 40):
-        for s in (ref, gas, gph):
+        for s in (ref, gas, gph, run, rgph):
             s.step(n)
         xr, vr, _, Fr = ref.particles()
-        for name, s in (("eager", gas), ("graph", gph)):
+        for name, s in (("eager", gas), ("graph", gph), ("persistent", run), ("persistent graph", rgph)):
             x, v, _, F = s.particles()
             ex, ev, eF = np.abs(x - xr).max(), rel_err(v, vr, FLOORS["v"]), rel_err(F, Fr, FLOORS["F"])
             _say(f"  after a call of {n} ({name}): |dx| {ex:.2e}, v {ev:.2e}, F {eF:.2e}")
@@ -146,8 +158,9 @@ def test_gas_matches_per_phase_and_graph(gpu, orc):
     assert np.abs(gas.read(L.F_GRID_M, device=False)).max() == 0.0   # every momentum buffer is clear after a call
 
 
+@pytest.mark.parametrize("pers", [0, 1])
 @pytest.mark.parametrize("sort_every,S", [(1000, 150), (50, 300)])
-def test_gas_far_drift(gpu, orc, sort_every, S):
+def test_gas_far_drift(gpu, orc, sort_every, S, pers):
     """A block translating rigidly at ~4.5 m/s (no gravity) moves several
     cells between sorts: its stencils leave the 8^3 tiles and reach bricks
     outside the static list (full clears of the momentum buffers they wrote).
@@ -160,8 +173,8 @@ def test_gas_far_drift(gpu, orc, sort_every, S):
     v[:] = u
     env = scenes.Env(n=64, x=x, v=v, C=C, F=F, E=1e4, nu=0.3, rho=1e3, V0=0.15 ** 3 / x.shape[0])
     sc = scenes.Scene("drift", [env], dt=1e-4, substeps=S, gravity=(0.0, 0.0, 0.0))
-    _say(f"grid at staging, far drift: {S} substeps, sort every {sort_every}")
-    sim = Sim(sc, options=_opts(L, sort_every=sort_every))
+    _say(f"grid at staging (persistent {pers}), far drift: {S} substeps, sort every {sort_every}")
+    sim = Sim(sc, options=_opts(L, sort_every=sort_every, pers=pers))
     sim.step(S // 2)
     sim.step(S - S // 2)
     xt, vt, Ct, Ft = sim.particles()
@@ -172,3 +185,25 @@ def test_gas_far_drift(gpu, orc, sort_every, S):
     assert moved > 2.5 * S / 150
     assert ex <= 2e-5 * S / 150 and ev <= 1e-4 and eF <= 1e-5
     assert sim.read(L.F_STATUS) == 0 and sim.read(L.F_STEP) == S
+
+
+def test_gas_run_barrier_timeout(gpu):
+    """A spin limit of one makes the persistent run's grid barrier time out
+    (forced from the host: every workgroup still leaves its bounded wait):
+    the call returns with MPM_FLAG_BARRIER_TIMEOUT set.  With the default
+    limit restored the same context runs on (the run resets its counters)
+    and a fresh context stays clean."""
+    Sim, L = gpu
+    sc = scenes.slab_scene(seed=6, substeps=120)
+    _say("persistent run, spin limit 1: 40 substeps")
+    sim = Sim(sc, options={**_opts(L, sort_every=32, pers=1), L.OPT_SPIN_LIMIT: 1})
+    sim.step(40)
+    st = sim.read(L.F_STATUS)
+    _say(f"  status {st}")
+    assert st & L.FLAG_BARRIER_TIMEOUT
+    sim.set_option(L.OPT_SPIN_LIMIT, 1 << 22)
+    sim.step(40)
+    assert np.isfinite(sim.particles()[0]).all()
+    clean = Sim(sc, options=_opts(L, sort_every=32, pers=1))
+    clean.step(40)
+    assert clean.read(L.F_STATUS) == 0 and clean.read(L.F_STEP) == 40
