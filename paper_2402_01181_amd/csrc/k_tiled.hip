@@ -119,10 +119,10 @@ template <int T>
 __device__ __forceinline__ GasClear gas_clear_issue(const TiledArgs &a)
 {
     GasClear c;
-    c.stamp = gload(a.far_stamp + a.clear_slot);
-    c.ns = gload(a.act.scount);
+    c.stamp = uload(a.far_stamp + a.clear_slot);
+    c.ns = uload(a.act.scount);
     const int i0 = blockIdx.x * (T >> 6) + (threadIdx.x >> 6);
-    c.sl = i0 < a.act.nbricks ? gload(a.act.slist + i0) : 0;
+    c.sl = i0 < a.act.nbricks ? uload(a.act.slist + i0) : 0;
     return c;
 }
 
@@ -280,10 +280,10 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
 
-    int4 next = first < end ? gload(a.items + first) : make_int4(0, 0, 0, 0);
+    int4 next = first < end ? uload(a.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
-        if (it + stride < end) next = gload(a.items + it + stride);
+        if (it + stride < end) next = uload(a.items + it + stride);
         if (GAS && G2P && item.w != gs.tw_env) gas_tools_issue(d, a.pose_in, gs, item.w);
         EnvDev e;
         Tile t;
@@ -310,8 +310,8 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
         float mu = 0.f, lam = 0.f, m = 0.f, V0 = 0.f;
         if (P2G) {
             const float *mat = d.material + 4 * t.env;
-            const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2);
-            V0 = gload(mat + 3);
+            const float E = uload(mat), nu = uload(mat + 1), rho = uload(mat + 2);
+            V0 = uload(mat + 3);
             lame(E, nu, mu, lam);
             m = rho * V0;
         }
@@ -346,24 +346,27 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
                     gas_tools_commit(d, sh.tl, gs);
                     __syncthreads();
                 }
+                // every lane takes the grid operation (a node outside the grid has no mass and
+                // leaves it at once), so each load is consumed on every path
 #pragma unroll
                 for (int q = 0; q < NG; ++q) {
                     const int n = tid + (g0 + q) * T;
                     const int la = n >> 6, lb = (n >> 3) & 7, lc = n & 7;
-                    float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (in[q]) {
-                        const float3 v = grid_node_velocity_tl<false>(d, e, sh.tl, P[q], t.o[0] - 1 + la,
-                                                                      t.o[1] - 1 + lb, t.o[2] - 1 + lc, nullptr);
-                        V = make_float4(v.x, v.y, v.z, 0.f);
-                        // the tail leaves the velocities of the item's own brick readable
-                        if (MODE == 2 && la >= 1 && la <= 4 && lb >= 1 && lb <= 4 && lc >= 1 && lc <= 4)
-                            gstore(d.gV + gid[q], V);
-                    }
+                    const float3 v = grid_node_velocity_tl<false>(d, e, sh.tl, P[q], t.o[0] - 1 + la,
+                                                                  t.o[1] - 1 + lb, t.o[2] - 1 + lc, nullptr);
+                    const float4 V = make_float4(v.x, v.y, v.z, 0.f);
+                    // the tail leaves the velocities of the item's own brick readable
+                    if (MODE == 2 && in[q] && la >= 1 && la <= 4 && lb >= 1 && lb <= 4 && lc >= 1 && lc <= 4)
+                        gstore(d.gV + gid[q], V);
                     tv[n] = V;
                 }
             }
         }
         __syncthreads();
+        // persistent run: the loads its substep issued before this item (tool velocities, stamp)
+        // were older than the staging loads just consumed, so they are complete; saying so here
+        // spares the flush a wait for every memory operation in flight
+        if (COH && GAS) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
         if (GAS && gs.clr_pending) {
             gas_clear_finish<T, COH>(a, gs.clr);
             gs.clr_pending = false;
@@ -511,7 +514,7 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
                     if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
                         // grid at staging and tape recompute: a stamp (that grid is then cleared or
                         // swept whole); otherwise the brick goes to a list
-                        if (a.far_stamp) {
+                        if (GAS || a.far_stamp) {   // (grid-at-staging kernels always stamp)
                             if (COH) cstore(a.far_stamp + a.write_slot, a.write_stamp);
                             else gstore(a.far_stamp + a.write_slot, a.write_stamp);
                         } else {
@@ -575,7 +578,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
         }
         // the last workgroup in launch order has the fewest items
         if (blockIdx.x == gridDim.x - 1) gas_poses<MODE, T>(d, a);
-        item_range(gload(a.totals).y, first, stride, end);
+        item_range(uload(a.totals).y, first, stride, end);
     }
     tiled_items<MODE, W, COH, GAS>(d, a, sh, first, stride, end, gs);
     if (GAS && gs.clr_pending) gas_clear_finish<T, COH>(a, gs.clr);   // a workgroup without items
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 {
     __shared__ TiledShared<W> sh;
     int first, stride, end;
-    item_range(gload(a.totals).y, first, stride, end);
+    item_range(uload(a.totals).y, first, stride, end);
     tiled_body<MODE, W>(d, a, sh, first, stride, end);
 }
 
@@ -606,8 +609,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
 // Grid barrier of a persistent run.  Every wavefront's loads, stores and
 // atomics have completed before its workgroup arrives; a workgroup counts
 // itself on its XCD's counter, the last of an XCD counts the XCD on the global
-// counter, and all wait for NXCD * gen there (bounded spin: a timeout sets
-// MPM_FLAG_BARRIER_TIMEOUT and returns false).
+// counter, and the last XCD writes gen into every XCD's release word; each
+// workgroup waits for its XCD's (bounded spin: a timeout sets
+// MPM_FLAG_BARRIER_TIMEOUT and returns false).  Arrivals and polls never share
+// a line, and each release word has one XCD's workgroups polling it.
 __device__ __forceinline__ bool run_barrier(const Dev &d, unsigned *ctr, unsigned gen, int spin_limit, int &ok_shared)
 {
     __builtin_amdgcn_s_waitcnt(0);
@@ -615,12 +620,15 @@ __device__ __forceinline__ bool run_barrier(const Dev &d, unsigned *ctr, unsigne
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         unsigned *g = ctr + NXCD * RUN_BARRIER_LINE;
+        unsigned *rel = ctr + (NXCD + 2) * RUN_BARRIER_LINE;
         const unsigned per = gridDim.x / NXCD, x = blockIdx.x % NXCD;
         if (__hip_atomic_fetch_add(gptr(ctr + x * RUN_BARRIER_LINE), 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * per)
-            __hip_atomic_fetch_add(gptr(g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(gptr(g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * NXCD)
+                for (int q = 0; q < NXCD; ++q)
+                    __hip_atomic_store(gptr(rel + q * RUN_BARRIER_LINE), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1, spins = 0;
-        while (__hip_atomic_load(gptr(g), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen * NXCD) {
+        while (__hip_atomic_load(gptr(rel + x * RUN_BARRIER_LINE), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
             if (++spins > spin_limit) { ok = 0; break; }
             __builtin_amdgcn_s_sleep(1);
         }
@@ -652,7 +660,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
     gs.e0 = load_env(d.env);
     const GasClear c0 = gas_clear_issue<T>(a);   // static list length and first entry (fixed for the run)
     int first, stride, end;
-    item_range(gload(a.totals).y, first, stride, end);
+    item_range(uload(a.totals).y, first, stride, end);
     gas_tools_commit(d, sh.tl, gs);
     __syncthreads();
     const int mt = d.max_tools;
@@ -701,7 +709,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (threadIdx.x == 0) {
         unsigned *ex = r.bar + (NXCD + 1) * RUN_BARRIER_LINE;
         if (__hip_atomic_fetch_add(gptr(ex), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gridDim.x)
-            for (int q = 0; q <= NXCD + 1; ++q)
+            for (int q = 0; q < 2 * NXCD + 2; ++q)
                 __hip_atomic_store(gptr(r.bar + q * RUN_BARRIER_LINE), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }

@@ -76,6 +76,28 @@ __device__ __forceinline__ int4 gload(const int4 *p)
     return make_int4(r.x, r.y, r.z, r.w);
 }
 
+// Loads of wavefront-uniform data that nothing writes while the kernel runs
+// (item lists, environment entries, materials, counts written by an earlier
+// launch) go through the scalar cache (constant address space): their waits
+// are then apart from those of the vector memory operations in flight.
+template <class T>
+__device__ __forceinline__ T uload(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+__device__ __forceinline__ int4 uload(const int4 *p)
+{
+    v4i r = *(const __attribute__((address_space(4))) v4i *)p;
+    return make_int4(r.x, r.y, r.z, r.w);
+}
+
+__device__ __forceinline__ int2 uload(const int2 *p)
+{
+    v2i r = *(const __attribute__((address_space(4))) v2i *)p;
+    return make_int2(r.x, r.y);
+}
+
 __device__ __forceinline__ int2 gload(const int2 *p)
 {
     v2i r = *(const __attribute__((address_space(1))) v2i *)p;
@@ -183,7 +205,7 @@ __device__ __forceinline__ EnvDev load_env(const EnvDev *p)
 {
     int w[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = gload(reinterpret_cast<const int *>(p) + k);
+    for (int k = 0; k < 12; ++k) w[k] = uload(reinterpret_cast<const int *>(p) + k);
     EnvDev e;
     __builtin_memcpy(&e, w, sizeof e);
     return e;
@@ -348,7 +370,7 @@ __device__ __forceinline__ void update_h(float H[9], const float C[9], float dt)
 __device__ __forceinline__ float3 tool_velocity(const ToolDev &t)
 {
     int k = t.k < t.n_traj ? t.k : t.n_traj - 1;
-    return make_float3(t.u[3 * k], t.u[3 * k + 1], t.u[3 * k + 2]);
+    return make_float3(gload(t.u + 3 * k), gload(t.u + 3 * k + 1), gload(t.u + 3 * k + 2));
 }
 
 // T_{s+1} = T_s + dt u_s in FP64, multiply then add (not fused, so the pose

@@ -123,10 +123,10 @@ struct GasRun {
     int sorted_at;             // the call's substep before which a sort ran (-10: none)
     int spin_limit;
 };
-// The run's grid barrier: a counter per XCD, a global one and an exit count,
-// each on its own 128-byte line.
+// The run's grid barrier: a counter per XCD, a global one, an exit count and
+// a release word per XCD, each on its own 128-byte line.
 constexpr int RUN_BARRIER_LINE = 32;
-constexpr int RUN_BARRIER_WORDS = 10 * RUN_BARRIER_LINE;
+constexpr int RUN_BARRIER_WORDS = 18 * RUN_BARRIER_LINE;
 
 // act.flag == nullptr: the static brick list is left as it is (act.brick_env is always used).
 void launch_sort(const Dev &d, const SortBuf &s, const ActiveBuf &act, int total_bricks, int P,
