@@ -142,13 +142,15 @@ enum {
                                  the grid operation (Sec. III-B item 2) to each node of its 8^3 velocity
                                  tile as it stages it, from the momentum of the substep, so no grid
                                  kernel runs in between; momentum grids rotate over three buffers.
-                                 Pays where work items are few and full (one slab); used without
-                                 sampled-SDF tools.  With MPM_OPT_PERSISTENT and one environment, the
-                                 substeps between two sorts are one persistent launch: every workgroup
-                                 resident, a grid barrier between substeps (bounded spin; a timeout sets
-                                 MPM_FLAG_BARRIER_TIMEOUT); with several environments MPM_OPT_PERSISTENT
-                                 takes precedence.  0 (default): a grid kernel over the listed bricks
-                                 between particle passes */
+                                 Pays where work items are few and full (one slab).  With
+                                 MPM_OPT_PERSISTENT and one environment, the substeps between two sorts
+                                 are one persistent launch: every workgroup resident, a grid barrier
+                                 between substeps (bounded spin; a timeout sets
+                                 MPM_FLAG_BARRIER_TIMEOUT); with several environments
+                                 MPM_OPT_PERSISTENT takes precedence.  With a sampled-SDF tool active the
+                                 form does not apply and substeps take the per-phase launches.  0
+                                 (default): a grid kernel over the listed bricks between particle
+                                 passes */
 };
 enum {
     MPM_SCHEME_DIRECT = 0,    /* one thread per particle, global float atomics, dense grid pass */

@@ -40,8 +40,18 @@ def shipped(key: str) -> Optional[Dict[int, int]]:
     return {int(k): int(v) for k, v in table[key]["options"].items()}
 
 
+def device_key() -> str:
+    """The GPU architecture and compute-unit count (the marketing name is not
+    reliable: it depends on a system table and reads empty under profilers)."""
+    if not torch.cuda.is_available():
+        return "cpu"
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return f"{arch.split(':')[0]} x{p.multi_processor_count}"
+
+
 def workload_key(scene) -> str:
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    dev = device_key()
     N = scene.n_particles
     bucket = 1 << max(0, int(N - 1).bit_length())
     grids = sorted({e.n for e in scene.envs})

@@ -546,12 +546,15 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         sort_into_alt(c, st);
         in = c->alt;
     }
-    // grid at staging: per-substep launches, or persistent runs for one environment
-    if (c->grid_at_staging && !c->has_sdf && (!c->persistent || c->n_envs == 1)) {
+    // grid at staging: per-substep launches, or persistent runs for one environment; where
+    // the form does not apply (a sampled-SDF tool) the substeps take the per-phase launches
+    const bool gas = c->grid_at_staging && (!c->persistent || c->n_envs == 1);
+    if (gas && !c->has_sdf) {
         substeps_gas(c, n, in, st);
         return;
     }
-    const bool pers = c->persistent && c->groups_n > 0 && c->groups_block == c->block && c->groups_item == c->item;
+    const bool pers = !gas && c->persistent && c->groups_n > 0 && c->groups_block == c->block &&
+                      c->groups_item == c->item;
     if (pers) {
         // runs of up to sort_every substeps, one persistent launch each, sorts in
         // between; the kernel finds far-drift bricks by their flags (no dynamic lists)

@@ -44,27 +44,30 @@ __device__ __forceinline__ int env_of_node(const Dev &d, const int64_t *env_gofs
 
 __device__ __forceinline__ bool tape_dense(const TapeList &tl)
 {
-    return tl.dense || gload(tl.far + tl.far_slot) == tl.far_stamp;
+    return tl.dense || uload(tl.far + tl.far_slot) == tl.far_stamp;
 }
 
 // Calls body(env, node, local index) for every node the pass visits: the
 // listed bricks, a wavefront each, or every node.
+// The kernels that call it run 256 threads a workgroup.
 template <class Body>
 __device__ __forceinline__ void tape_nodes(const Dev &d, const int64_t *env_gofs, int64_t total_nodes,
                                            const TapeList &tl, Body &&body)
 {
     if (tape_dense(tl)) {
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total_nodes; g += stride) {
+        constexpr int T = 256;
+        const int64_t stride = (int64_t)gridDim.x * T;
+        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < total_nodes; g += stride) {
             const int env = env_of_node(d, env_gofs, g);
             body(env, g, g - gload(env_gofs + env));
         }
         return;
     }
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    const int n = gload(tl.scount);
+    constexpr int nw = 256 >> 6;
+    const int lane = threadIdx.x & 63;
+    const int n = uload(tl.scount);
     for (int i = blockIdx.x * nw + (threadIdx.x >> 6); i < n; i += gridDim.x * nw) {
-        const int b = gload(tl.slist + i), env = gload(tl.brick_env + b);
+        const int b = uload(tl.slist + i), env = uload(tl.brick_env + b);
         const int64_t g = (int64_t)b * BRICK_NODES + lane;
         body(env, g, g - gload(env_gofs + env));
     }
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gof
                                                    ContactCode *dec, ToolDev *snap, int slots, TapeList tl)
 {
     if (snap)
-        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots; t += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < slots; t += (int64_t)gridDim.x * 256)
             snap[t] = d.tools[t];
     tape_nodes(d, env_gofs, total_nodes, tl, [&](int env, int64_t g, int64_t local) {
         grid_tape_node(d, load_env(d.env + env), env, g, local, dec);
@@ -229,6 +232,42 @@ __device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, in
     return make_float3(rb0, rb1, rb2);
 }
 
+// Add a wavefront's tool-gradient terms c (dL/du, then dL/dT, of tool `tool`,
+// -1: none) of environment env and reverse substep a.j: summed over the
+// wavefront first when one tool is concerned, then one set of atomics.
+__device__ __forceinline__ void wave_tool_add(const Dev &d, const AdjBuf &a, int env, int tool, const double c[6])
+{
+    const bool has = tool >= 0;
+    const uint64_t m = __ballot(has);
+    if (!m) return;
+    const int lead = __ffsll((unsigned long long)m) - 1, t0 = __shfl(tool, lead);
+    auto at = [&](int t) { return (((size_t)env * d.max_tools + t) * a.max_tape + a.j) * 3; };
+    if (__all(!has || tool == t0)) {
+        double s[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            s[q] = has ? c[q] : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off);
+        }
+        if ((threadIdx.x & 63) == lead) {
+            const size_t o = at(t0);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                gatomic_add(a.ubar + o + q, s[q]);
+                gatomic_add(a.Tbar + o + q, s[3 + q]);
+            }
+        }
+    } else if (has) {
+        const size_t o = at(tool);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            gatomic_add(a.ubar + o + q, c[q]);
+            gatomic_add(a.Tbar + o + q, c[3 + q]);
+        }
+    }
+}
+
 // Reverse grid operation at node g; clears the node-velocity adjoint and the
 // tape's (m, v-hat) there.
 __device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int env, int64_t g, int64_t local,
@@ -240,33 +279,28 @@ __device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int
     // never scattered to (still zero), its (m, mv) adjoint is never gathered and
     // its tape entry is already zero
     if (!__any(P.x > 0.0f)) return;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 vb4 = gload(a.gVb + g);
-    gstore(a.gVb + g, make_float4(0.f, 0.f, 0.f, 0.f));      // ready for the next reverse substep
-    gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));       // the tape grid is zero between recomputes
-    if (!(P.x > 0.0f)) {
-        gstore(a.gPb + g, make_float4(0.f, 0.f, 0.f, 0.f));
-        return;
+    gstore(a.gVb + g, zero);                // ready for the next reverse substep
+    gstore(d.gP + g, zero);                 // the tape grid is zero between recomputes
+    int tool = -1;
+    float3 ub = make_float3(0.f, 0.f, 0.f), Tb = make_float3(0.f, 0.f, 0.f);
+    if (P.x > 0.0f) {
+        int i, j, k;
+        brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
+        const float3 vh = make_float3(P.y, P.z, P.w);
+        const float3 vhb = node_adjoint(d, e, env, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z),
+                                        tool, ub, Tb);
+        // vhat = P/m + dt g:  Pbar = vhbar/m,  mbar = -vhbar . (P/m) / m
+        const float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
+        const float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
+        gstore(a.gPb + g, make_float4(mb, vhb.x / P.x, vhb.y / P.x, vhb.z / P.x));
+    } else {
+        gstore(a.gPb + g, zero);
     }
-    int i, j, k;
-    brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
-    int tool;
-    float3 ub, Tb;
-    const float3 vh = make_float3(P.y, P.z, P.w);
-    const float3 vhb = node_adjoint(d, e, env, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z), tool,
-                                    ub, Tb);
-    if (tool >= 0) {
-        size_t o = (((size_t)env * d.max_tools + tool) * a.max_tape + a.j) * 3;
-        gatomic_add(a.ubar + o + 0, (double)ub.x);
-        gatomic_add(a.ubar + o + 1, (double)ub.y);
-        gatomic_add(a.ubar + o + 2, (double)ub.z);
-        gatomic_add(a.Tbar + o + 0, (double)Tb.x);
-        gatomic_add(a.Tbar + o + 1, (double)Tb.y);
-        gatomic_add(a.Tbar + o + 2, (double)Tb.z);
-    }
-    // vhat = P/m + dt g:  Pbar = vhbar/m,  mbar = -vhbar . (P/m) / m
-    const float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
-    const float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
-    gstore(a.gPb + g, make_float4(mb, vhb.x / P.x, vhb.y / P.x, vhb.z / P.x));
+    // the tool gradients of the brick's contact nodes (every lane of the wavefront is here)
+    const double c6[6] = {ub.x, ub.y, ub.z, Tb.x, Tb.y, Tb.z};
+    wave_tool_add(d, a, env, tool, c6);
 }
 
 __global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs, int64_t total_nodes,
@@ -783,7 +817,7 @@ __device__ __forceinline__ void adj_material(const Dev &d, const EnvDev &e, int 
                                              float &kf)
 {
     const float *mat = d.material + 4 * env;
-    const float E = gload(mat), nu = gload(mat + 1), rho = gload(mat + 2), V0 = gload(mat + 3);
+    const float E = uload(mat), nu = uload(mat + 1), rho = uload(mat + 2), V0 = uload(mat + 3);
     lame(E, nu, mu, lam);
     m = rho * V0;
     kf = -d.dt * V0 * 4.0f * e.inv_dx * e.inv_dx;
@@ -803,13 +837,13 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
     const Dev &d = GV ? dg : dp;   // environment tables (shared by both)
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);
-    const int nitems = gload(ta.totals).y;
+    const int nitems = uload(ta.totals).y;
     int first, stride, end;
     item_range(nitems, first, stride, end);
-    int4 next = first < end ? gload(ta.items + first) : make_int4(0, 0, 0, 0);
+    int4 next = first < end ? uload(ta.items + first) : make_int4(0, 0, 0, 0);
     for (int it = first; it < end; it += stride) {
         const int4 item = next;   // loaded one iteration ahead
-        if (it + stride < end) next = gload(ta.items + it + stride);
+        if (it + stride < end) next = uload(ta.items + it + stride);
         const int item_end = item.y + item.z;
         EnvDev e;
         const Tile t = make_tile(d, item, e);
@@ -833,22 +867,41 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
             int key = 0;
             if (active) {
                 // reverse P2G terms first, into zeroed sums; the particle's adjoint
-                // state is loaded after them, so it is not held across the stencil sums
+                // state is loaded after them, so it is not held across the stencil sums.
+                // The recorded states of both substeps are loaded up front, together
                 float xb[3] = {0.f, 0.f, 0.f}, vb[3] = {0.f, 0.f, 0.f};
                 float Cb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 float Fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float px[3], pH[9], pC[9], pv[3], gx[3], gH[9];
+                if (PB) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) px[c] = gload(dp.x + (size_t)c * N + uq);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        pH[c] = gload(dp.H + (size_t)c * N + uq);
+                        pC[c] = gload(dp.C + (size_t)c * N + uq);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pv[c] = gload(dp.v + (size_t)c * N + uq);
+                }
+                if (GV) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gx[c] = gload(dg.x + (size_t)c * N + uq);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) gH[c] = gload(dg.H + (size_t)c * N + uq);
+                }
                 if (PB) {
                     Stencil s;
-                    make_stencil(gload(dp.x + uq), gload(dp.x + N + uq), gload(dp.x + 2 * N + uq), e.inv_dx, e.n, s);
+                    make_stencil(px[0], px[1], px[2], e.inv_dx, e.n, s);
                     if (!s.outside) {
                         float H[9], C[9], v[3];
 #pragma unroll
                         for (int c = 0; c < 9; ++c) {
-                            H[c] = gload(dp.H + (size_t)c * N + uq);
-                            C[c] = gload(dp.C + (size_t)c * N + uq);
+                            H[c] = pH[c];
+                            C[c] = pC[c];
                         }
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) v[c] = gload(dp.v + (size_t)c * N + uq);
+                        for (int c = 0; c < 3; ++c) v[c] = pv[c];
                         int l0, l1, l2;
                         const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
                         adj_p2g_particle(
@@ -870,11 +923,11 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
                 }
                 if (GV) {
                     Stencil s;
-                    make_stencil(gload(dg.x + uq), gload(dg.x + N + uq), gload(dg.x + 2 * N + uq), e.inv_dx, e.n, s);
+                    make_stencil(gx[0], gx[1], gx[2], e.inv_dx, e.n, s);
                     if (!s.outside) {   // a frozen particle's adjoints pass through
                         float H[9];
 #pragma unroll
-                        for (int c = 0; c < 9; ++c) H[c] = gload(dg.H + (size_t)c * N + uq);
+                        for (int c = 0; c < 9; ++c) H[c] = gH[c];
                         int l0, l1, l2;
                         const bool in_tile = stencil_in_tile(t, s, l0, l1, l2);
                         float vbt[3], Bb[9];
@@ -914,13 +967,18 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
             }
         }
         if (GV) {
+            // a node's 2W tile entries are read together, whole
             for (int n = tid; n < TILE_NODES; n += T) {
-                float4 sum = sh.tp[n];
+                float4 q4[2 * W];
+#pragma unroll
+                for (int w = 0; w < 2 * W; ++w) q4[w] = sh.tp[w * TILE_NODES + n];
+                float4 sum = q4[0];
 #pragma unroll
                 for (int w = 1; w < 2 * W; ++w) {
-                    const float4 q4 = sh.tp[w * TILE_NODES + n];
-                    sum.x += q4.x; sum.y += q4.y; sum.z += q4.z; sum.w += q4.w;
+                    sum.x += q4[w].x; sum.y += q4[w].y; sum.z += q4[w].z; sum.w += q4[w].w;
                 }
+                // keeps the adjoint sums from being sunk under the weight test
+                asm volatile("" : "+v"(sum.x), "+v"(sum.y), "+v"(sum.z), "+v"(sum.w));
                 if (sum.x != 0.f) {
                     const int i = t.o[0] + n / 36, j = t.o[1] + (n / 6) % 6, k = t.o[2] + n % 6;
                     float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
@@ -963,6 +1021,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBu
     __shared__ AdjShared<W, true, true> sh;
     adj_tiled_body<W, true, true>(dp, dg, a, ta, sh);
 }
+
 
 // dst[c][q] = src[c][perm[q]] (gather into slot order) or the reverse scatter.
 __global__ void k_permute(const float *src, const int32_t *perm, int ntot, int comps, float *dst, int scatter)

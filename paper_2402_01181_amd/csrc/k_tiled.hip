@@ -606,40 +606,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
     tiled_body<MODE, W, false, true>(d, a, sh, 0, 0, 0);   // item range from a.totals
 }
 
-// Grid barrier of a persistent run.  Every wavefront's loads, stores and
-// atomics have completed before its workgroup arrives; a workgroup counts
-// itself on its XCD's counter, the last of an XCD counts the XCD on the global
-// counter, and the last XCD writes gen into every XCD's release word; each
-// workgroup waits for its XCD's (bounded spin: a timeout sets
-// MPM_FLAG_BARRIER_TIMEOUT and returns false).  Arrivals and polls never share
-// a line, and each release word has one XCD's workgroups polling it.
-__device__ __forceinline__ bool run_barrier(const Dev &d, unsigned *ctr, unsigned gen, int spin_limit, int &ok_shared)
-{
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        unsigned *g = ctr + NXCD * RUN_BARRIER_LINE;
-        unsigned *rel = ctr + (NXCD + 2) * RUN_BARRIER_LINE;
-        const unsigned per = gridDim.x / NXCD, x = blockIdx.x % NXCD;
-        if (__hip_atomic_fetch_add(gptr(ctr + x * RUN_BARRIER_LINE), 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * per)
-            if (__hip_atomic_fetch_add(gptr(g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * NXCD)
-                for (int q = 0; q < NXCD; ++q)
-                    __hip_atomic_store(gptr(rel + q * RUN_BARRIER_LINE), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1, spins = 0;
-        while (__hip_atomic_load(gptr(rel + x * RUN_BARRIER_LINE), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (++spins > spin_limit) { ok = 0; break; }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (!ok) set_flag(d.status, 0, MPM_FLAG_BARRIER_TIMEOUT);
-        ok_shared = ok;
-    }
-    __syncthreads();
-    return ok_shared != 0;
-}
-
 // A persistent run of the grid-at-staging form (GasRun): the fused substeps
 // between two sorts of a single environment in one launch, with every
 // workgroup resident (the launch uses the occupancy-derived count).  Between
@@ -705,13 +671,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
         }
         if (threadIdx.x == 0) d.step[0] += done;
     }
-    // the last workgroup out zeroes the counters for the next run
-    if (threadIdx.x == 0) {
-        unsigned *ex = r.bar + (NXCD + 1) * RUN_BARRIER_LINE;
-        if (__hip_atomic_fetch_add(gptr(ex), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gridDim.x)
-            for (int q = 0; q < 2 * NXCD + 2; ++q)
-                __hip_atomic_store(gptr(r.bar + q * RUN_BARRIER_LINE), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    run_exit(r.bar);
 }
 
 // Grid operation at staging: the clear of one momentum buffer on its own.
@@ -727,12 +687,15 @@ __global__ __launch_bounds__(256) void k_gas_clear(TiledArgs a)
 template <bool SDF>
 __device__ __forceinline__ void grid_active_body(const Dev &d, const ActiveBuf &a, int par)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // 256 threads (k_grid_active's launch): the wavefront count is a constant, so the
+    // first list entry's address does not wait for the launch's size
+    constexpr int nw = 256 >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int stride = gridDim.x * nw;
     int i = blockIdx.x * nw + wave;
     // the first static entry is loaded together with the counts (used only if i < ns)
-    int bs = i < a.nbricks ? gload(a.slist + i) : 0;
-    const int ns = gload(a.scount), nd = gload(a.dcount + par);
+    int bs = i < a.nbricks ? uload(a.slist + i) : 0;
+    const int ns = uload(a.scount), nd = gload(a.dcount + par);
     const int32_t *dl = a.dlist + (size_t)par * a.nbricks;
     // one environment: its entry is loaded once, before the loop; several: each
     // brick's environment is looked up beside its P (not after the emptiness test),

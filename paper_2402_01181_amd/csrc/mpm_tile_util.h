@@ -79,6 +79,51 @@ __device__ __forceinline__ void mark_far_brick(const ActiveBuf &act, int par, in
     }
 }
 
+// Grid barrier of a persistent run.  Every wavefront's loads, stores and
+// atomics have completed before its workgroup arrives; a workgroup counts
+// itself on its XCD's counter, the last of an XCD counts the XCD on the global
+// counter, and the last XCD writes gen into every XCD's release word; each
+// workgroup waits for its XCD's (bounded spin: a timeout sets
+// MPM_FLAG_BARRIER_TIMEOUT and returns false).  Arrivals and polls never share
+// a line, and each release word has one XCD's workgroups polling it.
+__device__ __forceinline__ bool run_barrier(const Dev &d, unsigned *ctr, unsigned gen, int spin_limit, int &ok_shared)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        unsigned *g = ctr + NXCD * RUN_BARRIER_LINE;
+        unsigned *rel = ctr + (NXCD + 2) * RUN_BARRIER_LINE;
+        const unsigned per = gridDim.x / NXCD, x = blockIdx.x % NXCD;
+        if (__hip_atomic_fetch_add(gptr(ctr + x * RUN_BARRIER_LINE), 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * per)
+            if (__hip_atomic_fetch_add(gptr(g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gen * NXCD)
+                for (int q = 0; q < NXCD; ++q)
+                    __hip_atomic_store(gptr(rel + q * RUN_BARRIER_LINE), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(gptr(rel + x * RUN_BARRIER_LINE), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (++spins > spin_limit) { ok = 0; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (!ok) set_flag(d.status, 0, MPM_FLAG_BARRIER_TIMEOUT);
+        ok_shared = ok;
+    }
+    __syncthreads();
+    return ok_shared != 0;
+}
+
+// End of a persistent run: the last workgroup out zeroes the barrier's
+// counters for the next run (every other workgroup has left its last wait).
+__device__ __forceinline__ void run_exit(unsigned *bar)
+{
+    if (threadIdx.x != 0) return;
+    unsigned *ex = bar + (NXCD + 1) * RUN_BARRIER_LINE;
+    if (__hip_atomic_fetch_add(gptr(ex), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == gridDim.x)
+        for (int q = 0; q < 2 * NXCD + 2; ++q)
+            __hip_atomic_store(gptr(bar + q * RUN_BARRIER_LINE), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool stencil_in_tile(const Tile &t, const Stencil &s, int &l0, int &l1, int &l2)
 {
     l0 = s.b[0] - t.o[0];

@@ -41,20 +41,26 @@ def _pressing_scene(seed, N, n, S, contact=scenes.CONTACT_SLIP):
     return sc, env
 
 
-@pytest.mark.parametrize("scheme,contact,slots", [("tiled", scenes.CONTACT_SLIP, 3), ("direct", scenes.CONTACT_SLIP, 3),
-                                                  ("tiled", scenes.CONTACT_STICKY, 3), ("tiled", scenes.CONTACT_SLIP, 1)])
-def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots):
+@pytest.mark.parametrize("scheme,contact,slots,pers", [("tiled", scenes.CONTACT_SLIP, 3, 0),
+                                                       ("direct", scenes.CONTACT_SLIP, 3, 0),
+                                                       ("tiled", scenes.CONTACT_STICKY, 3, 0),
+                                                       ("tiled", scenes.CONTACT_SLIP, 1, 0),
+                                                       ("tiled", scenes.CONTACT_SLIP, 3, 1),
+                                                       ("tiled", scenes.CONTACT_STICKY, 1, 1)])
+def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots, pers):
+    """Every gradient against the oracle's FP64 adjoint; pers: the recorded
+    forward takes persistent runs of the grid at staging."""
     Sim, L, torch = gpu
     S, N, n, k = 12, 2000, 32, 5
     _say(f"adjoint vs oracle adjoint: {N} particles, {n}^3, {S} substeps, checkpoints every {k}, {scheme}, "
-         f"contact={contact}, node slots {slots}")
+         f"contact={contact}, node slots {slots}, persistent {pers}")
     sc, env = _pressing_scene(51 + contact, N, n, S, contact)
     rng = np.random.default_rng(3)
     W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
          rng.standard_normal((N, 3, 3))]
     sim = Sim(sc, max_tape=S, checkpoint_every=k,
               options={L.OPT_SCHEME: L.SCHEME_TILED if scheme == "tiled" else L.SCHEME_DIRECT, L.OPT_SORT_EVERY: 3,
-                       L.OPT_NODE_SLOTS: slots})
+                       L.OPT_NODE_SLOTS: slots, L.OPT_PERSISTENT: pers, L.OPT_GRID_AT_STAGING: pers})
     sim.step(S, record_tape=True)
     soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
     g = sim.adjoint(S, soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))
@@ -76,7 +82,8 @@ def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots):
         assert e <= TOL_GRAD, (name, e)
 
 
-def test_adjoint_with_particles_leaving_their_tiles(gpu, orc):
+@pytest.mark.parametrize("pers", [0, 1])
+def test_adjoint_with_particles_leaving_their_tiles(gpu, orc, pers):
     """The slab and the tool translate at 80 m/s along x, so within one tape
     segment (6 substeps, one sort at its start) every particle moves more than
     a cell and those at brick edges leave their work item's tile: the reverse
@@ -98,7 +105,8 @@ def test_adjoint_with_particles_leaving_their_tiles(gpu, orc):
     rng = np.random.default_rng(5)
     W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
          rng.standard_normal((N, 3, 3))]
-    sim = Sim(sc, max_tape=S, checkpoint_every=k, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: k})
+    sim = Sim(sc, max_tape=S, checkpoint_every=k,
+              options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: k, L.OPT_PERSISTENT: pers})
     sim.step(S, record_tape=True)
     assert sim.read(L.F_STATUS) == 0
     soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
@@ -120,15 +128,16 @@ def test_adjoint_with_particles_leaving_their_tiles(gpu, orc):
         assert e <= TOL_GRAD, (name, e)
 
 
-def test_adjoint_window_shorter_than_tape(gpu, orc):
+@pytest.mark.parametrize("pers", [0, 1])
+def test_adjoint_window_shorter_than_tape(gpu, orc, pers):
     """Reverse only the last 7 of 12 recorded substeps."""
     Sim, L, torch = gpu
     S, N, n, k, w = 12, 1500, 32, 4, 7
-    _say(f"adjoint window {w} of {S} substeps")
+    _say(f"adjoint window {w} of {S} substeps, persistent {pers}")
     sc, env = _pressing_scene(61, N, n, S)
     rng = np.random.default_rng(4)
     Wx = rng.standard_normal((N, 3))
-    sim = Sim(sc, max_tape=S, checkpoint_every=k)
+    sim = Sim(sc, max_tape=S, checkpoint_every=k, options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_PERSISTENT: pers})
     sim.step(S, record_tape=True)
     g = sim.adjoint(w, torch.tensor(Wx.T.copy(), dtype=torch.float32))
     o = oracle_sim_like(orc, sc)
@@ -144,19 +153,26 @@ def test_adjoint_window_shorter_than_tape(gpu, orc):
         assert e <= TOL_GRAD, (name, e)
 
 
-def test_autograd_diff_slab_full_size_vs_fd(gpu, orc):
+@pytest.mark.parametrize("shipped", [0, 1])
+def test_autograd_diff_slab_full_size_vs_fd(gpu, orc, shipped):
     """The differentiable workload at full size: 30K particles, 64^3, 200
     substeps, checkpoints every 20; loss = |centroid - target|^2; gradients
     with respect to E, nu and the 200 tool velocities against FP64 central
-    differences of the oracle."""
+    differences of the oracle.  shipped: the slab's benchmark launch options
+    (the forward in persistent runs of the grid at staging)."""
     Sim, L, torch = gpu
     from paper_2402_01181_amd.autograd import MPMRollout
     sc = scenes.diff_scene()
     env = sc.envs[0]
     S = sc.substeps
     target = torch.tensor(sc.extra["target"], dtype=torch.float64)
-    _say(f"autograd rollout: {env.N} particles, {S} substeps, checkpoints every {sc.extra['checkpoint_every']}")
-    sim = Sim(sc, max_tape=S, checkpoint_every=sc.extra["checkpoint_every"])
+    opts = {}
+    if shipped:
+        opts = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_BLOCK: 256, L.OPT_ITEM: 160, L.OPT_SORT_EVERY: 32,
+                L.OPT_NODE_SLOTS: 3, L.OPT_GRID_AT_STAGING: 1, L.OPT_PERSISTENT: 1}
+    _say(f"autograd rollout: {env.N} particles, {S} substeps, checkpoints every {sc.extra['checkpoint_every']}, "
+         f"options {opts}")
+    sim = Sim(sc, max_tape=S, checkpoint_every=sc.extra["checkpoint_every"], options=opts)
     E = torch.tensor([env.E], dtype=torch.float64, requires_grad=True)
     nu = torch.tensor([env.nu], dtype=torch.float64, requires_grad=True)
     u = torch.tensor(env.tools[0].traj[None, None], dtype=torch.float64, requires_grad=True)
