@@ -273,13 +273,20 @@ def stored_traffic(config: str, kernel: str, options) -> float | None:
     if t.get("source_sha256") != source_hash():
         return None
     from paper_2402_01181_amd import _lib as L
-    shape = (L.OPT_SCHEME, L.OPT_SORT_EVERY, L.OPT_BLOCK, L.OPT_ITEM, L.OPT_PERSISTENT, L.OPT_NODE_SLOTS)
+    shape = (L.OPT_SCHEME, L.OPT_SORT_EVERY, L.OPT_BLOCK, L.OPT_ITEM, L.OPT_PERSISTENT, L.OPT_NODE_SLOTS,
+             L.OPT_GRID_AT_STAGING)
     mine = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in options.items()}}
     theirs = {**L.OPT_DEFAULTS, **{int(k): int(v) for k, v in t.get("options", {}).items()}}
     if any(mine[k] != theirs[k] for k in shape):
         return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_dispatch"])
+    if k is None:
+        return None
+    # a persistent run's dispatch covers a variable number of substeps: its
+    # bytes are stored per substep and scaled by the caller
+    if "bytes_per_substep" in k:
+        return {"bytes_per_substep": float(k["bytes_per_substep"])}
+    return float(k["bytes_per_dispatch"])
 
 
 def _cpu_model() -> str:
@@ -340,11 +347,13 @@ def _roofline(rep, N, nodes, K, traffic, gas=False):
     dom = max(rep, key=lambda k: rep[k][0])
     t_ms, n_launch = rep[dom]
     avg_s = t_ms / n_launch * 1e-3
+    substeps_per_launch = 1.0
     if dom.startswith("persistent"):
         # one launch runs a whole run of substeps between sorts (with the grid at
         # staging, every substep of the call but its tail)
         per_substep = N * BYTES_PER_PARTICLE + nodes * (BYTES_PER_NODE_GAS if gas else BYTES_PER_NODE_SUBSTEP)
-        per_launch = per_substep * ((K - 1) if gas else K) / n_launch
+        substeps_per_launch = ((K - 1) if gas else K) / n_launch
+        per_launch = per_substep * substeps_per_launch
     elif dom.startswith("fused"):
         per_launch = N * BYTES_PER_PARTICLE + nodes * (BYTES_PER_NODE_GAS if gas else BYTES_PER_NODE_FUSED)
     elif dom.startswith("grid"):
@@ -352,8 +361,11 @@ def _roofline(rep, N, nodes, K, traffic, gas=False):
     else:
         per_launch = N * BYTES_PER_PARTICLE + nodes * BYTES_PER_NODE_SUBSTEP
     achieved = per_launch / avg_s / 1e9
+    measured = traffic(dom)
+    if isinstance(measured, dict):
+        measured = measured["bytes_per_substep"] * substeps_per_launch
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic(dom),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured,
             "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
 
 
