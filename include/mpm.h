@@ -62,7 +62,7 @@ enum {
     MPM_FLAG_OUT_OF_DOMAIN = 1u,    /* a particle's 3x3x3 stencil left the grid; it was frozen */
     MPM_FLAG_INVERTED = 2u,         /* det F <= 1e-6 (FP64); the stress used ln(1e-6) */
     MPM_FLAG_NONFINITE = 4u,        /* a particle position or velocity became non-finite */
-    MPM_FLAG_BARRIER_TIMEOUT = 8u   /* persistent kernel: a group barrier exceeded its spin limit */
+    MPM_FLAG_BARRIER_TIMEOUT = 8u   /* persistent kernels: a barrier exceeded its spin limit */
 };
 
 /* Fields for mpm_read_state. */
@@ -131,9 +131,10 @@ enum {
                                  proportion to its particles; small environments share one) and steps
                                  through the run alone: grid operation, then particle pass, separated by
                                  barriers of that group only (a counter per environment, bounded spin; a
-                                 timeout sets MPM_FLAG_BARRIER_TIMEOUT).  Setting it (or the block or
-                                 item size while it is on) builds the group table with a synchronous
-                                 copy, so set it outside stream capture */
+                                 timeout sets MPM_FLAG_BARRIER_TIMEOUT).  With MPM_OPT_GRID_AT_STAGING and
+                                 one environment the runs take that form instead (see there).  Setting it
+                                 (or the block or item size while it is on) builds the group table with a
+                                 synchronous copy, so set it outside stream capture */
     MPM_OPT_SPIN_LIMIT = 5,   /* persistent kernel: barrier spin limit (iterations), > 0 */
     MPM_OPT_ITEM = 6,         /* tiled scheme: max particles per work item, multiple of 16 in [16, 4096] */
     MPM_OPT_NODE_SLOTS = 7,   /* tiled scheme: particles per half-wavefront step of the P2G node pass, 1 or 3
