@@ -809,7 +809,8 @@ struct AdjShared {
     float4 tb[PB ? TILE_NODES : 1];
     float4 tv[GV ? TILE_NODES : 1];
     float4 tp[GV ? 2 * W * TILE_NODES : 1];
-    Payload4 pay[GV ? 64 * W : 1];
+    Payload pay[GV ? 64 * W : 1];
+    float2 wz[GV ? 64 * W : 1];
 };
 
 // Material of the tile's environment: mu, lambda, particle mass, stress factor.
@@ -864,7 +865,7 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
             const bool active = q < item_end;
             const uint32_t uq = (uint32_t)q;
             double mub = 0.0, lamb = 0.0;
-            int key = 0;
+            int key = KEY_NONE;
             if (active) {
                 // reverse P2G terms first, into zeroed sums; the particle's adjoint
                 // state is loaded after them, so it is not held across the stencil sums.
@@ -940,7 +941,7 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
                             vbt, Bb);
                         // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q)
                         key = in_tile ? key_in_tile(l0, l1, l2) : key_global(s.b);
-                        store_payload(sh.pay[tid], s.fx, key, vbt, Bb);
+                        store_payload(sh.pay[tid], sh.wz[tid], s.fx, s.w[2], key, vbt, Bb);
                     }
                 }
                 store_adj(a, N, uq, xb, vb, Cb, Fb);
@@ -951,12 +952,12 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
                 wave_env_add(a.lambar, t.env, lamb, active);
             }
             if (GV) {
-                if (!key) sh.pay[tid].fk.w = __int_as_float(0);
+                if (key == KEY_NONE) payload_none(sh.pay[tid]);
                 __syncthreads();
                 int r0, r1;
                 half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
                 // .x sums the weights (the flush skips nodes no particle reached)
-                node_pass(ta.slots, sh.pay, r0, r1, sh.tp + hw * TILE_NODES, lane, 1.0f,
+                node_pass(ta.slots, sh.pay, sh.wz, r0, r1, sh.tp + hw * TILE_NODES, lane, 1.0f,
                           [&](const float4 &c4, int i, int j, int k) {
                               float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
                               gatomic_add(g + 0, c4.y);
@@ -1016,7 +1017,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
 // Reverse P2G of substep j (dp: slot j) and reverse G2P of substep j - 1
 // (dg: slot j - 1) in one pass over the particles.
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBuf a, AdjTiledArgs ta)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBuf a, AdjTiledArgs ta)
 {
     __shared__ AdjShared<W, true, true> sh;
     adj_tiled_body<W, true, true>(dp, dg, a, ta, sh);

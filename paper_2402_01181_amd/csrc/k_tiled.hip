@@ -95,11 +95,12 @@ __device__ __forceinline__ void affine_stress_f(const Dev &d, const EnvDev &e, c
 // per clock per CU on this chip, far below plain LDS traffic.  The 2W tiles
 // are summed and flushed to the global grid with one float atomic per
 // component per non-empty node.
-template <int W, bool GAS = false>
+template <int W, bool GAS = false, bool P2G = true>
 struct TiledShared {
     float4 tv[GAS ? GTILE_NODES : TILE_NODES];   // node velocities (GAS: the 8^3 tile)
-    float4 tp[2 * W * TILE_NODES];               // per-half-wave (m, mv) tiles
-    Payload4 pay[64 * W];
+    float4 tp[P2G ? 2 * W * TILE_NODES : 1];     // per-half-wave (m, mv) tiles
+    Payload pay[P2G ? 64 * W : 1];
+    float2 wz[P2G ? 64 * W : 1];                 // the payloads' side array
     ToolDev tl[GAS ? MAX_TOOLS : 1];             // GAS: the item environment's tools at this substep
 };
 
@@ -267,15 +268,15 @@ __device__ __forceinline__ void gas_tools_commit(const Dev &d, ToolDev *tl, GasS
 // stages the 8^3 node velocities of its tile by applying the grid operation
 // to this substep's momentum (a.gP_read) with the tool slots gs carries into
 // LDS, and P2G writes the next substep's momentum to d.gP.
-template <int MODE, int W, bool COH, bool GAS>
-__device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
+template <int MODE, int W, bool COH, bool GAS, class SH>
+__device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, SH &sh, int first,
                                             int stride, int end, GasState<64 * W> &gs)
 {
     constexpr bool G2P = MODE >= 1, P2G = MODE <= 1 || MODE == 3;
     constexpr int T = 64 * W;
     constexpr int TS = GAS ? GTILE : TILE;   // velocity tile edge
     float4 *tv = sh.tv, *tp = sh.tp;
-    Payload4 *pay = sh.pay;
+    Payload *pay = sh.pay;
 
     const int N = d.ntot, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = 2 * wave + (lane >> 5);   // half-wave index
@@ -375,7 +376,7 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
         for (int chunk = item.y; chunk < item_end; chunk += T) {
             // ---- pass 1: lane = particle
             const int p = chunk + tid;
-            int key = 0;
+            int key = KEY_NONE;
             if (p < item_end) {
                 float x[3] = {px[0], px[1], px[2]};
                 float H[9], v[3], C[9];
@@ -416,13 +417,24 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
                             v[0] = v[1] = v[2] = 0.f;
                             const float4 *tb = tv + (l0 * TS + l1) * TS + l2;
 #pragma unroll
-                            for (int a0 = 0; a0 < 3; ++a0)
+                            for (int a0 = 0; a0 < 3; ++a0) {
+                                // a plane's nine reads are issued together (the barrier keeps
+                                // them ahead of the sums), so their latencies overlap
+                                float3 Vp[3][3];
+#pragma unroll
+                                for (int a1 = 0; a1 < 3; ++a1)
+#pragma unroll
+                                    for (int a2 = 0; a2 < 3; ++a2) {
+                                        const float4 V = tb[(a0 * TS + a1) * TS + a2];
+                                        Vp[a1][a2] = make_float3(V.x, V.y, V.z);
+                                    }
+                                asm volatile("" ::: "memory");
 #pragma unroll
                                 for (int a1 = 0; a1 < 3; ++a1) {
                                     float sx = 0.f, sy = 0.f, sz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
 #pragma unroll
                                     for (int a2 = 0; a2 < 3; ++a2) {
-                                        const float4 V = tb[(a0 * TS + a1) * TS + a2];
+                                        const float3 V = Vp[a1][a2];
                                         const float w2 = s.w[2][a2];
                                         sx = fmaf(w2, V.x, sx); sy = fmaf(w2, V.y, sy); sz = fmaf(w2, V.z, sz);
                                         ux = fmaf(w2q[a2], V.x, ux); uy = fmaf(w2q[a2], V.y, uy);
@@ -435,6 +447,7 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
                                     B[3] = fmaf(w0q, sy, B[3]); B[4] = fmaf(w1q, sy, B[4]); B[5] = fmaf(ww, uy, B[5]);
                                     B[6] = fmaf(w0q, sz, B[6]); B[7] = fmaf(w1q, sz, B[7]); B[8] = fmaf(ww, uz, B[8]);
                                 }
+                            }
                             const float cs = 4.0f * e.inv_dx;
 #pragma unroll
                             for (int c = 0; c < 9; ++c) C[c] = cs * B[c];
@@ -478,7 +491,7 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
                             const float mv[3] = {m * v[0], m * v[1], m * v[2]};
 #pragma unroll
                             for (int c = 0; c < 9; ++c) A[c] *= e.dx;
-                            store_payload(pay[tid], s2.fx, key, mv, A);
+                            store_payload(pay[tid], sh.wz[tid], s2.fx, s2.w[2], key, mv, A);
                         }
                     }
                     if (G2P) {
@@ -498,12 +511,12 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
             }
             if (chunk + T < item_end) prefetch(chunk + T);
             if (P2G) {
-                if (!key) pay[tid].fk.w = __int_as_float(0);
+                if (key == KEY_NONE) payload_none(pay[tid]);
                 __syncthreads();
                 // ---- pass 2: lane = stencil node, the chunk split into 2W contiguous runs
                 int r0, r1;
                 half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
-                node_pass(a.slots, pay, r0, r1, tp + hw * TILE_NODES, lane, m, [&](const float4 &c4, int i, int j, int k) {
+                node_pass(a.slots, pay, sh.wz, r0, r1, tp + hw * TILE_NODES, lane, m, [&](const float4 &c4, int i, int j, int k) {
                     // stencil outside the tile: straight to the global grid
                     float *g = reinterpret_cast<float *>(d.gP + node_id(e, i, j, k));
                     gatomic_add(g + 0, c4.x);
@@ -561,8 +574,8 @@ __device__ __forceinline__ void tiled_items(const Dev &d, const TiledArgs &a, Ti
 // item range from a.totals (first, stride and end are ignored), after issuing
 // the loads that do not depend on it: the momentum clear's, and a single
 // environment's entry and tool slots.
-template <int MODE, int W, bool COH = false, bool GAS = false>
-__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, TiledShared<W, GAS> &sh, int first,
+template <int MODE, int W, bool COH = false, bool GAS = false, class SH>
+__device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, SH &sh, int first,
                                            int stride, int end)
 {
     constexpr bool G2P = MODE >= 1;
@@ -591,7 +604,7 @@ __device__ __forceinline__ void tiled_body(const Dev &d, const TiledArgs &a, Til
 template <int MODE, int W>
 __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 {
-    __shared__ TiledShared<W> sh;
+    __shared__ TiledShared<W, false, MODE != 2> sh;
     int first, stride, end;
     item_range(uload(a.totals).y, first, stride, end);
     tiled_body<MODE, W>(d, a, sh, first, stride, end);
@@ -602,7 +615,7 @@ __global__ __launch_bounds__(64 * W) void k_tiled(Dev d, TiledArgs a)
 template <int MODE, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_tiled_gas(Dev d, TiledArgs a)
 {
-    __shared__ TiledShared<W, true> sh;
+    __shared__ TiledShared<W, true, MODE != 2> sh;
     tiled_body<MODE, W, false, true>(d, a, sh, 0, 0, 0);   // item range from a.totals
 }
 

@@ -143,47 +143,71 @@ __device__ __forceinline__ bool stencil_in_gtile(const Tile &t, const Stencil &s
 }
 
 // Per-particle inputs handed from a particle pass (lane = particle) to the
-// node pass of the same workgroup (lane = stencil node), 64 bytes = four LDS
-// vector reads: fx and a packed key, a 3-vector g, and a 3x3 matrix M row by
-// row.  Node o of the stencil receives w(o) (s, g + M (o - fx)); s is the
-// particle mass in P2G and 1 (a touch count) in the G2P adjoint.
-struct Payload4 {
-    float4 fk;         // fx0, fx1, fx2, key
-    float4 q1;         // g, M00
-    float4 q2;         // M01, M02, M10, M11
-    float4 q3;         // M12, M20, M21, M22
+// node pass of the same workgroup (lane = stencil node), 72 bytes = four LDS
+// vector reads of the payload and one of its side array.  Node o (integer
+// offsets from the stencil base) receives w(o) (s, g + M (o - fx)); s is the
+// particle mass in P2G and 1 (a touch count) in the G2P adjoint.  The
+// particle pass stores g0 = g - M fx, so a node lane forms g0 + M o from
+// integer offsets, and the third axis's three B-spline weights, which are
+// the same for every lane of a particle.
+struct Payload {
+    float4 fk;   // fx0, fx1, third-axis weight at offset 0, key (an int, see below)
+    float4 q1;   // g0, M00
+    float4 q2;   // M01, M02, M10, M11
+    float4 q3;   // M12, M20, M21, M22
 };
-// key: bit 0 valid; bit 1 stencil inside the tile, then bits 2.. hold the
-// tile index of the stencil base; otherwise bits 2-11, 12-21, 22-31 hold the
-// absolute base (grids are at most 512 nodes per axis).
-constexpr int KEY_VALID = 1, KEY_IN_TILE = 2;
+// The side array holds the third-axis weights at offsets 1 and 2 (a float2 per
+// payload: the payload stays 64 bytes, the LDS of the smaller workgroups
+// within what six of them may hold per CU).
+//
+// key: >= 0: the stencil is inside the tile and the key is the tile index of
+// its base; KEY_NONE: no particle; otherwise the stencil leaves the tile and
+// bits 0-9, 10-19, 20-29 hold its absolute base (grids are at most 512 nodes
+// per axis), bit 31 set.
+constexpr int KEY_NONE = -1;
 
-__device__ __forceinline__ int key_in_tile(int l0, int l1, int l2)
-{
-    return KEY_VALID | KEY_IN_TILE | (((l0 * TILE + l1) * TILE + l2) << 2);
-}
+__device__ __forceinline__ int key_in_tile(int l0, int l1, int l2) { return (l0 * TILE + l1) * TILE + l2; }
 __device__ __forceinline__ int key_global(const int b[3])
 {
-    return KEY_VALID | (b[0] << 2) | (b[1] << 12) | (b[2] << 22);
+    return (int)(0x80000000u | (unsigned)b[0] | ((unsigned)b[1] << 10) | ((unsigned)b[2] << 20));
 }
 
-__device__ __forceinline__ void store_payload(Payload4 &P, const float fx[3], int key, const float g[3],
-                                              const float M[9])
+// w2: the third axis's weights at offsets 0, 1, 2 (the particle pass has them
+// from its stencil).
+__device__ __forceinline__ void store_payload(Payload &P, float2 &wz, const float fx[3], const float w2[3], int key,
+                                              const float g[3], const float M[9])
 {
-    P.fk = make_float4(fx[0], fx[1], fx[2], __int_as_float(key));
-    P.q1 = make_float4(g[0], g[1], g[2], M[0]);
+    float g0[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) g0[r] = fmaf(-M[3 * r], fx[0], fmaf(-M[3 * r + 1], fx[1], fmaf(-M[3 * r + 2], fx[2], g[r])));
+    P.fk = make_float4(fx[0], fx[1], w2[0], __int_as_float(key));
+    P.q1 = make_float4(g0[0], g0[1], g0[2], M[0]);
     P.q2 = make_float4(M[1], M[2], M[3], M[4]);
     P.q3 = make_float4(M[5], M[6], M[7], M[8]);
+    wz = make_float2(w2[1], w2[2]);
+}
+
+
+// A payload slot without a particle.
+__device__ __forceinline__ void payload_none(Payload &P) { P.fk.w = __int_as_float(KEY_NONE); }
+
+// The absolute node of a stencil that leaves the tile: key's base + (o0, o1, o2).
+__device__ __forceinline__ void key_node(int key, int o0, int o1, int o2, int &i, int &j, int &k)
+{
+    i = (key & 1023) + o0;
+    j = ((key >> 10) & 1023) + o1;
+    k = ((key >> 20) & 1023) + o2;
 }
 
 // One particle per half-wave step (node_pass1).  Lane o < 27 of each
-// half-wave takes stencil node (o0, o1, o2); the quadratic B-spline of that
-// offset is alpha (fx - c)^2 + gamma per axis (fx in [0.5, 1.5)), three
-// constants instead of a branch.
+// half-wave takes stencil node (o0, o1, o2); the quadratic B-spline of the
+// first two offsets is alpha (fx - c)^2 + gamma (fx in [0.5, 1.5)), three
+// constants instead of a branch; the third comes with the payload.
 struct NodeLane1 {
     bool on;
     int o0, o1, o2, lo;   // lo: tile offset of the node from the stencil base
-    float wc[3], wa[3], wg[3];
+    float of[3];          // the offsets as floats
+    float wc[2], wa[2], wg[2];
 };
 
 // An opaque copy of a value: the out-of-tile path of the node pass is rare, and
@@ -204,7 +228,9 @@ __device__ __forceinline__ NodeLane1 node_lane1(int lane)
     L.lo = (L.o0 * TILE + L.o1) * TILE + L.o2;
     const int oo[3] = {L.o0, L.o1, L.o2};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 3; ++k) L.of[k] = (float)oo[k];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
         L.wc[k] = 1.5f - 0.5f * oo[k];
         L.wa[k] = oo[k] == 1 ? -1.0f : 0.5f;
         L.wg[k] = oo[k] == 1 ? 0.75f : 0.0f;
@@ -220,27 +246,27 @@ __device__ __forceinline__ NodeLane1 node_lane1(int lane)
 // half-wave writes the tile, so no atomic is needed.  A stencil outside the
 // tile goes to `outside(c4, i, j, k)` (node indices).
 template <class Outside>
-__device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, float4 *tile, int lane, float s,
-                                           Outside &&outside)
+__device__ __forceinline__ void node_pass1(const Payload *pay, const float2 *wzs, int r0, int r1, float4 *tile,
+                                           int lane, float s, Outside &&outside)
 {
     const NodeLane1 L = node_lane1(lane);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int cur = -1;
     for (int r = r0; L.on && r < r1; ++r) {
-        const Payload4 &P = pay[r];
+        const Payload &P = pay[r];
         const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
-        const int pk = __float_as_int(fk.w);
-        const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1], t2 = fk.z - L.wc[2];
-        const float w = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]) *
-                        fmaf(L.wa[2], t2 * t2, L.wg[2]);
-        const float d0 = L.o0 - fk.x, d1 = L.o1 - fk.y, d2 = L.o2 - fk.z;
-        // g + M d: the momentum term at this node before the weight
-        const float gx = fmaf(q1.w, d0, fmaf(q2.x, d1, fmaf(q2.y, d2, q1.x)));
-        const float gy = fmaf(q2.z, d0, fmaf(q2.w, d1, fmaf(q3.x, d2, q1.y)));
-        const float gz = fmaf(q3.y, d0, fmaf(q3.z, d1, fmaf(q3.w, d2, q1.z)));
-        if (!(pk & KEY_VALID)) continue;
-        if (pk & KEY_IN_TILE) {
-            const int l = (pk >> 2) + L.lo;
+        const float2 wz = wzs[r];
+        const int key = __float_as_int(fk.w);
+        if (key == KEY_NONE) continue;
+        const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1];
+        const float w2 = L.o2 == 0 ? fk.z : (L.o2 == 1 ? wz.x : wz.y);
+        const float w = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]) * w2;
+        // g0 + M o: the momentum term at this node before the weight
+        const float gx = fmaf(q1.w, L.of[0], fmaf(q2.x, L.of[1], fmaf(q2.y, L.of[2], q1.x)));
+        const float gy = fmaf(q2.z, L.of[0], fmaf(q2.w, L.of[1], fmaf(q3.x, L.of[2], q1.y)));
+        const float gz = fmaf(q3.y, L.of[0], fmaf(q3.z, L.of[1], fmaf(q3.w, L.of[2], q1.z)));
+        if (key >= 0) {
+            const int l = key + L.lo;
             if (l != cur) {
                 if (cur >= 0) {
                     float4 old = tile[cur];
@@ -251,9 +277,9 @@ __device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, 
             }
             acc.x = fmaf(w, s, acc.x); acc.y = fmaf(w, gx, acc.y); acc.z = fmaf(w, gy, acc.z); acc.w = fmaf(w, gz, acc.w);
         } else {
-            const int k = opaque(pk);
-            outside(make_float4(w * s, w * gx, w * gy, w * gz), ((k >> 2) & 1023) + L.o0, ((k >> 12) & 1023) + L.o1,
-                    ((k >> 22) & 1023) + L.o2);
+            int i, j, k;
+            key_node(opaque(key), L.o0, L.o1, L.o2, i, j, k);
+            outside(make_float4(w * s, w * gx, w * gy, w * gz), i, j, k);
         }
     }
     if (cur >= 0) {
@@ -269,6 +295,7 @@ __device__ __forceinline__ void node_pass1(const Payload4 *pay, int r0, int r1, 
 struct NodeLane3 {
     bool on;
     int slot, o0, o1, lo;   // lo: tile offset of node (o0, o1, 0) from the stencil base
+    float of0, of1;         // o0, o1 as floats
     float wc[2], wa[2], wg[2];
 };
 
@@ -281,6 +308,8 @@ __device__ __forceinline__ NodeLane3 node_lane3(int lane)
     L.o0 = (o % 9) / 3;
     L.o1 = o % 3;
     L.lo = (L.o0 * TILE + L.o1) * TILE;
+    L.of0 = (float)L.o0;
+    L.of1 = (float)L.o1;
     const int oo[2] = {L.o0, L.o1};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -301,8 +330,8 @@ __device__ __forceinline__ NodeLane3 node_lane3(int lane)
 // half-wave writes the tile), so no atomic is needed.  A stencil outside the
 // tile goes to `outside(c4, i, j, k)` (node indices), node by node.
 template <class Outside>
-__device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, float4 *tile, int lane, float s,
-                                           Outside &&outside)
+__device__ __forceinline__ void node_pass3(const Payload *pay, const float2 *wzs, int r0, int r1, float4 *tile,
+                                           int lane, float s, Outside &&outside)
 {
     const NodeLane3 L = node_lane3(lane);
     const int per = (r1 - r0 + 2) / 3;
@@ -332,11 +361,13 @@ __device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, 
     for (int i = 0; i < per; ++i) {
         const int r = my0 + i;
         const bool live = L.on && r < my1;
-        const Payload4 &P = pay[live ? r : r0];
+        const int rr = live ? r : r0;
+        const Payload &P = pay[rr];
         const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
-        const int pk = live ? __float_as_int(fk.w) : 0;
-        const bool in_tile = (pk & (KEY_VALID | KEY_IN_TILE)) == (KEY_VALID | KEY_IN_TILE);
-        const int l = (pk >> 2) + L.lo;
+        const float2 wz = wzs[opaque(rr)];   // its own shift, not an offset from the payload's address
+        const int key = live ? __float_as_int(fk.w) : KEY_NONE;
+        const bool in_tile = key >= 0;
+        const int l = key + L.lo;
         const bool change = in_tile && l != cur;
         if (__ballot(change && cur >= 0)) flush(change && cur >= 0);
         if (change) {
@@ -344,28 +375,29 @@ __device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, 
             for (int c = 0; c < 3; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
             cur = l;
         }
-        if (!(pk & KEY_VALID)) continue;
         const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1];
         const float w01 = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]);
-        const float f2 = fk.z;
-        const float w2[3] = {0.5f * (1.5f - f2) * (1.5f - f2), 0.75f - (f2 - 1.0f) * (f2 - 1.0f),
-                             0.5f * (f2 - 0.5f) * (f2 - 0.5f)};
-        const float d0 = L.o0 - fk.x, d1 = L.o1 - fk.y;
-        // g + M (d0, d1, .) for this column; the third axis is added per node
-        const float bx = fmaf(q1.w, d0, fmaf(q2.x, d1, q1.x));
-        const float by = fmaf(q2.z, d0, fmaf(q2.w, d1, q1.y));
-        const float bz = fmaf(q3.y, d0, fmaf(q3.z, d1, q1.z));
+        const float w[3] = {w01 * fk.z, w01 * wz.x, w01 * wz.y};
+        // g0 + M (o0, o1, c): the column's base term, then the third axis node by node
+        float g[3][3];
+        g[0][0] = fmaf(q1.w, L.of0, fmaf(q2.x, L.of1, q1.x));
+        g[0][1] = fmaf(q2.z, L.of0, fmaf(q2.w, L.of1, q1.y));
+        g[0][2] = fmaf(q3.y, L.of0, fmaf(q3.z, L.of1, q1.z));
+        g[1][0] = g[0][0] + q2.y; g[1][1] = g[0][1] + q3.x; g[1][2] = g[0][2] + q3.w;
+        g[2][0] = g[1][0] + q2.y; g[2][1] = g[1][1] + q3.x; g[2][2] = g[1][2] + q3.w;
+        if (in_tile) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float d2 = c - f2, w = w01 * w2[c];
-            const float gx = fmaf(q2.y, d2, bx), gy = fmaf(q3.x, d2, by), gz = fmaf(q3.w, d2, bz);
-            if (in_tile) {
-                acc[c].x = fmaf(w, s, acc[c].x); acc[c].y = fmaf(w, gx, acc[c].y);
-                acc[c].z = fmaf(w, gy, acc[c].z); acc[c].w = fmaf(w, gz, acc[c].w);
-            } else {
-                const int k = opaque(pk);
-                outside(make_float4(w * s, w * gx, w * gy, w * gz), ((k >> 2) & 1023) + L.o0,
-                        ((k >> 12) & 1023) + L.o1, ((k >> 22) & 1023) + c);
+            for (int c = 0; c < 3; ++c) {
+                acc[c].x = fmaf(w[c], s, acc[c].x); acc[c].y = fmaf(w[c], g[c][0], acc[c].y);
+                acc[c].z = fmaf(w[c], g[c][1], acc[c].z); acc[c].w = fmaf(w[c], g[c][2], acc[c].w);
+            }
+        } else if (key != KEY_NONE) {
+            const int k = opaque(key);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int ni, nj, nk;
+                key_node(k, L.o0, L.o1, c, ni, nj, nk);
+                outside(make_float4(w[c] * s, w[c] * g[c][0], w[c] * g[c][1], w[c] * g[c][2]), ni, nj, nk);
             }
         }
     }
@@ -376,11 +408,11 @@ __device__ __forceinline__ void node_pass3(const Payload4 *pay, int r0, int r1, 
 // particle per step keeps runs long at few particles per cell; three per step
 // need a third of the arithmetic per node when cells hold many particles.
 template <class Outside>
-__device__ __forceinline__ void node_pass(int slots, const Payload4 *pay, int r0, int r1, float4 *tile, int lane,
-                                          float s, Outside &&outside)
+__device__ __forceinline__ void node_pass(int slots, const Payload *pay, const float2 *wz, int r0, int r1,
+                                          float4 *tile, int lane, float s, Outside &&outside)
 {
-    if (slots == 3) node_pass3(pay, r0, r1, tile, lane, s, outside);
-    else node_pass1(pay, r0, r1, tile, lane, s, outside);
+    if (slots == 3) node_pass3(pay, wz, r0, r1, tile, lane, s, outside);
+    else node_pass1(pay, wz, r0, r1, tile, lane, s, outside);
 }
 
 // Half-wave hw of 2W takes the contiguous run [r0, r1) of a chunk of n payloads.
