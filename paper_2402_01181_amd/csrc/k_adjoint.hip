@@ -483,12 +483,30 @@ __global__ void k_adj_finish(Dev d, AdjBuf a, int n, double *gE, double *gnu, do
 }
 
 // dst[c][pid[q]] = src[c][q]  (slot order -> original order)
+// Component c of element `from` of src to element `to` of dst, c < comps, in
+// groups of eight whose loads are all issued before the group's stores (the
+// arrays may alias as far as the compiler knows: a store between two loads
+// would wait for the first load's round trip).
+__device__ __forceinline__ void move_components(const float *src, size_t from, float *dst, size_t to, size_t n,
+                                                int comps)
+{
+    for (int c0 = 0; c0 < comps; c0 += 8) {
+        float t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c0 + k < comps) t[k] = gload(src + (size_t)(c0 + k) * n + from);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c0 + k < comps) gstore(dst + (size_t)(c0 + k) * n + to, t[k]);
+    }
+}
+
 __global__ void k_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst)
 {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ntot) return;
     int o = gload(pid + q);
-    for (int c = 0; c < comps; ++c) gstore(dst + (size_t)c * ntot + o, gload(src + (size_t)c * ntot + q));
+    move_components(src, q, dst, o, ntot, comps);
 }
 
 __global__ void k_copy_words(uint32_t *dst, const uint32_t *src, size_t n)
@@ -1030,10 +1048,8 @@ __global__ void k_permute(const float *src, const int32_t *perm, int ntot, int c
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ntot) return;
     int o = gload(perm + q);
-    for (int c = 0; c < comps; ++c) {
-        if (scatter) gstore(dst + (size_t)c * ntot + o, gload(src + (size_t)c * ntot + q));
-        else gstore(dst + (size_t)c * ntot + q, gload(src + (size_t)c * ntot + o));
-    }
+    if (scatter) move_components(src, q, dst, o, ntot, comps);
+    else move_components(src, o, dst, q, ntot, comps);
 }
 
 static unsigned blocks_for(int64_t n)

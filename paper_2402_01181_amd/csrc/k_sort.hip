@@ -172,24 +172,38 @@ __global__ __launch_bounds__(256) void k_make_items(SortBuf s, const int32_t *br
     if (lane == 0) gstore(s.brick_count + k, 0);
 }
 
-// Move each particle to its slot; full = 1 also moves v and C.
+// Move each particle to its slot; full = 1 also moves v and C.  All of a
+// particle's loads are issued before its first store: the destination may
+// alias a source as far as the compiler knows, so stores placed between the
+// loads would each wait for the memory round trip of the load before them.
 __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, ParticleBuf dst, int full)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.ntot) return;
-    const int N = d.ntot;
-    const int to = s.offset[s.key[q]] + s.rank[q];
+    const size_t N = d.ntot;
+    float x[3], H[9];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) dst.x[(size_t)c * N + to] = d.x[(size_t)c * N + q];
+    for (int c = 0; c < 3; ++c) x[c] = gload(d.x + c * N + q);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dst.H[(size_t)c * N + to] = d.H[(size_t)c * N + q];
-    dst.pid[to] = d.pid[q];
+    for (int c = 0; c < 9; ++c) H[c] = gload(d.H + c * N + q);
+    const int pid = gload(d.pid + q);
+    const size_t to = gload(s.offset + gload(s.key + q)) + gload(s.rank + q);
     if (full) {
+        float v[3], C[9];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dst.v[(size_t)c * N + to] = d.v[(size_t)c * N + q];
+        for (int c = 0; c < 3; ++c) v[c] = gload(d.v + c * N + q);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dst.C[(size_t)c * N + to] = d.C[(size_t)c * N + q];
+        for (int c = 0; c < 9; ++c) C[c] = gload(d.C + c * N + q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gstore(dst.v + c * N + to, v[c]);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) gstore(dst.C + c * N + to, C[c]);
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gstore(dst.x + c * N + to, x[c]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gstore(dst.H + c * N + to, H[c]);
+    gstore(dst.pid + to, pid);
 }
 
 // Drop the previous static brick list (its flags).
