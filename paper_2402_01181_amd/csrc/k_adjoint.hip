@@ -828,7 +828,7 @@ struct AdjShared {
     float4 tv[GV ? TILE_NODES : 1];
     float4 tp[GV ? 2 * W * TILE_NODES : 1];
     Payload pay[GV ? 64 * W : 1];
-    float2 wz[GV ? 64 * W : 1];
+    float2 wz[1];   // the plain payload form has no side array
 };
 
 // Material of the tile's environment: mu, lambda, particle mass, stress factor.
@@ -957,9 +957,12 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
                                 return gload(dg.gV + node_id(e, s.b[0] + a0, s.b[1] + a1, s.b[2] + a2));
                             },
                             vbt, Bb);
-                        // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q)
+                        // node contributions w (vbar_t + Bbar q): the form of P2G's w (m v + A q),
+                        // in the plain payload form: the pair kernel then fits two wavefronts per
+                        // SIMD without a register cap (capped, with the forward's form, it ran 10%
+                        // longer)
                         key = in_tile ? key_in_tile(l0, l1, l2) : key_global(s.b);
-                        store_payload(sh.pay[tid], sh.wz[tid], s.fx, s.w[2], key, vbt, Bb);
+                        store_payload<false>(sh.pay[tid], sh.wz[tid], s.fx, s.w[2], key, vbt, Bb);
                     }
                 }
                 store_adj(a, N, uq, xb, vb, Cb, Fb);
@@ -975,7 +978,7 @@ __device__ __forceinline__ void adj_tiled_body(const Dev &dp, const Dev &dg, con
                 int r0, r1;
                 half_wave_run<W>(hw, min(T, item_end - chunk), r0, r1);
                 // .x sums the weights (the flush skips nodes no particle reached)
-                node_pass(ta.slots, sh.pay, sh.wz, r0, r1, sh.tp + hw * TILE_NODES, lane, 1.0f,
+                node_pass<false>(ta.slots, sh.pay, sh.wz, r0, r1, sh.tp + hw * TILE_NODES, lane, 1.0f,
                           [&](const float4 &c4, int i, int j, int k) {
                               float *g = reinterpret_cast<float *>(a.gVb + node_id(e, i, j, k));
                               gatomic_add(g + 0, c4.y);
@@ -1035,7 +1038,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_p2g_tiled(Dev d, AdjBuf a, AdjTi
 // Reverse P2G of substep j (dp: slot j) and reverse G2P of substep j - 1
 // (dg: slot j - 1) in one pass over the particles.
 template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBuf a, AdjTiledArgs ta)
+__global__ __launch_bounds__(64 * W) void k_adj_pair_tiled(Dev dp, Dev dg, AdjBuf a, AdjTiledArgs ta)
 {
     __shared__ AdjShared<W, true, true> sh;
     adj_tiled_body<W, true, true>(dp, dg, a, ta, sh);

@@ -173,18 +173,27 @@ __device__ __forceinline__ int key_global(const int b[3])
 }
 
 // w2: the third axis's weights at offsets 0, 1, 2 (the particle pass has them
-// from its stencil).
+// from its stencil).  G0 false (the plain form): the payload holds fx2 and g
+// itself, the side array is not used, and the node pass forms g + M (o - fx)
+// and the third-axis weights per lane.
+template <bool G0 = true>
 __device__ __forceinline__ void store_payload(Payload &P, float2 &wz, const float fx[3], const float w2[3], int key,
                                               const float g[3], const float M[9])
 {
-    float g0[3];
+    if constexpr (G0) {
+        float g0[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) g0[r] = fmaf(-M[3 * r], fx[0], fmaf(-M[3 * r + 1], fx[1], fmaf(-M[3 * r + 2], fx[2], g[r])));
-    P.fk = make_float4(fx[0], fx[1], w2[0], __int_as_float(key));
-    P.q1 = make_float4(g0[0], g0[1], g0[2], M[0]);
+        for (int r = 0; r < 3; ++r)
+            g0[r] = fmaf(-M[3 * r], fx[0], fmaf(-M[3 * r + 1], fx[1], fmaf(-M[3 * r + 2], fx[2], g[r])));
+        P.fk = make_float4(fx[0], fx[1], w2[0], __int_as_float(key));
+        P.q1 = make_float4(g0[0], g0[1], g0[2], M[0]);
+        wz = make_float2(w2[1], w2[2]);
+    } else {
+        P.fk = make_float4(fx[0], fx[1], fx[2], __int_as_float(key));
+        P.q1 = make_float4(g[0], g[1], g[2], M[0]);
+    }
     P.q2 = make_float4(M[1], M[2], M[3], M[4]);
     P.q3 = make_float4(M[5], M[6], M[7], M[8]);
-    wz = make_float2(w2[1], w2[2]);
 }
 
 
@@ -245,7 +254,7 @@ __device__ __forceinline__ NodeLane1 node_lane1(int lane)
 // stencil changes: the 27 lanes touch 27 distinct nodes and no other
 // half-wave writes the tile, so no atomic is needed.  A stencil outside the
 // tile goes to `outside(c4, i, j, k)` (node indices).
-template <class Outside>
+template <bool G0, class Outside>
 __device__ __forceinline__ void node_pass1(const Payload *pay, const float2 *wzs, int r0, int r1, float4 *tile,
                                            int lane, float s, Outside &&outside)
 {
@@ -255,16 +264,24 @@ __device__ __forceinline__ void node_pass1(const Payload *pay, const float2 *wzs
     for (int r = r0; L.on && r < r1; ++r) {
         const Payload &P = pay[r];
         const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
-        const float2 wz = wzs[r];
         const int key = __float_as_int(fk.w);
         if (key == KEY_NONE) continue;
         const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1];
-        const float w2 = L.o2 == 0 ? fk.z : (L.o2 == 1 ? wz.x : wz.y);
+        float w2, o[3];
+        if constexpr (G0) {
+            const float2 wz = wzs[r];
+            w2 = L.o2 == 0 ? fk.z : (L.o2 == 1 ? wz.x : wz.y);
+            o[0] = L.of[0]; o[1] = L.of[1]; o[2] = L.of[2];
+        } else {
+            const float t2 = fk.z - (1.5f - 0.5f * L.o2);
+            w2 = L.o2 == 1 ? 0.75f - t2 * t2 : 0.5f * t2 * t2;
+            o[0] = L.of[0] - fk.x; o[1] = L.of[1] - fk.y; o[2] = L.of[2] - fk.z;
+        }
         const float w = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]) * w2;
-        // g0 + M o: the momentum term at this node before the weight
-        const float gx = fmaf(q1.w, L.of[0], fmaf(q2.x, L.of[1], fmaf(q2.y, L.of[2], q1.x)));
-        const float gy = fmaf(q2.z, L.of[0], fmaf(q2.w, L.of[1], fmaf(q3.x, L.of[2], q1.y)));
-        const float gz = fmaf(q3.y, L.of[0], fmaf(q3.z, L.of[1], fmaf(q3.w, L.of[2], q1.z)));
+        // the momentum term at this node before the weight
+        const float gx = fmaf(q1.w, o[0], fmaf(q2.x, o[1], fmaf(q2.y, o[2], q1.x)));
+        const float gy = fmaf(q2.z, o[0], fmaf(q2.w, o[1], fmaf(q3.x, o[2], q1.y)));
+        const float gz = fmaf(q3.y, o[0], fmaf(q3.z, o[1], fmaf(q3.w, o[2], q1.z)));
         if (key >= 0) {
             const int l = key + L.lo;
             if (l != cur) {
@@ -329,7 +346,7 @@ __device__ __forceinline__ NodeLane3 node_lane3(int lane)
 // other (a slot's 9 lanes x 3 nodes are 27 distinct nodes, and no other
 // half-wave writes the tile), so no atomic is needed.  A stencil outside the
 // tile goes to `outside(c4, i, j, k)` (node indices), node by node.
-template <class Outside>
+template <bool G0, class Outside>
 __device__ __forceinline__ void node_pass3(const Payload *pay, const float2 *wzs, int r0, int r1, float4 *tile,
                                            int lane, float s, Outside &&outside)
 {
@@ -364,7 +381,8 @@ __device__ __forceinline__ void node_pass3(const Payload *pay, const float2 *wzs
         const int rr = live ? r : r0;
         const Payload &P = pay[rr];
         const float4 fk = P.fk, q1 = P.q1, q2 = P.q2, q3 = P.q3;
-        const float2 wz = wzs[opaque(rr)];   // its own shift, not an offset from the payload's address
+        // its own shift, not an offset from the payload's address
+        const float2 wz = G0 ? wzs[opaque(rr)] : make_float2(0.f, 0.f);
         const int key = live ? __float_as_int(fk.w) : KEY_NONE;
         const bool in_tile = key >= 0;
         const int l = key + L.lo;
@@ -377,14 +395,31 @@ __device__ __forceinline__ void node_pass3(const Payload *pay, const float2 *wzs
         }
         const float t0 = fk.x - L.wc[0], t1 = fk.y - L.wc[1];
         const float w01 = fmaf(L.wa[0], t0 * t0, L.wg[0]) * fmaf(L.wa[1], t1 * t1, L.wg[1]);
-        const float w[3] = {w01 * fk.z, w01 * wz.x, w01 * wz.y};
-        // g0 + M (o0, o1, c): the column's base term, then the third axis node by node
-        float g[3][3];
-        g[0][0] = fmaf(q1.w, L.of0, fmaf(q2.x, L.of1, q1.x));
-        g[0][1] = fmaf(q2.z, L.of0, fmaf(q2.w, L.of1, q1.y));
-        g[0][2] = fmaf(q3.y, L.of0, fmaf(q3.z, L.of1, q1.z));
-        g[1][0] = g[0][0] + q2.y; g[1][1] = g[0][1] + q3.x; g[1][2] = g[0][2] + q3.w;
-        g[2][0] = g[1][0] + q2.y; g[2][1] = g[1][1] + q3.x; g[2][2] = g[1][2] + q3.w;
+        float w[3], g[3][3];
+        if constexpr (G0) {
+            w[0] = w01 * fk.z; w[1] = w01 * wz.x; w[2] = w01 * wz.y;
+            // g0 + M (o0, o1, c): the column's base term, then the third axis node by node
+            g[0][0] = fmaf(q1.w, L.of0, fmaf(q2.x, L.of1, q1.x));
+            g[0][1] = fmaf(q2.z, L.of0, fmaf(q2.w, L.of1, q1.y));
+            g[0][2] = fmaf(q3.y, L.of0, fmaf(q3.z, L.of1, q1.z));
+            g[1][0] = g[0][0] + q2.y; g[1][1] = g[0][1] + q3.x; g[1][2] = g[0][2] + q3.w;
+            g[2][0] = g[1][0] + q2.y; g[2][1] = g[1][1] + q3.x; g[2][2] = g[1][2] + q3.w;
+        } else {
+            const float f2 = fk.z;
+            w[0] = w01 * (0.5f * (1.5f - f2) * (1.5f - f2));
+            w[1] = w01 * (0.75f - (f2 - 1.0f) * (f2 - 1.0f));
+            w[2] = w01 * (0.5f * (f2 - 0.5f) * (f2 - 0.5f));
+            // g + M (o - fx): the column's part, then the third axis node by node
+            const float d0 = L.of0 - fk.x, d1 = L.of1 - fk.y;
+            const float bx = fmaf(q1.w, d0, fmaf(q2.x, d1, q1.x));
+            const float by = fmaf(q2.z, d0, fmaf(q2.w, d1, q1.y));
+            const float bz = fmaf(q3.y, d0, fmaf(q3.z, d1, q1.z));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float d2 = c - f2;
+                g[c][0] = fmaf(q2.y, d2, bx); g[c][1] = fmaf(q3.x, d2, by); g[c][2] = fmaf(q3.w, d2, bz);
+            }
+        }
         if (in_tile) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -407,12 +442,12 @@ __device__ __forceinline__ void node_pass3(const Payload *pay, const float2 *wzs
 // Node pass with `slots` (1 or 3) particles in flight per half-wave: one
 // particle per step keeps runs long at few particles per cell; three per step
 // need a third of the arithmetic per node when cells hold many particles.
-template <class Outside>
+template <bool G0 = true, class Outside>
 __device__ __forceinline__ void node_pass(int slots, const Payload *pay, const float2 *wz, int r0, int r1,
                                           float4 *tile, int lane, float s, Outside &&outside)
 {
-    if (slots == 3) node_pass3(pay, wz, r0, r1, tile, lane, s, outside);
-    else node_pass1(pay, wz, r0, r1, tile, lane, s, outside);
+    if (slots == 3) node_pass3<G0>(pay, wz, r0, r1, tile, lane, s, outside);
+    else node_pass1<G0>(pay, wz, r0, r1, tile, lane, s, outside);
 }
 
 // Half-wave hw of 2W takes the contiguous run [r0, r1) of a chunk of n payloads.
