@@ -304,9 +304,14 @@ TiledArgs tiled_args(const mpm_ctx *c, const ParticleBuf &in, const ParticleBuf 
 }
 
 // Sort live particles into the alternate buffers and rebuild the items.
-void sort_into_alt(mpm_ctx *c, hipStream_t st)
+// mid_call: between the fused substeps of a call, where v and C are carried
+// by frozen particles only (the sort moves them for particles near the
+// domain edge); otherwise the whole state moves.
+void sort_into_alt(mpm_ctx *c, hipStream_t st, bool mid_call = false)
 {
-    timed(c, st, PK_SORT, [&] { launch_sort(c->dev(), c->sort, c->act, c->total_bricks, c->item, c->alt, 1, st); });
+    timed(c, st, PK_SORT, [&] {
+        launch_sort(c->dev(), c->sort, c->act, c->total_bricks, c->item, c->alt, mid_call ? 0 : 1, st);
+    });
     c->items_valid = true;
     c->items_P = c->item;
     c->since_sort = 0;
@@ -473,7 +478,7 @@ void substeps_gas(mpm_ctx *c, int n, ParticleBuf in, hipStream_t st)
     const bool runs = c->persistent && c->n_envs == 1 && c->run_blocks > 0;
     for (int i = 0; runs && i < n - 1;) {
         if (i > 0 && c->since_sort >= c->sort_every && in.x == A.x) {
-            sort_into_alt(c, st);
+            sort_into_alt(c, st, true);
             in = c->alt;
             sorted_at = i;
         }
@@ -496,7 +501,7 @@ void substeps_gas(mpm_ctx *c, int n, ParticleBuf in, hipStream_t st)
     }
     for (int i = runs ? n - 1 : 0; i < n; ++i) {
         if (i > 0 && i < n - 1 && c->since_sort >= c->sort_every && in.x == A.x) {
-            sort_into_alt(c, st);
+            sort_into_alt(c, st, true);
             in = c->alt;
             sorted_at = i;
         }
@@ -568,7 +573,7 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
         const EnvGroups g{c->wg_tab, c->arrive, c->sort, c->total_bricks};
         for (int done = 0; done < n;) {
             if (done > 0) {
-                sort_into_alt(c, st);
+                sort_into_alt(c, st, true);
                 in = c->alt;
             }
             const int m = std::min(n - done, c->sort_every);
@@ -592,7 +597,7 @@ void substeps_tiled(mpm_ctx *c, int n, hipStream_t st)
             timed(c, st, PK_G2P_TILED, [&] { launch_g2p_tiled(d, tiled_args(c, in, A, 0), c->block, nb, st); });
         } else {
             if (c->since_sort >= c->sort_every && in.x == A.x) {
-                sort_into_alt(c, st);
+                sort_into_alt(c, st, true);
                 in = c->alt;
             }
             timed(c, st, PK_FUSED_TILED, [&] { launch_fused_tiled(d, tiled_args(c, in, A, (i + 1) & 1), c->block, nb, st); });

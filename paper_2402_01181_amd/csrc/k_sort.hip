@@ -29,6 +29,27 @@ __device__ __forceinline__ int particle_cell(const EnvDev &e, float x0, float x1
     return brick * 64 + ((t[0] & 3) * 4 + (t[1] & 3)) * 4 + (t[2] & 3);
 }
 
+// Whether a particle may be frozen out of the domain, with half a cell to
+// spare: its stencil base within half a cell of where the particle kernels
+// freeze it (or a non-finite position).  Between the fused substeps of a
+// call only such particles carry v and C (the others' are recomputed from
+// the grid), so a sort there moves those two fields for them alone.  The
+// margin keeps the decision independent of how either side rounds the test.
+__device__ __forceinline__ bool near_domain_edge(const EnvDev &e, float x0, float x1, float x2)
+{
+    const float xs[3] = {x0, x1, x2};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float tb = xs[a] * e.inv_dx - 0.5f;
+        in = in && tb >= 0.5f && tb < (float)(e.n - 2) - 0.5f;
+    }
+    return !in;
+}
+
+// Bit of a particle's rank that marks it near the domain edge.
+constexpr int RANK_EDGE = (int)0x80000000u;
+
 // Cell key and rank of each particle, and the particle count of every cell
 // and brick.  Particles arrive mostly in cell order (from the previous sort),
 // so a wavefront holds few distinct cells and bricks.  The lanes of one cell
@@ -43,9 +64,12 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf 
     const bool valid = q < d.ntot;
     const int N = d.ntot;
     int key = -1;
+    bool edge = false;
     if (valid) {
         const EnvDev e = load_env(d.env + env_of_particle(d, q));
-        key = particle_cell(e, gload(d.x + q), gload(d.x + N + q), gload(d.x + 2 * N + q));
+        const float x0 = gload(d.x + q), x1 = gload(d.x + N + q), x2 = gload(d.x + 2 * N + q);
+        key = particle_cell(e, x0, x1, x2);
+        edge = near_domain_edge(e, x0, x1, x2);
         gstore(s.key + q, key);
     }
     const unsigned long long lower = (1ull << lane) - 1ull;
@@ -77,7 +101,7 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf 
     if (valid && lane == leader) base = gatomic_add(s.count + key, size);
     if (valid && lane == bleader) gatomic_add(s.brick_count + brick, bsize);
     base = __shfl(base, leader);
-    if (valid) gstore(s.rank + q, base + pos);
+    if (valid) gstore(s.rank + q, (base + pos) | (edge ? RANK_EDGE : 0));
 }
 
 // Block-wide exclusive scan of int2 over 256 threads x 4 elements.
@@ -172,10 +196,13 @@ __global__ __launch_bounds__(256) void k_make_items(SortBuf s, const int32_t *br
     if (lane == 0) gstore(s.brick_count + k, 0);
 }
 
-// Move each particle to its slot; full = 1 also moves v and C.  All of a
-// particle's loads are issued before its first store: the destination may
-// alias a source as far as the compiler knows, so stores placed between the
-// loads would each wait for the memory round trip of the load before them.
+// Move each particle to its slot: x, H and the particle index, and v and C
+// too for every particle (full = 1: the state at the start of a call) or for
+// the particles near the domain edge only (full = 0: between fused substeps,
+// where only frozen particles carry v and C).  All of a particle's loads are
+// issued before its first store: the destination may alias a source as far
+// as the compiler knows, so stores placed between the loads would each wait
+// for the memory round trip of the load before them.
 __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, ParticleBuf dst, int full)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,8 +214,9 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Dev d, SortBuf s, Particle
 #pragma unroll
     for (int c = 0; c < 9; ++c) H[c] = gload(d.H + c * N + q);
     const int pid = gload(d.pid + q);
-    const size_t to = gload(s.offset + gload(s.key + q)) + gload(s.rank + q);
-    if (full) {
+    const int rank = gload(s.rank + q);
+    const size_t to = gload(s.offset + gload(s.key + q)) + (rank & ~RANK_EDGE);
+    if (full || (rank & RANK_EDGE)) {
         float v[3], C[9];
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[c] = gload(d.v + c * N + q);

@@ -176,6 +176,42 @@ def test_status_flags_and_read_errors(gpu, orc, scheme):
     assert sim.lib.mpm_set_tool(sim.ctx, 0, 3, None, None, 0) == L.MPM_E_ARG
 
 
+@pytest.mark.parametrize("gas,persistent", [(0, 0), (1, 0), (1, 1), (0, 1)])
+def test_frozen_state_kept_across_sorts_within_a_call(gpu, orc, gas, persistent):
+    """Particles whose stencil leaves the grid are frozen (x, v, C, F
+    unchanged, Sec. III-B: no transfer for them).  Between the fused substeps
+    of a call only such particles carry v and C, and a sort there moves those
+    two fields for particles near the domain edge alone: twelve substeps in
+    one call, sorting every two, must leave every frozen particle's state
+    exactly as it was, in each launch form."""
+    Sim, L = gpu
+    _say(f"frozen particles across sorts within a call (grid at staging {gas}, persistent {persistent})")
+    sc = scenes.small_slab_scene(seed=6, n_particles=3000, n=32, substeps=12)
+    env = sc.envs[0]
+    rng = np.random.default_rng(11)
+    frozen = [3, 70, 511, 1200, 2999]
+    places = [[0.01, 0.5, 0.5], [0.5, 0.995, 0.5], [0.5, 0.2, 0.004], [0.99, 0.3, 0.6], [0.4, 0.001, 0.98]]
+    for k, p in zip(frozen, places):
+        env.x[k] = p
+        env.v[k] = rng.uniform(-0.3, 0.3, 3)
+        env.C[k] = rng.uniform(-2.0, 2.0, (3, 3))
+        env.F[k] = np.eye(3) + rng.uniform(-0.02, 0.02, (3, 3))
+    opts = {L.OPT_SORT_EVERY: 2, L.OPT_GRID_AT_STAGING: gas, L.OPT_PERSISTENT: persistent, L.OPT_ITEM: 128}
+    sim = Sim(sc, options=opts)
+    x0, v0, C0, F0 = (a.copy() for a in sim.particles())
+    sim.step(12)
+    assert sim.read(L.F_STATUS) & L.FLAG_OUT_OF_DOMAIN
+    x, v, C, F = sim.particles()
+    for k in frozen:
+        np.testing.assert_array_equal(x[k], x0[k])
+        np.testing.assert_array_equal(v[k], v0[k])
+        np.testing.assert_array_equal(C[k], C0[k])
+        np.testing.assert_array_equal(F[k], F0[k])
+    moved = np.setdiff1d(np.arange(sc.n_particles), frozen)
+    assert np.abs(x[moved] - x0[moved]).max() > 0.0     # the rest of the slab did step
+    sim.close()
+
+
 @pytest.mark.parametrize("scheme", ["direct", "tiled"])
 def test_nonfinite_flag(gpu, orc, scheme):
     """A particle given a NaN velocity makes its node momenta NaN; the G2P
