@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf 
     unsigned long long pending = __ballot(valid);
     while (pending) {
         const int l = __builtin_ctzll(pending);
-        const int kc = __shfl(key, l);
+        const int kc = __builtin_amdgcn_readlane(key, l);   // l is the same on every lane
         const unsigned long long same = __ballot(valid && key == kc);
         if ((same >> lane) & 1ull) {
             leader = l;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_cell_count(Dev d, SortBuf s, ActiveBuf 
     pending = __ballot(valid);
     while (pending) {
         const int l = __builtin_ctzll(pending);
-        const int kb = __shfl(brick, l);
+        const int kb = __builtin_amdgcn_readlane(brick, l);
         const unsigned long long same = __ballot(valid && brick == kb);
         if ((same >> lane) & 1ull) bleader = l;
         if (lane == l) bsize = (int)__popcll(same);
