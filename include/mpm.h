@@ -172,6 +172,16 @@ typedef struct {
     const float *x0, *v0, *C0, *F0;  /* device SoA as above; copied by mpm_create */
     const float *material;       /* device [n_envs][4] = {E, nu, rho, V0}; read at every substep,
                                     so the caller may change it between calls (graph-safe) */
+    int32_t hold_tape;           /* adjoint, 0 or 1.  1: the workspace holds the recomputed tape of every
+                                    segment of the longest recording (ceil(max_tape_substeps /
+                                    checkpoint_every) segments; at 30K particles on 64^3 and 20-substep
+                                    segments, about 11.5 MB per substep).  mpm_substep with record_tape then
+                                    computes each segment's tape itself (the tiled recompute passes, sorted
+                                    at each segment start) instead of running the forward form, and the next
+                                    mpm_substep_adjoint reverses the held tapes without recomputing them.  It
+                                    consumes them: a second adjoint of the same recording recomputes from the
+                                    checkpoints.  With the direct scheme a recording keeps checkpoints only.
+                                    0: checkpoints only (every adjoint recomputes) */
 } mpm_desc;
 
 typedef struct {

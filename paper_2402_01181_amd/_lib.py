@@ -41,7 +41,7 @@ class MpmDesc(ct.Structure):
                 ("bound", ct.c_int32), ("max_tools", ct.c_int32), ("checkpoint_every", ct.c_int32),
                 ("max_tape_substeps", ct.c_int32),
                 ("x0", ct.c_void_p), ("v0", ct.c_void_p), ("C0", ct.c_void_p), ("F0", ct.c_void_p),
-                ("material", ct.c_void_p)]
+                ("material", ct.c_void_p), ("hold_tape", ct.c_int32)]
 
 
 class MpmTool(ct.Structure):

@@ -42,6 +42,7 @@ struct Shape {
     int64_t total_nodes, max_env_nodes, max_env_cells;
     int32_t total_bricks;
     int max_tape, ck;
+    int hold;   // segment tapes kept for a whole recording
 };
 
 // One description of the workspace layout, used both to size and to carve it.
@@ -110,23 +111,35 @@ void carve(mpm_ctx &c, const Shape &s, Carver &cv)
         T.ckpt_state = cv.take<float>(st24 * T.n_ckpt);
         T.ckpt_tools = cv.take<ToolDev>(slots * T.n_ckpt);
         T.ckpt_step = cv.take<int32_t>((size_t)s.n_envs * T.n_ckpt);
-        T.seg_state = cv.take<float>(st24 * (k + 1));
-        T.seg_tools = cv.take<ToolDev>(slots * k);
-        T.seg_P = cv.take<float4>((size_t)s.total_nodes * k);
-        T.seg_V = cv.take<float4>((size_t)s.total_nodes * k);
-        T.seg_dec = cv.take<ContactCode>((size_t)s.total_nodes * k);
+        // segment tapes: one, or one per segment of the longest recording (held tape)
+        const int nseg = s.hold ? (s.max_tape + k - 1) / k : 1;
+        T.segs.assign(nseg, {});
+        for (auto &g : T.segs) {
+            g.state = cv.take<float>(st24 * (k + 1));
+            g.tools = cv.take<ToolDev>(slots * k);
+            g.P = cv.take<float4>((size_t)s.total_nodes * k);
+            g.V = cv.take<float4>((size_t)s.total_nodes * k);
+            g.dec = cv.take<ContactCode>((size_t)s.total_nodes * k);
+            g.perm = cv.take<int32_t>(s.ntot);
+            g.tflag = cv.take<int32_t>(s.total_bricks);
+            g.tslist = cv.take<int32_t>(s.total_bricks);
+            g.tscount = cv.take<int32_t>(1);
+            g.tfar = cv.take<int32_t>(k + 1);
+            g.items = s.hold ? cv.take<int4>(c.max_items) : c.sort.items;
+            g.totals = s.hold ? cv.take<int2>(1) : c.sort.totals;
+        }
         T.work = cv.take<float>(st24);
         T.work_tools = cv.take<ToolDev>(slots);
         T.work_step = cv.take<int32_t>(s.n_envs);
         T.work_status = cv.take<uint32_t>(s.n_envs);
         T.adj_state = cv.take<float>(st24);
         T.adj_slot = cv.take<float>(st24);
-        T.perm = cv.take<int32_t>(s.ntot);
         T.iota = cv.take<int32_t>(s.ntot);
-        T.tflag = cv.take<int32_t>(s.total_bricks);
-        T.tslist = cv.take<int32_t>(s.total_bricks);
-        T.tscount = cv.take<int32_t>(1);
-        T.tfar = cv.take<int32_t>(k + 1);
+        T.live_items = c.sort.items;
+        T.live_totals = c.sort.totals;
+        const auto &g0 = T.segs[0];
+        T.seg_state = g0.state; T.seg_tools = g0.tools; T.seg_P = g0.P; T.seg_V = g0.V; T.seg_dec = g0.dec;
+        T.perm = g0.perm; T.tflag = g0.tflag; T.tslist = g0.tslist; T.tscount = g0.tscount; T.tfar = g0.tfar;
         T.adj.xb = T.adj_state;
         T.adj.vb = T.adj_state ? T.adj_state + (size_t)3 * s.ntot : nullptr;
         T.adj.Cb = T.adj_state ? T.adj_state + (size_t)6 * s.ntot : nullptr;
@@ -160,6 +173,12 @@ bool all_carved(const mpm_ctx &c)
                            T.tflag, T.tslist, T.tscount, T.tfar};
         for (const void *q : t)
             if (!q) return false;
+        for (const auto &g : T.segs) {
+            const void *u[] = {g.state, g.tools, g.P, g.V, g.dec, g.perm, g.tflag, g.tslist, g.tscount, g.tfar,
+                               g.items, g.totals};
+            for (const void *q : u)
+                if (!q) return false;
+        }
     }
     return true;
 }
@@ -176,6 +195,7 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
     if (d->max_tools < 0 || d->max_tools > MAX_TOOLS) { why = "max_tools must be in [0, 8]"; return false; }
     if (d->max_tape_substeps < 0) { why = "max_tape_substeps must be >= 0"; return false; }
     if (d->max_tape_substeps > 0 && d->checkpoint_every < 1) { why = "checkpoint_every must be >= 1"; return false; }
+    if (d->hold_tape != 0 && d->hold_tape != 1) { why = "hold_tape must be 0 or 1"; return false; }
     if (!d->x0 || !d->v0 || !d->C0 || !d->F0 || !d->material) { why = "x0, v0, C0, F0 and material must be device pointers"; return false; }
     int64_t ntot = 0, nodes = 0, bricks = 0, max_nodes = 0, max_cells = 0;
     for (int e = 0; e < d->n_envs; ++e) {
@@ -195,6 +215,7 @@ bool validate(const mpm_desc *d, std::string &why, Shape &s)
     s.max_tools = d->max_tools;
     s.max_tape = d->max_tape_substeps;
     s.ck = d->max_tape_substeps > 0 ? std::min(d->checkpoint_every, d->max_tape_substeps) : 1;
+    s.hold = d->max_tape_substeps > 0 && d->hold_tape != 0;
     s.ntot = (int)ntot;
     s.total_nodes = nodes;
     s.max_env_nodes = max_nodes;
@@ -694,6 +715,27 @@ void save_checkpoint(mpm_ctx *c, int k, hipStream_t st)
 // The recompute's brick bookkeeping: its own static list (built by the
 // segment's sort, so the forward's lists are left as they were); far reaches
 // are stamped, not listed.
+// Point the tape's segment fields and the sort's work items at segment tape b
+// (with one segment tape the items are the live state's, as before).
+void select_seg(mpm_ctx *c, int b)
+{
+    auto &T = c->tape;
+    const auto &g = T.segs[b];
+    T.seg_state = g.state; T.seg_tools = g.tools; T.seg_P = g.P; T.seg_V = g.V; T.seg_dec = g.dec;
+    T.perm = g.perm; T.tflag = g.tflag; T.tslist = g.tslist; T.tscount = g.tscount; T.tfar = g.tfar;
+    c->sort.items = g.items;
+    c->sort.totals = g.totals;
+    T.stamp = g.stamp;
+    T.sel = b;
+}
+
+// Back to the live state's work items after using held segment tapes.
+void select_live_items(mpm_ctx *c)
+{
+    c->sort.items = c->tape.live_items;
+    c->sort.totals = c->tape.live_totals;
+}
+
 ActiveBuf tape_act(const mpm_ctx *c)
 {
     ActiveBuf a = c->act;
@@ -795,7 +837,9 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
     };
     // tape grids are zero outside the listed bricks (the reverse grid pass clears what it
     // visits), so no P needs clearing here; a P2G that reaches beyond the list stamps its slot
-    T.stamp += 1;
+    // with a stamp no earlier recompute used
+    T.stamp = ++T.stamp_top;
+    T.segs[T.sel].stamp = T.stamp;
     auto stamped = [&](TiledArgs a, int slot) {
         a.act = ta;
         a.far_stamp = T.tfar;
@@ -827,6 +871,46 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
             timed(c, st, PK_FUSED_TILED, [&] { launch_fused_full_tiled(d, step, c->block, c->tiled_blocks, st); });
         }
     }
+}
+
+// A recording kept whole (held tape): the tiled recompute passes run as the
+// forward, segment by segment, each into its own segment tape.  The last slot
+// of a segment is the next segment's checkpoint (in original order) and, at
+// the end, the live state (original order, identity particle index); tool
+// table, step counters and status flags continue from the recompute's.
+void record_held(mpm_ctx *c, int n, hipStream_t st)
+{
+    auto &T = c->tape;
+    const int k = c->checkpoint_every;
+    const size_t N = c->ntot, slots = c->tool_slots();
+    const int nseg = (n + k - 1) / k;
+    timed(c, st, PK_ADJ_MISC, [&] { launch_copy_bytes(T.work_status, c->status, sizeof(uint32_t) * c->n_envs, st); });
+    for (int seg = 0; seg < nseg; ++seg) {
+        const int sb = seg * k, se = std::min(sb + k, n);
+        select_seg(c, seg);
+        recompute_segment_tiled(c, seg, sb, se, st);
+        const float *last = T.seg_state + (size_t)(se - sb) * 24 * N;
+        timed(c, st, PK_ADJ_MISC, [&] {
+            if (seg + 1 < nseg) {
+                launch_unpermute(last, T.perm, c->ntot, 24, T.ckpt_state + (size_t)(seg + 1) * 24 * N, st);
+                launch_copy_bytes(T.ckpt_tools + (size_t)(seg + 1) * slots, T.work_tools, sizeof(ToolDev) * slots, st);
+                launch_copy_bytes(T.ckpt_step + (size_t)(seg + 1) * c->n_envs, T.work_step,
+                                  sizeof(int32_t) * c->n_envs, st);
+            } else {
+                launch_unpermute(last, T.perm, c->ntot, 3, c->x, st);
+                launch_unpermute(last + 3 * N, T.perm, c->ntot, 3, c->v, st);
+                launch_unpermute(last + 6 * N, T.perm, c->ntot, 9, c->C, st);
+                launch_unpermute(last + 15 * N, T.perm, c->ntot, 9, c->H, st);
+                launch_copy_bytes(c->pid, T.iota, sizeof(int32_t) * N, st);
+                launch_copy_bytes(c->tools, T.work_tools, sizeof(ToolDev) * slots, st);
+                launch_copy_bytes(c->step, T.work_step, sizeof(int32_t) * c->n_envs, st);
+                launch_copy_bytes(c->status, T.work_status, sizeof(uint32_t) * c->n_envs, st);
+            }
+        });
+    }
+    select_live_items(c);
+    c->items_valid = false;
+    T.held = nseg;
 }
 
 // Reverse the recomputed segment's substeps [lo, s_end) in its sorted slot
@@ -1072,10 +1156,12 @@ mpm_status create_in(const mpm_desc *desc, void *workspace, size_t workspace_byt
         if (c->max_tape > 0) {
             launch_iota(c->tape.iota, s.ntot, st);
             // tape grids start zero and are left zero by every reverse pass
-            launch_fill_f4(c->tape.seg_P, (int64_t)s.total_nodes * s.ck, st);
-            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tflag), s.total_bricks, 0u, st);
-            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tscount), 1, 0u, st);
-            launch_fill_u32(reinterpret_cast<uint32_t *>(c->tape.tfar), s.ck + 1, 0xffffffffu, st);
+            for (const auto &g : c->tape.segs) {
+                launch_fill_f4(g.P, (int64_t)s.total_nodes * s.ck, st);
+                launch_fill_u32(reinterpret_cast<uint32_t *>(g.tflag), s.total_bricks, 0u, st);
+                launch_fill_u32(reinterpret_cast<uint32_t *>(g.tscount), 1, 0u, st);
+                launch_fill_u32(reinterpret_cast<uint32_t *>(g.tfar), s.ck + 1, 0xffffffffu, st);
+            }
         }
         launch_fill_u32(c->status, s.n_envs, 0u, st);
         launch_fill_u32(reinterpret_cast<uint32_t *>(c->step), s.n_envs, 0u, st);
@@ -1295,12 +1381,17 @@ mpm_status mpm_substep(mpm_ctx *c, int32_t n_substeps, int32_t record_tape, void
     if (n_substeps > c->max_tape) return fail(c, MPM_E_ARG, "n_substeps exceeds max_tape_substeps");
     const int k = c->checkpoint_every;
     c->tape.len = 0;
+    c->tape.held = 0;
     save_checkpoint(c, 0, st);
-    for (int done = 0; done < n_substeps;) {
-        int m = std::min(k, n_substeps - done);
-        run_substeps(c, m, st);
-        done += m;
-        if (done < n_substeps) save_checkpoint(c, done / k, st);
+    if (c->tape.segs.size() > 1 && c->scheme == MPM_SCHEME_TILED) {
+        record_held(c, n_substeps, st);
+    } else {
+        for (int done = 0; done < n_substeps;) {
+            int m = std::min(k, n_substeps - done);
+            run_substeps(c, m, st);
+            done += m;
+            if (done < n_substeps) save_checkpoint(c, done / k, st);
+        }
     }
     c->tape.len = n_substeps;
     return check_launch(c, "mpm_substep");
@@ -1402,11 +1493,15 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
         launch_fill_f64(T.adj.mubar, c->n_envs, st);
         launch_fill_f64(T.adj.lambar, c->n_envs, st);
     });
+    // held segment tapes (a recording kept whole) are reversed as they are, once
+    const bool held = T.held > 0 && c->scheme == MPM_SCHEME_TILED;
+    const bool multi = T.segs.size() > 1;
     for (int seg = (len - 1) / k; seg >= s0 / k; --seg) {
         const int sb = seg * k, se = std::min(sb + k, len), lo = std::max(sb, s0);
         const bool tiled = c->scheme == MPM_SCHEME_TILED;
+        select_seg(c, multi ? seg : 0);
         if (tiled) {
-            recompute_segment_tiled(c, seg, sb, se, st);
+            if (!held) recompute_segment_tiled(c, seg, sb, se, st);
             reverse_segment_tiled(c, sb, lo, se, s0, st);
         } else {
             recompute_segment(c, seg, sb, se, st);
@@ -1421,6 +1516,11 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
                 launch_tape_clear(d, c->env_gofs, c->total_nodes, tiled ? tape_list(c, j - sb) : dense_list(c), st);
             });
         }
+    }
+    T.held = 0;
+    if (multi) {
+        select_seg(c, 0);
+        select_live_items(c);
     }
     timed(c, st, PK_ADJ_MISC, [&] {
         launch_adj_finish(c->dev(), T.adj, n_substeps, io->gE, io->gnu, io->gu, io->gT, st);

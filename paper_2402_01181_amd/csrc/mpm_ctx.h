@@ -134,8 +134,27 @@ struct mpm_ctx {
         // stamps per tape slot; tape grids are zero outside listed bricks between uses
         int32_t *tflag = nullptr, *tslist = nullptr, *tscount = nullptr;
         int32_t *tfar = nullptr;            // [k + 1]
-        int stamp = 0;
+        int stamp = 0;                      // stamp of the selected segment tape's recompute
+        int stamp_top = 0;                  // largest stamp given out (stamps never repeat)
         int len = 0;                        // recorded substeps
+        // Segment tapes: one, or (held tape) one per segment of the longest recording.  The
+        // fields above point into the selected one; items and totals are its sort's work
+        // items (with one segment tape, the live state's arrays).
+        struct Seg {
+            float *state = nullptr;
+            mpm::ToolDev *tools = nullptr;
+            float4 *P = nullptr, *V = nullptr;
+            mpm::ContactCode *dec = nullptr;
+            int32_t *perm = nullptr, *tflag = nullptr, *tslist = nullptr, *tscount = nullptr, *tfar = nullptr;
+            int4 *items = nullptr;
+            int2 *totals = nullptr;
+            int stamp = 0;
+        };
+        std::vector<Seg> segs;
+        int sel = 0;                        // the selected segment tape
+        int held = 0;                       // segment tapes of the current recording already computed
+        int4 *live_items = nullptr;         // the live state's work items (restored after a held tape)
+        int2 *live_totals = nullptr;
     } tape;
     size_t tool_slots() const { return (size_t)n_envs * (max_tools > 0 ? max_tools : 1); }
 

@@ -28,10 +28,13 @@ class Sim:
     """All environments of a scene in one context on one GPU."""
 
     def __init__(self, scene, device="cuda", max_tape: int = 0, checkpoint_every: int = 20,
-                 options: Optional[Dict[int, int]] = None, stream=None, static_workspace: bool = False):
+                 options: Optional[Dict[int, int]] = None, stream=None, static_workspace: bool = False,
+                 hold_tape: bool = False):
         """static_workspace: create the context with mpm_create_static (the
         library's own per-device workspace of STATIC_WORKSPACE_BYTES; one such
-        context per device at a time) instead of a torch-allocated workspace."""
+        context per device at a time) instead of a torch-allocated workspace.
+        hold_tape: keep every segment's recomputed tape of a recording, so the
+        adjoint that follows it does not recompute (mpm_desc.hold_tape)."""
         if not torch.cuda.is_available():
             raise RuntimeError("a ROCm GPU is required (there is no CPU path)")
         self.lib = L.load()
@@ -57,7 +60,7 @@ class Sim:
             gravity=(ct.c_float * 3)(*scene.gravity), bound=int(scene.bound), max_tools=self.max_tools,
             checkpoint_every=int(checkpoint_every), max_tape_substeps=int(max_tape),
             x0=self._x0.data_ptr(), v0=self._v0.data_ptr(), C0=self._C0.data_ptr(), F0=self._F0.data_ptr(),
-            material=self.material.data_ptr())
+            material=self.material.data_ptr(), hold_tape=int(bool(hold_tape)))
         size = self.lib.mpm_workspace_size(ct.byref(self.desc))
         if size == 0:
             raise L.MpmError(L.MPM_E_ARG, self.lib.mpm_last_error(None).decode())

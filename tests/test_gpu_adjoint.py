@@ -82,6 +82,69 @@ def test_adjoint_matches_oracle_adjoint(gpu, orc, scheme, contact, slots, pers):
         assert e <= TOL_GRAD, (name, e)
 
 
+def test_held_tape_matches_oracle_adjoint(gpu, orc):
+    """A recording kept whole (hold_tape): the forward runs the recompute
+    passes segment by segment (three segments, the last one short) and the
+    adjoint reverses the held tapes without recomputing.  Every gradient
+    against the oracle's FP64 adjoint; the final forward state against the
+    ordinary forward's; a second adjoint of the same recording (the held
+    tapes are consumed, so it recomputes from the checkpoints) and a reverse
+    window shorter than the recording against the oracle too."""
+    Sim, L, torch = gpu
+    S, N, n, k = 12, 2000, 32, 5
+    _say(f"held tape: {N} particles, {n}^3, {S} substeps, segments of {k}")
+    sc, env = _pressing_scene(53, N, n, S)
+    rng = np.random.default_rng(8)
+    W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
+         rng.standard_normal((N, 3, 3))]
+    opts = {L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 3}
+    soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
+    plain = Sim(sc, max_tape=S, checkpoint_every=k, options=opts)
+    plain.step(S, record_tape=True)
+    held = Sim(sc, max_tape=S, checkpoint_every=k, options=opts, hold_tape=True)
+    assert held.workspace_bytes > plain.workspace_bytes
+    held.step(S, record_tape=True)
+    for a, b, name in zip(held.particles(), plain.particles(), ("x", "v", "C", "F")):
+        e = _rel(a, b)
+        _say(f"  final {name}: held vs ordinary forward rel err {e:.2e}")
+        assert e <= 1e-4, (name, e)
+    np.testing.assert_array_equal(held.read(L.F_TOOL_T), plain.read(L.F_TOOL_T))
+    o = oracle_sim_like(orc, sc).adjoint(S, *W)
+
+    def check(g, what):
+        checks = {
+            "xbar0": (g["xbar0"].cpu().numpy().T, o["xbar"].reshape(N, 3)),
+            "vbar0": (g["vbar0"].cpu().numpy().T, o["vbar"].reshape(N, 3)),
+            "Cbar0": (g["Cbar0"].cpu().numpy().T, o["Cbar"].reshape(N, 9)),
+            "Fbar0": (g["Fbar0"].cpu().numpy().T, o["Fbar"].reshape(N, 9)),
+            "gE": (g["gE"].cpu().numpy(), [o["gE"]]),
+            "gnu": (g["gnu"].cpu().numpy(), [o["gnu"]]),
+            "gu": (g["gu"].cpu().numpy()[0, 0], o["gu"][:, 0]),
+            "gT": (g["gT"].cpu().numpy()[0, 0], o["gT0"][0]),
+        }
+        for name, (a, b) in checks.items():
+            e = _rel(a, b)
+            _say(f"  {what} {name}: rel err {e:.2e}")
+            assert e <= TOL_GRAD, (what, name, e)
+
+    seeds = (soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))
+    check(held.adjoint(S, *seeds), "held")
+    check(held.adjoint(S, *seeds), "recomputed")
+    # a reverse window of 7 of the 12 recorded substeps
+    held.close()
+    held = Sim(sc, max_tape=S, checkpoint_every=k, options=opts, hold_tape=True)
+    held.step(S, record_tape=True)
+    w = 7
+    gw = held.adjoint(w, seeds[0])
+    plain_w = plain.adjoint(w, seeds[0])
+    for name in ("xbar0", "vbar0", "Cbar0", "Fbar0", "gE", "gnu", "gu", "gT"):
+        e = _rel(gw[name].cpu().numpy(), plain_w[name].cpu().numpy())
+        _say(f"  window {w}: {name} held vs recomputed rel err {e:.2e}")
+        assert e <= TOL_GRAD, (name, e)
+    held.close()
+    plain.close()
+
+
 @pytest.mark.parametrize("pers", [0, 1])
 def test_adjoint_with_particles_leaving_their_tiles(gpu, orc, pers):
     """The slab and the tool translate at 80 m/s along x, so within one tape
