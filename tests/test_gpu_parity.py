@@ -212,6 +212,38 @@ def test_frozen_state_kept_across_sorts_within_a_call(gpu, orc, gas, persistent)
     sim.close()
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_frozen_state_kept_across_sorts_two_environments(gpu, orc, persistent):
+    """The edge test of the sort between fused substeps with two
+    environments of different grid sizes (the test looks each particle's
+    environment up): frozen particles in both keep x, v, C and F exactly over
+    twelve substeps sorted every two."""
+    Sim, L = gpu
+    _say(f"frozen particles across sorts, two environments (persistent {persistent})")
+    a = scenes.small_slab_scene(seed=7, n_particles=2500, n=32, substeps=12)
+    b = scenes.small_slab_scene(seed=8, n_particles=1800, n=24, substeps=12)
+    sc = scenes.Scene("two-slabs", [a.envs[0], b.envs[0]], dt=a.dt, substeps=12)
+    rng = np.random.default_rng(12)
+    frozen = {0: [5, 900, 2499], 1: [0, 777, 1799]}
+    places = [[0.01, 0.5, 0.5], [0.5, 0.997, 0.3], [0.6, 0.3, 0.002]]
+    for e, ks in frozen.items():
+        env = sc.envs[e]
+        for k, p in zip(ks, places):
+            env.x[k] = p
+            env.v[k] = rng.uniform(-0.3, 0.3, 3)
+            env.C[k] = rng.uniform(-2.0, 2.0, (3, 3))
+    sim = Sim(sc, options={L.OPT_SORT_EVERY: 2, L.OPT_PERSISTENT: persistent, L.OPT_ITEM: 128})
+    before = {e: [q.copy() for q in sim.particles(e)] for e in frozen}
+    sim.step(12)
+    for e, ks in frozen.items():
+        assert sim.read(L.F_STATUS, e) & L.FLAG_OUT_OF_DOMAIN
+        after = sim.particles(e)
+        for k in ks:
+            for q0, q1 in zip(before[e], after):
+                np.testing.assert_array_equal(q1[k], q0[k])
+    sim.close()
+
+
 @pytest.mark.parametrize("scheme", ["direct", "tiled"])
 def test_nonfinite_flag(gpu, orc, scheme):
     """A particle given a NaN velocity makes its node momenta NaN; the G2P
