@@ -707,8 +707,9 @@ void save_checkpoint(mpm_ctx *c, int k, hipStream_t st)
         launch_unpermute(c->v, c->pid, c->ntot, 3, dst + 3 * N, st);
         launch_unpermute(c->C, c->pid, c->ntot, 9, dst + 6 * N, st);
         launch_unpermute(c->H, c->pid, c->ntot, 9, dst + 15 * N, st);
-        launch_copy_bytes(T.ckpt_tools + (size_t)k * c->tool_slots(), c->tools, sizeof(ToolDev) * c->tool_slots(), st);
-        launch_copy_bytes(T.ckpt_step + (size_t)k * c->n_envs, c->step, sizeof(int32_t) * c->n_envs, st);
+        launch_copies({{T.ckpt_tools + (size_t)k * c->tool_slots(), c->tools, sizeof(ToolDev) * c->tool_slots()},
+                       {T.ckpt_step + (size_t)k * c->n_envs, c->step, sizeof(int32_t) * c->n_envs}},
+                      st);
     });
 }
 
@@ -772,9 +773,10 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
     auto &T = c->tape;
     const size_t N = c->ntot, slots = c->tool_slots();
     timed(c, st, PK_ADJ_MISC, [&] {
-        launch_copy_bytes(T.work, T.ckpt_state + (size_t)seg * 24 * N, sizeof(float) * 24 * N, st);
-        launch_copy_bytes(T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots, st);
-        launch_copy_bytes(T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs, st);
+        launch_copies({{T.work, T.ckpt_state + (size_t)seg * 24 * N, sizeof(float) * 24 * N},
+                       {T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots},
+                       {T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs}},
+                      st);
     });
     for (int j = s_begin; j < s_end; ++j) {
         const int slot = j - s_begin;
@@ -785,8 +787,9 @@ void recompute_segment(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t 
         d.gP = T.seg_P + (size_t)slot * c->total_nodes;
         d.gV = T.seg_V + (size_t)slot * c->total_nodes;
         timed(c, st, PK_ADJ_MISC, [&] {
-            launch_copy_bytes(T.seg_state + (size_t)slot * 24 * N, T.work, sizeof(float) * 24 * N, st);
-            launch_copy_bytes(T.seg_tools + (size_t)slot * slots, T.work_tools, sizeof(ToolDev) * slots, st);
+            launch_copies({{T.seg_state + (size_t)slot * 24 * N, T.work, sizeof(float) * 24 * N},
+                           {T.seg_tools + (size_t)slot * slots, T.work_tools, sizeof(ToolDev) * slots}},
+                          st);
             launch_fill_f4(d.gP, c->total_nodes, st);
         });
         timed(c, st, PK_P2G_DIRECT, [&] { launch_p2g_direct(d, st); });
@@ -820,8 +823,9 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
     c->items_valid = false;   // the live state's work items were overwritten
     if (c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
     timed(c, st, PK_ADJ_MISC, [&] {
-        launch_copy_bytes(T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots, st);
-        launch_copy_bytes(T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs, st);
+        launch_copies({{T.work_tools, T.ckpt_tools + (size_t)seg * slots, sizeof(ToolDev) * slots},
+                       {T.work_step, T.ckpt_step + (size_t)seg * c->n_envs, sizeof(int32_t) * c->n_envs}},
+                      st);
     });
     const ActiveBuf ta = tape_act(c);
     // substep j: grid pass on slot j's P, then G2P(j) into slot j + 1 fused with P2G(j + 1)
@@ -893,18 +897,20 @@ void record_held(mpm_ctx *c, int n, hipStream_t st)
         timed(c, st, PK_ADJ_MISC, [&] {
             if (seg + 1 < nseg) {
                 launch_unpermute(last, T.perm, c->ntot, 24, T.ckpt_state + (size_t)(seg + 1) * 24 * N, st);
-                launch_copy_bytes(T.ckpt_tools + (size_t)(seg + 1) * slots, T.work_tools, sizeof(ToolDev) * slots, st);
-                launch_copy_bytes(T.ckpt_step + (size_t)(seg + 1) * c->n_envs, T.work_step,
-                                  sizeof(int32_t) * c->n_envs, st);
+                launch_copies({{T.ckpt_tools + (size_t)(seg + 1) * slots, T.work_tools, sizeof(ToolDev) * slots},
+                               {T.ckpt_step + (size_t)(seg + 1) * c->n_envs, T.work_step,
+                                sizeof(int32_t) * c->n_envs}},
+                              st);
             } else {
                 launch_unpermute(last, T.perm, c->ntot, 3, c->x, st);
                 launch_unpermute(last + 3 * N, T.perm, c->ntot, 3, c->v, st);
                 launch_unpermute(last + 6 * N, T.perm, c->ntot, 9, c->C, st);
                 launch_unpermute(last + 15 * N, T.perm, c->ntot, 9, c->H, st);
-                launch_copy_bytes(c->pid, T.iota, sizeof(int32_t) * N, st);
-                launch_copy_bytes(c->tools, T.work_tools, sizeof(ToolDev) * slots, st);
-                launch_copy_bytes(c->step, T.work_step, sizeof(int32_t) * c->n_envs, st);
-                launch_copy_bytes(c->status, T.work_status, sizeof(uint32_t) * c->n_envs, st);
+                launch_copies({{c->pid, T.iota, sizeof(int32_t) * N},
+                               {c->tools, T.work_tools, sizeof(ToolDev) * slots},
+                               {c->step, T.work_step, sizeof(int32_t) * c->n_envs},
+                               {c->status, T.work_status, sizeof(uint32_t) * c->n_envs}},
+                              st);
             }
         });
     }

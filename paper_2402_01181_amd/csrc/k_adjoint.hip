@@ -10,22 +10,25 @@
 //   k_adj_p2g : P2G and the Neo-Hookean stress reversed; gathers the node
 //               adjoints and accumulates dL/dmu, dL/dlambda.
 // The last three also give the adjoints of the state before substep j.
+#include <stdexcept>
+
 #include "mpm_adjoint.h"
 #include "mpm_tile_util.h"
 
 namespace mpm {
 
 // Grid pass of a tape recompute at node g (local index `local` in
-// environment env's grid): like the grid operation, but it writes (m, vhat)
-// back into P, the final velocity into V and the contact decision of the node.
-__device__ __forceinline__ void grid_tape_node(const Dev &d, const EnvDev &e, int env, int64_t g, int64_t local,
-                                               ContactCode *dec)
+// environment env's grid, tool slots at tl): like the grid operation, but it
+// writes (m, vhat) back into P, the final velocity into V and the contact
+// decision of the node.
+__device__ __forceinline__ void grid_tape_node(const Dev &d, const EnvDev &e, const ToolDev *tl, int64_t g,
+                                               int64_t local, ContactCode *dec)
 {
     int i, j, k;
     brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
     const float4 P = gload(d.gP + g);
     ContactRec rec;
-    const float3 v = grid_node_velocity(d, e, env, P, i, j, k, &rec);
+    const float3 v = grid_node_velocity_tl(d, e, tl, P, i, j, k, &rec);
     const float3 vh = node_vhat(d, P);
     gstore(d.gV + g, make_float4(v.x, v.y, v.z, 0.f));
     gstore(d.gP + g, make_float4(P.x, vh.x, vh.y, vh.z));
@@ -42,46 +45,68 @@ __device__ __forceinline__ int env_of_node(const Dev &d, const int64_t *env_gofs
     return lo;
 }
 
-__device__ __forceinline__ bool tape_dense(const TapeList &tl)
-{
-    return tl.dense || uload(tl.far + tl.far_slot) == tl.far_stamp;
-}
-
-// Calls body(env, node, local index) for every node the pass visits: the
-// listed bricks, a wavefront each, or every node.
-// The kernels that call it run 256 threads a workgroup.
-template <class Body>
+// Calls body(env, environment entry, its tool slots, node, local index) for
+// every node the pass visits: the listed bricks, a wavefront each, or every
+// node.  The kernels that call it run 256 threads a workgroup; tls is their
+// LDS room for one environment's tool slots.  The listed pass of a single
+// environment reads its entry, grid offset and tool slots (into tls, with
+// TOOLS) once, in the same round of loads as the list count and each wave's
+// first brick, so a brick's nodes wait for one load (its id) before their own.
+template <bool TOOLS, class Body>
 __device__ __forceinline__ void tape_nodes(const Dev &d, const int64_t *env_gofs, int64_t total_nodes,
-                                           const TapeList &tl, Body &&body)
+                                           const TapeList &tl, ToolDev *tls, Body &&body)
 {
-    if (tape_dense(tl)) {
-        constexpr int T = 256;
-        const int64_t stride = (int64_t)gridDim.x * T;
-        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < total_nodes; g += stride) {
+    constexpr int T = 256, nw = T >> 6;
+    const int lane = threadIdx.x & 63, stride = gridDim.x * nw;
+    int i = blockIdx.x * nw + (threadIdx.x >> 6);
+    // the list holds at most one entry per brick of the grid
+    const int64_t cap = total_nodes / BRICK_NODES;
+    const int n = uload(tl.scount);
+    int b0 = i < cap ? uload(tl.slist + i) : 0;
+    const bool dense = tl.dense || uload(tl.far + tl.far_slot) == tl.far_stamp;
+    if (dense) {
+        const int64_t gs = (int64_t)gridDim.x * T;
+        for (int64_t g = (int64_t)blockIdx.x * T + threadIdx.x; g < total_nodes; g += gs) {
             const int env = env_of_node(d, env_gofs, g);
-            body(env, g, g - gload(env_gofs + env));
+            body(env, load_env(d.env + env), d.tools + (size_t)env * d.max_tools, g, g - gload(env_gofs + env));
         }
         return;
     }
-    constexpr int nw = 256 >> 6;
-    const int lane = threadIdx.x & 63;
-    const int n = uload(tl.scount);
-    for (int i = blockIdx.x * nw + (threadIdx.x >> 6); i < n; i += gridDim.x * nw) {
-        const int b = uload(tl.slist + i), env = uload(tl.brick_env + b);
-        const int64_t g = (int64_t)b * BRICK_NODES + lane;
-        body(env, g, g - gload(env_gofs + env));
+    if (d.n_envs == 1) {
+        const EnvDev e = load_env(d.env);
+        const int64_t o = gload(env_gofs);
+        const ToolDev *t = d.tools;
+        if (TOOLS) {
+            const int words = d.max_tools * (int)(sizeof(ToolDev) / 4);
+            for (int w = threadIdx.x; w < words; w += T)
+                reinterpret_cast<int *>(tls)[w] = gload(reinterpret_cast<const int *>(d.tools) + w);
+            __syncthreads();
+            t = tls;
+        }
+        for (; i < n; i += stride, b0 = i < cap ? uload(tl.slist + i) : 0) {
+            const int64_t g = (int64_t)b0 * BRICK_NODES + lane;
+            body(0, e, t, g, g - o);
+        }
+        return;
+    }
+    for (; i < n; i += stride, b0 = i < cap ? uload(tl.slist + i) : 0) {
+        const int env = uload(tl.brick_env + b0);
+        const int64_t g = (int64_t)b0 * BRICK_NODES + lane;
+        body(env, load_env(d.env + env), d.tools + (size_t)env * d.max_tools, g, g - gload(env_gofs + env));
     }
 }
 
 __global__ __launch_bounds__(256) void k_grid_tape(Dev d, const int64_t *env_gofs, int64_t total_nodes,
                                                    ContactCode *dec, ToolDev *snap, int slots, TapeList tl)
 {
+    __shared__ ToolDev tls[MAX_TOOLS];
     if (snap)
         for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < slots; t += (int64_t)gridDim.x * 256)
             snap[t] = d.tools[t];
-    tape_nodes(d, env_gofs, total_nodes, tl, [&](int env, int64_t g, int64_t local) {
-        grid_tape_node(d, load_env(d.env + env), env, g, local, dec);
-    });
+    tape_nodes<true>(d, env_gofs, total_nodes, tl, tls,
+                     [&](int, const EnvDev &e, const ToolDev *t, int64_t g, int64_t local) {
+                         grid_tape_node(d, e, t, g, local, dec);
+                     });
 }
 
 __device__ __forceinline__ void weight_grads(const Stencil &s, float dw[3][3])
@@ -198,7 +223,7 @@ __global__ __launch_bounds__(256) void k_adj_g2p(Dev d, AdjBuf a)
 // Reverse of the grid operation at one node with mass; vb is the adjoint of
 // the node's final velocity.  Returns the adjoint of vhat and adds the
 // contact tool's velocity / position adjoints.
-__device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, int env, float3 vh, int i, int j, int k,
+__device__ __forceinline__ float3 node_adjoint(const ToolDev *tl, const EnvDev &e, float3 vh, int i, int j, int k,
                                                ContactCode code, float3 vb, int &tool, float3 &ub, float3 &Tb)
 {
     tool = -1;
@@ -207,7 +232,7 @@ __device__ __forceinline__ float3 node_adjoint(const Dev &d, const EnvDev &e, in
     if (boundary_node(e, i, j, k)) return make_float3(0.f, 0.f, 0.f);
     if (code < 0) return vb;
     const int t = code >> 2, branch = code & 3;
-    const ToolDev &T = d.tools[(size_t)env * d.max_tools + t];
+    const ToolDev &T = tl[t];
     tool = t;
     ub = vb;                                   // v = v_rel' + u
     if (branch == 2) return make_float3(0.f, 0.f, 0.f);
@@ -270,17 +295,19 @@ __device__ __forceinline__ void wave_tool_add(const Dev &d, const AdjBuf &a, int
 
 // Reverse grid operation at node g; clears the node-velocity adjoint and the
 // tape's (m, v-hat) there.
-__device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int env, int64_t g, int64_t local,
-                                              const ContactCode *dec, const AdjBuf &a)
+__device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, const ToolDev *tl, int env, int64_t g,
+                                              int64_t local, const ContactCode *dec, const AdjBuf &a)
 {
+    // the node's tape entries and velocity adjoint, loaded together
     const float4 P = gload(d.gP + g);                                // (m, vhat)
+    const float4 vb4 = gload(a.gVb + g);
+    const ContactCode code = gload(dec + g);
     // a wavefront is one brick (environments' grids start at multiples of 64 nodes);
     // a brick without mass is in no particle's stencil: its velocity adjoint was
     // never scattered to (still zero), its (m, mv) adjoint is never gathered and
     // its tape entry is already zero
     if (!__any(P.x > 0.0f)) return;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 vb4 = gload(a.gVb + g);
     gstore(a.gVb + g, zero);                // ready for the next reverse substep
     gstore(d.gP + g, zero);                 // the tape grid is zero between recomputes
     int tool = -1;
@@ -289,8 +316,7 @@ __device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int
         int i, j, k;
         brick_local_to_ijk(e, (int)(local >> 6), (int)(local & 63), i, j, k);
         const float3 vh = make_float3(P.y, P.z, P.w);
-        const float3 vhb = node_adjoint(d, e, env, vh, i, j, k, gload(dec + g), make_float3(vb4.x, vb4.y, vb4.z),
-                                        tool, ub, Tb);
+        const float3 vhb = node_adjoint(tl, e, vh, i, j, k, code, make_float3(vb4.x, vb4.y, vb4.z), tool, ub, Tb);
         // vhat = P/m + dt g:  Pbar = vhbar/m,  mbar = -vhbar . (P/m) / m
         const float pm0 = vh.x - d.dt * d.gx, pm1 = vh.y - d.dt * d.gy, pm2 = vh.z - d.dt * d.gz;
         const float mb = -(vhb.x * pm0 + vhb.y * pm1 + vhb.z * pm2) / P.x;
@@ -306,9 +332,11 @@ __device__ __forceinline__ void adj_grid_node(const Dev &d, const EnvDev &e, int
 __global__ __launch_bounds__(256) void k_adj_grid(Dev d, const int64_t *env_gofs, int64_t total_nodes,
                                                   const ContactCode *dec, AdjBuf a, TapeList tl)
 {
-    tape_nodes(d, env_gofs, total_nodes, tl, [&](int env, int64_t g, int64_t local) {
-        adj_grid_node(d, load_env(d.env + env), env, g, local, dec, a);
-    });
+    __shared__ ToolDev tls[MAX_TOOLS];
+    tape_nodes<true>(d, env_gofs, total_nodes, tl, tls,
+                     [&](int env, const EnvDev &e, const ToolDev *t, int64_t g, int64_t local) {
+                         adj_grid_node(d, e, t, env, g, local, dec, a);
+                     });
 }
 
 // Sum per environment over a wavefront, then one double atomic per wave.
@@ -452,20 +480,38 @@ __global__ __launch_bounds__(256) void k_adj_p2g(Dev d, AdjBuf a)
 
 // Chain the per-substep tool gradients through T_{s+1} = T_s + dt u_s and
 // the Lame parameters through (E, nu).  One thread per (env, tool).
-__global__ void k_adj_finish(Dev d, AdjBuf a, int n, double *gE, double *gnu, double *gu, double *gT)
+__global__ __launch_bounds__(256) void k_adj_finish(Dev d, AdjBuf a, int n, double *gE, double *gnu, double *gu, double *gT)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     int nt = d.max_tools > 0 ? d.max_tools : 1;
     if (t >= d.n_envs * nt) return;
     int env = t / nt, tool = t % nt;
     if (d.max_tools > 0) {
+        // dL/du_j = ubar_j + dt (Tbar_{j+1} + ... + Tbar_{n-1}), summed from the last
+        // substep down; K substeps' terms are loaded together before they are used
+        constexpr int K = 16;
+        const size_t ib = ((size_t)env * d.max_tools + tool) * a.max_tape * 3;
+        const size_t ob = ((size_t)env * d.max_tools + tool) * (size_t)n * 3;
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int j = n - 1; j >= 0; --j) {
-            size_t o = (((size_t)env * d.max_tools + tool) * a.max_tape + j) * 3;
-            size_t oo = (((size_t)env * d.max_tools + tool) * n + j) * 3;
-            for (int c = 0; c < 3; ++c) {
-                if (gu) gstore(gu + oo + c, gload(a.ubar + o + c) + (double)d.dt * acc[c]);
-                acc[c] += gload(a.Tbar + o + c);
+        for (int j1 = n; j1 > 0; j1 -= K) {
+            double ub[K][3], tb[K][3];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const int j = j1 - 1 - q;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ub[q][c] = j >= 0 && gu ? gload(a.ubar + ib + (size_t)j * 3 + c) : 0.0;
+                    tb[q][c] = j >= 0 ? gload(a.Tbar + ib + (size_t)j * 3 + c) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const int j = j1 - 1 - q;   // j < 0: past the first substep, its terms are zero
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (gu && j >= 0) gstore(gu + ob + (size_t)j * 3 + c, ub[q][c] + (double)d.dt * acc[c]);
+                    acc[c] += tb[q][c];
+                }
             }
         }
         if (gT)
@@ -511,6 +557,17 @@ __global__ void k_unpermute(const float *src, const int32_t *pid, int ntot, int 
 
 __global__ void k_copy_words(uint32_t *dst, const uint32_t *src, size_t n)
 {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        gstore(dst + i, gload(src + i));
+}
+
+// Up to COPY_JOBS word copies in one launch: job blockIdx.y.
+__global__ void k_copy_jobs(CopyJobs j)
+{
+    const int q = blockIdx.y;
+    uint32_t *dst = j.dst[q];
+    const uint32_t *src = j.src[q];
+    const size_t n = j.words[q];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         gstore(dst + i, gload(src + i));
 }
@@ -1082,8 +1139,10 @@ void launch_adj_g2p(const Dev &d, const AdjBuf &a, hipStream_t st)
 
 __global__ __launch_bounds__(256) void k_tape_clear(Dev d, const int64_t *env_gofs, int64_t total_nodes, TapeList tl)
 {
-    tape_nodes(d, env_gofs, total_nodes, tl,
-               [&](int, int64_t g, int64_t) { gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f)); });
+    tape_nodes<false>(d, env_gofs, total_nodes, tl, nullptr,
+                      [&](int, const EnvDev &, const ToolDev *, int64_t g, int64_t) {
+                          gstore(d.gP + g, make_float4(0.f, 0.f, 0.f, 0.f));
+                      });
 }
 
 void launch_tape_clear(const Dev &d, const int64_t *env_gofs, int64_t total_nodes, const TapeList &tl,
@@ -1153,6 +1212,22 @@ void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
     size_t n = bytes / 4;
     launch_k(k_copy_words, dim3(blocks_for((int64_t)n)), dim3(256), 0, st, static_cast<uint32_t *>(dst),
                        static_cast<const uint32_t *>(src), n);
+}
+
+void launch_copies(std::initializer_list<CopySpec> jobs, hipStream_t st)
+{
+    if (jobs.size() == 0 || jobs.size() > (size_t)COPY_JOBS) throw std::logic_error("launch_copies: 1 to 4 jobs");
+    CopyJobs j{};
+    size_t most = 0;
+    int q = 0;
+    for (const CopySpec &c : jobs) {
+        j.dst[q] = static_cast<uint32_t *>(c.dst);
+        j.src[q] = static_cast<const uint32_t *>(c.src);
+        j.words[q] = c.bytes / 4;
+        most = j.words[q] > most ? j.words[q] : most;
+        ++q;
+    }
+    launch_k(k_copy_jobs, dim3(blocks_for((int64_t)most), q), dim3(256), 0, st, j);
 }
 
 void launch_fill_f64(double *p, int64_t n, hipStream_t st)

@@ -1,5 +1,7 @@
 // Reverse-mode (adjoint) substep: tape layout and kernel launchers.
 #pragma once
+#include <initializer_list>
+
 #include "mpm_tiled.h"
 
 namespace mpm {
@@ -66,6 +68,19 @@ void launch_permute(const float *src, const int32_t *perm, int ntot, int comps, 
                     hipStream_t st);
 void launch_unpermute(const float *src, const int32_t *pid, int ntot, int comps, float *dst, hipStream_t st);
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
+// Several copies (bytes a multiple of 4, regions disjoint) in one launch.
+constexpr int COPY_JOBS = 4;
+struct CopySpec {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+struct CopyJobs {
+    uint32_t *dst[COPY_JOBS];
+    const uint32_t *src[COPY_JOBS];
+    size_t words[COPY_JOBS];
+};
+void launch_copies(std::initializer_list<CopySpec> jobs, hipStream_t st);
 void launch_fill_f64(double *p, int64_t n, hipStream_t st);
 
 }  // namespace mpm
