@@ -191,6 +191,55 @@ def test_adjoint_with_particles_leaving_their_tiles(gpu, orc, pers):
         assert e <= TOL_GRAD, (name, e)
 
 
+@pytest.mark.parametrize("pers,hold", [(0, False), (1, True)])
+def test_adjoint_two_environments_match_oracle(gpu, orc, pers, hold):
+    """Two environments of different sizes (32^3 and 64^3 grids), particle
+    counts, materials and tool paths in one context: the reverse grid passes
+    then look up each brick's environment and tool slots, and the gradient
+    chain runs once per (environment, tool).  Each environment's gradients
+    against the oracle's adjoint of that environment alone; hold: the tape
+    kept whole."""
+    Sim, L, torch = gpu
+    S, k = 12, 5
+    sa, ea = _pressing_scene(81, 1500, 32, S)
+    sb, eb = _pressing_scene(82, 2500, 64, S, scenes.CONTACT_STICKY)
+    eb.E, eb.nu = float(np.float32(2.5e4)), float(np.float32(0.3))
+    sc = scenes.Scene("two-slabs", [ea, eb], dt=sa.dt, substeps=S)
+    sizes = [ea.x.shape[0], eb.x.shape[0]]
+    ofs = np.concatenate([[0], np.cumsum(sizes)])
+    _say(f"adjoint, two environments: {sizes} particles on 32^3 / 64^3, {S} substeps, checkpoints every {k}, "
+         f"persistent {pers}, held tape {hold}")
+    rng = np.random.default_rng(9)
+    W = [[rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 3, 3)),
+          rng.standard_normal((n, 3, 3))] for n in sizes]
+    sim = Sim(sc, max_tape=S, checkpoint_every=k, hold_tape=hold,
+              options={L.OPT_SCHEME: L.SCHEME_TILED, L.OPT_SORT_EVERY: 3, L.OPT_PERSISTENT: pers,
+                       L.OPT_GRID_AT_STAGING: pers})
+    sim.step(S, record_tape=True)
+    assert [sim.read(L.F_STATUS, e) for e in range(2)] == [0, 0]
+    soa = lambda f, c: torch.tensor(np.concatenate([w[f].reshape(-1, c) for w in W]).T.copy(), dtype=torch.float32)
+    g = sim.adjoint(S, soa(0, 3), soa(1, 3), soa(2, 9), soa(3, 9))
+    for e in range(2):
+        o = oracle_sim_like(orc, sc, e).adjoint(S, *W[e])
+        assert np.abs(o["gu"]).max() > 0
+        sl = slice(int(ofs[e]), int(ofs[e + 1]))
+        n = sizes[e]
+        checks = {
+            "xbar0": (g["xbar0"][:, sl].cpu().numpy().T, o["xbar"].reshape(n, 3)),
+            "vbar0": (g["vbar0"][:, sl].cpu().numpy().T, o["vbar"].reshape(n, 3)),
+            "Cbar0": (g["Cbar0"][:, sl].cpu().numpy().T, o["Cbar"].reshape(n, 9)),
+            "Fbar0": (g["Fbar0"][:, sl].cpu().numpy().T, o["Fbar"].reshape(n, 9)),
+            "gE": (g["gE"].cpu().numpy()[e:e + 1], [o["gE"]]),
+            "gnu": (g["gnu"].cpu().numpy()[e:e + 1], [o["gnu"]]),
+            "gu": (g["gu"].cpu().numpy()[e, 0], o["gu"][:, 0]),
+            "gT": (g["gT"].cpu().numpy()[e, 0], o["gT0"][0]),
+        }
+        for name, (a, b) in checks.items():
+            err = _rel(a, b)
+            _say(f"  env {e} {name}: rel err {err:.2e}")
+            assert err <= TOL_GRAD, (e, name, err)
+
+
 @pytest.mark.parametrize("pers", [0, 1])
 def test_adjoint_window_shorter_than_tape(gpu, orc, pers):
     """Reverse only the last 7 of 12 recorded substeps."""
