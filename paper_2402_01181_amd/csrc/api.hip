@@ -817,6 +817,14 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
 {
     auto &T = c->tape;
     const size_t N = c->ntot, slots = c->tool_slots();
+    // a held recording that was not reversed (or only partly) left its grids in this
+    // segment tape: clear them, over the bricks its recompute listed, before the sort
+    // below replaces that list
+    for (int slot = 0; slot < T.segs[T.sel].dirty; ++slot) {
+        Dev d = c->dev();
+        d.gP = T.seg_P + (size_t)slot * c->total_nodes;
+        timed(c, st, PK_ADJ_MISC, [&] { launch_tape_clear(d, c->env_gofs, c->total_nodes, tape_list(c, slot), st); });
+    }
     Dev dc = state_view(c, T.ckpt_state + (size_t)seg * 24 * N);
     dc.pid = T.iota;
     timed(c, st, PK_SORT, [&] { launch_sort(dc, c->sort, tape_act(c), c->total_bricks, c->item, seg_view(c, 0), 1, st); });
@@ -844,6 +852,9 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
     // with a stamp no earlier recompute used
     T.stamp = ++T.stamp_top;
     T.segs[T.sel].stamp = T.stamp;
+    // P2G fills the grids of slots 0 .. s_end - s_begin - 1; the reverse, or the clears of
+    // the substeps before its window, zero them again
+    T.segs[T.sel].dirty = s_end - s_begin;
     auto stamped = [&](TiledArgs a, int slot) {
         a.act = ta;
         a.far_stamp = T.tfar;
@@ -1522,6 +1533,7 @@ mpm_status mpm_substep_adjoint(mpm_ctx *c, int32_t n_substeps, const mpm_adjoint
                 launch_tape_clear(d, c->env_gofs, c->total_nodes, tiled ? tape_list(c, j - sb) : dense_list(c), st);
             });
         }
+        T.segs[T.sel].dirty = 0;
     }
     T.held = 0;
     if (multi) {

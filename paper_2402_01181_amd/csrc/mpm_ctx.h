@@ -149,6 +149,7 @@ struct mpm_ctx {
             int4 *items = nullptr;
             int2 *totals = nullptr;
             int stamp = 0;
+            int dirty = 0;                  // slots whose tape grid P a recompute filled and no reverse cleared
         };
         std::vector<Seg> segs;
         int sel = 0;                        // the selected segment tape
