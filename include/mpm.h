@@ -180,7 +180,11 @@ typedef struct {
                                     at each segment start) instead of running the forward form, and the next
                                     mpm_substep_adjoint reverses the held tapes without recomputing them.  It
                                     consumes them: a second adjoint of the same recording recomputes from the
-                                    checkpoints.  With the direct scheme a recording keeps checkpoints only.
+                                    checkpoints.  Any sequence of recordings, substeps and adjoint windows
+                                    is valid: tapes a reverse did not consume (an adjoint window shorter
+                                    than the recording, a recording never reversed) are cleared by the next
+                                    recompute into them.  With the direct scheme a recording keeps
+                                    checkpoints only.
                                     0: checkpoints only (every adjoint recomputes) */
 } mpm_desc;
 
