@@ -253,6 +253,38 @@ def test_held_tape_grids_cleared_before_reuse(gpu, orc):
     held.close()
 
 
+def test_held_tape_option_with_direct_scheme(gpu, orc):
+    """hold_tape with the direct (untiled) scheme: the recording keeps
+    checkpoints only and every adjoint recomputes, each segment into its own
+    tape buffers.  Two adjoints of one recording against the oracle."""
+    Sim, L, torch = gpu
+    S, N, n, k = 12, 2000, 32, 5
+    sc, env = _pressing_scene(55, N, n, S)
+    _say(f"held tape option, direct scheme: {N} particles, {n}^3, {S} substeps, segments of {k}")
+    rng = np.random.default_rng(12)
+    W = [rng.standard_normal((N, 3)), rng.standard_normal((N, 3)), rng.standard_normal((N, 3, 3)),
+         rng.standard_normal((N, 3, 3))]
+    soa = lambda a, c: torch.tensor(a.reshape(N, c).T.copy(), dtype=torch.float32)
+    seeds = (soa(W[0], 3), soa(W[1], 3), soa(W[2], 9), soa(W[3], 9))
+    sim = Sim(sc, max_tape=S, checkpoint_every=k, options={L.OPT_SCHEME: L.SCHEME_DIRECT}, hold_tape=True)
+    sim.step(S, record_tape=True)
+    o = oracle_sim_like(orc, sc).adjoint(S, *W)
+    for what in ("first", "second"):
+        g = sim.adjoint(S, *seeds)
+        checks = {
+            "xbar0": (g["xbar0"].cpu().numpy().T, o["xbar"].reshape(N, 3)),
+            "Fbar0": (g["Fbar0"].cpu().numpy().T, o["Fbar"].reshape(N, 9)),
+            "gE": (g["gE"].cpu().numpy(), [o["gE"]]),
+            "gu": (g["gu"].cpu().numpy()[0, 0], o["gu"][:, 0]),
+            "gT": (g["gT"].cpu().numpy()[0, 0], o["gT0"][0]),
+        }
+        for name, (a, b) in checks.items():
+            e = _rel(a, b)
+            _say(f"  {what} adjoint {name}: rel err {e:.2e}")
+            assert e <= TOL_GRAD, (what, name, e)
+    sim.close()
+
+
 @pytest.mark.parametrize("pers,hold", [(0, False), (1, True)])
 def test_adjoint_two_environments_match_oracle(gpu, orc, pers, hold):
     """Two environments of different sizes (32^3 and 64^3 grids), particle
