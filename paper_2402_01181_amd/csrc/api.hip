@@ -813,7 +813,7 @@ ParticleBuf seg_view(const mpm_ctx *c, int slot)
 // checkpoint is counting-sorted by brick into tape slot 0 (its permutation
 // kept), then each substep runs the tiled P2G head into its own tape grid,
 // the dense tape grid pass, and the tiled G2P tail writing the next slot.
-void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t st)
+void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStream_t st, const Dev *src = nullptr)
 {
     auto &T = c->tape;
     const size_t N = c->ntot, slots = c->tool_slots();
@@ -825,8 +825,11 @@ void recompute_segment_tiled(mpm_ctx *c, int seg, int s_begin, int s_end, hipStr
         d.gP = T.seg_P + (size_t)slot * c->total_nodes;
         timed(c, st, PK_ADJ_MISC, [&] { launch_tape_clear(d, c->env_gofs, c->total_nodes, tape_list(c, slot), st); });
     }
+    // the sort's input: the checkpoint (original order), or src, the same state held
+    // elsewhere with its particle index
     Dev dc = state_view(c, T.ckpt_state + (size_t)seg * 24 * N);
     dc.pid = T.iota;
+    if (src) dc = *src;
     timed(c, st, PK_SORT, [&] { launch_sort(dc, c->sort, tape_act(c), c->total_bricks, c->item, seg_view(c, 0), 1, st); });
     c->items_valid = false;   // the live state's work items were overwritten
     if (c->tiled_blocks == 0) c->tiled_blocks = tiled_workgroups(c->block);
@@ -902,8 +905,17 @@ void record_held(mpm_ctx *c, int n, hipStream_t st)
     timed(c, st, PK_ADJ_MISC, [&] { launch_copy_bytes(T.work_status, c->status, sizeof(uint32_t) * c->n_envs, st); });
     for (int seg = 0; seg < nseg; ++seg) {
         const int sb = seg * k, se = std::min(sb + k, n);
+        // the segment's sort reads particles already in cell order (the live state, then the
+        // previous segment's last slot), not the checkpoint: its histogram atomics then
+        // aggregate per wavefront
+        Dev src = c->dev();
+        if (seg > 0) {
+            const auto &p = T.segs[seg - 1];
+            src = state_view(c, p.state + (size_t)k * 24 * N);
+            src.pid = p.perm;
+        }
         select_seg(c, seg);
-        recompute_segment_tiled(c, seg, sb, se, st);
+        recompute_segment_tiled(c, seg, sb, se, st, &src);
         const float *last = T.seg_state + (size_t)(se - sb) * 24 * N;
         timed(c, st, PK_ADJ_MISC, [&] {
             if (seg + 1 < nseg) {
